@@ -1,0 +1,680 @@
+// far_oracle.cpp -- TEST INFRASTRUCTURE ONLY (see far_oracle.h).
+//
+// A plain, deliberately unoptimised FP64 CPU implementation of the FAR-LIO
+// registration hot path (arXiv 2606.26010, Sec. III-A).  Every function below
+// names the passage of the paper it follows; where the paper is silent the
+// reading taken is stated in the comment.  Build flags: -O2 -ffp-contract=off
+// (no fused multiply-add, no fast-math), so every expression is evaluated
+// exactly in the order written.
+//
+// OpenMP is used only across independent queries; every sum is taken
+// sequentially in point order, so results do not depend on the thread count.
+
+#include "far_oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Voxel keys (Sec. III-A.2, the cuVoxelMap paragraph): a key is the triple of
+// integer voxel indices floor(x / v) of a point.  Floor, not truncation, so
+// that negative coordinates fall into the voxel below.  Keys are limited to
+// [-2^20, 2^20) per axis (the library packs 21 bits per axis); a point outside
+// that range is an invalid input.
+// ---------------------------------------------------------------------------
+const int64_t kKeyLimit = int64_t(1) << 20;
+
+struct Key {
+  int64_t x, y, z;
+  bool operator==(const Key& o) const { return x == o.x && y == o.y && z == o.z; }
+};
+struct KeyHash {
+  size_t operator()(const Key& k) const {
+    // Any hash works: the oracle's results are defined without one.
+    uint64_t h = uint64_t(k.x) * 0x9E3779B97F4A7C15ull;
+    h ^= uint64_t(k.y) + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
+    h ^= uint64_t(k.z) + 0x94D049BB133111EBull + (h << 6) + (h >> 2);
+    return size_t(h);
+  }
+};
+
+Key key_of(double x, double y, double z, double v) {
+  return Key{int64_t(std::floor(x / v)), int64_t(std::floor(y / v)),
+             int64_t(std::floor(z / v))};
+}
+bool key_in_range(const Key& k) {
+  return k.x >= -kKeyLimit && k.x < kKeyLimit && k.y >= -kKeyLimit &&
+         k.y < kKeyLimit && k.z >= -kKeyLimit && k.z < kKeyLimit;
+}
+
+// Squared distance in FP64, evaluated as (dx*dx + dy*dy) + dz*dz with each
+// difference formed from the FP64 values of the operands.  This fixed order is
+// the ranking key of every neighbour decision.
+double dist2(double ax, double ay, double az, double bx, double by, double bz) {
+  double dx = ax - bx, dy = ay - by, dz = az - bz;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+struct Pt {
+  double x, y, z;
+};
+
+// ---------------------------------------------------------------------------
+// Covariance regularisation, Eq. (1): Sigma = (C^-1 / ||C^-1||_F)^-1 with
+// C = Sigma_hat + 1e-3 I.  Written out literally: invert C, normalise the
+// inverse by its Frobenius norm, invert again.  The 3x3 inverses use the
+// adjugate over the determinant.
+// ---------------------------------------------------------------------------
+void inv3(const double A[9], double out[9]) {
+  double c00 = A[4] * A[8] - A[5] * A[7];
+  double c01 = A[5] * A[6] - A[3] * A[8];
+  double c02 = A[3] * A[7] - A[4] * A[6];
+  double c10 = A[2] * A[7] - A[1] * A[8];
+  double c11 = A[0] * A[8] - A[2] * A[6];
+  double c12 = A[1] * A[6] - A[0] * A[7];
+  double c20 = A[1] * A[5] - A[2] * A[4];
+  double c21 = A[2] * A[3] - A[0] * A[5];
+  double c22 = A[0] * A[4] - A[1] * A[3];
+  double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  // adj(A) is the transpose of the cofactor matrix
+  out[0] = c00 / det; out[1] = c10 / det; out[2] = c20 / det;
+  out[3] = c01 / det; out[4] = c11 / det; out[5] = c21 / det;
+  out[6] = c02 / det; out[7] = c12 / det; out[8] = c22 / det;
+}
+
+void regularize(const double S_hat[9], double Sigma[9]) {
+  double C[9];
+  for (int i = 0; i < 9; ++i) C[i] = S_hat[i];
+  C[0] += 1e-3; C[4] += 1e-3; C[8] += 1e-3;
+  double Ci[9];
+  inv3(C, Ci);
+  double fro = 0.0;
+  for (int i = 0; i < 9; ++i) fro += Ci[i] * Ci[i];
+  fro = std::sqrt(fro);
+  double Cn[9];
+  for (int i = 0; i < 9; ++i) Cn[i] = Ci[i] / fro;
+  inv3(Cn, Sigma);
+}
+
+// Sample covariance of k points, two passes (mean first, then the centred
+// outer products), normalised by 1/k.  The neighbourhood includes the point
+// itself (Sec. III-A.2: covariance from the k nearest neighbours).
+void covariance_of(const std::vector<Pt>& nb, double S[9]) {
+  double k = double(nb.size());
+  double mx = 0, my = 0, mz = 0;
+  for (const Pt& q : nb) { mx += q.x; my += q.y; mz += q.z; }
+  mx /= k; my /= k; mz /= k;
+  double sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+  for (const Pt& q : nb) {
+    double dx = q.x - mx, dy = q.y - my, dz = q.z - mz;
+    sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+    syy += dy * dy; syz += dy * dz; szz += dz * dz;
+  }
+  S[0] = sxx / k; S[1] = sxy / k; S[2] = sxz / k;
+  S[3] = sxy / k; S[4] = syy / k; S[5] = syz / k;
+  S[6] = sxz / k; S[7] = syz / k; S[8] = szz / k;
+}
+
+// ---------------------------------------------------------------------------
+// A voxel grid: voxel key -> ids of its points in insertion order.  Used both
+// for the submap Q and for the per-scan cloud whose covariances are needed
+// (Sec. III-A.2: the scan covariances use their own voxel-map instance).
+// ---------------------------------------------------------------------------
+struct Grid {
+  double v = 1.0;
+  std::unordered_map<Key, std::vector<int64_t>, KeyHash> vox;
+  std::vector<Pt> pts;  // by id, FP64 copies of the stored FP32 values
+};
+
+// k nearest points of the grid within radius r of q, ranked by (d2, id).
+// Candidates are every point of the 27 voxels around key(q).  For r <= v this
+// equals the brute-force k nearest of the whole cloud within r: a point within
+// r of q differs from q by at most v per axis, so its voxel index differs by
+// at most one per axis.
+void knn(const Grid& g, double qx, double qy, double qz, int k, double r,
+         std::vector<std::pair<double, int64_t>>& out) {
+  out.clear();
+  double r2 = r * r;
+  Key kq = key_of(qx, qy, qz, g.v);
+  std::vector<std::pair<double, int64_t>> cand;
+  for (int64_t dx = -1; dx <= 1; ++dx)
+    for (int64_t dy = -1; dy <= 1; ++dy)
+      for (int64_t dz = -1; dz <= 1; ++dz) {
+        auto it = g.vox.find(Key{kq.x + dx, kq.y + dy, kq.z + dz});
+        if (it == g.vox.end()) continue;
+        for (int64_t id : it->second) {
+          const Pt& p = g.pts[size_t(id)];
+          double d2 = dist2(p.x, p.y, p.z, qx, qy, qz);
+          if (d2 <= r2) cand.push_back({d2, id});
+        }
+      }
+  std::sort(cand.begin(), cand.end());  // lexicographic (d2, id)
+  size_t m = std::min(cand.size(), size_t(k));
+  out.assign(cand.begin(), cand.begin() + m);
+}
+
+// Regularised covariance of point p of grid g, as six upper-triangle values.
+// valid <=> exactly k neighbours within r = v (reading of "lacks sufficient
+// neighbors", Sec. III-A.2, sparsity-aware GICP paragraph).
+bool point_covariance(const Grid& g, const Pt& p, int k, double out6[6]) {
+  std::vector<std::pair<double, int64_t>> nb;
+  knn(g, p.x, p.y, p.z, k, g.v, nb);
+  if (int(nb.size()) != k) {
+    for (int i = 0; i < 6; ++i) out6[i] = 0.0;
+    return false;
+  }
+  std::vector<Pt> pts;
+  for (auto& e : nb) pts.push_back(g.pts[size_t(e.second)]);
+  double S[9], Sig[9];
+  covariance_of(pts, S);
+  regularize(S, Sig);
+  out6[0] = Sig[0]; out6[1] = Sig[1]; out6[2] = Sig[2];
+  out6[3] = Sig[4]; out6[4] = Sig[5]; out6[5] = Sig[8];
+  return true;
+}
+
+bool finite3(double x, double y, double z) {
+  return std::isfinite(x) && std::isfinite(y) && std::isfinite(z);
+}
+
+// 4x4 row-major helpers.
+void matmul4(const double A[16], const double B[16], double C[16]) {
+  double t[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < 4; ++l) s += A[i * 4 + l] * B[l * 4 + j];
+      t[i * 4 + j] = s;
+    }
+  std::memcpy(C, t, sizeof(t));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The submap (Sec. III-A.3 "Adaptive, Local Submap", and the cuVoxelMap
+// paragraph of Sec. III-A.2): voxels of edge v holding at most N_max points,
+// each point carrying a regularised covariance computed when it is added.
+// ---------------------------------------------------------------------------
+struct orc_map {
+  Grid g;
+  int32_t nmax = 20;
+  double dmin = 0.0;
+  int32_t k_cov = 5;
+  int64_t point_cap = 0, voxel_cap = 0;
+  std::vector<float> fx, fy, fz;  // stored FP32 coordinates, by id
+  std::vector<float> cov;         // 6 per id, FP32
+  std::vector<uint8_t> valid;
+};
+
+extern "C" {
+
+orc_map* orc_map_new(double v, int32_t nmax, double dmin, int32_t k_cov,
+                     int64_t point_cap, int64_t voxel_cap) {
+  if (!(v > 0.0) || nmax < 1 || k_cov < 1 || point_cap < 1 || voxel_cap < 1)
+    return nullptr;
+  orc_map* m = new orc_map();
+  m->g.v = v;
+  m->nmax = nmax;
+  m->dmin = dmin;
+  m->k_cov = k_cov;
+  m->point_cap = point_cap;
+  m->voxel_cap = voxel_cap;
+  return m;
+}
+
+void orc_map_free(orc_map* m) { delete m; }
+int64_t orc_map_size(const orc_map* m) { return int64_t(m->g.pts.size()); }
+int64_t orc_map_nvoxels(const orc_map* m) { return int64_t(m->g.vox.size()); }
+
+// Capped insert (Sec. III-A.3: points enter their voxel "as long as the number
+// of points inside it is below" the cap; Sec. III-A.2: "regularly spaced"
+// points with a minimum spacing).  Semantics, taken as sequential in input
+// order:
+//   for each finite point i in order, with K = key(p_i):
+//     accept iff count(K) < cap_i and, when dmin > 0, every point already in
+//     K (including points accepted earlier in this batch) is at squared
+//     distance >= dmin^2;  an accepted point receives the next id.
+// Then the covariances of the added points are computed on the updated map;
+// existing points keep theirs (Sec. III-A.3, last paragraph).
+// Capacity rules: keys of every finite batch point are added to the voxel set
+// (a voxel may end up empty); if that would exceed voxel_cap the batch is
+// refused unchanged.  An acceptance beyond point_cap stops the batch: the
+// points accepted before it stay.
+int orc_map_insert(orc_map* m, const float* xyz, int64_t n, const int32_t* caps,
+                   int64_t* n_accepted, int64_t* n_skipped) {
+  if (n < 0) return 1;
+  const float* X = xyz;
+  const float* Y = xyz + n;
+  const float* Z = xyz + 2 * n;
+  double v = m->g.v;
+  // Range check and voxel-capacity check first; nothing changes on failure.
+  std::unordered_map<Key, int, KeyHash> fresh;
+  int64_t skipped = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double x = X[i], y = Y[i], z = Z[i];
+    if (!finite3(x, y, z)) { ++skipped; continue; }
+    Key K = key_of(x, y, z, v);
+    if (!key_in_range(K)) return 1;
+    if (m->g.vox.find(K) == m->g.vox.end()) fresh[K] = 1;
+  }
+  if (n_skipped) *n_skipped = skipped;
+  if (int64_t(m->g.vox.size()) + int64_t(fresh.size()) > m->voxel_cap) {
+    if (n_accepted) *n_accepted = 0;
+    return 2;
+  }
+  for (auto& kv : fresh) m->g.vox[kv.first];  // create the (empty) voxels
+
+  double dmin2 = m->dmin * m->dmin;
+  int64_t first_new = int64_t(m->g.pts.size());
+  int status = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double x = X[i], y = Y[i], z = Z[i];
+    if (!finite3(x, y, z)) continue;
+    Key K = key_of(x, y, z, v);
+    std::vector<int64_t>& ids = m->g.vox[K];
+    int64_t cap = m->nmax;
+    if (caps) cap = std::min<int64_t>(caps[i], m->nmax);
+    if (int64_t(ids.size()) >= cap) continue;
+    bool spaced = true;
+    if (m->dmin > 0.0) {
+      for (int64_t id : ids) {
+        const Pt& q = m->g.pts[size_t(id)];
+        if (dist2(x, y, z, q.x, q.y, q.z) < dmin2) { spaced = false; break; }
+      }
+    }
+    if (!spaced) continue;
+    if (int64_t(m->g.pts.size()) >= m->point_cap) { status = 2; break; }
+    int64_t id = int64_t(m->g.pts.size());
+    ids.push_back(id);
+    m->g.pts.push_back(Pt{x, y, z});
+    m->fx.push_back(X[i]); m->fy.push_back(Y[i]); m->fz.push_back(Z[i]);
+  }
+  int64_t n_new = int64_t(m->g.pts.size()) - first_new;
+  m->cov.resize(size_t(m->g.pts.size()) * 6, 0.0f);
+  m->valid.resize(m->g.pts.size(), 0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t j = 0; j < n_new; ++j) {
+    int64_t id = first_new + j;
+    double c6[6];
+    bool ok = point_covariance(m->g, m->g.pts[size_t(id)], m->k_cov, c6);
+    for (int t = 0; t < 6; ++t) m->cov[size_t(id) * 6 + t] = float(c6[t]);
+    m->valid[size_t(id)] = ok ? 1 : 0;
+  }
+  if (n_accepted) *n_accepted = n_new;
+  return status;
+}
+
+void orc_map_export(const orc_map* m, float* xyz, float* cov6, uint8_t* valid) {
+  int64_t N = int64_t(m->g.pts.size());
+  for (int64_t i = 0; i < N; ++i) {
+    if (xyz) {
+      xyz[i] = m->fx[size_t(i)];
+      xyz[N + i] = m->fy[size_t(i)];
+      xyz[2 * N + i] = m->fz[size_t(i)];
+    }
+    if (cov6)
+      for (int t = 0; t < 6; ++t) cov6[t * N + i] = m->cov[size_t(i) * 6 + t];
+    if (valid) valid[i] = m->valid[size_t(i)];
+  }
+}
+
+int orc_map_knn(const orc_map* m, const float* q, int64_t n, int32_t k, double r,
+                int32_t* idx, double* d2, int32_t* count) {
+  if (n < 0 || k < 1 || !(r > 0.0) || r > m->g.v) return 1;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    double x = q[i], y = q[n + i], z = q[2 * n + i];
+    std::vector<std::pair<double, int64_t>> nb;
+    if (finite3(x, y, z) && key_in_range(key_of(x, y, z, m->g.v)))
+      knn(m->g, x, y, z, k, r, nb);
+    for (int32_t j = 0; j < k; ++j) {
+      bool have = j < int32_t(nb.size());
+      idx[i * k + j] = have ? int32_t(nb[size_t(j)].second) : -1;
+      if (d2) d2[i * k + j] = have ? nb[size_t(j)].first : -1.0;
+    }
+    if (count) count[i] = int32_t(nb.size());
+  }
+  return 0;
+}
+
+// Covariances of a scan against itself (Sec. III-A.2: "computing the point
+// covariances using an instance of the cuVoxelMap"): every point of the scan
+// goes into the grid (no cap), then each point's covariance uses its k nearest
+// scan points within r = v, itself included.
+int orc_scan_covariances(const float* xyz, int64_t n, double v, int32_t k,
+                         double* cov6, uint8_t* valid) {
+  if (n < 0 || !(v > 0.0) || k < 1) return 1;
+  Grid g;
+  g.v = v;
+  g.pts.resize(size_t(n));
+  std::vector<char> ok(size_t(n), 0);
+  for (int64_t i = 0; i < n; ++i) {
+    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    g.pts[size_t(i)] = Pt{x, y, z};
+    if (!finite3(x, y, z)) continue;
+    Key K = key_of(x, y, z, v);
+    if (!key_in_range(K)) return 1;
+    ok[size_t(i)] = 1;
+    g.vox[K].push_back(i);
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    double c6[6] = {0, 0, 0, 0, 0, 0};
+    bool good = ok[size_t(i)] && point_covariance(g, g.pts[size_t(i)], k, c6);
+    for (int t = 0; t < 6; ++t) cov6[t * n + i] = good ? c6[t] : 0.0;
+    valid[i] = good ? 1 : 0;
+  }
+  return 0;
+}
+
+void orc_regularize_cov(const double S[9], double out[9]) { regularize(S, out); }
+
+void orc_voxel_keys(const float* xyz, int64_t n, double v, int64_t* keys3) {
+  for (int64_t i = 0; i < n; ++i) {
+    Key K = key_of(xyz[i], xyz[n + i], xyz[2 * n + i], v);
+    keys3[i * 3 + 0] = K.x;
+    keys3[i * 3 + 1] = K.y;
+    keys3[i * 3 + 2] = K.z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SE(3) exponential of the twist delta = (omega, v): rotation by Rodrigues'
+// formula, translation V v with V = I + B W + C W^2 (W = [omega]x).  Used for
+// the left-multiplicative iterate update of Eq. (6).
+// ---------------------------------------------------------------------------
+void orc_se3_exp(const double d[6], double T[16]) {
+  double wx = d[0], wy = d[1], wz = d[2];
+  double th2 = wx * wx + wy * wy + wz * wz;
+  double th = std::sqrt(th2);
+  double A, B, C;
+  if (th < 1e-6) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = std::sin(th) / th;
+    B = (1.0 - std::cos(th)) / th2;
+    C = (th - std::sin(th)) / (th2 * th);
+  }
+  double W[9] = {0, -wz, wy, wz, 0, -wx, -wy, wx, 0};
+  double W2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += W[i * 3 + l] * W[l * 3 + j];
+      W2[i * 3 + j] = s;
+    }
+  double R[9], V[9];
+  for (int i = 0; i < 9; ++i) {
+    double I = (i % 4 == 0) ? 1.0 : 0.0;
+    R[i] = I + A * W[i] + B * W2[i];
+    V[i] = I + B * W[i] + C * W2[i];
+  }
+  for (int i = 0; i < 16; ++i) T[i] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) T[i * 4 + j] = R[i * 3 + j];
+    T[i * 4 + 3] = V[i * 3 + 0] * d[3] + V[i * 3 + 1] * d[4] + V[i * 3 + 2] * d[5];
+  }
+  T[15] = 1.0;
+}
+
+// Cholesky factorisation H = L L^T and the solve H x = b.  A pivot that is not
+// above 1e-12 times the largest diagonal entry (or not finite) means H is not
+// positive definite: returns 4.
+int orc_cholesky_solve6(const double H[36], const double b[6], double x[6]) {
+  double L[36] = {0};
+  double dmax = 0.0;
+  for (int i = 0; i < 6; ++i) dmax = std::max(dmax, std::fabs(H[i * 7]));
+  for (int j = 0; j < 6; ++j) {
+    double s = H[j * 6 + j];
+    for (int l = 0; l < j; ++l) s -= L[j * 6 + l] * L[j * 6 + l];
+    if (!(s > 1e-12 * dmax) || !std::isfinite(s)) return 4;
+    L[j * 6 + j] = std::sqrt(s);
+    for (int i = j + 1; i < 6; ++i) {
+      double t = H[i * 6 + j];
+      for (int l = 0; l < j; ++l) t -= L[i * 6 + l] * L[j * 6 + l];
+      L[i * 6 + j] = t / L[j * 6 + j];
+    }
+  }
+  double y[6];
+  for (int i = 0; i < 6; ++i) {
+    double s = b[i];
+    for (int l = 0; l < i; ++l) s -= L[i * 6 + l] * y[l];
+    y[i] = s / L[i * 6 + i];
+  }
+  for (int i = 5; i >= 0; --i) {
+    double s = y[i];
+    for (int l = i + 1; l < 6; ++l) s -= L[l * 6 + i] * x[l];
+    x[i] = s / L[i * 6 + i];
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// One linearisation of the GICP objective, Eq. (4), at pose T.
+//  - Eq. (2)/(6): p_i = R s_i + t, in FP64 as ((R00 sx + R01 sy) + R02 sz) + tx.
+//  - Correspondence: the nearest map point within min(tau, v) (Sec. III-A.2,
+//    "closest Euclidean neighbor" plus the adaptive threshold); none = outlier.
+//  - Eq. (3): d_i = r_i - p_i.
+//  - Eq. (4): M = Sigma_r + R Sigma_s R^T, W = M^-1, e2 = d^T W d.
+//    Sparsity-aware case: if either covariance is invalid, Sigma_r = I and
+//    Sigma_s = 0, i.e. M = I (point-to-point).
+//  - Eq. (5), Cauchy kernel on the Mahalanobis norm e = sqrt(e2):
+//    rho = kappa^2/2 ln(1 + e2/kappa^2), IRLS weight w = kappa^2/(kappa^2+e2).
+//  - Jacobian of d with respect to a left perturbation about the centre c,
+//    p(delta) = c + Exp(delta)(p - c), delta = (omega, v):
+//    J = [ [p - c]x , -I ].
+//  - H = sum w J^T W J, b = sum w J^T W d, cost = sum rho.
+// ---------------------------------------------------------------------------
+int orc_linearize(const orc_map* m, const float* src, const float* src_cov6,
+                  const uint8_t* src_valid, int64_t n, const double T[16],
+                  double tau, double kappa, const double c[3], double H[36],
+                  double b[6], double* cost, int64_t* n_inliers, int32_t* corr,
+                  double* detail) {
+  if (n < 0 || !(tau > 0.0) || !(kappa > 0.0)) return 1;
+  const double R00 = T[0], R01 = T[1], R02 = T[2], tx = T[3];
+  const double R10 = T[4], R11 = T[5], R12 = T[6], ty = T[7];
+  const double R20 = T[8], R21 = T[9], R22 = T[10], tz = T[11];
+  const double cx = c ? c[0] : 0.0, cy = c ? c[1] : 0.0, cz = c ? c[2] : 0.0;
+  const double r = std::min(tau, m->g.v);
+  const double k2 = kappa * kappa;
+
+  // Per-point contributions first (parallel), then sums in point order.
+  std::vector<double> rowH(size_t(n) * 21, 0.0), rowb(size_t(n) * 6, 0.0);
+  std::vector<double> rowrho(size_t(n), 0.0);
+  std::vector<int32_t> rowj(size_t(n), -1);
+
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    if (detail)
+      for (int t = 0; t < 18; ++t) detail[i * 18 + t] = NAN;
+    double sx = src[i], sy = src[n + i], sz = src[2 * n + i];
+    if (!finite3(sx, sy, sz)) continue;
+    double px = ((R00 * sx + R01 * sy) + R02 * sz) + tx;
+    double py = ((R10 * sx + R11 * sy) + R12 * sz) + ty;
+    double pz = ((R20 * sx + R21 * sy) + R22 * sz) + tz;
+    if (!key_in_range(key_of(px, py, pz, m->g.v))) continue;
+    std::vector<std::pair<double, int64_t>> nb;
+    knn(m->g, px, py, pz, 1, r, nb);
+    if (nb.empty()) continue;
+    int64_t j = nb[0].second;
+    rowj[size_t(i)] = int32_t(j);
+    const Pt& q = m->g.pts[size_t(j)];
+    double d[3] = {q.x - px, q.y - py, q.z - pz};
+
+    double M[9];
+    bool vs = src_valid[i] != 0, vr = m->valid[size_t(j)] != 0;
+    if (vs && vr) {
+      const float* cr = &m->cov[size_t(j) * 6];
+      double Sr[9] = {cr[0], cr[1], cr[2], cr[1], cr[3], cr[4], cr[2], cr[4], cr[5]};
+      double cs[6];
+      for (int t = 0; t < 6; ++t) cs[t] = src_cov6[t * n + i];
+      double Ss[9] = {cs[0], cs[1], cs[2], cs[1], cs[3], cs[4], cs[2], cs[4], cs[5]};
+      double R[9] = {R00, R01, R02, R10, R11, R12, R20, R21, R22};
+      double RS[9], RSRt[9];
+      for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) {
+          double s = 0.0;
+          for (int l = 0; l < 3; ++l) s += R[a * 3 + l] * Ss[l * 3 + bb];
+          RS[a * 3 + bb] = s;
+        }
+      for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) {
+          double s = 0.0;
+          for (int l = 0; l < 3; ++l) s += RS[a * 3 + l] * R[bb * 3 + l];
+          RSRt[a * 3 + bb] = s;
+        }
+      for (int t = 0; t < 9; ++t) M[t] = Sr[t] + RSRt[t];
+    } else {
+      for (int t = 0; t < 9; ++t) M[t] = (t % 4 == 0) ? 1.0 : 0.0;
+    }
+    double W[9];
+    inv3(M, W);
+    double Wd[3];
+    for (int a = 0; a < 3; ++a)
+      Wd[a] = W[a * 3 + 0] * d[0] + W[a * 3 + 1] * d[1] + W[a * 3 + 2] * d[2];
+    double e2 = d[0] * Wd[0] + d[1] * Wd[1] + d[2] * Wd[2];
+    double w = k2 / (k2 + e2);
+    double rho = 0.5 * k2 * std::log1p(e2 / k2);
+
+    // J (3x6) = [ [a]x , -I ], a = p - c.
+    double ax = px - cx, ay = py - cy, az = pz - cz;
+    double J[18] = {0.0, -az, ay, -1.0, 0.0, 0.0,
+                    az, 0.0, -ax, 0.0, -1.0, 0.0,
+                    -ay, ax, 0.0, 0.0, 0.0, -1.0};
+    double WJ[18];
+    for (int a = 0; a < 3; ++a)
+      for (int col = 0; col < 6; ++col) {
+        double s = 0.0;
+        for (int l = 0; l < 3; ++l) s += W[a * 3 + l] * J[l * 6 + col];
+        WJ[a * 6 + col] = s;
+      }
+    int t = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int bcol = a; bcol < 6; ++bcol) {
+        double s = 0.0;
+        for (int l = 0; l < 3; ++l) s += J[l * 6 + a] * WJ[l * 6 + bcol];
+        rowH[size_t(i) * 21 + t++] = w * s;
+      }
+    for (int a = 0; a < 6; ++a) {
+      double s = 0.0;
+      for (int l = 0; l < 3; ++l) s += J[l * 6 + a] * Wd[l];
+      rowb[size_t(i) * 6 + a] = w * s;
+    }
+    rowrho[size_t(i)] = rho;
+    if (detail) {
+      double* D = &detail[i * 18];
+      D[0] = px; D[1] = py; D[2] = pz;
+      D[3] = q.x; D[4] = q.y; D[5] = q.z;
+      for (int u = 0; u < 9; ++u) D[6 + u] = W[u];
+      D[15] = w; D[16] = rho; D[17] = e2;
+    }
+  }
+
+  double Hs[21] = {0}, bs[6] = {0}, cs = 0.0;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (corr) corr[i] = rowj[size_t(i)];
+    if (rowj[size_t(i)] < 0) continue;
+    for (int t = 0; t < 21; ++t) Hs[t] += rowH[size_t(i) * 21 + t];
+    for (int t = 0; t < 6; ++t) bs[t] += rowb[size_t(i) * 6 + t];
+    cs += rowrho[size_t(i)];
+    ++cnt;
+  }
+  int t = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int bcol = a; bcol < 6; ++bcol) {
+      H[a * 6 + bcol] = Hs[t];
+      H[bcol * 6 + a] = Hs[t];
+      ++t;
+    }
+  for (int a = 0; a < 6; ++a) b[a] = bs[a];
+  *cost = cs;
+  *n_inliers = cnt;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Newton align (Sec. III-A.2, Eq. (6) and the stopping rule after it).
+// Each iteration linearises about c (the current translation when recenter is
+// set, else the origin), solves H delta = -b by Cholesky and applies
+// T <- T_c Exp(delta) T_c^-1 T.  Stops when ||delta||_2 <= eps (reading of the
+// garbled norm criterion as the norm of the increment's twist) or after
+// max_iters iterations (replacing the wall-clock limit).  Fewer than six
+// inliers or a non positive definite H stop the loop with T unchanged by that
+// iteration.
+// ---------------------------------------------------------------------------
+int orc_align(const orc_map* m, const float* src, const float* src_cov6,
+              const uint8_t* src_valid, int64_t n, const double T0[16],
+              double tau, double kappa, int32_t max_iters, double eps,
+              int32_t recenter, double T_out[16], int32_t* iters,
+              int32_t* converged, double H[36], double b[6], double* cost,
+              int64_t* n_inliers) {
+  if (max_iters < 1) return 1;
+  double T[16];
+  std::memcpy(T, T0, sizeof(T));
+  int status = 0;
+  *iters = 0;
+  *converged = 0;
+  for (int it = 0; it < max_iters; ++it) {
+    double c[3] = {0.0, 0.0, 0.0};
+    if (recenter) { c[0] = T[3]; c[1] = T[7]; c[2] = T[11]; }
+    int rc = orc_linearize(m, src, src_cov6, src_valid, n, T, tau, kappa, c, H,
+                           b, cost, n_inliers, nullptr, nullptr);
+    if (rc) { status = rc; break; }
+    if (*n_inliers < 6) { status = 5; break; }
+    double nb[6], delta[6];
+    for (int a = 0; a < 6; ++a) nb[a] = -b[a];
+    if (orc_cholesky_solve6(H, nb, delta)) { status = 4; break; }
+    double E[16], Tc[16], Tci[16], A1[16], A2[16];
+    orc_se3_exp(delta, E);
+    for (int a = 0; a < 16; ++a) Tc[a] = Tci[a] = (a % 5 == 0) ? 1.0 : 0.0;
+    Tc[3] = c[0]; Tc[7] = c[1]; Tc[11] = c[2];
+    Tci[3] = -c[0]; Tci[7] = -c[1]; Tci[11] = -c[2];
+    matmul4(Tci, T, A1);
+    matmul4(E, A1, A2);
+    matmul4(Tc, A2, T);
+    *iters = it + 1;
+    double nrm = 0.0;
+    for (int a = 0; a < 6; ++a) nrm += delta[a] * delta[a];
+    if (std::sqrt(nrm) <= eps) { *converged = 1; break; }
+  }
+  std::memcpy(T_out, T, sizeof(T));
+  return status;
+}
+
+void orc_touch_stats(const orc_map* m, const float* src, int64_t n,
+                     const double T[16], int64_t* n_voxels, int64_t* n_points) {
+  std::unordered_map<Key, int, KeyHash> seen;
+  for (int64_t i = 0; i < n; ++i) {
+    double sx = src[i], sy = src[n + i], sz = src[2 * n + i];
+    if (!finite3(sx, sy, sz)) continue;
+    double px = ((T[0] * sx + T[1] * sy) + T[2] * sz) + T[3];
+    double py = ((T[4] * sx + T[5] * sy) + T[6] * sz) + T[7];
+    double pz = ((T[8] * sx + T[9] * sy) + T[10] * sz) + T[11];
+    Key K = key_of(px, py, pz, m->g.v);
+    for (int64_t dx = -1; dx <= 1; ++dx)
+      for (int64_t dy = -1; dy <= 1; ++dy)
+        for (int64_t dz = -1; dz <= 1; ++dz) {
+          Key N{K.x + dx, K.y + dy, K.z + dz};
+          auto it = m->g.vox.find(N);
+          if (it != m->g.vox.end() && !it->second.empty()) seen[N] = 1;
+        }
+  }
+  int64_t pts = 0;
+  for (auto& kv : seen) pts += int64_t(m->g.vox.at(kv.first).size());
+  *n_voxels = int64_t(seen.size());
+  *n_points = pts;
+}
+
+}  // extern "C"

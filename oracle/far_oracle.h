@@ -1,0 +1,86 @@
+/*
+ * far_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU implementation of the FAR-LIO registration hot path
+ * (arXiv 2606.26010, Sec. III-A "LiDAR Scan Pipeline"), written to check the
+ * GPU library against.  It shares no code with the GPU library; only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load it.
+ *
+ * Layouts: every point array is SoA float32 [3][n] (x row, then y, then z);
+ * every covariance array is SoA [6][n] holding the upper triangle in the order
+ * xx, xy, xz, yy, yz, zz.  Poses are row-major 4x4 doubles (map <- sensor).
+ *
+ * Return codes mirror the library's status values:
+ *   0 ok, 1 invalid argument, 2 capacity, 4 not positive definite,
+ *   5 too few correspondences.
+ */
+#ifndef FAR_ORACLE_H
+#define FAR_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_map orc_map;
+
+/* Map with voxel edge v, per-voxel cap nmax, insert spacing dmin (0 = off),
+ * k_cov neighbours for covariances, fixed point / voxel capacities. */
+orc_map* orc_map_new(double v, int32_t nmax, double dmin, int32_t k_cov,
+                     int64_t point_cap, int64_t voxel_cap);
+void     orc_map_free(orc_map* m);
+int64_t  orc_map_size(const orc_map* m);      /* points held */
+int64_t  orc_map_nvoxels(const orc_map* m);   /* voxel keys held */
+
+/* Sequential capped insert (input order), then covariances of the added
+ * points on the updated map.  caps: per-point cap or NULL (= nmax). */
+int orc_map_insert(orc_map* m, const float* xyz, int64_t n, const int32_t* caps,
+                   int64_t* n_accepted, int64_t* n_skipped);
+
+/* Export in ID order: xyz [3][N], cov6 [6][N] (float), valid [N]. */
+void orc_map_export(const orc_map* m, float* xyz, float* cov6, uint8_t* valid);
+
+/* k nearest map points within radius r (r <= v) of each query.
+ * idx [n][k] (-1 pad), d2 [n][k] (FP64, -1 pad), count [n]. */
+int orc_map_knn(const orc_map* m, const float* q, int64_t n, int32_t k, double r,
+                int32_t* idx, double* d2, int32_t* count);
+
+/* Per-point regularised covariances of a cloud against itself (no cap). */
+int orc_scan_covariances(const float* xyz, int64_t n, double v, int32_t k,
+                         double* cov6, uint8_t* valid);
+
+/* One linearisation at pose T about centre c (NULL = origin).
+ * src_cov6 is float SoA [6][n] (the stored precision).
+ * Outputs: H [36] row-major, b [6], cost, inlier count; optional per-point
+ * correspondence ids corr [n] (-1 = none) and per-point detail rows
+ * detail [n][22] = (p[3], r[3], W[9], w, rho, e2, pad...) or NULL. */
+int orc_linearize(const orc_map* m, const float* src, const float* src_cov6,
+                  const uint8_t* src_valid, int64_t n, const double T[16],
+                  double tau, double kappa, const double c[3],
+                  double H[36], double b[6], double* cost, int64_t* n_inliers,
+                  int32_t* corr, double* detail);
+
+/* Gauss-Newton align.  Returns status; writes T_out, iterations, converged and
+ * the last linearisation. */
+int orc_align(const orc_map* m, const float* src, const float* src_cov6,
+              const uint8_t* src_valid, int64_t n, const double T0[16],
+              double tau, double kappa, int32_t max_iters, double eps,
+              int32_t recenter, double T_out[16], int32_t* iters,
+              int32_t* converged, double H[36], double b[6], double* cost,
+              int64_t* n_inliers);
+
+/* Building blocks exposed for pinning. */
+void orc_voxel_keys(const float* xyz, int64_t n, double v, int64_t* keys3);
+void orc_se3_exp(const double delta[6], double T[16]);
+int  orc_cholesky_solve6(const double H[36], const double b[6], double x[6]);
+void orc_regularize_cov(const double S[9], double out[9]);
+
+/* Map-side work counters of one linearisation at pose T: number of distinct
+ * non-empty map voxels in the 27-neighbourhoods of the transformed queries and
+ * the number of points they hold (used for the algorithmic byte model). */
+void orc_touch_stats(const orc_map* m, const float* src, int64_t n,
+                     const double T[16], int64_t* n_voxels, int64_t* n_points);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,220 @@
+"""ctypes wrapper of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Every array crossing this wrapper is a C-contiguous numpy array; points are
+SoA float32 [3, n], covariances SoA [6, n] (xx, xy, xz, yy, yz, zz), poses
+row-major float64 [4, 4].
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+
+
+def _opt(t):
+    """Pointer argument that also accepts None."""
+    class _P(C.c_void_p):
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return t.from_param(obj)
+    return _P
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
+                os.path.join(_HERE, "far_oracle.cpp")):
+            _build.build()
+        L = C.CDLL(path)
+        L.orc_map_new.restype = C.c_void_p
+        L.orc_map_new.argtypes = [C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_int64, C.c_int64]
+        L.orc_map_free.argtypes = [C.c_void_p]
+        L.orc_map_size.restype = C.c_int64
+        L.orc_map_size.argtypes = [C.c_void_p]
+        L.orc_map_nvoxels.restype = C.c_int64
+        L.orc_map_nvoxels.argtypes = [C.c_void_p]
+        L.orc_map_insert.argtypes = [C.c_void_p, _f32p, C.c_int64, _opt(_i32p),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.orc_map_export.argtypes = [C.c_void_p, _opt(_f32p), _opt(_f32p), _opt(_u8p)]
+        L.orc_map_knn.argtypes = [C.c_void_p, _f32p, C.c_int64, C.c_int32, C.c_double,
+                                  _i32p, _opt(_f64p), _opt(_i32p)]
+        L.orc_scan_covariances.argtypes = [_f32p, C.c_int64, C.c_double, C.c_int32, _f64p, _u8p]
+        L.orc_linearize.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p,
+                                    C.c_double, C.c_double, _opt(_f64p), _f64p, _f64p,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                    _opt(_i32p), _opt(_f64p)]
+        L.orc_align.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p,
+                                C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                _f64p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                _f64p, _f64p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.orc_voxel_keys.argtypes = [_f32p, C.c_int64, C.c_double, _i64p]
+        L.orc_se3_exp.argtypes = [_f64p, _f64p]
+        L.orc_cholesky_solve6.argtypes = [_f64p, _f64p, _f64p]
+        L.orc_regularize_cov.argtypes = [_f64p, _f64p]
+        L.orc_touch_stats.argtypes = [C.c_void_p, _f32p, C.c_int64, _f64p,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        _lib = L
+    return _lib
+
+
+def _soa(xyz):
+    a = np.ascontiguousarray(xyz, dtype=np.float32)
+    assert a.ndim == 2 and a.shape[0] == 3, "points are SoA float32 [3, n]"
+    return a
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+class Map:
+    """Oracle voxel map (sequential capped insert, FP64 decisions)."""
+
+    def __init__(self, voxel_size, max_pts_per_voxel, min_spacing, k_cov,
+                 point_capacity=1 << 24, voxel_capacity=1 << 22):
+        self._h = lib().orc_map_new(voxel_size, max_pts_per_voxel, min_spacing, k_cov,
+                                    point_capacity, voxel_capacity)
+        if not self._h:
+            raise OracleError(1, "orc_map_new")
+        self.voxel_size = voxel_size
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_map_free(self._h)
+            self._h = None
+
+    def insert(self, xyz, caps=None, check=True):
+        a = _soa(xyz)
+        n = a.shape[1]
+        c = None if caps is None else np.ascontiguousarray(caps, dtype=np.int32)
+        acc, skip = C.c_int64(0), C.c_int64(0)
+        rc = lib().orc_map_insert(self._h, a, n, c, C.byref(acc), C.byref(skip))
+        if check and rc != 0:
+            raise OracleError(rc, "orc_map_insert")
+        return (rc, acc.value, skip.value) if not check else acc.value
+
+    @property
+    def size(self):
+        return lib().orc_map_size(self._h)
+
+    @property
+    def n_voxels(self):
+        return lib().orc_map_nvoxels(self._h)
+
+    def export(self):
+        N = self.size
+        xyz = np.zeros((3, N), np.float32)
+        cov = np.zeros((6, N), np.float32)
+        val = np.zeros(N, np.uint8)
+        lib().orc_map_export(self._h, xyz, cov, val)
+        return xyz, cov, val
+
+    def knn(self, q, k, r):
+        a = _soa(q)
+        n = a.shape[1]
+        idx = np.zeros((n, k), np.int32)
+        d2 = np.zeros((n, k), np.float64)
+        cnt = np.zeros(n, np.int32)
+        rc = lib().orc_map_knn(self._h, a, n, k, r, idx, d2, cnt)
+        if rc:
+            raise OracleError(rc, "orc_map_knn")
+        return idx, d2, cnt
+
+    def linearize(self, src, cov6, valid, T, tau, kappa, c=None, want_corr=False,
+                  want_detail=False):
+        a = _soa(src)
+        n = a.shape[1]
+        cov = np.ascontiguousarray(cov6, dtype=np.float32)
+        val = np.ascontiguousarray(valid, dtype=np.uint8)
+        T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+        cc = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        H = np.zeros(36); b = np.zeros(6)
+        cost, cnt = C.c_double(0), C.c_int64(0)
+        corr = np.zeros(n, np.int32) if want_corr else None
+        det = np.zeros((n, 18)) if want_detail else None
+        rc = lib().orc_linearize(self._h, a, cov, val, n, T, tau, kappa, cc, H, b,
+                                 C.byref(cost), C.byref(cnt), corr, det)
+        if rc:
+            raise OracleError(rc, "orc_linearize")
+        out = dict(H=H.reshape(6, 6), b=b, cost=cost.value, n_inliers=cnt.value)
+        if want_corr:
+            out["corr"] = corr
+        if want_detail:
+            out["detail"] = det
+        return out
+
+    def align(self, src, cov6, valid, T0, tau, kappa, max_iters=10, eps=1e-6, recenter=1):
+        a = _soa(src)
+        n = a.shape[1]
+        cov = np.ascontiguousarray(cov6, dtype=np.float32)
+        val = np.ascontiguousarray(valid, dtype=np.uint8)
+        T0 = np.ascontiguousarray(T0, dtype=np.float64).reshape(16)
+        Tout = np.zeros(16)
+        it, conv = C.c_int32(0), C.c_int32(0)
+        H = np.zeros(36); b = np.zeros(6)
+        cost, cnt = C.c_double(0), C.c_int64(0)
+        rc = lib().orc_align(self._h, a, cov, val, n, T0, tau, kappa, max_iters, eps,
+                             recenter, Tout, C.byref(it), C.byref(conv), H, b,
+                             C.byref(cost), C.byref(cnt))
+        return dict(status=rc, T=Tout.reshape(4, 4), iters=it.value, converged=conv.value,
+                    H=H.reshape(6, 6), b=b, cost=cost.value, n_inliers=cnt.value)
+
+    def touch_stats(self, src, T):
+        a = _soa(src)
+        T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+        u, p = C.c_int64(0), C.c_int64(0)
+        lib().orc_touch_stats(self._h, a, a.shape[1], T, C.byref(u), C.byref(p))
+        return u.value, p.value
+
+
+def scan_covariances(xyz, voxel_size, k):
+    a = _soa(xyz)
+    n = a.shape[1]
+    cov = np.zeros((6, n), np.float64)
+    val = np.zeros(n, np.uint8)
+    rc = lib().orc_scan_covariances(a, n, voxel_size, k, cov, val)
+    if rc:
+        raise OracleError(rc, "orc_scan_covariances")
+    return cov, val
+
+
+def voxel_keys(xyz, v):
+    a = _soa(xyz)
+    out = np.zeros((a.shape[1], 3), np.int64)
+    lib().orc_voxel_keys(a, a.shape[1], v, out)
+    return out
+
+
+def se3_exp(delta):
+    T = np.zeros(16)
+    lib().orc_se3_exp(np.ascontiguousarray(delta, dtype=np.float64), T)
+    return T.reshape(4, 4)
+
+
+def cholesky_solve6(H, b):
+    x = np.zeros(6)
+    rc = lib().orc_cholesky_solve6(np.ascontiguousarray(H, dtype=np.float64).reshape(36),
+                                   np.ascontiguousarray(b, dtype=np.float64), x)
+    return rc, x
+
+
+def regularize_cov(S):
+    out = np.zeros(9)
+    lib().orc_regularize_cov(np.ascontiguousarray(S, dtype=np.float64).reshape(9), out)
+    return out.reshape(3, 3)

@@ -1,0 +1,349 @@
+"""Seeded synthetic inputs shaped like the paper's LiDAR workloads.
+
+The paper evaluates on KITTI, MulRan and racing recordings, none of which are
+available here; these generators stand in for them.  This module holds none of
+the registration method's arithmetic (no voxel keys, covariances, matching or
+optimisation): only scene geometry, a spinning-LiDAR ray caster, ground-truth
+poses and random sampling.  Both the GPU library's tests and the FP64 oracle
+consume what it produces.
+
+Every generator takes an integer seed and draws from
+numpy.random.Generator(PCG64(seed)); per-scan draws use the sub-seed
+seed * 1000 + scan.  Points are returned SoA float32 [3, n]; poses are
+row-major float64 [4, 4] mapping sensor coordinates into the map frame.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# Poses
+# ---------------------------------------------------------------------------
+def pose(R: np.ndarray, t) -> np.ndarray:
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = t
+    return T
+
+
+def pose_inverse(T: np.ndarray) -> np.ndarray:
+    R = T[:3, :3]
+    return pose(R.T, -R.T @ T[:3, 3])
+
+
+def unit_vector(g: np.random.Generator) -> np.ndarray:
+    v = g.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def random_offset(g: np.random.Generator, trans: float, angle_deg: float,
+                  exact: bool = True) -> np.ndarray:
+    """Rigid offset with rotation angle_deg about a random axis and translation
+    of norm trans along a random direction (exact=True), or uniform in the ball
+    and angle (exact=False)."""
+    axis = unit_vector(g)
+    ang = math.radians(angle_deg) * (1.0 if exact else g.uniform())
+    tr = trans * (1.0 if exact else g.uniform() ** (1.0 / 3.0))
+    return pose(Rotation.from_rotvec(axis * ang).as_matrix(), unit_vector(g) * tr)
+
+
+def apply(T: np.ndarray, xyz: np.ndarray) -> np.ndarray:
+    """Transform SoA points by T in float64 and round to float32."""
+    p = T[:3, :3] @ xyz.astype(np.float64) + T[:3, 3:4]
+    return p.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Tiny scene: ground, two walls, two vertical cylinders
+# ---------------------------------------------------------------------------
+def _sample_rect(g, n, origin, u, v):
+    a, b = g.uniform(size=n), g.uniform(size=n)
+    return (np.asarray(origin)[:, None] + np.outer(u, a) + np.outer(v, b))
+
+
+def _sample_cyl(g, n, cx, cy, r, h):
+    th = g.uniform(0, 2 * math.pi, size=n)
+    z = g.uniform(0, h, size=n)
+    return np.stack([cx + r * np.cos(th), cy + r * np.sin(th), z])
+
+
+def tiny_scene_samples(g: np.random.Generator, n: int) -> np.ndarray:
+    """n area-uniform samples of: ground z=0 over [-20,20]^2, wall x=16 and wall
+    y=16 (40 m long, 5 m high) and cylinders r=0.5 m, h=4 m at (-3,2), (4,-5)."""
+    parts = [
+        (1600.0, lambda m: _sample_rect(g, m, (-20, -20, 0), (40, 0, 0), (0, 40, 0))),
+        (200.0, lambda m: _sample_rect(g, m, (16, -20, 0), (0, 40, 0), (0, 0, 5))),
+        (200.0, lambda m: _sample_rect(g, m, (-20, 16, 0), (40, 0, 0), (0, 0, 5))),
+        (2 * math.pi * 0.5 * 4, lambda m: _sample_cyl(g, m, -3.0, 2.0, 0.5, 4.0)),
+        (2 * math.pi * 0.5 * 4, lambda m: _sample_cyl(g, m, 4.0, -5.0, 0.5, 4.0)),
+    ]
+    w = np.array([a for a, _ in parts])
+    which = g.choice(len(parts), size=n, p=w / w.sum())
+    out = np.empty((3, n))
+    for j, (_, f) in enumerate(parts):
+        idx = np.nonzero(which == j)[0]
+        if idx.size:
+            out[:, idx] = f(idx.size)
+    return out.astype(np.float32)
+
+
+@dataclass
+class TinyCase:
+    """Plain GICP case: map batches, a noisy moved source and its ground truth."""
+    map_batches: list
+    source: np.ndarray
+    T_gt: np.ndarray
+    voxel_size: float = 1.0
+    max_pts_per_voxel: int = 20
+    min_spacing: float = 1.0 / math.sqrt(20.0)
+    k: int = 5
+    tau: float = 1.0
+    kappa: float = 1.0 / 9.0
+    max_iters: int = 10
+
+
+def make_tiny(seed: int = 1, n_batches: int = 11, batch: int = 5000,
+              n_source: int = 5000, noise: float = 0.02, trans: float = 0.3,
+              angle_deg: float = 2.0) -> TinyCase:
+    g = rng(seed)
+    batches = [tiny_scene_samples(g, batch) for _ in range(n_batches)]
+    x = tiny_scene_samples(g, n_source).astype(np.float64)
+    x += g.normal(scale=noise, size=x.shape)
+    T_gt = random_offset(g, trans, angle_deg)
+    src = apply(pose_inverse(T_gt), x)
+    return TinyCase(batches, src, T_gt)
+
+
+# ---------------------------------------------------------------------------
+# Corridor scene and spinning-LiDAR ray caster
+# ---------------------------------------------------------------------------
+@dataclass
+class Corridor:
+    length: float = 1000.0
+    half_width: float = 15.0
+    wall_height: float = 10.0
+    pole_radius: float = 0.2
+    pole_height: float = 6.0
+    pole_spacing: float = 20.0
+    pole_inset: float = 3.0
+    seed: int = 7
+    poles: np.ndarray = field(default=None, repr=False)  # [P, 2] centres
+
+    def __post_init__(self):
+        if self.poles is None:
+            g = rng(self.seed)
+            xs = np.arange(self.pole_spacing / 2, self.length, self.pole_spacing)
+            ys = self.half_width - self.pole_inset
+            left = np.stack([xs + g.uniform(-2, 2, xs.size), np.full(xs.size, ys)], 1)
+            right = np.stack([xs + g.uniform(-2, 2, xs.size), np.full(xs.size, -ys)], 1)
+            self.poles = np.concatenate([left, right])
+
+    def surface_area(self):
+        return (self.length * 2 * self.half_width + 2 * self.length * self.wall_height
+                + len(self.poles) * 2 * math.pi * self.pole_radius * self.pole_height)
+
+    def surface_samples(self, g: np.random.Generator, n: int) -> np.ndarray:
+        L, W, H = self.length, self.half_width, self.wall_height
+        pa = 2 * math.pi * self.pole_radius * self.pole_height
+        w = np.array([L * 2 * W, L * H, L * H, pa * len(self.poles)])
+        which = g.choice(4, size=n, p=w / w.sum())
+        out = np.empty((3, n))
+        for j in range(4):
+            idx = np.nonzero(which == j)[0]
+            m = idx.size
+            if not m:
+                continue
+            if j == 0:
+                pts = _sample_rect(g, m, (0, -W, 0), (L, 0, 0), (0, 2 * W, 0))
+            elif j == 1:
+                pts = _sample_rect(g, m, (0, W, 0), (L, 0, 0), (0, 0, H))
+            elif j == 2:
+                pts = _sample_rect(g, m, (0, -W, 0), (L, 0, 0), (0, 0, H))
+            else:
+                k = g.integers(0, len(self.poles), size=m)
+                th = g.uniform(0, 2 * math.pi, size=m)
+                pts = np.stack([self.poles[k, 0] + self.pole_radius * np.cos(th),
+                                self.poles[k, 1] + self.pole_radius * np.sin(th),
+                                g.uniform(0, self.pole_height, size=m)])
+            out[:, idx] = pts
+        return out.astype(np.float32)
+
+    def cast(self, origin: np.ndarray, dirs: np.ndarray, max_range: float) -> np.ndarray:
+        """First-hit distance of rays origin + t*dir (dirs [3, m], unit); inf = none."""
+        ox, oy, oz = origin
+        dx, dy, dz = dirs
+        best = np.full(dirs.shape[1], np.inf)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            # ground z = 0 inside the corridor footprint
+            t = -oz / dz
+            x, y = ox + t * dx, oy + t * dy
+            ok = (t > 0) & (x >= 0) & (x <= self.length) & (np.abs(y) <= self.half_width)
+            best = np.where(ok & (t < best), t, best)
+            for ywall in (self.half_width, -self.half_width):
+                t = (ywall - oy) / dy
+                x, z = ox + t * dx, oz + t * dz
+                ok = (t > 0) & (x >= 0) & (x <= self.length) & (z >= 0) & (z <= self.wall_height)
+                best = np.where(ok & (t < best), t, best)
+            near = self.poles[np.hypot(self.poles[:, 0] - ox, self.poles[:, 1] - oy)
+                              < max_range + 1.0]
+            a = dx * dx + dy * dy
+            for cx, cy in near:
+                fx, fy = ox - cx, oy - cy
+                bq = 2 * (fx * dx + fy * dy)
+                cq = fx * fx + fy * fy - self.pole_radius ** 2
+                disc = bq * bq - 4 * a * cq
+                t = (-bq - np.sqrt(np.maximum(disc, 0))) / (2 * a)
+                z = oz + t * dz
+                ok = (disc >= 0) & (t > 0) & (z >= 0) & (z <= self.pole_height)
+                best = np.where(ok & (t < best), t, best)
+        return best
+
+
+@dataclass
+class Lidar:
+    beams: int = 128
+    azimuths: int = 1024
+    elev_min_deg: float = -22.5
+    elev_max_deg: float = 22.5
+    min_range: float = 1.0
+    max_range: float = 120.0
+    range_noise: float = 0.03
+    drop: float = 0.1
+
+    def directions(self) -> np.ndarray:
+        el = np.radians(np.linspace(self.elev_min_deg, self.elev_max_deg, self.beams))
+        az = np.linspace(0, 2 * math.pi, self.azimuths, endpoint=False)
+        # azimuth-major firing order: one column of all beams per azimuth step
+        A, E = np.meshgrid(az, el, indexing="ij")
+        A, E = A.ravel(), E.ravel()
+        return np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), np.sin(E)])
+
+
+def scan(scene: Corridor, lidar: Lidar, T_world_sensor: np.ndarray,
+         g: np.random.Generator) -> np.ndarray:
+    """One instantaneous spinning-LiDAR scan, returned in the sensor frame."""
+    d_s = lidar.directions()
+    R, t = T_world_sensor[:3, :3], T_world_sensor[:3, 3]
+    rng_ = scene.cast(t, R @ d_s, lidar.max_range)
+    rng_ = rng_ + g.normal(scale=lidar.range_noise, size=rng_.shape)
+    keep = np.isfinite(rng_) & (rng_ >= lidar.min_range) & (rng_ <= lidar.max_range)
+    keep &= g.uniform(size=rng_.shape) >= lidar.drop
+    return (d_s[:, keep] * rng_[keep]).astype(np.float32)
+
+
+def trajectory_pose(t: float, speed: float = 70.0, amp: float = 3.0,
+                    period: float = 8.0, height: float = 2.0, x0: float = 5.0) -> np.ndarray:
+    """Smooth path along the corridor: x = x0 + speed t, y = amp sin(2 pi t / period),
+    heading along the velocity."""
+    x = x0 + speed * t
+    y = amp * math.sin(2 * math.pi * t / period)
+    vx = speed
+    vy = amp * 2 * math.pi / period * math.cos(2 * math.pi * t / period)
+    yaw = math.atan2(vy, vx)
+    return pose(Rotation.from_euler("z", yaw).as_matrix(), (x, y, height))
+
+
+@dataclass
+class SequenceCase:
+    scans: list
+    poses: list
+    scene: Corridor
+    voxel_size: float = 1.0
+    max_pts_per_voxel: int = 20
+    min_spacing: float = 1.0 / math.sqrt(20.0)
+    downsample: float = 0.5
+    k: int = 5
+    map_capacity: int = 2_000_000
+    sigma0: float = 1.0 / 3.0
+    r_max: float = 120.0
+
+
+def make_sequence(seed: int = 2, n_scans: int = 100, rate_hz: float = 10.0,
+                  lidar: Lidar | None = None) -> SequenceCase:
+    """Spinning-LiDAR sequence: 128 x 1024 rays per scan along a 70 m/s path."""
+    lidar = lidar or Lidar()
+    scene = Corridor()
+    poses, scans = [], []
+    for s in range(n_scans):
+        T = trajectory_pose(s / rate_hz)
+        poses.append(T)
+        scans.append(scan(scene, lidar, T, rng(seed * 1000 + s)))
+    return SequenceCase(scans, poses, scene)
+
+
+@dataclass
+class BatchCase:
+    """Independent scans of uneven size against one prebuilt map."""
+    map_batches: list
+    map_capacity: int
+    scans: list           # sensor-frame SoA float32 [3, n_s]
+    T_gt: list            # ground-truth poses
+    T0: list              # initial guesses (ground truth times a random offset)
+    scene: Corridor
+    voxel_size: float = 1.0
+    max_pts_per_voxel: int = 20
+    min_spacing: float = 1.0 / math.sqrt(20.0)
+    k: int = 5
+    tau: float = 1.0
+    kappa: float = 1.0 / 9.0
+    max_iters: int = 10
+
+
+def make_batch(seed: int = 3, n_scans: int = 64, n_min: int = 8000, n_max: int = 130000,
+               map_points: int = 2_000_000, map_batch: int = 1_000_000,
+               n_map_batches: int = 8, max_offset_m: float = 0.5,
+               max_offset_deg: float = 3.0, scene: Corridor | None = None) -> BatchCase:
+    """64 scans at random ground-truth poses along a widened corridor (the map
+    needs about 2e5 m^2 of surface to hold 2M points at the default spacing),
+    each subsampled without replacement to n_s ~ U{n_min..n_max} (clamped to the
+    hits of its 128 x 1024 rays) and given its own initial offset."""
+    scene = scene or Corridor(half_width=50.0, wall_height=50.0, pole_height=20.0,
+                              pole_inset=10.0)
+    g = rng(seed)
+    map_batches = [scene.surface_samples(rng(seed * 1000 + 900 + b), map_batch)
+                   for b in range(n_map_batches)]
+    lidar = Lidar()
+    scans, T_gt, T0 = [], [], []
+    for s in range(n_scans):
+        gs = rng(seed * 1000 + s)
+        x = gs.uniform(60.0, scene.length - 60.0)
+        y = gs.uniform(-0.5, 0.5) * scene.half_width
+        yaw = gs.uniform(-math.pi, math.pi)
+        T = pose(Rotation.from_euler("z", yaw).as_matrix(), (x, y, 2.0))
+        pts = scan(scene, lidar, T, gs)
+        n_s = int(gs.integers(n_min, n_max + 1))
+        n_s = min(n_s, pts.shape[1])
+        sel = np.sort(gs.choice(pts.shape[1], size=n_s, replace=False))
+        scans.append(np.ascontiguousarray(pts[:, sel]))
+        T_gt.append(T)
+        T0.append(T @ random_offset(gs, max_offset_m, max_offset_deg, exact=False))
+    del g
+    return BatchCase(map_batches, map_points, scans, T_gt, T0, scene)
+
+
+def random_cloud(seed: int, n: int, extent: float = 4.0, dup_frac: float = 0.0,
+                 on_faces: float = 0.0, v: float = 1.0) -> np.ndarray:
+    """Uniform random cloud in [-extent, extent]^3 with optional exact duplicates
+    and points snapped onto voxel faces (multiples of v) for tie and boundary
+    cases."""
+    g = rng(seed)
+    p = g.uniform(-extent, extent, size=(3, n))
+    if on_faces > 0:
+        m = g.uniform(size=(3, n)) < on_faces
+        p[m] = np.round(p[m] / v) * v
+    p = p.astype(np.float32)
+    if dup_frac > 0:
+        nd = int(n * dup_frac)
+        src = g.integers(0, n, size=nd)
+        dst = g.integers(0, n, size=nd)
+        p[:, dst] = p[:, src]
+    return np.ascontiguousarray(p)

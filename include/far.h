@@ -1,0 +1,221 @@
+/*
+ * far.h -- C ABI of the MI355X (gfx950) FAR-LIO registration hot path.
+ *
+ * FAR-LIO (arXiv 2606.26010) registers each LiDAR scan P* to a local submap Q
+ * with a sparsity-aware GICP (Sec. III-A.2) on top of a GPU voxel hash map
+ * with a per-voxel point cap (Sec. III-A.2 cuVoxelMap paragraph, Sec. III-A.3).
+ * This library implements that hot path in hand-written HIP: the capped map
+ * insert with per-point regularised covariances (Eq. 1), the 27-voxel
+ * neighbour search, the per-point GICP term (Eqs. 3-5) reduced into a 6x6 H,
+ * a 6-vector b and a cost, and the Gauss-Newton iteration (Eq. 6), for one
+ * scan or for many scans in one launch.
+ *
+ * Conventions shared by every entry point
+ *  - [dev]  pointer to HIP device memory owned by the caller; the call only
+ *           borrows it for the stream-ordered work it enqueues on `stream`.
+ *    [host] pointer to host memory, read or written before the call returns.
+ *  - Points are SoA float32 [3][n]: n x values, then n y values, then n z.
+ *  - Covariances are SoA float32 [6][n] holding the upper triangle of the
+ *    symmetric 3x3 matrix in the order xx, xy, xz, yy, yz, zz.
+ *  - Poses are row-major double[16] 4x4 rigid transforms, map <- sensor.
+ *  - `stream` is a hipStream_t (NULL = the null stream).
+ *  - Every function returns a far_status_t and never throws; on failure
+ *    far_last_error() gives a thread-local message.  Arguments are checked
+ *    before any work is enqueued (FAR_E_INVALID).  A HIP runtime failure is
+ *    FAR_E_HIP.
+ *  - Calls on one map must be ordered: issue them on one stream, or
+ *    synchronise between streams yourself.
+ *  - Every neighbour decision (voxel key, squared distance, radius test,
+ *    ranking, spacing test) is taken in FP64 with the squared distance
+ *    evaluated as (dx*dx + dy*dy) + dz*dz without fused multiply-add, and
+ *    ties ranked by point id, so neighbour sets are reproducible bit for bit.
+ */
+#ifndef FAR_H
+#define FAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* far_stream_t;                /* a hipStream_t */
+typedef struct far_map_s* far_map_t;       /* opaque; owns its device storage */
+
+typedef enum {
+  FAR_OK = 0,
+  FAR_E_INVALID = 1,      /* bad argument or out-of-range coordinates       */
+  FAR_E_CAPACITY = 2,     /* point or voxel capacity of the map exceeded     */
+  FAR_E_HIP = 3,          /* HIP runtime error                               */
+  FAR_E_NOT_PD = 4,       /* H not positive definite (degenerate geometry)  */
+  FAR_E_FEW_CORR = 5,     /* fewer than 6 correspondences                    */
+  FAR_E_UNSUPPORTED = 6   /* no usable gfx950 device / feature unavailable   */
+} far_status_t;
+
+typedef enum {
+  FAR_PREC_FP32 = 0,      /* FP32 per-point term, compensated FP32 wave sums */
+  FAR_PREC_FP64 = 1       /* every per-point term and sum in FP64            */
+} far_precision_t;
+
+/* Map parameters (Sec. III-A.2: voxel edge v, at most N_max "regularly
+ * spaced" points per voxel; covariances from k neighbours).  Capacities are
+ * fixed at create; the map never grows. */
+typedef struct {
+  double voxel_size;          /* v > 0, metres                                */
+  int32_t max_pts_per_voxel;  /* N_max in [1, 64]                             */
+  double min_spacing;         /* < 0: v / sqrt(N_max); 0: off; > 0: metres    */
+  int64_t point_capacity;     /* >= 1, < 2^31                                 */
+  int64_t voxel_capacity;     /* <= 0: = point_capacity                       */
+  int32_t k_cov;              /* neighbours per covariance, [1, 32]           */
+} far_map_params_t;
+
+/* One linearisation: H = sum w J^T W J (row-major 6x6, symmetric),
+ * b = sum w J^T W d, cost = sum rho, over n_inliers correspondences, with the
+ * twist ordered (omega, v). */
+typedef struct {
+  double H[36];
+  double b[6];
+  double cost;
+  int64_t n_inliers;
+} far_lin_t;
+
+/* Gauss-Newton parameters.  tau: correspondence threshold (the search radius
+ * is min(tau, v)); kappa: Cauchy scale (Eq. 5); eps: stop when the norm of
+ * the increment twist is <= eps; recenter: linearise about the current
+ * translation (1) or the origin (0); precision: far_precision_t. */
+typedef struct {
+  double tau;
+  double kappa;
+  int32_t max_iters;          /* [1, 64] */
+  double eps;
+  int32_t recenter;
+  int32_t precision;
+} far_align_params_t;
+
+typedef struct {
+  int32_t iters;              /* Gauss-Newton updates applied                 */
+  int32_t converged;          /* 1 if the last increment was <= eps           */
+  int32_t status;             /* far_status_t of this scan                    */
+  int32_t reserved;
+  far_lin_t last;             /* linearisation of the last iteration          */
+} far_align_stats_t;
+
+typedef struct {
+  int64_t n_points;
+  int64_t n_voxels;           /* voxel keys held (a voxel may be empty)       */
+  int64_t table_slots;        /* open-addressing slots (power of two)         */
+  double load_factor;         /* n_voxels / table_slots                       */
+  double mean_probe;          /* mean slots inspected to find a held key      */
+  int32_t max_probe;          /* longest such probe                           */
+  int32_t max_pts_per_voxel;
+  double voxel_size;
+  double min_spacing;         /* resolved spacing, metres                     */
+  int64_t bytes_device;       /* device memory owned by the map               */
+} far_map_stats_t;
+
+/* Create an empty map (all storage allocated here, sized by the
+ * capacities).  *out receives the handle.  FAR_E_INVALID on bad params. */
+far_status_t far_map_create(const far_map_params_t* params /* [host] */,
+                            far_stream_t stream, far_map_t* out /* [host] */);
+
+/* Release the map and its device storage (synchronises the device). */
+far_status_t far_map_destroy(far_map_t map);
+
+/* Capped insert of n points xyz [dev, SoA 3 x n, map frame]
+ * (Sec. III-A.3).  Result equals inserting the points one at a time in input
+ * order: point i enters voxel K = floor(p_i / v) iff the voxel holds fewer
+ * than cap_i = min(voxel_cap[i], N_max) points (N_max when voxel_cap is NULL)
+ * and, when spacing is on, every point already in K is at least min_spacing
+ * away.  Accepted points get consecutive ids.  Afterwards the regularised
+ * covariance (Eq. 1, k_cov neighbours within v, the point itself included;
+ * valid iff exactly k_cov exist) of every added point is computed on the
+ * updated map; existing points keep theirs.
+ * Non-finite points are skipped.  Keys outside [-2^20, 2^20) per axis:
+ * FAR_E_INVALID with the map unchanged.  More new voxels than the voxel
+ * capacity allows: FAR_E_CAPACITY with the map unchanged.  More accepted
+ * points than the point capacity allows: FAR_E_CAPACITY, the points accepted
+ * before the overflow are kept.  Synchronises `stream`.
+ * voxel_cap: [dev] int32 per point, or NULL.  n_accepted: [host] or NULL. */
+far_status_t far_map_insert(far_map_t map, const float* xyz, int64_t n,
+                            const int32_t* voxel_cap, far_stream_t stream,
+                            int64_t* n_accepted);
+
+/* k nearest map points (k in [1, 32]) within radius (0 < radius <= v) of each
+ * query q [dev, SoA 3 x n], searched over the 27 voxels around the query's
+ * voxel (Sec. III-A.2, Fig. 3), ranked by (squared distance, id).
+ * idx [dev, n x k] receives ids, padded with -1; d2 [dev, n x k, or NULL] the
+ * squared distances rounded to float (-1 pad); count [dev, n, or NULL] the
+ * number found.  Asynchronous. */
+far_status_t far_map_knn(far_map_t map, const float* q, int64_t n, int32_t k,
+                         double radius, int32_t* idx, float* d2, int32_t* count,
+                         far_stream_t stream);
+
+/* Regularised covariances of a scan against itself (Sec. III-A.2: the scan's
+ * covariances come from its own voxel map, no cap): for each point, Eq. 1 on
+ * its k nearest scan points within r = voxel_size (itself included).
+ * xyz [dev, SoA 3 x n, sensor frame]; cov6 [dev, SoA 6 x n] (zero where
+ * invalid); valid [dev, n] = 1 iff exactly k neighbours exist.  Keys outside
+ * [-2^20, 2^20): FAR_E_INVALID.  Asynchronous apart from one small copy. */
+far_status_t far_scan_covariances(const float* xyz, int64_t n, double voxel_size,
+                                  int32_t k, float* cov6, uint8_t* valid,
+                                  far_stream_t stream);
+
+/* One GICP linearisation (Eqs. 3-5, sparsity-aware) of the scan src
+ * [dev, SoA 3 x n] with covariances cov6 [dev, SoA 6 x n] and valid [dev, n]
+ * against the map at pose T [host]: p = R s + t in FP64; correspondence = the
+ * nearest map point within min(tau, v), none = outlier; d = r - p;
+ * M = Sigma_r + R Sigma_s R^T (M = I unless both covariances are valid);
+ * e2 = d^T M^-1 d; Cauchy weight w = kappa^2/(kappa^2 + e2) and cost
+ * rho = kappa^2/2 ln(1 + e2/kappa^2); J = [[p - c]x, -I] for the perturbation
+ * p -> c + Exp(delta)(p - c).  c [host, 3] or NULL for the origin.
+ * corr [dev, n] or NULL receives each point's correspondence id (-1 none).
+ * Synchronises `stream`; out [host]. */
+far_status_t far_gicp_linearize(far_map_t map, const float* src, const float* cov6,
+                                const uint8_t* valid, int64_t n, const double T[16],
+                                double tau, double kappa, const double c[3],
+                                int32_t precision, int32_t* corr, far_lin_t* out,
+                                far_stream_t stream);
+
+/* Gauss-Newton align of one scan (Eq. 6): up to max_iters iterations of
+ * linearise, solve H delta = -b by FP64 Cholesky, T <- T_c Exp(delta) T_c^-1 T
+ * (T_c = translation by the linearisation centre), stopping when
+ * ||delta|| <= eps.  Fewer than 6 inliers (FAR_E_FEW_CORR) or a non positive
+ * definite H (FAR_E_NOT_PD) stop the loop leaving T as it was.  The solve runs
+ * on the GPU; the host sees only the final copy.  T0, T_out, stats: [host].
+ * Returns the scan's status. */
+far_status_t far_gicp_align(far_map_t map, const float* src, const float* cov6,
+                            const uint8_t* valid, int64_t n, const double T0[16],
+                            const far_align_params_t* params, double T_out[16],
+                            far_align_stats_t* stats, far_stream_t stream);
+
+/* Gauss-Newton align of S scans in one pass per iteration: scan s holds
+ * points [offsets[s], offsets[s+1]) of src [dev, SoA 3 x n_total], cov6
+ * [dev, SoA 6 x n_total] and valid [dev, n_total]; offsets [dev, S+1] int64,
+ * non-decreasing, offsets[0] = 0, offsets[S] = n_total.  T [dev, S x 16] holds
+ * the initial poses and receives the results; stats [dev, S].  Each
+ * iteration is one linearisation launch over all scans' point tiles, one
+ * reduction-and-solve launch with a block per scan, captured in a HIP graph
+ * and replayed; finished scans skip their tiles.  No host synchronisation. */
+far_status_t far_gicp_align_batch(far_map_t map, const float* src, const int64_t* offsets,
+                                  int32_t S, int64_t n_total, const float* cov6,
+                                  const uint8_t* valid, double* T,
+                                  const far_align_params_t* params,
+                                  far_align_stats_t* stats, far_stream_t stream);
+
+/* Occupancy and probe statistics of the map's hash table.  Synchronises. */
+far_status_t far_map_stats(far_map_t map, far_map_stats_t* out, far_stream_t stream);
+
+/* Copy the map out in id order: xyz [dev, SoA 3 x N], cov6 [dev, SoA 6 x N],
+ * valid [dev, N] (any may be NULL); N = the map's point count, written to
+ * n_out [host].  The buffers must hold `capacity` points; FAR_E_CAPACITY if
+ * N exceeds it (nothing written).  Synchronises. */
+far_status_t far_map_export(far_map_t map, float* xyz, float* cov6, uint8_t* valid,
+                            int64_t capacity, int64_t* n_out, far_stream_t stream);
+
+const char* far_status_str(far_status_t s);
+const char* far_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAR_H */

@@ -1,0 +1,209 @@
+// far_internal.h -- shared internals of the gfx950 library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/far.h"
+
+namespace far {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+far_status_t hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define FAR_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t far_e_ = (call);                                              \
+    if (far_e_ != hipSuccess) return far::hip_fail(far_e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define FAR_TRY(call)                                                        \
+  do {                                                                       \
+    far_status_t far_s_ = (call);                                            \
+    if (far_s_ != FAR_OK) return far_s_;                                     \
+  } while (0)
+
+inline hipStream_t S(far_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- keys
+// A voxel key is the triple floor(x / v) per axis; keys are limited to
+// [-2^20, 2^20) and packed as three 21-bit fields biased by 2^20 into the low
+// 63 bits of a uint64.  The all-ones word marks an empty hash slot and sorts
+// after every key (used for non-finite points).
+constexpr int64_t kKeyBias = int64_t(1) << 20;
+constexpr uint64_t kEmptyKey = ~uint64_t(0);
+constexpr int kKeyBits = 63;
+
+__host__ __device__ inline uint64_t pack_key(int64_t kx, int64_t ky, int64_t kz) {
+  return (uint64_t(kx + kKeyBias) << 42) | (uint64_t(ky + kKeyBias) << 21) |
+         uint64_t(kz + kKeyBias);
+}
+__host__ __device__ inline bool key_ok(int64_t k) { return k >= -kKeyBias && k < kKeyBias; }
+__host__ __device__ inline int64_t key_x(uint64_t k) { return int64_t((k >> 42) & 0x1FFFFF) - kKeyBias; }
+__host__ __device__ inline int64_t key_y(uint64_t k) { return int64_t((k >> 21) & 0x1FFFFF) - kKeyBias; }
+__host__ __device__ inline int64_t key_z(uint64_t k) { return int64_t(k & 0x1FFFFF) - kKeyBias; }
+
+// Spatial hash of Teschner et al. as used by Niessner et al. (the hash the
+// paper's voxel map employs): XOR of the three indices times large primes,
+// folded to the power-of-two table by Fibonacci hashing of the 32-bit result.
+__host__ __device__ inline uint32_t voxel_hash(int64_t kx, int64_t ky, int64_t kz,
+                                               int log2_slots) {
+  uint32_t h = (uint32_t(kx) * 73856093u) ^ (uint32_t(ky) * 19349669u) ^
+               (uint32_t(kz) * 83492791u);
+  return uint32_t((uint64_t(h) * 0x9E3779B97F4A7C15ull) >> (64 - log2_slots));
+}
+
+struct alignas(16) Slot {
+  uint64_t key;   // kEmptyKey when free
+  int32_t vox;    // compact voxel index
+  int32_t pad;
+};
+
+// Device view of a map, passed by value to kernels.
+struct MapView {
+  const Slot* slots;
+  const int32_t* vox_count;     // [voxel_cap]
+  const float4* vox_pts;        // [voxel_cap * nmax]: x, y, z, id (int bits)
+  const float4* cov;            // [point_cap * 2]: (xx,xy,xz,yy), (yz,zz,valid,0)
+  const float* pt_xyz;          // [3][point_cap]
+  int64_t point_cap;
+  double v;
+  int32_t nmax;
+  int32_t log2_slots;
+  uint32_t slot_mask;
+};
+
+__device__ inline int32_t map_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz) {
+  if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
+  uint64_t key = pack_key(kx, ky, kz);
+  uint32_t s = voxel_hash(kx, ky, kz, m.log2_slots);
+  for (uint32_t probe = 0; probe <= m.slot_mask; ++probe) {
+    Slot sl = m.slots[s];
+    if (sl.key == key) return sl.vox;
+    if (sl.key == kEmptyKey) return -1;
+    s = (s + 1) & m.slot_mask;
+  }
+  return -1;
+}
+
+// FP64 squared distance, fixed evaluation order, no contraction (the library
+// is compiled with -ffp-contract=off).
+__host__ __device__ inline double dist2(double ax, double ay, double az, double bx,
+                                        double by, double bz) {
+  double dx = ax - bx, dy = ay - by, dz = az - bz;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// (d2, id) lexicographic order used by every ranking.
+__host__ __device__ inline bool rank_less(double da, int32_t ia, double db, int32_t ib) {
+  return da < db || (da == db && ia < ib);
+}
+
+// Conservative squared lower bound of the distance from q to any point of the
+// voxel at offset (ox, oy, oz) from q's voxel (kq).  A slack of 1e-7 v per
+// axis absorbs every rounding of the key and distance arithmetic, so a voxel
+// is skipped only when none of its points could rank.
+__device__ inline double voxel_lb2(double qx, double qy, double qz, int64_t kqx,
+                                   int64_t kqy, int64_t kqz, int ox, int oy, int oz,
+                                   double v) {
+  double slack = 1e-7 * v;
+  double g, s = 0.0;
+  if (ox < 0) { g = qx - double(kqx) * v - slack; s += g > 0 ? g * g : 0.0; }
+  if (ox > 0) { g = double(kqx + 1) * v - qx - slack; s += g > 0 ? g * g : 0.0; }
+  if (oy < 0) { g = qy - double(kqy) * v - slack; s += g > 0 ? g * g : 0.0; }
+  if (oy > 0) { g = double(kqy + 1) * v - qy - slack; s += g > 0 ? g * g : 0.0; }
+  if (oz < 0) { g = qz - double(kqz) * v - slack; s += g > 0 ? g * g : 0.0; }
+  if (oz > 0) { g = double(kqz + 1) * v - qz - slack; s += g > 0 ? g * g : 0.0; }
+  return s;
+}
+
+// The 27 neighbour offsets, own voxel first, then the 6 faces, 12 edges and
+// 8 corners (increasing minimum distance), encoded as (ox+1)*9+(oy+1)*3+(oz+1).
+static __constant__ int8_t kNbrOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1,  3,  5,
+                                            7,  9, 11, 15, 17, 19, 21, 23, 25, 0,
+                                            2,  6,  8, 18, 20, 24, 26};
+
+// ---------------------------------------------------------------- scratch
+// Stream-ordered device scratch, freed when the guard leaves scope.
+struct Scratch {
+  hipStream_t stream;
+  void* ptrs[32];
+  int n = 0;
+  explicit Scratch(hipStream_t s) : stream(s) {}
+  ~Scratch() {
+    for (int i = 0; i < n; ++i) (void)hipFreeAsync(ptrs[i], stream);
+  }
+  template <class T>
+  far_status_t get(T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    FAR_HIP(hipMallocAsync(&p, count * sizeof(T), stream));
+    ptrs[n++] = p;
+    *out = static_cast<T*>(p);
+    return FAR_OK;
+  }
+};
+
+// ---------------------------------------------------------------- primitives
+// Stable LSD radix sort of (key, value) pairs by key bits [0, bits); the
+// result lands in keys/vals (the *_alt buffers are scratch of the same size).
+far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                              uint32_t* vals_alt, int64_t n, int bits, hipStream_t st,
+                              Scratch& scr);
+// Exclusive prefix sum of n uint32 values; the total goes to *total [dev]
+// when total is not NULL.  in and out may alias.
+far_status_t scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                            hipStream_t st, Scratch& scr);
+
+// ---------------------------------------------------------------- covariances
+// Regularised covariances of the map points with ids [id0, id1) on the map.
+far_status_t map_covariances(const MapView& m, float4* cov_out, int64_t id0, int64_t id1,
+                             int32_t k, hipStream_t st);
+
+int device_cu_count();
+
+// Align workspace owned by a map (defined with the GICP kernels).
+struct AlignWS;
+void free_ws(AlignWS* w);
+
+}  // namespace far
+
+// Host-side map object.
+struct far_map_s {
+  far_map_params_t p;
+  double dmin;
+  int64_t slots;
+  int log2_slots;
+  int64_t voxel_cap;
+  far::Slot* slots_d = nullptr;
+  int32_t* vox_count = nullptr;
+  uint64_t* vox_key = nullptr;
+  float4* vox_pts = nullptr;
+  float4* cov = nullptr;
+  float* pt_xyz = nullptr;
+  int32_t* pt_loc = nullptr;
+  int64_t n_points = 0;
+  int64_t n_voxels = 0;
+  int device = 0;
+  int64_t bytes = 0;
+  far::AlignWS* ws = nullptr;
+  far::MapView view() const {
+    far::MapView m;
+    m.slots = slots_d;
+    m.vox_count = vox_count;
+    m.vox_pts = vox_pts;
+    m.cov = cov;
+    m.pt_xyz = pt_xyz;
+    m.point_cap = p.point_capacity;
+    m.v = p.voxel_size;
+    m.nmax = p.max_pts_per_voxel;
+    m.log2_slots = log2_slots;
+    m.slot_mask = uint32_t(slots - 1);
+    return m;
+  }
+};

@@ -1,0 +1,776 @@
+// far_map.hip -- the voxel hash map (Sec. III-A.2 cuVoxelMap paragraph,
+// Sec. III-A.3 Adaptive, Local Submap): create, capped insert with the
+// covariances of the added points, k-nearest-neighbour query, export, stats,
+// and the covariances of a scan against its own (uncapped) voxel grid.
+//
+// Layout in HBM (all fixed at create):
+//   slots     Slot[S]            open addressing, linear probing step 1,
+//                                S = 2^ceil(log2(2 * voxel_capacity))
+//   vox_count int32[Vc]          points held per voxel
+//   vox_key   uint64[Vc]         packed key per voxel
+//   vox_pts   float4[Vc * Nmax]  voxel-major point store: x, y, z, id bits
+//   cov       float4[Pc * 2]     per id: (xx, xy, xz, yy), (yz, zz, valid, 0)
+//   pt_xyz    float[3][Pc]       per id coordinates (SoA)
+//   pt_loc    int32[Pc]          per id slot in vox_pts
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <type_traits>
+
+#include "far_knn.h"
+
+namespace far {
+
+// ---------------------------------------------------------------- errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+far_status_t hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  set_error("HIP error %d (%s) in %s at %s:%d", int(e), hipGetErrorString(e), what, file, line);
+  return FAR_E_HIP;
+}
+
+int device_cu_count() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+    cus[dev] = prop.multiProcessorCount;
+  }
+  return cus[dev];
+}
+
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned blocks_for(int64_t n, int per = kT) {
+  int64_t b = (n + per - 1) / per;
+  return unsigned(b < 1 ? 1 : b);
+}
+
+// ---------------------------------------------------------------- keys
+// Voxel key of every point (Sec. III-A.2: the key is the voxel's 3-D index).
+// Non-finite points get the empty key (they sort last and are skipped);
+// out-of-range points are counted and make the call fail.
+__global__ __launch_bounds__(kT) void k_keys(const float* xyz, int64_t n, double v,
+                                             uint64_t* keys, uint32_t* vals,
+                                             uint32_t* counters) {
+  int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+  uint64_t key = kEmptyKey;
+  if (isfinite(x) && isfinite(y) && isfinite(z)) {
+    int64_t kx, ky, kz;
+    if (voxel_index(double(x), v, &kx) && voxel_index(double(y), v, &ky) &&
+        voxel_index(double(z), v, &kz))
+      key = pack_key(kx, ky, kz);
+    else
+      atomicAdd(&counters[1], 1u);
+  } else {
+    atomicAdd(&counters[0], 1u);
+  }
+  keys[i] = key;
+  vals[i] = uint32_t(i);
+}
+
+// Segment heads of the sorted keys (first element of each run of equal keys).
+__global__ __launch_bounds__(kT) void k_heads(const uint64_t* keys, int64_t n,
+                                              uint32_t* head) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  uint64_t k = keys[j];
+  head[j] = (k != kEmptyKey && (j == 0 || keys[j - 1] != k)) ? 1u : 0u;
+}
+
+// Segment bounds: seg_start[s] and seg_end[s] for every run s.
+__global__ __launch_bounds__(kT) void k_seg_bounds(const uint64_t* keys, int64_t n,
+                                                   const uint32_t* head,
+                                                   const uint32_t* head_scan,
+                                                   uint32_t* seg_start, uint32_t* seg_end) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  uint64_t k = keys[j];
+  if (k == kEmptyKey) return;
+  uint32_t s = head_scan[j] + head[j] - 1;
+  if (head[j]) seg_start[s] = uint32_t(j);
+  if (j == n - 1 || keys[j + 1] != k) seg_end[s] = uint32_t(j + 1);
+}
+
+// Look each run's key up in the table; flag runs whose voxel is new.
+__global__ __launch_bounds__(kT) void k_seg_lookup(MapView m, const uint64_t* keys,
+                                                   const uint32_t* seg_start,
+                                                   const uint32_t* n_seg, int64_t n,
+                                                   int32_t* seg_vox, uint32_t* is_new) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n) return;
+  if (s >= int64_t(*n_seg)) {
+    is_new[s] = 0;
+    return;
+  }
+  uint64_t key = keys[seg_start[s]];
+  int32_t vox = map_find(m, key_x(key), key_y(key), key_z(key));
+  seg_vox[s] = vox;
+  is_new[s] = vox < 0 ? 1u : 0u;
+}
+
+// Claim a slot for every new voxel; new voxels are numbered in sorted key
+// order after the existing ones, so the layout is deterministic.
+__global__ __launch_bounds__(kT) void k_seg_claim(Slot* slots, uint32_t slot_mask,
+                                                  int log2_slots, const uint64_t* keys,
+                                                  const uint32_t* seg_start,
+                                                  const uint32_t* is_new,
+                                                  const uint32_t* new_rank, int64_t n_seg,
+                                                  int64_t n_vox_old, int32_t* seg_vox,
+                                                  uint64_t* vox_key) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg || !is_new[s]) return;
+  uint64_t key = keys[seg_start[s]];
+  int32_t vox = int32_t(n_vox_old + new_rank[s]);
+  uint32_t h = voxel_hash(key_x(key), key_y(key), key_z(key), log2_slots);
+  for (uint32_t probe = 0; probe <= slot_mask; ++probe) {
+    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[h].key),
+                                       (unsigned long long)kEmptyKey,
+                                       (unsigned long long)key);
+    if (old == kEmptyKey) {
+      slots[h].vox = vox;
+      break;
+    }
+    h = (h + 1) & slot_mask;
+  }
+  seg_vox[s] = vox;
+  vox_key[vox] = key;
+}
+
+// Sequential capped insert of one voxel's candidates in input order (one
+// thread per voxel run; runs are stable-sorted so candidates appear in input
+// order).  A candidate is accepted while the voxel holds fewer than its cap
+// and, with spacing on, it is at least dmin from every point already there.
+// Accepted points are appended to the voxel's store right away, so later
+// candidates of the same run are checked against them.
+__global__ __launch_bounds__(kT) void k_greedy(const float* xyz, int64_t n,
+                                               const int32_t* caps, int32_t nmax,
+                                               double dmin2, const uint32_t* vals,
+                                               const uint32_t* seg_start,
+                                               const uint32_t* seg_end, int64_t n_seg,
+                                               const int32_t* seg_vox,
+                                               const int32_t* vox_count, float4* vox_pts,
+                                               uint32_t* acc_flag, int32_t* acc_pos,
+                                               int32_t* seg_newcount) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  int32_t vox = seg_vox[s];
+  int32_t cnt = vox_count[vox];
+  float4* store = vox_pts + int64_t(vox) * nmax;
+  for (uint32_t j = seg_start[s]; j < seg_end[s]; ++j) {
+    uint32_t i = vals[j];
+    int32_t cap = caps ? min(caps[i], nmax) : nmax;
+    if (cnt >= cap) continue;
+    float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    bool ok = true;
+    if (dmin2 > 0.0) {
+      for (int32_t q = 0; q < cnt; ++q) {
+        float4 p = store[q];
+        if (dist2(double(x), double(y), double(z), double(p.x), double(p.y), double(p.z)) <
+            dmin2) {
+          ok = false;
+          break;
+        }
+      }
+    }
+    if (!ok) continue;
+    store[cnt] = make_float4(x, y, z, __int_as_float(-1));
+    acc_flag[i] = 1u;
+    acc_pos[i] = int32_t(int64_t(vox) * nmax + cnt);
+    ++cnt;
+  }
+  seg_newcount[s] = cnt;
+}
+
+// Give accepted points their ids (input order) and record them by id.
+__global__ __launch_bounds__(kT) void k_commit(const float* xyz, int64_t n,
+                                               const uint32_t* acc_flag,
+                                               const uint32_t* id_local,
+                                               const int32_t* acc_pos, int64_t id0,
+                                               int64_t point_cap, float4* vox_pts,
+                                               float* pt_xyz, int32_t* pt_loc) {
+  int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n || !acc_flag[i]) return;
+  int64_t id = id0 + id_local[i];
+  if (id >= point_cap) return;
+  int32_t pos = acc_pos[i];
+  vox_pts[pos].w = __int_as_float(int32_t(id));
+  pt_xyz[id] = xyz[i];
+  pt_xyz[point_cap + id] = xyz[n + i];
+  pt_xyz[2 * point_cap + id] = xyz[2 * n + i];
+  pt_loc[id] = pos;
+}
+
+// New per-voxel counts.  When the point capacity truncated the batch, only
+// the accepted prefix whose ids fit is kept.
+__global__ __launch_bounds__(kT) void k_counts(int64_t n_seg, const int32_t* seg_vox,
+                                               const int32_t* seg_newcount, bool truncated,
+                                               const uint32_t* vals, const uint32_t* seg_start,
+                                               const uint32_t* seg_end,
+                                               const uint32_t* acc_flag,
+                                               const uint32_t* id_local, int64_t n_commit,
+                                               int32_t* vox_count) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  int32_t vox = seg_vox[s];
+  if (!truncated) {
+    vox_count[vox] = seg_newcount[s];
+    return;
+  }
+  int32_t c = vox_count[vox];
+  for (uint32_t j = seg_start[s]; j < seg_end[s]; ++j) {
+    uint32_t i = vals[j];
+    if (acc_flag[i] && int64_t(id_local[i]) < n_commit) ++c;
+  }
+  vox_count[vox] = c;
+}
+
+// Covariances of map points [id0, id1): k nearest within v on the map.
+template <int K>
+__global__ __launch_bounds__(kT) void k_map_cov(MapView m, float4* cov, int64_t id0,
+                                                int64_t id1, int32_t k) {
+  int64_t id = id0 + int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (id >= id1) return;
+  double qx = m.pt_xyz[id], qy = m.pt_xyz[m.point_cap + id], qz = m.pt_xyz[2 * m.point_cap + id];
+  TopK<K> top;
+  map_knn_query<K>(m, qx, qy, qz, m.v * m.v, top);
+  double c6[6] = {0, 0, 0, 0, 0, 0};
+  bool ok = top.found() >= k;
+  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return m.vox_pts[pos]; }, c6);
+  cov[2 * id] = make_float4(float(c6[0]), float(c6[1]), float(c6[2]), float(c6[3]));
+  cov[2 * id + 1] = make_float4(float(c6[4]), float(c6[5]), ok ? 1.0f : 0.0f, 0.0f);
+}
+
+template <int K>
+__global__ __launch_bounds__(kT) void k_map_knn(MapView m, const float* q, int64_t n, int32_t k,
+                                                double r2, int32_t* idx, float* d2,
+                                                int32_t* count) {
+  int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  float x = q[i], y = q[n + i], z = q[2 * n + i];
+  TopK<K> top;
+  if (isfinite(x) && isfinite(y) && isfinite(z))
+    map_knn_query<K>(m, double(x), double(y), double(z), r2, top);
+  else
+    top.init();
+  int f = top.found();
+  int c = f < k ? f : k;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    if (s < k) {
+      idx[i * k + s] = s < c ? top.id[s] : -1;
+      if (d2) d2[i * k + s] = s < c ? float(top.d[s]) : -1.0f;
+    }
+  }
+  if (count) count[i] = c;
+}
+
+// ---------------------------------------------------------------- scan grid
+// The scan's own voxel grid is CSR: points sorted by key (sorted[j] = x, y, z,
+// original index bits), runs [seg_start, seg_end), and a hash table from key to
+// run index.
+struct GridView {
+  const Slot* slots;
+  const float4* sorted;
+  const uint32_t* seg_start;
+  const uint32_t* seg_end;
+  double v;
+  int32_t log2_slots;
+  uint32_t slot_mask;
+};
+
+__device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, int64_t kz) {
+  if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
+  uint64_t key = pack_key(kx, ky, kz);
+  uint32_t s = voxel_hash(kx, ky, kz, g.log2_slots);
+  for (uint32_t probe = 0; probe <= g.slot_mask; ++probe) {
+    Slot sl = g.slots[s];
+    if (sl.key == key) return sl.vox;
+    if (sl.key == kEmptyKey) return -1;
+    s = (s + 1) & g.slot_mask;
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t n,
+                                                      const uint32_t* vals, int64_t n_valid,
+                                                      float4* sorted) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n_valid) return;
+  uint32_t i = vals[j];
+  sorted[j] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], __int_as_float(int32_t(i)));
+}
+
+__global__ __launch_bounds__(kT) void k_grid_claim(Slot* slots, uint32_t slot_mask,
+                                                   int log2_slots, const uint64_t* keys,
+                                                   const uint32_t* seg_start, int64_t n_seg) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  uint64_t key = keys[seg_start[s]];
+  uint32_t h = voxel_hash(key_x(key), key_y(key), key_z(key), log2_slots);
+  for (uint32_t probe = 0; probe <= slot_mask; ++probe) {
+    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[h].key),
+                                       (unsigned long long)kEmptyKey,
+                                       (unsigned long long)key);
+    if (old == kEmptyKey) {
+      slots[h].vox = int32_t(s);
+      return;
+    }
+    h = (h + 1) & slot_mask;
+  }
+}
+
+// Covariance of every scan point from its k nearest scan points within v
+// (processed in key-sorted order for locality; written at the original index).
+template <int K>
+__global__ __launch_bounds__(kT) void k_grid_cov(GridView g, int64_t n_valid, int64_t n,
+                                                 int32_t k, float* cov6, uint8_t* valid) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n_valid) return;
+  float4 me = g.sorted[j];
+  double qx = me.x, qy = me.y, qz = me.z;
+  double r2 = g.v * g.v;
+  TopK<K> top;
+  top.init();
+  int64_t kx, ky, kz;
+  voxel_index(qx, g.v, &kx);
+  voxel_index(qy, g.v, &ky);
+  voxel_index(qz, g.v, &kz);
+  for (int t = 0; t < 27; ++t) {
+    int code = kNbrOrder[t];
+    int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+    double bnd = fmin(r2, top.bound());
+    if (voxel_lb2(qx, qy, qz, kx, ky, kz, ox, oy, oz, g.v) > bnd) continue;
+    int32_t s = grid_find(g, kx + ox, ky + oy, kz + oz);
+    if (s < 0) continue;
+    for (uint32_t c = g.seg_start[s]; c < g.seg_end[s]; ++c) {
+      float4 p = g.sorted[c];
+      double d = dist2(double(p.x), double(p.y), double(p.z), qx, qy, qz);
+      if (d <= r2) top.push(d, __float_as_int(p.w), int32_t(c));
+    }
+  }
+  double c6[6] = {0, 0, 0, 0, 0, 0};
+  bool ok = top.found() >= k;
+  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
+  int64_t i = __float_as_int(me.w);
+#pragma unroll
+  for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
+  valid[i] = ok ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kT) void k_probe_stats(const Slot* slots, int64_t n_slots,
+                                                    uint32_t slot_mask, int log2_slots,
+                                                    unsigned long long* sum,
+                                                    uint32_t* maxp) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_slots) return;
+  uint64_t key = slots[s].key;
+  if (key == kEmptyKey) return;
+  uint32_t h = voxel_hash(key_x(key), key_y(key), key_z(key), log2_slots);
+  uint32_t len = ((uint32_t(s) - h) & slot_mask) + 1;
+  atomicAdd(sum, (unsigned long long)len);
+  atomicMax(maxp, len);
+}
+
+__global__ __launch_bounds__(kT) void k_export(const float4* cov, const float* pt_xyz,
+                                               int64_t point_cap, int64_t N, float* xyz,
+                                               float* cov6, uint8_t* valid) {
+  int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= N) return;
+  if (xyz) {
+    xyz[i] = pt_xyz[i];
+    xyz[N + i] = pt_xyz[point_cap + i];
+    xyz[2 * N + i] = pt_xyz[2 * point_cap + i];
+  }
+  float4 a = cov[2 * i], b = cov[2 * i + 1];
+  if (cov6) {
+    cov6[i] = a.x;
+    cov6[N + i] = a.y;
+    cov6[2 * N + i] = a.z;
+    cov6[3 * N + i] = a.w;
+    cov6[4 * N + i] = b.x;
+    cov6[5 * N + i] = b.y;
+  }
+  if (valid) valid[i] = b.z != 0.0f ? 1 : 0;
+}
+
+template <class F>
+far_status_t dispatch_k(int32_t k, F&& f) {
+  if (k <= 1) return f(std::integral_constant<int, 1>());
+  if (k <= 4) return f(std::integral_constant<int, 4>());
+  if (k <= 8) return f(std::integral_constant<int, 8>());
+  if (k <= 16) return f(std::integral_constant<int, 16>());
+  return f(std::integral_constant<int, 32>());
+}
+
+// Keys, stable sort and runs of a point batch: the common front half of the
+// insert and of the scan covariances.
+struct Runs {
+  uint64_t* keys;
+  uint32_t* vals;
+  uint32_t* head;
+  uint32_t* head_scan;
+  uint32_t* seg_start;
+  uint32_t* seg_end;
+  uint32_t* counters;   // [0] non-finite, [1] out of range, [2] runs
+};
+
+far_status_t build_runs(const float* xyz, int64_t n, double v, hipStream_t st, Scratch& scr,
+                        Runs& r) {
+  uint64_t* keys_alt;
+  uint32_t* vals_alt;
+  FAR_TRY(scr.get(&r.keys, size_t(n)));
+  FAR_TRY(scr.get(&r.vals, size_t(n)));
+  FAR_TRY(scr.get(&keys_alt, size_t(n)));
+  FAR_TRY(scr.get(&vals_alt, size_t(n)));
+  FAR_TRY(scr.get(&r.head, size_t(n)));
+  FAR_TRY(scr.get(&r.head_scan, size_t(n)));
+  FAR_TRY(scr.get(&r.seg_start, size_t(n)));
+  FAR_TRY(scr.get(&r.seg_end, size_t(n)));
+  FAR_TRY(scr.get(&r.counters, 4));
+  FAR_HIP(hipMemsetAsync(r.counters, 0, 4 * sizeof(uint32_t), st));
+  k_keys<<<blocks_for(n), kT, 0, st>>>(xyz, n, v, r.keys, r.vals, r.counters);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(radix_sort_pairs(r.keys, r.vals, keys_alt, vals_alt, n, kKeyBits, st, scr));
+  k_heads<<<blocks_for(n), kT, 0, st>>>(r.keys, n, r.head);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(r.head, r.head_scan, n, r.counters + 2, st, scr));
+  k_seg_bounds<<<blocks_for(n), kT, 0, st>>>(r.keys, n, r.head, r.head_scan, r.seg_start,
+                                              r.seg_end);
+  FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
+
+inline int ceil_log2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+}  // namespace
+
+far_status_t map_covariances(const MapView& m, float4* cov_out, int64_t id0, int64_t id1,
+                             int32_t k, hipStream_t st) {
+  if (id1 <= id0) return FAR_OK;
+  return dispatch_k(k, [&](auto KK) -> far_status_t {
+    constexpr int K = decltype(KK)::value;
+    k_map_cov<K><<<blocks_for(id1 - id0), kT, 0, st>>>(m, cov_out, id0, id1, k);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  });
+}
+
+}  // namespace far
+
+using namespace far;
+
+extern "C" {
+
+const char* far_status_str(far_status_t s) {
+  switch (s) {
+    case FAR_OK: return "ok";
+    case FAR_E_INVALID: return "invalid argument";
+    case FAR_E_CAPACITY: return "capacity exceeded";
+    case FAR_E_HIP: return "HIP runtime error";
+    case FAR_E_NOT_PD: return "H not positive definite";
+    case FAR_E_FEW_CORR: return "too few correspondences";
+    case FAR_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* far_last_error(void) { return g_err; }
+
+far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
+                            far_map_t* out) {
+  if (!params || !out) {
+    set_error("far_map_create: null argument");
+    return FAR_E_INVALID;
+  }
+  *out = nullptr;
+  far_map_params_t p = *params;
+  if (!(p.voxel_size > 0.0) || !std::isfinite(p.voxel_size) || p.max_pts_per_voxel < 1 ||
+      p.max_pts_per_voxel > 64 || p.point_capacity < 1 || p.point_capacity >= (int64_t(1) << 31) ||
+      p.k_cov < 1 || p.k_cov > 32 || !std::isfinite(p.min_spacing)) {
+    set_error("far_map_create: parameter out of range");
+    return FAR_E_INVALID;
+  }
+  if (p.voxel_capacity <= 0) p.voxel_capacity = p.point_capacity;
+  if (p.voxel_capacity >= (int64_t(1) << 29) ||
+      p.voxel_capacity * p.max_pts_per_voxel >= (int64_t(1) << 31)) {
+    set_error("far_map_create: voxel_capacity * max_pts_per_voxel must stay below 2^31");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  far_map_s* m = new far_map_s();
+  m->p = p;
+  m->dmin = p.min_spacing < 0 ? p.voxel_size / std::sqrt(double(p.max_pts_per_voxel))
+                              : p.min_spacing;
+  m->voxel_cap = p.voxel_capacity;
+  m->log2_slots = ceil_log2(2 * p.voxel_capacity);
+  if (m->log2_slots < 10) m->log2_slots = 10;
+  m->slots = int64_t(1) << m->log2_slots;
+  if (hipGetDevice(&m->device) != hipSuccess) m->device = 0;
+  auto fail = [&](hipError_t e, const char* what) {
+    far_map_destroy(m);
+    return hip_fail(e, what, __FILE__, __LINE__);
+  };
+  hipError_t e;
+  size_t b_slots = size_t(m->slots) * sizeof(Slot);
+  size_t b_cnt = size_t(m->voxel_cap) * sizeof(int32_t);
+  size_t b_key = size_t(m->voxel_cap) * sizeof(uint64_t);
+  size_t b_pts = size_t(m->voxel_cap) * p.max_pts_per_voxel * sizeof(float4);
+  size_t b_cov = size_t(p.point_capacity) * 2 * sizeof(float4);
+  size_t b_xyz = size_t(p.point_capacity) * 3 * sizeof(float);
+  size_t b_loc = size_t(p.point_capacity) * sizeof(int32_t);
+  if ((e = hipMalloc(&m->slots_d, b_slots)) != hipSuccess) return fail(e, "hipMalloc slots");
+  if ((e = hipMalloc(&m->vox_count, b_cnt)) != hipSuccess) return fail(e, "hipMalloc counts");
+  if ((e = hipMalloc(&m->vox_key, b_key)) != hipSuccess) return fail(e, "hipMalloc keys");
+  if ((e = hipMalloc(&m->vox_pts, b_pts)) != hipSuccess) return fail(e, "hipMalloc points");
+  if ((e = hipMalloc(&m->cov, b_cov)) != hipSuccess) return fail(e, "hipMalloc cov");
+  if ((e = hipMalloc(&m->pt_xyz, b_xyz)) != hipSuccess) return fail(e, "hipMalloc xyz");
+  if ((e = hipMalloc(&m->pt_loc, b_loc)) != hipSuccess) return fail(e, "hipMalloc loc");
+  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_xyz + b_loc);
+  if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
+  if ((e = hipMemsetAsync(m->vox_count, 0, b_cnt, st)) != hipSuccess) return fail(e, "memset");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "sync");
+  *out = m;
+  return FAR_OK;
+}
+
+far_status_t far_map_destroy(far_map_t m) {
+  if (!m) return FAR_OK;
+  hipError_t e = hipDeviceSynchronize();
+  free_ws(m->ws);
+  m->ws = nullptr;
+  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->pt_xyz, m->pt_loc};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize", __FILE__, __LINE__);
+  return FAR_OK;
+}
+
+far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int32_t* caps,
+                            far_stream_t stream, int64_t* n_accepted) {
+  if (n_accepted) *n_accepted = 0;
+  if (!m || n < 0 || n >= (int64_t(1) << 31) || (n > 0 && !xyz)) {
+    set_error("far_map_insert: invalid argument");
+    return FAR_E_INVALID;
+  }
+  if (n == 0) return FAR_OK;
+  hipStream_t st = S(stream);
+  Scratch scr(st);
+  Runs r;
+  FAR_TRY(build_runs(xyz, n, m->p.voxel_size, st, scr, r));
+  MapView mv = m->view();
+  int32_t* seg_vox;
+  uint32_t *is_new, *new_rank;
+  FAR_TRY(scr.get(&seg_vox, size_t(n)));
+  FAR_TRY(scr.get(&is_new, size_t(n)));
+  FAR_TRY(scr.get(&new_rank, size_t(n)));
+  k_seg_lookup<<<blocks_for(n), kT, 0, st>>>(mv, r.keys, r.seg_start, r.counters + 2, n,
+                                             seg_vox, is_new);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(is_new, new_rank, n, r.counters + 3, st, scr));
+  uint32_t h_cnt[4];
+  FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  const int64_t n_seg = h_cnt[2], n_new = h_cnt[3];
+  if (h_cnt[1] > 0) {
+    set_error("far_map_insert: %u points have voxel keys outside [-2^20, 2^20)", h_cnt[1]);
+    return FAR_E_INVALID;
+  }
+  if (m->n_voxels + n_new > m->voxel_cap) {
+    set_error("far_map_insert: %lld new voxels exceed the voxel capacity %lld",
+              (long long)n_new, (long long)m->voxel_cap);
+    return FAR_E_CAPACITY;
+  }
+  if (n_seg == 0) return FAR_OK;
+  k_seg_claim<<<blocks_for(n_seg), kT, 0, st>>>(m->slots_d, uint32_t(m->slots - 1),
+                                                m->log2_slots, r.keys, r.seg_start, is_new,
+                                                new_rank, n_seg, m->n_voxels, seg_vox,
+                                                m->vox_key);
+  FAR_HIP(hipGetLastError());
+  uint32_t *acc_flag, *id_local, *acc_total;
+  int32_t *acc_pos, *seg_newcount;
+  FAR_TRY(scr.get(&acc_flag, size_t(n)));
+  FAR_TRY(scr.get(&id_local, size_t(n)));
+  FAR_TRY(scr.get(&acc_pos, size_t(n)));
+  FAR_TRY(scr.get(&seg_newcount, size_t(n_seg)));
+  FAR_TRY(scr.get(&acc_total, 1));
+  FAR_HIP(hipMemsetAsync(acc_flag, 0, size_t(n) * sizeof(uint32_t), st));
+  double dmin2 = m->dmin > 0 ? m->dmin * m->dmin : 0.0;
+  k_greedy<<<blocks_for(n_seg), kT, 0, st>>>(xyz, n, caps, m->p.max_pts_per_voxel, dmin2,
+                                             r.vals, r.seg_start, r.seg_end, n_seg, seg_vox,
+                                             m->vox_count, m->vox_pts, acc_flag, acc_pos,
+                                             seg_newcount);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(acc_flag, id_local, n, acc_total, st, scr));
+  uint32_t h_acc = 0;
+  FAR_HIP(hipMemcpyAsync(&h_acc, acc_total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  int64_t room = m->p.point_capacity - m->n_points;
+  int64_t n_commit = int64_t(h_acc) < room ? int64_t(h_acc) : room;
+  bool truncated = int64_t(h_acc) > n_commit;
+  k_commit<<<blocks_for(n), kT, 0, st>>>(xyz, n, acc_flag, id_local, acc_pos, m->n_points,
+                                         m->p.point_capacity, m->vox_pts, m->pt_xyz,
+                                         m->pt_loc);
+  FAR_HIP(hipGetLastError());
+  k_counts<<<blocks_for(n_seg), kT, 0, st>>>(n_seg, seg_vox, seg_newcount, truncated, r.vals,
+                                             r.seg_start, r.seg_end, acc_flag, id_local,
+                                             n_commit, m->vox_count);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(map_covariances(m->view(), m->cov, m->n_points, m->n_points + n_commit,
+                          m->p.k_cov, st));
+  m->n_points += n_commit;
+  m->n_voxels += n_new;
+  if (n_accepted) *n_accepted = n_commit;
+  FAR_HIP(hipStreamSynchronize(st));
+  if (truncated) {
+    set_error("far_map_insert: point capacity %lld reached; %lld accepted points dropped",
+              (long long)m->p.point_capacity, (long long)(int64_t(h_acc) - n_commit));
+    return FAR_E_CAPACITY;
+  }
+  return FAR_OK;
+}
+
+far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, double radius,
+                         int32_t* idx, float* d2, int32_t* count, far_stream_t stream) {
+  if (!m || n < 0 || k < 1 || k > 32 || !(radius > 0.0) || radius > m->p.voxel_size ||
+      (n > 0 && (!q || !idx))) {
+    set_error("far_map_knn: invalid argument (need 1 <= k <= 32, 0 < radius <= v)");
+    return FAR_E_INVALID;
+  }
+  if (n == 0) return FAR_OK;
+  hipStream_t st = S(stream);
+  MapView mv = m->view();
+  double r2 = radius * radius;
+  return dispatch_k(k, [&](auto KK) -> far_status_t {
+    constexpr int K = decltype(KK)::value;
+    k_map_knn<K><<<blocks_for(n), kT, 0, st>>>(mv, q, n, k, r2, idx, d2, count);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  });
+}
+
+far_status_t far_scan_covariances(const float* xyz, int64_t n, double voxel_size, int32_t k,
+                                  float* cov6, uint8_t* valid, far_stream_t stream) {
+  if (n < 0 || n >= (int64_t(1) << 31) || !(voxel_size > 0.0) || k < 1 || k > 32 ||
+      (n > 0 && (!xyz || !cov6 || !valid))) {
+    set_error("far_scan_covariances: invalid argument");
+    return FAR_E_INVALID;
+  }
+  if (n == 0) return FAR_OK;
+  hipStream_t st = S(stream);
+  Scratch scr(st);
+  Runs r;
+  FAR_TRY(build_runs(xyz, n, voxel_size, st, scr, r));
+  uint32_t h_cnt[4];
+  FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  if (h_cnt[1] > 0) {
+    set_error("far_scan_covariances: %u points have voxel keys outside [-2^20, 2^20)",
+              h_cnt[1]);
+    return FAR_E_INVALID;
+  }
+  const int64_t n_seg = h_cnt[2];
+  const int64_t n_valid = n - h_cnt[0];
+  // non-finite points: zero covariance, invalid
+  FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
+  FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
+  if (n_valid == 0) return FAR_OK;
+  int log2_slots = ceil_log2(2 * n_seg);
+  if (log2_slots < 6) log2_slots = 6;
+  int64_t n_slots = int64_t(1) << log2_slots;
+  Slot* slots;
+  float4* sorted;
+  FAR_TRY(scr.get(&slots, size_t(n_slots)));
+  FAR_TRY(scr.get(&sorted, size_t(n_valid)));
+  FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
+  k_gather_sorted<<<blocks_for(n_valid), kT, 0, st>>>(xyz, n, r.vals, n_valid, sorted);
+  FAR_HIP(hipGetLastError());
+  k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
+                                                 r.keys, r.seg_start, n_seg);
+  FAR_HIP(hipGetLastError());
+  GridView g{slots, sorted, r.seg_start, r.seg_end, voxel_size, log2_slots,
+             uint32_t(n_slots - 1)};
+  return dispatch_k(k, [&](auto KK) -> far_status_t {
+    constexpr int K = decltype(KK)::value;
+    k_grid_cov<K><<<blocks_for(n_valid), kT, 0, st>>>(g, n_valid, n, k, cov6, valid);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  });
+}
+
+far_status_t far_map_stats(far_map_t m, far_map_stats_t* out, far_stream_t stream) {
+  if (!m || !out) {
+    set_error("far_map_stats: null argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  Scratch scr(st);
+  unsigned long long* sum;
+  uint32_t* maxp;
+  FAR_TRY(scr.get(&sum, 1));
+  FAR_TRY(scr.get(&maxp, 1));
+  FAR_HIP(hipMemsetAsync(sum, 0, sizeof(unsigned long long), st));
+  FAR_HIP(hipMemsetAsync(maxp, 0, sizeof(uint32_t), st));
+  k_probe_stats<<<blocks_for(m->slots), kT, 0, st>>>(m->slots_d, m->slots,
+                                                     uint32_t(m->slots - 1), m->log2_slots,
+                                                     sum, maxp);
+  FAR_HIP(hipGetLastError());
+  unsigned long long h_sum = 0;
+  uint32_t h_max = 0;
+  FAR_HIP(hipMemcpyAsync(&h_sum, sum, sizeof(h_sum), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipMemcpyAsync(&h_max, maxp, sizeof(h_max), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  out->n_points = m->n_points;
+  out->n_voxels = m->n_voxels;
+  out->table_slots = m->slots;
+  out->load_factor = double(m->n_voxels) / double(m->slots);
+  out->mean_probe = m->n_voxels ? double(h_sum) / double(m->n_voxels) : 0.0;
+  out->max_probe = int32_t(h_max);
+  out->max_pts_per_voxel = m->p.max_pts_per_voxel;
+  out->voxel_size = m->p.voxel_size;
+  out->min_spacing = m->dmin;
+  out->bytes_device = m->bytes;
+  return FAR_OK;
+}
+
+far_status_t far_map_export(far_map_t m, float* xyz, float* cov6, uint8_t* valid,
+                            int64_t capacity, int64_t* n_out, far_stream_t stream) {
+  if (!m || !n_out) {
+    set_error("far_map_export: null argument");
+    return FAR_E_INVALID;
+  }
+  *n_out = m->n_points;
+  if (m->n_points > capacity) {
+    set_error("far_map_export: map holds %lld points, buffers hold %lld",
+              (long long)m->n_points, (long long)capacity);
+    return FAR_E_CAPACITY;
+  }
+  if (m->n_points == 0) return FAR_OK;
+  hipStream_t st = S(stream);
+  k_export<<<blocks_for(m->n_points), kT, 0, st>>>(m->cov, m->pt_xyz, m->p.point_capacity,
+                                                   m->n_points, xyz, cov6, valid);
+  FAR_HIP(hipGetLastError());
+  FAR_HIP(hipStreamSynchronize(st));
+  return FAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+// far_prim.hip -- device-wide primitives: stable LSD radix sort of (uint64 key,
+// uint32 value) pairs and an exclusive prefix sum, written for wave64.
+//
+// The insert needs a *stable* grouping of points by voxel key so that each
+// voxel's candidates are visited in input order (the sequential capped-insert
+// semantics); an LSD radix sort whose every pass is stable gives exactly that.
+#include "far_internal.h"
+
+namespace far {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;
+
+// Exclusive scan of one value per thread across the block; returns the
+// thread's exclusive prefix and writes the block total.
+__device__ inline uint32_t block_exscan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    uint32_t s = lds[w];
+    pre += (w < wave) ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_tile_sums(const uint32_t* in, int64_t n,
+                                                             uint32_t* sums) {
+  __shared__ uint32_t lds[kWaves];
+  int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) s += (base + j < n) ? in[base + j] : 0u;
+  uint32_t tot;
+  (void)block_exscan(s, lds, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Scan each tile, adding carry[blockIdx.x] (scanned tile sums) when given.
+// The last tile writes the grand total.
+__global__ __launch_bounds__(kThreads) void k_scan_tiles(const uint32_t* in, uint32_t* out,
+                                                         int64_t n, const uint32_t* carry,
+                                                         uint32_t* total) {
+  __shared__ uint32_t lds[kWaves];
+  int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0u;
+    s += v[j];
+  }
+  uint32_t tot;
+  uint32_t pre = block_exscan(s, lds, &tot);
+  uint32_t c = carry ? carry[blockIdx.x] : 0u;
+  uint32_t run = c + pre;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = c + tot;
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kThreads * kSortItems;
+
+__global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t* keys, int64_t n,
+                                                      int shift, uint32_t* hist,
+                                                      int64_t nblocks) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = base + int64_t(r) * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[uint32_t(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter of one 8-bit digit.  Each block walks its tile in rounds of
+// 256 elements in index order; within a round an element's rank among equal
+// digits is (equal digits in lower waves) + (equal digits in lower lanes),
+// the latter found with eight ballots.
+__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* kin,
+                                                         const uint32_t* vin, uint64_t* kout,
+                                                         uint32_t* vout, int64_t n, int shift,
+                                                         const uint32_t* hist,
+                                                         int64_t nblocks) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kWaves][256];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  base[t] = hist[int64_t(t) * nblocks + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
+  __syncthreads();
+  const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t blk = int64_t(blockIdx.x) * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = blk + int64_t(r) * kThreads + t;
+    bool ok = i < n;
+    uint64_t k = ok ? kin[i] : 0ull;
+    uint32_t val = ok ? vin[i] : 0u;
+    uint32_t d = uint32_t(k >> shift) & 255u;
+    uint64_t m = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t bal = __ballot(bit);
+      m &= bit ? bal : ~bal;
+    }
+    uint32_t rank = __popcll(m & lower);
+    if (ok && rank == 0) wcnt[wave][d] = __popcll(m);
+    __syncthreads();
+    if (ok) {
+      uint32_t off = base[d] + rank;
+      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+      kout[off] = k;
+      vout[off] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      add += wcnt[w][t];
+      wcnt[w][t] = 0;
+    }
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+far_status_t scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                            hipStream_t st, Scratch& scr) {
+  if (n <= 0) {
+    if (total) FAR_HIP(hipMemsetAsync(total, 0, sizeof(uint32_t), st));
+    return FAR_OK;
+  }
+  int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles == 1) {
+    k_scan_tiles<<<1, kThreads, 0, st>>>(in, out, n, nullptr, total);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  }
+  uint32_t* sums = nullptr;
+  FAR_TRY(scr.get(&sums, size_t(tiles)));
+  k_scan_tile_sums<<<dim3(uint32_t(tiles)), kThreads, 0, st>>>(in, n, sums);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(sums, sums, tiles, nullptr, st, scr));
+  k_scan_tiles<<<dim3(uint32_t(tiles)), kThreads, 0, st>>>(in, out, n, sums, total);
+  FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
+
+far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                              uint32_t* vals_alt, int64_t n, int bits, hipStream_t st,
+                              Scratch& scr) {
+  if (n <= 1 || bits <= 0) return FAR_OK;
+  int64_t nblocks = (n + kSortTile - 1) / kSortTile;
+  uint32_t* hist = nullptr;
+  FAR_TRY(scr.get(&hist, size_t(256 * nblocks)));
+  uint64_t *ka = keys, *kb = keys_alt;
+  uint32_t *va = vals, *vb = vals_alt;
+  int passes = (bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    k_rs_hist<<<dim3(uint32_t(nblocks)), kThreads, 0, st>>>(ka, n, shift, hist, nblocks);
+    FAR_HIP(hipGetLastError());
+    FAR_TRY(scan_exclusive(hist, hist, 256 * nblocks, nullptr, st, scr));
+    k_rs_scatter<<<dim3(uint32_t(nblocks)), kThreads, 0, st>>>(ka, va, kb, vb, n, shift,
+                                                               hist, nblocks);
+    FAR_HIP(hipGetLastError());
+    uint64_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+  }
+  if (ka != keys) {
+    FAR_HIP(hipMemcpyAsync(keys, ka, size_t(n) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    FAR_HIP(hipMemcpyAsync(vals, va, size_t(n) * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+  return FAR_OK;
+}
+
+}  // namespace far

@@ -1,0 +1,305 @@
+"""Thin ctypes binding of libfar.so, with the C ABI's names (include/far.h).
+
+Argument marshalling only: torch CUDA tensors supply device pointers and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  The library is loaded on first use; if it is missing, every call
+raises (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfar.so")
+_lib = None
+
+FAR_OK, FAR_E_INVALID, FAR_E_CAPACITY, FAR_E_HIP, FAR_E_NOT_PD, FAR_E_FEW_CORR, \
+    FAR_E_UNSUPPORTED = range(7)
+FAR_PREC_FP32, FAR_PREC_FP64 = 0, 1
+
+
+class far_map_params_t(C.Structure):
+    _fields_ = [("voxel_size", C.c_double), ("max_pts_per_voxel", C.c_int32),
+                ("min_spacing", C.c_double), ("point_capacity", C.c_int64),
+                ("voxel_capacity", C.c_int64), ("k_cov", C.c_int32)]
+
+
+class far_lin_t(C.Structure):
+    _fields_ = [("H", C.c_double * 36), ("b", C.c_double * 6), ("cost", C.c_double),
+                ("n_inliers", C.c_int64)]
+
+
+class far_align_params_t(C.Structure):
+    _fields_ = [("tau", C.c_double), ("kappa", C.c_double), ("max_iters", C.c_int32),
+                ("eps", C.c_double), ("recenter", C.c_int32), ("precision", C.c_int32)]
+
+
+class far_align_stats_t(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("last", far_lin_t)]
+
+
+class far_map_stats_t(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("n_voxels", C.c_int64), ("table_slots", C.c_int64),
+                ("load_factor", C.c_double), ("mean_probe", C.c_double),
+                ("max_probe", C.c_int32), ("max_pts_per_voxel", C.c_int32),
+                ("voxel_size", C.c_double), ("min_spacing", C.c_double),
+                ("bytes_device", C.c_int64)]
+
+
+STATS_DTYPE = np.dtype([("iters", np.int32), ("converged", np.int32), ("status", np.int32),
+                        ("reserved", np.int32), ("H", np.float64, (36,)),
+                        ("b", np.float64, (6,)), ("cost", np.float64),
+                        ("n_inliers", np.int64)])
+assert STATS_DTYPE.itemsize == C.sizeof(far_align_stats_t)
+
+_P = C.c_void_p
+_SIGS = {
+    "far_map_create": (C.c_int, [C.POINTER(far_map_params_t), _P, C.POINTER(_P)]),
+    "far_map_destroy": (C.c_int, [_P]),
+    "far_map_insert": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.POINTER(C.c_int64)]),
+    "far_map_knn": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_double, _P, _P, _P, _P]),
+    "far_scan_covariances": (C.c_int, [_P, C.c_int64, C.c_double, C.c_int32, _P, _P, _P]),
+    "far_gicp_linearize": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
+                                     C.c_double, C.c_double, C.POINTER(C.c_double),
+                                     C.c_int32, _P, C.POINTER(far_lin_t), _P]),
+    "far_gicp_align": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
+                                 C.POINTER(far_align_params_t), C.POINTER(C.c_double),
+                                 C.POINTER(far_align_stats_t), _P]),
+    "far_gicp_align_batch": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P,
+                                       C.POINTER(far_align_params_t), _P, _P]),
+    "far_map_stats": (C.c_int, [_P, C.POINTER(far_map_stats_t), _P]),
+    "far_map_export": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
+    "far_status_str": (C.c_char_p, [C.c_int]),
+    "far_last_error": (C.c_char_p, []),
+}
+
+
+class FarError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib().far_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib().far_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libfar.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2606_26010_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where, ok=(FAR_OK,)):
+    if status not in ok:
+        raise FarError(status, where)
+    return status
+
+
+def _dev(t: torch.Tensor | None, dtype, name):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _pts(t, name="xyz"):
+    if t.dim() != 2 or t.shape[0] != 3:
+        raise ValueError(f"{name} must be SoA [3, n]")
+    return _dev(t, torch.float32, name), t.shape[1]
+
+
+def _mat4(T):
+    a = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(16))
+    return (C.c_double * 16)(*a)
+
+
+# ---------------------------------------------------------------- functions
+def far_map_create(voxel_size, max_pts_per_voxel, min_spacing=-1.0, point_capacity=1 << 20,
+                   voxel_capacity=0, k_cov=5, stream=None):
+    p = far_map_params_t(voxel_size, max_pts_per_voxel, min_spacing, point_capacity,
+                         voxel_capacity, k_cov)
+    h = C.c_void_p()
+    _check(lib().far_map_create(C.byref(p), _stream(stream), C.byref(h)), "far_map_create")
+    return h
+
+
+def far_map_destroy(h):
+    _check(lib().far_map_destroy(h), "far_map_destroy")
+
+
+def far_map_insert(h, xyz, voxel_cap=None, stream=None, raise_on=True):
+    """Returns (status, n_accepted); raises on errors other than capacity unless
+    raise_on is False."""
+    p, n = _pts(xyz)
+    acc = C.c_int64(0)
+    st = lib().far_map_insert(h, p, n, _dev(voxel_cap, torch.int32, "voxel_cap"),
+                              _stream(stream), C.byref(acc))
+    if raise_on:
+        _check(st, "far_map_insert", ok=(FAR_OK, FAR_E_CAPACITY))
+    return st, acc.value
+
+
+def far_map_knn(h, q, k, radius, want_d2=True, stream=None):
+    p, n = _pts(q, "q")
+    dev = q.device
+    idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((n, k), dtype=torch.float32, device=dev) if want_d2 else None
+    cnt = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib().far_map_knn(h, p, n, k, radius, _dev(idx, torch.int32, "idx"),
+                             _dev(d2, torch.float32, "d2"), _dev(cnt, torch.int32, "count"),
+                             _stream(stream)), "far_map_knn")
+    return idx, d2, cnt
+
+
+def far_scan_covariances(xyz, voxel_size, k, stream=None):
+    p, n = _pts(xyz)
+    cov = torch.empty((6, n), dtype=torch.float32, device=xyz.device)
+    val = torch.empty(n, dtype=torch.uint8, device=xyz.device)
+    _check(lib().far_scan_covariances(p, n, voxel_size, k, _dev(cov, torch.float32, "cov6"),
+                                      _dev(val, torch.uint8, "valid"), _stream(stream)),
+           "far_scan_covariances")
+    return cov, val
+
+
+def _lin_dict(lin: far_lin_t):
+    return dict(H=np.array(lin.H[:]).reshape(6, 6), b=np.array(lin.b[:]), cost=lin.cost,
+                n_inliers=lin.n_inliers)
+
+
+def far_gicp_linearize(h, src, cov6, valid, T, tau, kappa, c=None, precision=FAR_PREC_FP32,
+                       want_corr=False, stream=None):
+    p, n = _pts(src, "src")
+    corr = torch.empty(n, dtype=torch.int32, device=src.device) if want_corr else None
+    cc = None if c is None else (C.c_double * 3)(*[float(x) for x in c])
+    out = far_lin_t()
+    _check(lib().far_gicp_linearize(h, p, _dev(cov6, torch.float32, "cov6"),
+                                    _dev(valid, torch.uint8, "valid"), n, _mat4(T), tau, kappa,
+                                    cc, precision, _dev(corr, torch.int32, "corr"),
+                                    C.byref(out), _stream(stream)), "far_gicp_linearize")
+    d = _lin_dict(out)
+    if want_corr:
+        d["corr"] = corr
+    return d
+
+
+def align_params(tau, kappa, max_iters=10, eps=1e-6, recenter=1, precision=FAR_PREC_FP32):
+    return far_align_params_t(tau, kappa, max_iters, eps, recenter, precision)
+
+
+def far_gicp_align(h, src, cov6, valid, T0, params: far_align_params_t, stream=None):
+    """Returns (status, T (4x4 numpy), stats dict)."""
+    p, n = _pts(src, "src")
+    Tout = (C.c_double * 16)()
+    st = far_align_stats_t()
+    status = lib().far_gicp_align(h, p, _dev(cov6, torch.float32, "cov6"),
+                                  _dev(valid, torch.uint8, "valid"), n, _mat4(T0),
+                                  C.byref(params), Tout, C.byref(st), _stream(stream))
+    _check(status, "far_gicp_align", ok=(FAR_OK, FAR_E_NOT_PD, FAR_E_FEW_CORR))
+    d = dict(iters=st.iters, converged=st.converged, status=st.status, **_lin_dict(st.last))
+    return status, np.array(Tout[:]).reshape(4, 4), d
+
+
+def far_gicp_align_batch(h, src, offsets, cov6, valid, T, params: far_align_params_t,
+                         stats=None, stream=None):
+    """T: float64 [S, 16] on the GPU (in/out).  stats: uint8 [S * sizeof] buffer or
+    None (allocated).  Asynchronous; returns the stats buffer (decode with
+    decode_stats after synchronising)."""
+    p, n = _pts(src, "src")
+    S = offsets.shape[0] - 1
+    if stats is None:
+        stats = torch.empty(S * STATS_DTYPE.itemsize, dtype=torch.uint8, device=src.device)
+    _check(lib().far_gicp_align_batch(h, p, _dev(offsets, torch.int64, "offsets"), S, n,
+                                      _dev(cov6, torch.float32, "cov6"),
+                                      _dev(valid, torch.uint8, "valid"),
+                                      _dev(T, torch.float64, "T"), C.byref(params),
+                                      _dev(stats, torch.uint8, "stats"), _stream(stream)),
+           "far_gicp_align_batch")
+    return stats
+
+
+def decode_stats(stats: torch.Tensor):
+    return np.frombuffer(stats.cpu().numpy().tobytes(), dtype=STATS_DTYPE)
+
+
+def far_map_stats(h, stream=None):
+    s = far_map_stats_t()
+    _check(lib().far_map_stats(h, C.byref(s), _stream(stream)), "far_map_stats")
+    return {f: getattr(s, f) for f, _ in far_map_stats_t._fields_}
+
+
+def far_map_export(h, capacity=None, device="cuda", stream=None):
+    n = far_map_stats(h, stream)["n_points"] if capacity is None else capacity
+    xyz = torch.empty((3, max(n, 1)), dtype=torch.float32, device=device)
+    cov = torch.empty((6, max(n, 1)), dtype=torch.float32, device=device)
+    val = torch.empty(max(n, 1), dtype=torch.uint8, device=device)
+    out = C.c_int64(0)
+    _check(lib().far_map_export(h, _dev(xyz, torch.float32, "xyz"),
+                                _dev(cov, torch.float32, "cov6"),
+                                _dev(val, torch.uint8, "valid"), n, C.byref(out),
+                                _stream(stream)), "far_map_export")
+    N = out.value
+    if N == 0:
+        return xyz[:, :0], cov[:, :0], val[:0]
+    # SoA rows were written with stride N
+    return (xyz.view(-1)[:3 * N].view(3, N), cov.view(-1)[:6 * N].view(6, N), val[:N])
+
+
+class Map:
+    """Owning wrapper of a far_map_t."""
+
+    def __init__(self, voxel_size, max_pts_per_voxel, min_spacing=-1.0,
+                 point_capacity=1 << 20, voxel_capacity=0, k_cov=5, stream=None):
+        self.h = far_map_create(voxel_size, max_pts_per_voxel, min_spacing, point_capacity,
+                                voxel_capacity, k_cov, stream)
+        self.voxel_size = voxel_size
+
+    def close(self):
+        if getattr(self, "h", None):
+            far_map_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, xyz, voxel_cap=None, stream=None):
+        return far_map_insert(self.h, xyz, voxel_cap, stream)
+
+    def knn(self, q, k, radius, stream=None):
+        return far_map_knn(self.h, q, k, radius, stream=stream)
+
+    def linearize(self, *a, **kw):
+        return far_gicp_linearize(self.h, *a, **kw)
+
+    def align(self, *a, **kw):
+        return far_gicp_align(self.h, *a, **kw)
+
+    def align_batch(self, *a, **kw):
+        return far_gicp_align_batch(self.h, *a, **kw)
+
+    def stats(self, stream=None):
+        return far_map_stats(self.h, stream)
+
+    def export(self, stream=None):
+        return far_map_export(self.h, stream=stream)

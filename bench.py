@@ -1,0 +1,358 @@
+#!/usr/bin/env python
+"""Benchmark of the batched GICP linearize+kNN hot path on one MI355X.
+
+Workload (the batched-scans configuration the throughput target is quoted on):
+64 independent spinning-LiDAR scans of uneven size (U[8k, 130k] points,
+clamped to each scan's ray hits) at random poses along a corridor, each with
+its own initial offset (<= 0.5 m, <= 3 deg), registered against one prebuilt
+2,000,000-point voxel map (v = 1 m, N_max = 20, spacing v/sqrt(20), k = 5).
+All data is seeded and synthetic (the paper's datasets are not available).
+
+One step = the whole per-batch hot path with inputs resident in HBM:
+  1. regularised covariances of every scan against itself (one batched call);
+  2. batched Gauss-Newton align of all scans: each iteration is one
+     linearisation launch over all scans' point tiles plus one
+     reduce-and-solve launch, the whole align replayed as one HIP graph.
+
+value = linearize+kNN points/s = sum over scans of (GN iterations x points)
+divided by the step time.  Also reported: scans/s, the one-scan-per-launch
+path, the roofline of the dominant kernel (HIP-event timed inside the
+library), pose error against the oracle and ground truth, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2606_26010_amd/csrc/far_gicp.hip", "paper_2606_26010_amd/csrc/far_knn.h",
+                  "paper_2606_26010_amd/csrc/far_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_linearize_batch64_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_fingerprint():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pose_err(A, B):
+    import numpy as np
+    E = A[:3, :3] @ B[:3, :3].T
+    ang = math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(E) - 1) / 2))))
+    return float(np.linalg.norm(A[:3, 3] - B[:3, 3])), ang
+
+
+def touched_voxels(map_keys_counts, scan_xyz, T, v):
+    """Distinct non-empty map voxels in the 27-neighbourhoods of a scan's
+    transformed points, and the points they hold (host-side byte model)."""
+    import numpy as np
+    keys, counts = map_keys_counts
+    p = T[:3, :3] @ scan_xyz.astype(np.float64) + T[:3, 3:4]
+    k = np.floor(p / v).astype(np.int64)
+    k = np.unique(k, axis=1)
+    offs = np.array([[a, b, c] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]).T
+    nb = (k[:, :, None] + offs[:, None, :]).reshape(3, -1)
+    packed = ((nb[0] + (1 << 20)) << 42) | ((nb[1] + (1 << 20)) << 21) | (nb[2] + (1 << 20))
+    packed = np.unique(packed)
+    idx = np.searchsorted(keys, packed)
+    idx = np.clip(idx, 0, len(keys) - 1)
+    hit = keys[idx] == packed
+    return packed[hit], counts[idx[hit]]
+
+
+def read_traffic(fp):
+    """HBM bytes per linearisation launch from the committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("kernel_sources_sha256_16") != fp:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--scans", type=int, default=64)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--eps", type=float, default=5e-3,
+                    help="stop when |delta| <= eps (the paper's 5e-3; 0: always run --iters)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the one-scan-per-launch path")
+    ap.add_argument("--cpu-sample-scans", type=int, default=2)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_26010_amd import far, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_per_copy": a.numel() * 4}))
+        return
+
+    t_gen = time.time()
+    case = synth.make_batch(args.seed, n_scans=args.scans)
+    log(f"[bench] generated {len(case.scans)} scans, {sum(s.shape[1] for s in case.scans)} points "
+        f"in {time.time() - t_gen:.1f}s")
+    S = len(case.scans)
+    sizes = np.array([s.shape[1] for s in case.scans], np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    N = int(offsets[-1])
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        # ---------------- map build (not timed as part of the step)
+        gm = far.Map(case.voxel_size, case.max_pts_per_voxel, case.min_spacing,
+                     point_capacity=case.map_capacity, voxel_capacity=1 << 19,
+                     k_cov=case.k)
+        t0 = time.time()
+        inserted = 0
+        for b in case.map_batches:
+            st, acc = gm.insert(torch.from_numpy(b).to(dev))
+            inserted += b.shape[1]
+            if st == far.FAR_E_CAPACITY:
+                break
+        stream.synchronize()
+        t_map = time.time() - t0
+        mstats = gm.stats()
+        log(f"[bench] map: {mstats['n_points']} points in {mstats['n_voxels']} voxels, "
+            f"{inserted} candidates, {t_map:.2f}s, load {mstats['load_factor']:.3f}, "
+            f"mean probe {mstats['mean_probe']:.3f}")
+
+        src = torch.from_numpy(np.ascontiguousarray(np.concatenate(case.scans, 1))).to(dev)
+        offs = torch.from_numpy(offsets).to(dev)
+        T0 = torch.from_numpy(np.stack([t.reshape(16) for t in case.T0])).to(dev)
+        T = T0.clone()
+        stats_buf = torch.empty(S * far.STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        prec = far.FAR_PREC_FP64 if args.precision == "fp64" else far.FAR_PREC_FP32
+        prm = far.align_params(case.tau, case.kappa, max_iters=args.iters, eps=args.eps,
+                               recenter=1, precision=prec)
+
+        cov_buf = torch.empty((6, N), dtype=torch.float32, device=dev)
+        val_buf = torch.empty(N, dtype=torch.uint8, device=dev)
+
+        def step():
+            cov, val = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
+                                                      out=(cov_buf, val_buf))
+            T.copy_(T0)
+            far.far_gicp_align_batch(gm.h, src, offs, cov, val, T, prm, stats=stats_buf)
+            return cov, val
+
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cov, val = step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / args.steps
+        stats = far.decode_stats(stats_buf)
+        T_gpu = T.cpu().numpy().reshape(S, 4, 4)
+        iters = stats["iters"].astype(np.int64)
+        failed = stats["status"] != 0
+        lin_per_scan = iters + failed.astype(np.int64)   # a failing iteration still linearised
+        point_lins = int(np.sum(lin_per_scan * sizes))
+        log(f"[bench] step {t_step * 1e3:.3f} ms, iterations {iters.min()}..{iters.max()}, "
+            f"status {np.bincount(stats['status'], minlength=6).tolist()}")
+
+        # ---------------- roofline of the dominant kernel (event-timed launches)
+        far.far_timing_read(reset=True)
+        far.far_timing_enable(True)
+        n_timed = max(1, min(args.steps, 5))
+        for _ in range(n_timed):
+            step()
+        stream.synchronize()
+        lin_ms, lin_launches = far.far_timing_read(reset=True)
+        far.far_timing_enable(False)
+        stats_t = far.decode_stats(stats_buf)
+        T_fin = T.cpu().numpy().reshape(S, 4, 4)
+        # algorithmic bytes: every launch reads each active source point
+        # (xyz 12 B, cov6 24 B, valid 1 B), the matched map covariance record of
+        # each inlier (32 B), and once the slot (16 B), count (4 B) and points
+        # (16 B each) of every distinct map voxel its active points touch, and
+        # writes 29 FP64 partials per 256-point tile.
+        mx, _, _ = gm.export()
+        mk = np.floor(mx.cpu().numpy().astype(np.float64) / case.voxel_size).astype(np.int64)
+        mp = ((mk[0] + (1 << 20)) << 42) | ((mk[1] + (1 << 20)) << 21) | (mk[2] + (1 << 20))
+        mkeys, mcounts = np.unique(mp, return_counts=True)
+        per_scan_vox = [touched_voxels((mkeys, mcounts), case.scans[s], T_fin[s], case.voxel_size)
+                        for s in range(S)]
+        it_t = stats_t["iters"].astype(np.int64) + (stats_t["status"] != 0)
+        n_inl = stats_t["n_inliers"].astype(np.int64)
+        launches_per_step = args.iters
+        bytes_step = 0.0
+        for it in range(launches_per_step):
+            active = np.nonzero(it_t > it)[0]
+            if active.size == 0:
+                continue
+            vk = np.concatenate([per_scan_vox[s][0] for s in active])
+            vc = np.concatenate([per_scan_vox[s][1] for s in active])
+            uk, ui = np.unique(vk, return_index=True)
+            tiles = int(np.sum((sizes[active] + 255) // 256))
+            bytes_step += (37.0 * sizes[active].sum() + 32.0 * n_inl[active].sum()
+                           + 20.0 * uk.size + 16.0 * vc[ui].sum() + 29 * 8.0 * tiles)
+        bytes_per_launch = bytes_step / launches_per_step
+        avg_launch_ms = lin_ms / max(lin_launches, 1)
+        achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+        fp = kernel_fingerprint()
+        traffic = read_traffic(fp)
+        log(f"[bench] linearize: {lin_launches} launches, avg {avg_launch_ms * 1e3:.1f} us, "
+            f"{bytes_per_launch / 1e6:.1f} MB algorithmic per launch, {achieved:.0f} GB/s")
+
+        # ---------------- one-scan-per-launch path (same work, per-scan calls)
+        single = None
+        if not args.no_single:
+            scan_t = [torch.from_numpy(np.ascontiguousarray(s)).to(dev) for s in case.scans]
+            prm1 = far.align_params(case.tau, case.kappa, max_iters=args.iters, eps=args.eps,
+                                    recenter=1, precision=prec)
+
+            def single_step():
+                out = []
+                for s in range(S):
+                    c1, v1 = far.far_scan_covariances(scan_t[s], case.voxel_size, case.k)
+                    out.append(far.far_gicp_align(gm.h, scan_t[s], c1, v1, case.T0[s], prm1))
+                return out
+
+            single_step()
+            stream.synchronize()
+            n_single = max(1, min(args.steps, 3))
+            t0 = time.perf_counter()
+            for _ in range(n_single):
+                res1 = single_step()
+            stream.synchronize()
+            t_single = (time.perf_counter() - t0) / n_single
+            dmax = max(pose_err(res1[s][1], T_gpu[s])[0] for s in range(S))
+            single = {"ms_per_step": round(t_single * 1e3, 3),
+                      "scans_per_s": round(S / t_single, 2),
+                      "batched_speedup": round(t_single / t_step, 2),
+                      "max_pose_diff_vs_batched_m": dmax}
+            log(f"[bench] single-scan path {t_single * 1e3:.2f} ms/step")
+
+        gt_err = [pose_err(T_gpu[s], case.T_gt[s]) for s in range(S)]
+
+        # ---------------- CPU oracle on a bounded sample of the same workload
+        cpu = None
+        oracle_err = None
+        if not args.no_cpu_baseline:
+            from oracle import far_oracle as O
+            om = O.Map(case.voxel_size, case.max_pts_per_voxel, case.min_spacing, case.k,
+                       point_capacity=case.map_capacity, voxel_capacity=case.map_capacity)
+            t0 = time.time()
+            for b in case.map_batches:
+                om.insert(b, check=False)
+                if om.size >= case.map_capacity:
+                    break
+            log(f"[bench] oracle map built in {time.time() - t0:.1f}s ({om.size} points)")
+            ns = min(args.cpu_sample_scans, S)
+            t0 = time.perf_counter()
+            o_lins, o_res = 0, []
+            for s in range(ns):
+                oc, ov = O.scan_covariances(case.scans[s], case.voxel_size, case.k)
+                r = om.align(case.scans[s], oc.astype(np.float32), ov, case.T0[s], case.tau,
+                             case.kappa, max_iters=args.iters, eps=args.eps)
+                o_res.append(r)
+                o_lins += (r["iters"] + (1 if r["status"] else 0)) * case.scans[s].shape[1]
+            t_cpu = time.perf_counter() - t0
+            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+            cpu = {"value": round(o_lins / t_cpu, 1), "unit": "points/s", "cores": threads,
+                   "kind": "oracle",
+                   "sample": f"{ns} of {S} scans ({int(sizes[:ns].sum())} points): FP64 oracle "
+                             f"scan covariances + align, {args.iters} GN iterations max, "
+                             f"{t_cpu:.1f} s"}
+            oracle_err = [pose_err(T_gpu[s], o_res[s]["T"]) for s in range(ns)]
+
+    result = {
+        "metric": "GICP linearize+kNN points/s and scans/s on 1 MI355X; % HBM roofline; pose err",
+        "value": round(point_lins / t_step, 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == far.FAR_PREC_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched uneven scans: {S} spinning-LiDAR scans "
+                               f"({N} points, {int(sizes.min())}..{int(sizes.max())} per scan) "
+                               f"vs a {mstats['n_points']}-point voxel map (v=1 m, N_max=20, k=5), "
+                               f"{args.iters} GN iterations max, eps={args.eps}",
+                   "scans": S, "points": N, "map_points": mstats["n_points"],
+                   "map_voxels": mstats["n_voxels"], "iters": args.iters, "eps": args.eps,
+                   "parallelism": "single GPU"},
+        "scans_per_s": round(S / t_step, 2),
+        "point_linearizations_per_step": point_lins,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic, "kernel": "k_linearize<float>",
+                     "avg_launch_us": round(avg_launch_ms * 1e3, 2),
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                     "kernel_sources_sha256_16": fp},
+        "cpu_baseline": cpu,
+        "single_scan_path": single,
+        "pose_err_vs_gt": {"max_m": max(e[0] for e in gt_err),
+                           "max_deg": max(e[1] for e in gt_err)},
+        "pose_err_vs_oracle": None if oracle_err is None else
+        {"max_m": max(e[0] for e in oracle_err), "max_deg": max(e[1] for e in oracle_err),
+         "scans": len(oracle_err)},
+        "map_build": {"seconds": round(t_map, 3), "candidates": inserted,
+                      "mean_probe": mstats["mean_probe"], "max_probe": mstats["max_probe"],
+                      "load_factor": mstats["load_factor"]},
+    }
+    if prec == far.FAR_PREC_FP64:
+        result["roofline"]["kernel"] = "k_linearize<double>"
+    print(json.dumps(result), flush=True)
+    gm.close()
+
+
+if __name__ == "__main__":
+    main()

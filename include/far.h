@@ -160,6 +160,15 @@ far_status_t far_scan_covariances(const float* xyz, int64_t n, double voxel_size
                                   int32_t k, float* cov6, uint8_t* valid,
                                   far_stream_t stream);
 
+/* Covariances of S scans in one pass: scan s holds points
+ * [offsets[s], offsets[s+1]) of xyz [dev, SoA 3 x n_total]; each point's
+ * covariance uses only points of its own scan (as far_scan_covariances does
+ * for one scan).  offsets [dev, S+1] int64, non-decreasing, offsets[0] = 0,
+ * offsets[S] = n_total.  cov6 [dev, SoA 6 x n_total], valid [dev, n_total]. */
+far_status_t far_scan_covariances_batch(const float* xyz, const int64_t* offsets, int32_t S,
+                                        int64_t n_total, double voxel_size, int32_t k,
+                                        float* cov6, uint8_t* valid, far_stream_t stream);
+
 /* One GICP linearisation (Eqs. 3-5, sparsity-aware) of the scan src
  * [dev, SoA 3 x n] with covariances cov6 [dev, SoA 6 x n] and valid [dev, n]
  * against the map at pose T [host]: p = R s + t in FP64; correspondence = the
@@ -211,6 +220,15 @@ far_status_t far_map_stats(far_map_t map, far_map_stats_t* out, far_stream_t str
  * N exceeds it (nothing written).  Synchronises. */
 far_status_t far_map_export(far_map_t map, float* xyz, float* cov6, uint8_t* valid,
                             int64_t capacity, int64_t* n_out, far_stream_t stream);
+
+/* Instrumentation.  With timing on, every linearisation launch is bracketed
+ * by HIP events recorded on the stream it runs on, and the align entry points
+ * launch their kernels directly instead of through a graph.  far_timing_read
+ * waits for the recorded launches and returns their summed kernel time (ms)
+ * and count since the last reset (reset != 0 clears them after reading).
+ * Process-wide; not meant for concurrent use from several threads. */
+far_status_t far_timing_enable(int32_t on);
+far_status_t far_timing_read(double* linearize_ms, int64_t* launches, int32_t reset);
 
 const char* far_status_str(far_status_t s);
 const char* far_last_error(void);

@@ -13,7 +13,10 @@
 // graph per argument set and replayed.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "far_knn.h"
 
@@ -118,148 +121,338 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// ---------------------------------------------------------------- linearise
-// One GICP term per thread (Eqs. (3)-(5), sparsity-aware):
-//   p = R s + t (FP64, ((R0 sx + R1 sy) + R2 sz) + t, no FMA)
-//   j = nearest map point within min(tau, v), ranked by (d2, id)
-//   d = r_j - p,  a = p - c
+// ---------------------------------------------------------------- locality
+// Before the iterations every point is given a locality key (scan id, then
+// the Morton code of its sensor-frame voxel) and the source is packed, in key
+// order, into 40 bytes per point:
+//   A float4 (x, y, z, original index bits)
+//   B float4 (xx or -1 when the covariance is invalid, xy, xz, yy)
+//   C float2 (yz, zz)
+// so that a 256-point tile is a compact patch of one scan: its lanes share
+// map voxels and its map neighbourhood fits in LDS.  The order only changes
+// the rounding order of the sums, never which points are summed.
+__device__ inline uint32_t spread10(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000FFu;
+  x = (x | (x << 8)) & 0x0300F00Fu;
+  x = (x | (x << 4)) & 0x030C30C3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+__device__ inline uint32_t quant10(float x, double v) {
+  double q = floor(double(x) / v) + 512.0;
+  q = q < 0.0 ? 0.0 : (q > 1023.0 ? 1023.0 : q);
+  return uint32_t(q);
+}
+
+__global__ __launch_bounds__(256) void k_order_keys(const float* src, int64_t n,
+                                                    const int64_t* offsets, int32_t S, double v,
+                                                    uint64_t* keys, uint32_t* vals) {
+  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  int32_t lo = 0, hi = S;
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    if (offsets[mid] <= i) lo = mid; else hi = mid;
+  }
+  float x = src[i], y = src[n + i], z = src[2 * n + i];
+  uint32_t code = (1u << 30) - 1u;
+  if (isfinite(x) && isfinite(y) && isfinite(z))
+    code = spread10(quant10(x, v)) | (spread10(quant10(y, v)) << 1) |
+           (spread10(quant10(z, v)) << 2);
+  keys[i] = (uint64_t(lo) << 30) | code;
+  vals[i] = uint32_t(i);
+}
+
+__global__ __launch_bounds__(256) void k_pack(const float* src, const float* cov6,
+                                              const uint8_t* valid, int64_t n,
+                                              const uint32_t* perm, float4* A, float4* B,
+                                              float2* C) {
+  int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (m >= n) return;
+  uint32_t i = perm[m];
+  A[m] = make_float4(src[i], src[n + i], src[2 * n + i], __int_as_float(int32_t(i)));
+  bool ok = valid[i] != 0;
+  B[m] = make_float4(ok ? cov6[i] : -1.0f, cov6[n + i], cov6[2 * n + i], cov6[3 * n + i]);
+  C[m] = make_float2(cov6[4 * n + i], cov6[5 * n + i]);
+}
+
+// ---------------------------------------------------------------- GICP term
+// One GICP term (Eqs. (3)-(5), sparsity-aware), accumulated into acc:
+//   d = r - p, a = p - c
 //   M = Sigma_r + R Sigma_s R^T if both covariances are valid, else I
 //   W = M^-1, e2 = d^T W d, w = k2/(k2 + e2), rho = k2/2 ln(1 + e2/k2)
-//   J = [[a]x, -I]: H += w J^T W J, b += w J^T W d, cost += rho, n += 1
+//   J = [[a]x, -I]: H += w J^T W J (21 upper entries), b += w J^T W d,
+//   cost += rho, count += 1
+template <class Real>
+__device__ inline void gicp_term(double px, double py, double pz, float4 r, float4 ca,
+                                 float4 cb, float4 sB, float2 sC, const double* R, double cx,
+                                 double cy, double cz, double kappa2, Real* acc) {
+  const Real d0 = Real(double(r.x) - px), d1 = Real(double(r.y) - py),
+             d2 = Real(double(r.z) - pz);
+  const Real a0 = Real(px - cx), a1 = Real(py - cy), a2 = Real(pz - cz);
+  Real M00, M01, M02, M11, M12, M22;
+  if (sB.x >= 0.0f && cb.z != 0.0f) {
+    const Real q00 = sB.x, q01 = sB.y, q02 = sB.z, q11 = sB.w, q12 = sC.x, q22 = sC.y;
+    const Real r00 = Real(R[0]), r01 = Real(R[1]), r02 = Real(R[2]);
+    const Real r10 = Real(R[3]), r11 = Real(R[4]), r12 = Real(R[5]);
+    const Real r20 = Real(R[6]), r21 = Real(R[7]), r22 = Real(R[8]);
+    // U = R Sigma_s, then M = Sigma_r + U R^T
+    const Real u00 = r00 * q00 + r01 * q01 + r02 * q02;
+    const Real u01 = r00 * q01 + r01 * q11 + r02 * q12;
+    const Real u02 = r00 * q02 + r01 * q12 + r02 * q22;
+    const Real u10 = r10 * q00 + r11 * q01 + r12 * q02;
+    const Real u11 = r10 * q01 + r11 * q11 + r12 * q12;
+    const Real u12 = r10 * q02 + r11 * q12 + r12 * q22;
+    const Real u20 = r20 * q00 + r21 * q01 + r22 * q02;
+    const Real u21 = r20 * q01 + r21 * q11 + r22 * q12;
+    const Real u22 = r20 * q02 + r21 * q12 + r22 * q22;
+    M00 = Real(ca.x) + (u00 * r00 + u01 * r01 + u02 * r02);
+    M01 = Real(ca.y) + (u00 * r10 + u01 * r11 + u02 * r12);
+    M02 = Real(ca.z) + (u00 * r20 + u01 * r21 + u02 * r22);
+    M11 = Real(ca.w) + (u10 * r10 + u11 * r11 + u12 * r12);
+    M12 = Real(cb.x) + (u10 * r20 + u11 * r21 + u12 * r22);
+    M22 = Real(cb.y) + (u20 * r20 + u21 * r21 + u22 * r22);
+  } else {
+    M00 = Real(1); M01 = Real(0); M02 = Real(0);
+    M11 = Real(1); M12 = Real(0); M22 = Real(1);
+  }
+  // W = M^-1 by the adjugate (M is symmetric positive definite)
+  const Real A00 = M11 * M22 - M12 * M12;
+  const Real A01 = M02 * M12 - M01 * M22;
+  const Real A02 = M01 * M12 - M02 * M11;
+  const Real A11 = M00 * M22 - M02 * M02;
+  const Real A12 = M01 * M02 - M00 * M12;
+  const Real A22 = M00 * M11 - M01 * M01;
+  const Real inv_det = Real(1) / (M00 * A00 + M01 * A01 + M02 * A02);
+  const Real W00 = A00 * inv_det, W01 = A01 * inv_det, W02 = A02 * inv_det;
+  const Real W11 = A11 * inv_det, W12 = A12 * inv_det, W22 = A22 * inv_det;
+  const Real g0 = W00 * d0 + W01 * d1 + W02 * d2;
+  const Real g1 = W01 * d0 + W11 * d1 + W12 * d2;
+  const Real g2 = W02 * d0 + W12 * d1 + W22 * d2;
+  const Real e2 = d0 * g0 + d1 * g1 + d2 * g2;
+  const Real k2 = Real(kappa2);
+  const Real w = k2 / (k2 + e2);
+  const Real rho = Real(0.5) * k2 * log1p(e2 / k2);
+  // Columns of A = [a]x: A0 = (0, a2, -a1), A1 = (-a2, 0, a0), A2 = (a1, -a0, 0);
+  // B = W A column by column.  H_rr[p][q] = A_p . B_q, H_rt[p][q] = -B[q][p],
+  // H_tt = W; b = (A_p . g, -g).
+  const Real B00 = W01 * a2 - W02 * a1, B10 = W11 * a2 - W12 * a1, B20 = W12 * a2 - W22 * a1;
+  const Real B01 = W02 * a0 - W00 * a2, B11 = W12 * a0 - W01 * a2, B21 = W22 * a0 - W02 * a2;
+  const Real B02 = W00 * a1 - W01 * a0, B12 = W01 * a1 - W11 * a0, B22 = W02 * a1 - W12 * a0;
+  auto dotA0 = [&](Real x1, Real x2) { return a2 * x1 - a1 * x2; };
+  auto dotA1 = [&](Real x0, Real x2) { return a0 * x2 - a2 * x0; };
+  auto dotA2 = [&](Real x0, Real x1) { return a1 * x0 - a0 * x1; };
+  int v = 0;
+  acc[v++] = w * dotA0(B10, B20);
+  acc[v++] = w * dotA0(B11, B21);
+  acc[v++] = w * dotA0(B12, B22);
+  acc[v++] = -w * B00; acc[v++] = -w * B10; acc[v++] = -w * B20;
+  acc[v++] = w * dotA1(B01, B21);
+  acc[v++] = w * dotA1(B02, B22);
+  acc[v++] = -w * B01; acc[v++] = -w * B11; acc[v++] = -w * B21;
+  acc[v++] = w * dotA2(B02, B12);
+  acc[v++] = -w * B02; acc[v++] = -w * B12; acc[v++] = -w * B22;
+  acc[v++] = w * W00; acc[v++] = w * W01; acc[v++] = w * W02;
+  acc[v++] = w * W11; acc[v++] = w * W12;
+  acc[v++] = w * W22;
+  acc[v++] = w * dotA0(g1, g2);
+  acc[v++] = w * dotA1(g0, g2);
+  acc[v++] = w * dotA2(g0, g1);
+  acc[v++] = -w * g0; acc[v++] = -w * g1; acc[v++] = -w * g2;
+  acc[v++] = rho;
+  acc[v++] = Real(1);
+}
+
+// ---------------------------------------------------------------- linearise
+// One 256-thread block per tile of 256 locality-ordered points, persistent
+// over tiles.  The tiles are split into eight contiguous ranges, one per XCD
+// (blocks are dealt to the eight XCDs round-robin), so neighbouring tiles -
+// which share map voxels - meet in the same L2.
+//
+// Per tile: every lane transforms its point (FP64, no FMA) and takes its map
+// voxel key; the block forms the key box of the tile grown by one voxel.  If
+// the box has at most kBoxMax cells and holds at most kLdsPts map points, the
+// block probes the hash table once per cell, prefix-sums the counts into a
+// dense local voxel table and copies the points into LDS; every lane then
+// searches its 27-voxel neighbourhood in LDS.  Otherwise the lanes search the
+// global map directly.  Both give the same nearest point: the same voxels'
+// points, the same FP64 squared distances, the same (d2, id) ranking.
+constexpr int kBoxMax = 1024;
+constexpr int kLdsPts = 1024;
+
+__device__ inline int block_exscan_int(int v, int* lds, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kTile / 64; ++w) {
+    int s = lds[w];
+    pre += (w < wave) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
 template <class Real>
 __global__ __launch_bounds__(kTile) void k_linearize(
-    MapView m, const float* __restrict__ src, const float* __restrict__ cov6,
-    const uint8_t* __restrict__ valid, int64_t n_total, const int32_t* __restrict__ tile_scan,
+    MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
+    const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
     int32_t* __restrict__ corr) {
   __shared__ double red[kTile / 64][kVals];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  __shared__ int s_box[6];
+  __shared__ int s_start[kBoxMax + 1];
+  __shared__ int s_vox[kBoxMax];
+  __shared__ float4 s_pts[kLdsPts];
+  __shared__ int s_scan[kTile / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double v = m.v;
+
+  const int64_t per = gridDim.x >> 3;
+  const int64_t chunk = (n_tiles + 7) >> 3;
+  const int64_t t_begin = int64_t(blockIdx.x & 7) * chunk;
+  const int64_t t_end = t_begin + chunk < n_tiles ? t_begin + chunk : n_tiles;
+  for (int64_t t = t_begin + (blockIdx.x >> 3); t < t_end; t += per) {
     const int32_t s = tile_scan[t];
     if (s < 0 || done[s]) continue;
     const double* Ts = T + 16 * int64_t(s);
-    const double R00 = Ts[0], R01 = Ts[1], R02 = Ts[2], tx = Ts[3];
-    const double R10 = Ts[4], R11 = Ts[5], R12 = Ts[6], ty = Ts[7];
-    const double R20 = Ts[8], R21 = Ts[9], R22 = Ts[10], tz = Ts[11];
+    double R[9] = {Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]};
+    const double tx = Ts[3], ty = Ts[7], tz = Ts[11];
     const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
-    const int64_t i = int64_t(tile_lo[t]) + threadIdx.x;
+    const int64_t i = int64_t(tile_lo[t]) + tid;
+
+    // transform and voxel key of this lane's point
+    bool have = false;
+    double px = 0, py = 0, pz = 0;
+    int64_t kx = 0, ky = 0, kz = 0;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < int64_t(tile_hi[t])) {
+      a = pA[i];
+      if (isfinite(a.x) && isfinite(a.y) && isfinite(a.z)) {
+        const double sx = a.x, sy = a.y, sz = a.z;
+        px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
+        py = ((R[3] * sx + R[4] * sy) + R[5] * sz) + ty;
+        pz = ((R[6] * sx + R[7] * sy) + R[8] * sz) + tz;
+        have = voxel_index(px, v, &kx) && voxel_index(py, v, &ky) && voxel_index(pz, v, &kz);
+      }
+    }
+    // key box of the tile
+    if (tid < 3) s_box[tid] = INT_MAX;
+    else if (tid < 6) s_box[tid] = INT_MIN;
+    __syncthreads();
+    if (have) {
+      atomicMin(&s_box[0], int(kx)); atomicMin(&s_box[1], int(ky)); atomicMin(&s_box[2], int(kz));
+      atomicMax(&s_box[3], int(kx)); atomicMax(&s_box[4], int(ky)); atomicMax(&s_box[5], int(kz));
+    }
+    __syncthreads();
+    const int bx0 = s_box[0] - 1, by0 = s_box[1] - 1, bz0 = s_box[2] - 1;
+    const int64_t dx = int64_t(s_box[3]) - bx0 + 2, dy = int64_t(s_box[4]) - by0 + 2,
+                  dz = int64_t(s_box[5]) - bz0 + 2;
+    const bool any = s_box[0] != INT_MAX;
+    const int64_t ncell64 = any ? dx * dy * dz : 0;
+    bool staged = any && ncell64 <= kBoxMax;
+    int total = 0;
+    if (staged) {
+      const int ncell = int(ncell64);
+      int cnt[kBoxMax / kTile];
+#pragma unroll
+      for (int q = 0; q < kBoxMax / kTile; ++q) {
+        const int c = tid * (kBoxMax / kTile) + q;
+        cnt[q] = 0;
+        if (c < ncell) {
+          const int cz_ = c % int(dz), cy_ = (c / int(dz)) % int(dy), cx_ = c / int(dz * dy);
+          const int32_t vox = map_find(m, bx0 + cx_, by0 + cy_, bz0 + cz_);
+          s_vox[c] = vox;
+          cnt[q] = vox >= 0 ? m.vox_count[vox] : 0;
+        }
+      }
+      int sum = 0;
+#pragma unroll
+      for (int q = 0; q < kBoxMax / kTile; ++q) sum += cnt[q];
+      int run = block_exscan_int(sum, s_scan, &total);
+#pragma unroll
+      for (int q = 0; q < kBoxMax / kTile; ++q) {
+        const int c = tid * (kBoxMax / kTile) + q;
+        if (c < ncell) s_start[c] = run;
+        run += cnt[q];
+      }
+      if (tid == 0) s_start[ncell] = total;
+      staged = total <= kLdsPts;          // block-uniform
+      __syncthreads();
+      if (staged) {
+        for (int e = tid; e < total; e += kTile) {
+          int lo = 0, hi = ncell;           // s_start[lo] <= e < s_start[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_start[mid] <= e) lo = mid; else hi = mid;
+          }
+          s_pts[e] = m.vox_pts[int64_t(s_vox[lo]) * m.nmax + (e - s_start[lo])];
+        }
+      }
+      __syncthreads();
+    }
 
     Real acc[kVals];
 #pragma unroll
-    for (int v = 0; v < kVals; ++v) acc[v] = Real(0);
+    for (int q = 0; q < kVals; ++q) acc[q] = Real(0);
     int32_t match = -1;
-
-    if (i < int64_t(tile_hi[t])) {
-      const float sx = src[i], sy = src[n_total + i], sz = src[2 * n_total + i];
-      if (isfinite(sx) && isfinite(sy) && isfinite(sz)) {
-        const double dsx = sx, dsy = sy, dsz = sz;
-        const double px = ((R00 * dsx + R01 * dsy) + R02 * dsz) + tx;
-        const double py = ((R10 * dsx + R11 * dsy) + R12 * dsz) + ty;
-        const double pz = ((R20 * dsx + R21 * dsy) + R22 * dsz) + tz;
-        TopK<1> top;
-        map_knn_query<1>(m, px, py, pz, prm.r2, top);
-        if (top.pos[0] >= 0) {
-          match = top.id[0];
-          const float4 r = m.vox_pts[top.pos[0]];
-          const float4 ca = m.cov[2 * int64_t(match)];
-          const float4 cb = m.cov[2 * int64_t(match) + 1];
-          const Real d0 = Real(double(r.x) - px), d1 = Real(double(r.y) - py),
-                     d2 = Real(double(r.z) - pz);
-          const Real a0 = Real(px - cx), a1 = Real(py - cy), a2 = Real(pz - cz);
-          Real M00, M01, M02, M11, M12, M22;
-          if (valid[i] && cb.z != 0.0f) {
-            // R Sigma_s R^T
-            const Real q00 = cov6[i], q01 = cov6[n_total + i], q02 = cov6[2 * n_total + i];
-            const Real q11 = cov6[3 * n_total + i], q12 = cov6[4 * n_total + i],
-                       q22 = cov6[5 * n_total + i];
-            const Real r00 = Real(R00), r01 = Real(R01), r02 = Real(R02);
-            const Real r10 = Real(R10), r11 = Real(R11), r12 = Real(R12);
-            const Real r20 = Real(R20), r21 = Real(R21), r22 = Real(R22);
-            // RS = R * Sigma_s (rows of R times the symmetric matrix)
-            const Real u00 = r00 * q00 + r01 * q01 + r02 * q02;
-            const Real u01 = r00 * q01 + r01 * q11 + r02 * q12;
-            const Real u02 = r00 * q02 + r01 * q12 + r02 * q22;
-            const Real u10 = r10 * q00 + r11 * q01 + r12 * q02;
-            const Real u11 = r10 * q01 + r11 * q11 + r12 * q12;
-            const Real u12 = r10 * q02 + r11 * q12 + r12 * q22;
-            const Real u20 = r20 * q00 + r21 * q01 + r22 * q02;
-            const Real u21 = r20 * q01 + r21 * q11 + r22 * q12;
-            const Real u22 = r20 * q02 + r21 * q12 + r22 * q22;
-            M00 = Real(ca.x) + (u00 * r00 + u01 * r01 + u02 * r02);
-            M01 = Real(ca.y) + (u00 * r10 + u01 * r11 + u02 * r12);
-            M02 = Real(ca.z) + (u00 * r20 + u01 * r21 + u02 * r22);
-            M11 = Real(ca.w) + (u10 * r10 + u11 * r11 + u12 * r12);
-            M12 = Real(cb.x) + (u10 * r20 + u11 * r21 + u12 * r22);
-            M22 = Real(cb.y) + (u20 * r20 + u21 * r21 + u22 * r22);
-          } else {
-            M00 = Real(1); M01 = Real(0); M02 = Real(0);
-            M11 = Real(1); M12 = Real(0); M22 = Real(1);
+    if (have) {
+      TopK<1> top;
+      float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (staged) {
+        top.init();
+        for (int q = 0; q < 27; ++q) {
+          const int code = kNbrOrder[q];
+          const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+          const double bnd = fmin(prm.r2, top.bound());
+          if (voxel_lb2(px, py, pz, kx, ky, kz, ox, oy, oz, v) > bnd) continue;
+          const int c = ((int(kx) + ox - bx0) * int(dy) + (int(ky) + oy - by0)) * int(dz) +
+                        (int(kz) + oz - bz0);
+          const int e1 = s_start[c + 1];
+          for (int e = s_start[c]; e < e1; ++e) {
+            const float4 q4 = s_pts[e];
+            const double d = dist2(double(q4.x), double(q4.y), double(q4.z), px, py, pz);
+            if (d <= prm.r2) top.push(d, __float_as_int(q4.w), e);
           }
-          // W = M^-1 by the adjugate (M is symmetric positive definite)
-          const Real A00 = M11 * M22 - M12 * M12;
-          const Real A01 = M02 * M12 - M01 * M22;
-          const Real A02 = M01 * M12 - M02 * M11;
-          const Real A11 = M00 * M22 - M02 * M02;
-          const Real A12 = M01 * M02 - M00 * M12;
-          const Real A22 = M00 * M11 - M01 * M01;
-          const Real inv_det = Real(1) / (M00 * A00 + M01 * A01 + M02 * A02);
-          const Real W00 = A00 * inv_det, W01 = A01 * inv_det, W02 = A02 * inv_det;
-          const Real W11 = A11 * inv_det, W12 = A12 * inv_det, W22 = A22 * inv_det;
-          // Wd, Mahalanobis e2, Cauchy weight and cost
-          const Real g0 = W00 * d0 + W01 * d1 + W02 * d2;
-          const Real g1 = W01 * d0 + W11 * d1 + W12 * d2;
-          const Real g2 = W02 * d0 + W12 * d1 + W22 * d2;
-          const Real e2 = d0 * g0 + d1 * g1 + d2 * g2;
-          const Real k2 = Real(prm.kappa2);
-          const Real w = k2 / (k2 + e2);
-          const Real rho = Real(0.5) * k2 * log1p(e2 / k2);
-          // Columns of A = [a]x: A0 = (0, a2, -a1), A1 = (-a2, 0, a0), A2 = (a1, -a0, 0).
-          // B = W A (column j = W A_j).
-          const Real B00 = W01 * a2 - W02 * a1, B10 = W11 * a2 - W12 * a1, B20 = W12 * a2 - W22 * a1;
-          const Real B01 = W02 * a0 - W00 * a2, B11 = W12 * a0 - W01 * a2, B21 = W22 * a0 - W02 * a2;
-          const Real B02 = W00 * a1 - W01 * a0, B12 = W01 * a1 - W11 * a0, B22 = W02 * a1 - W12 * a0;
-          // H_rr[p][q] = A_p . B_q ; H_rt[p][q] = -B[q][p] ; H_tt = W
-          auto dotA0 = [&](Real x0, Real x1, Real x2) { return a2 * x1 - a1 * x2; };
-          auto dotA1 = [&](Real x0, Real x1, Real x2) { return a0 * x2 - a2 * x0; };
-          auto dotA2 = [&](Real x0, Real x1, Real x2) { return a1 * x0 - a0 * x1; };
-          const Real h00 = dotA0(B00, B10, B20), h01 = dotA0(B01, B11, B21), h02 = dotA0(B02, B12, B22);
-          const Real h11 = dotA1(B01, B11, B21), h12 = dotA1(B02, B12, B22);
-          const Real h22 = dotA2(B02, B12, B22);
-          int v = 0;
-          acc[v++] = w * h00; acc[v++] = w * h01; acc[v++] = w * h02;
-          acc[v++] = -w * B00; acc[v++] = -w * B10; acc[v++] = -w * B20;
-          acc[v++] = w * h11; acc[v++] = w * h12;
-          acc[v++] = -w * B01; acc[v++] = -w * B11; acc[v++] = -w * B21;
-          acc[v++] = w * h22;
-          acc[v++] = -w * B02; acc[v++] = -w * B12; acc[v++] = -w * B22;
-          acc[v++] = w * W00; acc[v++] = w * W01; acc[v++] = w * W02;
-          acc[v++] = w * W11; acc[v++] = w * W12;
-          acc[v++] = w * W22;
-          // b = w J^T W d: rotation part A_p . g, translation part -g
-          acc[v++] = w * dotA0(g0, g1, g2);
-          acc[v++] = w * dotA1(g0, g1, g2);
-          acc[v++] = w * dotA2(g0, g1, g2);
-          acc[v++] = -w * g0; acc[v++] = -w * g1; acc[v++] = -w * g2;
-          acc[v++] = rho;
-          acc[v++] = Real(1);
         }
+        if (top.pos[0] >= 0) r = s_pts[top.pos[0]];
+      } else {
+        map_knn_query<1>(m, px, py, pz, prm.r2, top);
+        if (top.pos[0] >= 0) r = m.vox_pts[top.pos[0]];
       }
-      if (corr) corr[i] = match;
+      if (top.pos[0] >= 0) {
+        match = top.id[0];
+        const float4 ca = m.cov[2 * int64_t(match)];
+        const float4 cb = m.cov[2 * int64_t(match) + 1];
+        gicp_term<Real>(px, py, pz, r, ca, cb, pB[i], pC[i], R, cx, cy, cz, prm.kappa2, acc);
+      }
     }
-    // Wave sums (compensated in FP32), then the block's four waves in FP64.
+    if (corr && i < int64_t(tile_hi[t])) corr[__float_as_int(a.w)] = match;
+    // wave sums (compensated in FP32), then the block's four waves in FP64
 #pragma unroll
-    for (int v = 0; v < kVals; ++v) {
-      double sv = wave_sum(acc[v]);
-      if (lane == 0) red[wave][v] = sv;
+    for (int q = 0; q < kVals; ++q) {
+      const double sv = wave_sum(acc[q]);
+      if (lane == 0) red[wave][q] = sv;
     }
     __syncthreads();
-    if (threadIdx.x < kVals) {
+    if (tid < kVals) {
       double sum = 0.0;
 #pragma unroll
-      for (int w = 0; w < kTile / 64; ++w) sum += red[w][threadIdx.x];
-      partial[t * kStride + threadIdx.x] = sum;
+      for (int w = 0; w < kTile / 64; ++w) sum += red[w][tid];
+      partial[t * kStride + tid] = sum;
     }
     __syncthreads();
   }
@@ -312,19 +505,31 @@ __device__ void se3_apply(const double* dl, const double* c, double* T) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_reduce_solve(int32_t S, const int32_t* begin,
-                                                     const double* partial, double* T,
-                                                     double* ctr, int32_t* done,
-                                                     far_align_stats_t* stats, Params prm,
-                                                     int32_t solve) {
+__global__ __launch_bounds__(256) void k_reduce_solve(int32_t S, const int32_t* begin,
+                                                      const double* partial, double* T,
+                                                      double* ctr, int32_t* done,
+                                                      far_align_stats_t* stats, Params prm,
+                                                      int32_t solve) {
+  // eight groups of 32 lanes: group g sums tiles begin+g, begin+g+8, ... of
+  // the scan, then the eight group sums are added in group order
+  __shared__ double part[8][kVals];
   __shared__ double lin[kVals];
   const int32_t s = blockIdx.x;
   if (s >= S || done[s]) return;
-  const int v = threadIdx.x;
+  const int g = threadIdx.x >> 5, v = threadIdx.x & 31;
   if (v < kVals) {
     double acc = 0.0;
-    for (int32_t t = begin[s]; t < begin[s + 1]; ++t) acc += partial[int64_t(t) * kStride + v];
-    lin[v] = acc;
+    const int32_t t1 = begin[s + 1];
+#pragma unroll 4
+    for (int32_t t = begin[s] + g; t < t1; t += 8) acc += partial[int64_t(t) * kStride + v];
+    part[g][v] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < kVals) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += part[q][threadIdx.x];
+    lin[threadIdx.x] = acc;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -403,11 +608,25 @@ __global__ __launch_bounds__(64) void k_reduce_solve(int32_t S, const int32_t* b
 
 }  // namespace
 
+// Kernel timing instrumentation (far_timing_enable / far_timing_read).
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+
 // Device workspace of the align driver, owned by the map and reused (with its
 // captured graph) while the call arguments stay the same.
 struct AlignWS {
   int32_t S = 0;
   int64_t max_tiles = 0;
+  int64_t n_cap = 0;
   int32_t* tile_scan = nullptr;
   uint32_t* tile_lo = nullptr;
   uint32_t* tile_hi = nullptr;
@@ -420,9 +639,20 @@ struct AlignWS {
   double* T = nullptr;          // single-scan path
   double* cfix = nullptr;       // fixed centre (linearize)
   far_align_stats_t* stats = nullptr;   // single-scan path
+  // locality-ordered packed source and its sort buffers
+  float4* pA = nullptr;
+  float4* pB = nullptr;
+  float2* pC = nullptr;
+  uint64_t* okeys = nullptr;
+  uint64_t* okeys_alt = nullptr;
+  uint32_t* ovals = nullptr;
+  uint32_t* ovals_alt = nullptr;
+  void* arena = nullptr;
+  size_t arena_cap = 0;
   hipGraphExec_t exec = nullptr;
   // argument set the graph was captured for
   const void* key[10] = {};
+  const void* pending[10] = {};
   int64_t key_n = -1;
   Params key_prm{};
   int32_t key_prec = -1;
@@ -433,7 +663,8 @@ void free_ws(AlignWS* w) {
   if (!w) return;
   if (w->exec) (void)hipGraphExecDestroy(w->exec);
   void* ptrs[] = {w->tile_scan, w->tile_lo, w->tile_hi, w->begin, w->bad, w->done, w->ctr,
-                  w->partial, w->offsets, w->T, w->cfix, w->stats};
+                  w->partial, w->offsets, w->T, w->cfix, w->stats, w->pA, w->pB, w->pC,
+                  w->okeys, w->okeys_alt, w->ovals, w->ovals_alt, w->arena};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete w;
@@ -441,9 +672,15 @@ void free_ws(AlignWS* w) {
 
 namespace {
 
-far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, AlignWS** out) {
+int ceil_log2_i(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, int64_t n, AlignWS** out) {
   AlignWS* w = m->ws;
-  if (w && w->S >= S && w->max_tiles >= max_tiles) {
+  if (w && w->S >= S && w->max_tiles >= max_tiles && w->n_cap >= n) {
     *out = w;
     return FAR_OK;
   }
@@ -456,6 +693,8 @@ far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, AlignWS** out
   m->ws = w;
   w->S = S < 64 ? 64 : S;
   w->max_tiles = max_tiles < 1024 ? 1024 : max_tiles;
+  w->n_cap = n < 4096 ? 4096 : n;
+  const size_t nc = size_t(w->n_cap);
   FAR_HIP(hipMalloc(&w->tile_scan, size_t(w->max_tiles) * sizeof(int32_t)));
   FAR_HIP(hipMalloc(&w->tile_lo, size_t(w->max_tiles) * sizeof(uint32_t)));
   FAR_HIP(hipMalloc(&w->tile_hi, size_t(w->max_tiles) * sizeof(uint32_t)));
@@ -468,6 +707,15 @@ far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, AlignWS** out
   FAR_HIP(hipMalloc(&w->T, 16 * sizeof(double)));
   FAR_HIP(hipMalloc(&w->cfix, 3 * sizeof(double)));
   FAR_HIP(hipMalloc(&w->stats, sizeof(far_align_stats_t)));
+  FAR_HIP(hipMalloc(&w->pA, nc * sizeof(float4)));
+  FAR_HIP(hipMalloc(&w->pB, nc * sizeof(float4)));
+  FAR_HIP(hipMalloc(&w->pC, nc * sizeof(float2)));
+  FAR_HIP(hipMalloc(&w->okeys, nc * sizeof(uint64_t)));
+  FAR_HIP(hipMalloc(&w->okeys_alt, nc * sizeof(uint64_t)));
+  FAR_HIP(hipMalloc(&w->ovals, nc * sizeof(uint32_t)));
+  FAR_HIP(hipMalloc(&w->ovals_alt, nc * sizeof(uint32_t)));
+  w->arena_cap = radix_sort_scratch_bytes(w->n_cap);
+  FAR_HIP(hipMalloc(&w->arena, w->arena_cap));
   *out = w;
   return FAR_OK;
 }
@@ -487,7 +735,8 @@ struct Job {
   int32_t precision;
 };
 
-// Enqueue the whole job (init + iterations) on st.
+// Enqueue the whole job (init, locality packing, iterations) on st.  Nothing
+// here allocates or clears memory, so it can be recorded into a graph.
 far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
                      hipStream_t st) {
   MapView mv = m->view();
@@ -497,23 +746,48 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
   k_init<<<(j.S + 255) / 256, 256, 0, st>>>(j.S, j.T, w->bad, j.prm.recenter, j.c_fixed,
                                             j.stats, w->done, w->ctr);
   FAR_HIP(hipGetLastError());
-  int64_t grid = max_tiles;
-  int64_t cap = int64_t(device_cu_count()) * 16;
+  if (j.n_total > 0) {
+    const unsigned nb = unsigned((j.n_total + 255) / 256);
+    k_order_keys<<<nb, 256, 0, st>>>(j.src, j.n_total, j.offsets, j.S, m->p.voxel_size,
+                                     w->okeys, w->ovals);
+    FAR_HIP(hipGetLastError());
+    Scratch scr(st, w->arena, w->arena_cap);
+    bool in_alt = false;
+    FAR_TRY(radix_sort_pairs(w->okeys, w->ovals, w->okeys_alt, w->ovals_alt, j.n_total,
+                             30 + ceil_log2_i(j.S), st, scr, &in_alt));
+    k_pack<<<nb, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total,
+                               in_alt ? w->ovals_alt : w->ovals, w->pA, w->pB, w->pC);
+    FAR_HIP(hipGetLastError());
+  }
+  int64_t grid = ((max_tiles + 7) / 8) * 8;
+  const int64_t cap = int64_t(device_cu_count()) * 8;
   if (grid > cap) grid = cap;
-  if (grid < 1) grid = 1;
+  if (grid < 8) grid = 8;
   const int iters = j.c_fixed ? 1 : j.prm.max_iters;
+  const bool timed = timing().on;
   for (int it = 0; it < iters; ++it) {
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (timed) {
+      FAR_HIP(hipEventCreate(&ev0));
+      FAR_HIP(hipEventCreate(&ev1));
+      FAR_HIP(hipEventRecord(ev0, st));
+    }
     if (j.precision == FAR_PREC_FP64)
       k_linearize<double><<<unsigned(grid), kTile, 0, st>>>(
-          mv, j.src, j.cov6, j.valid, j.n_total, w->tile_scan, w->tile_lo, w->tile_hi,
-          max_tiles, j.T, w->ctr, w->done, j.prm, w->partial, j.corr);
+          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
+          w->ctr, w->done, j.prm, w->partial, j.corr);
     else
       k_linearize<float><<<unsigned(grid), kTile, 0, st>>>(
-          mv, j.src, j.cov6, j.valid, j.n_total, w->tile_scan, w->tile_lo, w->tile_hi,
-          max_tiles, j.T, w->ctr, w->done, j.prm, w->partial, j.corr);
+          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
+          w->ctr, w->done, j.prm, w->partial, j.corr);
     FAR_HIP(hipGetLastError());
-    k_reduce_solve<<<unsigned(j.S), 64, 0, st>>>(j.S, w->begin, w->partial, j.T, w->ctr,
-                                                 w->done, j.stats, j.prm, j.c_fixed ? 0 : 1);
+    if (timed) {
+      FAR_HIP(hipEventRecord(ev1, st));
+      std::lock_guard<std::mutex> lk(timing().mu);
+      timing().pending.push_back({ev0, ev1});
+    }
+    k_reduce_solve<<<unsigned(j.S), 256, 0, st>>>(j.S, w->begin, w->partial, j.T, w->ctr,
+                                                  w->done, j.stats, j.prm, j.c_fixed ? 0 : 1);
     FAR_HIP(hipGetLastError());
   }
   return FAR_OK;
@@ -523,15 +797,21 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
 far_status_t run_job(far_map_s* m, const Job& j, hipStream_t st, bool use_graph) {
   const int64_t max_tiles = (j.n_total + kTile - 1) / kTile + j.S;
   AlignWS* w = nullptr;
-  FAR_TRY(ensure_ws(m, j.S, max_tiles, &w));
+  FAR_TRY(ensure_ws(m, j.S, max_tiles, j.n_total, &w));
   (void)device_cu_count();   // query the device outside any capture
-  if (!use_graph || st == nullptr) return enqueue(m, w, j, max_tiles, st);
+  if (!use_graph || st == nullptr || timing().on) return enqueue(m, w, j, max_tiles, st);
   const void* key[10] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
                          m->vox_pts, nullptr};
   bool same = w->exec && w->key_n == j.n_total && w->key_S == j.S &&
               w->key_prec == j.precision && memcmp(w->key, key, sizeof(key)) == 0 &&
               memcmp(&w->key_prm, &j.prm, sizeof(Params)) == 0;
   if (!same) {
+    // Capture only once an argument set repeats: a one-off call (e.g. a
+    // different scan every time) launches directly and pays no capture.
+    if (memcmp(w->pending, key, sizeof(key)) != 0) {
+      memcpy(w->pending, key, sizeof(key));
+      return enqueue(m, w, j, max_tiles, st);
+    }
     if (w->exec) {
       FAR_HIP(hipGraphExecDestroy(w->exec));
       w->exec = nullptr;
@@ -603,7 +883,7 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
   if (n == 0) return FAR_OK;
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
-  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, &w));
+  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, n, &w));
   int64_t offs[2] = {0, n};
   double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
   FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
@@ -638,7 +918,7 @@ far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
   }
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
-  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, &w));
+  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, n, &w));
   int64_t offs[2] = {0, n};
   FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
   FAR_HIP(hipMemcpyAsync(w->T, T0, 16 * sizeof(double), hipMemcpyHostToDevice, st));
@@ -652,6 +932,34 @@ far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
   FAR_HIP(hipStreamSynchronize(st));
   if (stats) *stats = hs;
   return far_status_t(hs.status);
+}
+
+far_status_t far_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(timing().mu);
+  timing().on = on != 0;
+  return FAR_OK;
+}
+
+far_status_t far_timing_read(double* linearize_ms, int64_t* launches, int32_t reset) {
+  std::lock_guard<std::mutex> lk(timing().mu);
+  Timing& t = timing();
+  for (auto& pr : t.pending) {
+    FAR_HIP(hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    FAR_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    t.ms += ms;
+    t.launches += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  t.pending.clear();
+  if (linearize_ms) *linearize_ms = t.ms;
+  if (launches) *launches = t.launches;
+  if (reset) {
+    t.ms = 0.0;
+    t.launches = 0;
+  }
+  return FAR_OK;
 }
 
 far_status_t far_gicp_align_batch(far_map_t m, const float* src, const int64_t* offsets,

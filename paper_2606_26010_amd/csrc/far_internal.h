@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/far.h"
 
@@ -129,32 +130,64 @@ static __constant__ int8_t kNbrOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1,  3,  5
 
 // ---------------------------------------------------------------- scratch
 // Stream-ordered device scratch, freed when the guard leaves scope.
+// With an arena (a preallocated device buffer) it hands out 256-byte aligned
+// pieces of it instead, which is what code recorded into a graph needs.
 struct Scratch {
   hipStream_t stream;
-  void* ptrs[32];
-  int n = 0;
+  std::vector<void*> ptrs;
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
   explicit Scratch(hipStream_t s) : stream(s) {}
+  Scratch(hipStream_t s, void* buf, size_t cap)
+      : stream(s), arena(static_cast<char*>(buf)), arena_cap(cap) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
   ~Scratch() {
-    for (int i = 0; i < n; ++i) (void)hipFreeAsync(ptrs[i], stream);
+    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
   }
   template <class T>
   far_status_t get(T** out, size_t count) {
     *out = nullptr;
     if (count == 0) count = 1;
+    size_t bytes = count * sizeof(T);
+    if (arena) {
+      size_t at = (arena_used + 255) & ~size_t(255);
+      if (at + bytes > arena_cap) {
+        set_error("internal: scratch arena of %zu bytes exhausted", arena_cap);
+        return FAR_E_CAPACITY;
+      }
+      arena_used = at + bytes;
+      *out = reinterpret_cast<T*>(arena + at);
+      return FAR_OK;
+    }
     void* p = nullptr;
-    FAR_HIP(hipMallocAsync(&p, count * sizeof(T), stream));
-    ptrs[n++] = p;
+    FAR_HIP(hipMallocAsync(&p, bytes, stream));
+    ptrs.push_back(p);
     *out = static_cast<T*>(p);
     return FAR_OK;
   }
 };
 
+// Upper bound of the scratch bytes radix_sort_pairs takes for n elements.
+inline size_t radix_sort_scratch_bytes(int64_t n) {
+  size_t nb = size_t((n + 4095) / 4096) + 1;
+  size_t hist = 256 * nb * 4 + 256;
+  size_t sums = 0, m = 256 * nb;
+  for (int lvl = 0; lvl < 4; ++lvl) {
+    m = (m + 2047) / 2048;
+    sums += m * 4 + 256;
+  }
+  return hist + 8 * sums + 4096;
+}
+
 // ---------------------------------------------------------------- primitives
 // Stable LSD radix sort of (key, value) pairs by key bits [0, bits); the
-// result lands in keys/vals (the *_alt buffers are scratch of the same size).
+// *_alt buffers are scratch of the same size.  With in_alt NULL the result
+// lands in keys/vals; otherwise it stays in whichever pair the last pass
+// wrote and *in_alt says whether that is the *_alt pair (no copy is made).
 far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                               uint32_t* vals_alt, int64_t n, int bits, hipStream_t st,
-                              Scratch& scr);
+                              Scratch& scr, bool* in_alt = nullptr);
 // Exclusive prefix sum of n uint32 values; the total goes to *total [dev]
 // when total is not NULL.  in and out may alias.
 far_status_t scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,

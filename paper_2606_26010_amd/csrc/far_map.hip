@@ -280,12 +280,15 @@ __global__ __launch_bounds__(kT) void k_map_knn(MapView m, const float* q, int64
 }
 
 // ---------------------------------------------------------------- scan grid
-// The scan's own voxel grid is CSR: points sorted by key (sorted[j] = x, y, z,
-// original index bits), runs [seg_start, seg_end), and a hash table from key to
-// run index.
+// Each scan's own voxel grid is CSR: the points of all scans sorted by (scan,
+// voxel key) (sorted[j] = x, y, z, original index bits), runs [seg_start,
+// seg_end) of equal (scan, key), and a hash table from (scan, key) to run
+// index (the scan id is kept in the slot's spare word and mixed into the hash).
 struct GridView {
   const Slot* slots;
   const float4* sorted;
+  const uint64_t* keys;       // sorted keys (kEmptyKey for non-finite points)
+  const uint32_t* sid;        // scan id per sorted position (NULL: one scan)
   const uint32_t* seg_start;
   const uint32_t* seg_end;
   double v;
@@ -293,54 +296,119 @@ struct GridView {
   uint32_t slot_mask;
 };
 
-__device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, int64_t kz) {
+__device__ inline uint32_t grid_hash(int64_t kx, int64_t ky, int64_t kz, uint32_t sid,
+                                     int log2_slots) {
+  return voxel_hash(kx ^ int64_t(sid * 2654435761u), ky, kz, log2_slots);
+}
+
+__device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, int64_t kz,
+                                    uint32_t sid) {
   if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
   uint64_t key = pack_key(kx, ky, kz);
-  uint32_t s = voxel_hash(kx, ky, kz, g.log2_slots);
+  uint32_t s = grid_hash(kx, ky, kz, sid, g.log2_slots);
   for (uint32_t probe = 0; probe <= g.slot_mask; ++probe) {
     Slot sl = g.slots[s];
-    if (sl.key == key) return sl.vox;
+    if (sl.key == key && uint32_t(sl.pad) == sid) return sl.vox;
     if (sl.key == kEmptyKey) return -1;
     s = (s + 1) & g.slot_mask;
   }
   return -1;
 }
 
-__global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t n,
-                                                      const uint32_t* vals, int64_t n_valid,
-                                                      float4* sorted) {
+// Scan id of each key-sorted point (binary search of its original index in
+// the scan offsets); the result is the key of a second, stable sort.
+__global__ __launch_bounds__(kT) void k_scan_ids(const uint32_t* vals, int64_t n,
+                                                 const int64_t* offsets, int32_t S,
+                                                 uint64_t* sid_key, uint32_t* pos) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n_valid) return;
+  if (j >= n) return;
+  int64_t i = vals[j];
+  int32_t lo = 0, hi = S;            // find s with offsets[s] <= i < offsets[s+1]
+  while (hi - lo > 1) {
+    int32_t mid = (lo + hi) >> 1;
+    if (offsets[mid] <= i) lo = mid; else hi = mid;
+  }
+  sid_key[j] = uint64_t(lo);
+  pos[j] = uint32_t(j);
+}
+
+__global__ __launch_bounds__(kT) void k_apply_perm(const uint32_t* perm, int64_t n,
+                                                   const uint64_t* keys_in,
+                                                   const uint32_t* vals_in, uint64_t* keys_out,
+                                                   uint32_t* vals_out, const uint64_t* sid_key,
+                                                   uint32_t* sid_out) {
+  int64_t m = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (m >= n) return;
+  uint32_t j = perm[m];
+  keys_out[m] = keys_in[j];
+  vals_out[m] = vals_in[j];
+  sid_out[m] = uint32_t(sid_key[m]);
+}
+
+__global__ __launch_bounds__(kT) void k_grid_heads(const uint64_t* keys, const uint32_t* sid,
+                                                   int64_t n, uint32_t* head) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  uint64_t k = keys[j];
+  bool h = k != kEmptyKey &&
+           (j == 0 || keys[j - 1] != k || (sid && sid[j - 1] != sid[j]));
+  head[j] = h ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kT) void k_grid_bounds(const uint64_t* keys, const uint32_t* sid,
+                                                    int64_t n, const uint32_t* head,
+                                                    const uint32_t* head_scan,
+                                                    uint32_t* seg_start, uint32_t* seg_end) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  uint64_t k = keys[j];
+  if (k == kEmptyKey) return;
+  uint32_t s = head_scan[j] + head[j] - 1;
+  if (head[j]) seg_start[s] = uint32_t(j);
+  if (j == n - 1 || keys[j + 1] != k || (sid && sid[j + 1] != sid[j]))
+    seg_end[s] = uint32_t(j + 1);
+}
+
+__global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t n,
+                                                      const uint32_t* vals, float4* sorted) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
   uint32_t i = vals[j];
   sorted[j] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], __int_as_float(int32_t(i)));
 }
 
 __global__ __launch_bounds__(kT) void k_grid_claim(Slot* slots, uint32_t slot_mask,
                                                    int log2_slots, const uint64_t* keys,
+                                                   const uint32_t* sid,
                                                    const uint32_t* seg_start, int64_t n_seg) {
   int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (s >= n_seg) return;
-  uint64_t key = keys[seg_start[s]];
-  uint32_t h = voxel_hash(key_x(key), key_y(key), key_z(key), log2_slots);
+  uint32_t j = seg_start[s];
+  uint64_t key = keys[j];
+  uint32_t sc = sid ? sid[j] : 0u;
+  uint32_t h = grid_hash(key_x(key), key_y(key), key_z(key), sc, log2_slots);
   for (uint32_t probe = 0; probe <= slot_mask; ++probe) {
     unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[h].key),
                                        (unsigned long long)kEmptyKey,
                                        (unsigned long long)key);
     if (old == kEmptyKey) {
       slots[h].vox = int32_t(s);
+      slots[h].pad = int32_t(sc);
       return;
     }
     h = (h + 1) & slot_mask;
   }
 }
 
-// Covariance of every scan point from its k nearest scan points within v
-// (processed in key-sorted order for locality; written at the original index).
+// Covariance of every scan point from its k nearest points of the same scan
+// within v (processed in sorted order for locality; written at the original
+// index).  Non-finite points keep the zero covariance / invalid flag.
 template <int K>
-__global__ __launch_bounds__(kT) void k_grid_cov(GridView g, int64_t n_valid, int64_t n,
-                                                 int32_t k, float* cov6, uint8_t* valid) {
+__global__ __launch_bounds__(kT) void k_grid_cov(GridView g, int64_t n, int32_t k, float* cov6,
+                                                 uint8_t* valid) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n_valid) return;
+  if (j >= n || g.keys[j] == kEmptyKey) return;
+  const uint32_t sc = g.sid ? g.sid[j] : 0u;
   float4 me = g.sorted[j];
   double qx = me.x, qy = me.y, qz = me.z;
   double r2 = g.v * g.v;
@@ -355,7 +423,7 @@ __global__ __launch_bounds__(kT) void k_grid_cov(GridView g, int64_t n_valid, in
     int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
     double bnd = fmin(r2, top.bound());
     if (voxel_lb2(qx, qy, qz, kx, ky, kz, ox, oy, oz, g.v) > bnd) continue;
-    int32_t s = grid_find(g, kx + ox, ky + oy, kz + oz);
+    int32_t s = grid_find(g, kx + ox, ky + oy, kz + oz, sc);
     if (s < 0) continue;
     for (uint32_t c = g.seg_start[s]; c < g.seg_end[s]; ++c) {
       float4 p = g.sorted[c];
@@ -412,7 +480,9 @@ template <class F>
 far_status_t dispatch_k(int32_t k, F&& f) {
   if (k <= 1) return f(std::integral_constant<int, 1>());
   if (k <= 4) return f(std::integral_constant<int, 4>());
+  if (k == 5) return f(std::integral_constant<int, 5>());
   if (k <= 8) return f(std::integral_constant<int, 8>());
+  if (k <= 10) return f(std::integral_constant<int, 10>());
   if (k <= 16) return f(std::integral_constant<int, 16>());
   return f(std::integral_constant<int, 32>());
 }
@@ -668,6 +738,75 @@ far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, doub
   });
 }
 
+static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
+                                  int64_t n, double voxel_size, int32_t k, float* cov6,
+                                  uint8_t* valid, hipStream_t st, const char* who) {
+  Scratch scr(st);
+  Runs r;
+  FAR_TRY(build_runs(xyz, n, voxel_size, st, scr, r));
+  uint64_t* keys = r.keys;
+  uint32_t* vals = r.vals;
+  uint32_t* sid = nullptr;
+  if (S_ > 1) {
+    // second stable sort, by scan id, keeps the key order inside every scan
+    uint64_t *sid_key, *sid_alt, *keys2;
+    uint32_t *perm, *perm_alt, *vals2;
+    FAR_TRY(scr.get(&sid_key, size_t(n)));
+    FAR_TRY(scr.get(&sid_alt, size_t(n)));
+    FAR_TRY(scr.get(&perm, size_t(n)));
+    FAR_TRY(scr.get(&perm_alt, size_t(n)));
+    FAR_TRY(scr.get(&keys2, size_t(n)));
+    FAR_TRY(scr.get(&vals2, size_t(n)));
+    FAR_TRY(scr.get(&sid, size_t(n)));
+    k_scan_ids<<<blocks_for(n), kT, 0, st>>>(r.vals, n, offsets, S_, sid_key, perm);
+    FAR_HIP(hipGetLastError());
+    FAR_TRY(radix_sort_pairs(sid_key, perm, sid_alt, perm_alt, n, ceil_log2(S_), st, scr));
+    k_apply_perm<<<blocks_for(n), kT, 0, st>>>(perm, n, r.keys, r.vals, keys2, vals2,
+                                               sid_key, sid);
+    FAR_HIP(hipGetLastError());
+    keys = keys2;
+    vals = vals2;
+    k_grid_heads<<<blocks_for(n), kT, 0, st>>>(keys, sid, n, r.head);
+    FAR_HIP(hipGetLastError());
+    FAR_TRY(scan_exclusive(r.head, r.head_scan, n, r.counters + 2, st, scr));
+    k_grid_bounds<<<blocks_for(n), kT, 0, st>>>(keys, sid, n, r.head, r.head_scan,
+                                                r.seg_start, r.seg_end);
+    FAR_HIP(hipGetLastError());
+  }
+  uint32_t h_cnt[4];
+  FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  if (h_cnt[1] > 0) {
+    set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, h_cnt[1]);
+    return FAR_E_INVALID;
+  }
+  const int64_t n_seg = h_cnt[2];
+  FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
+  FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
+  if (n_seg == 0) return FAR_OK;
+  int log2_slots = ceil_log2(2 * n_seg);
+  if (log2_slots < 6) log2_slots = 6;
+  int64_t n_slots = int64_t(1) << log2_slots;
+  Slot* slots;
+  float4* sorted;
+  FAR_TRY(scr.get(&slots, size_t(n_slots)));
+  FAR_TRY(scr.get(&sorted, size_t(n)));
+  FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
+  k_gather_sorted<<<blocks_for(n), kT, 0, st>>>(xyz, n, vals, sorted);
+  FAR_HIP(hipGetLastError());
+  k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
+                                                 keys, sid, r.seg_start, n_seg);
+  FAR_HIP(hipGetLastError());
+  GridView g{slots, sorted, keys, sid, r.seg_start, r.seg_end, voxel_size, log2_slots,
+             uint32_t(n_slots - 1)};
+  return dispatch_k(k, [&](auto KK) -> far_status_t {
+    constexpr int K = decltype(KK)::value;
+    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, n, k, cov6, valid);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  });
+}
+
 far_status_t far_scan_covariances(const float* xyz, int64_t n, double voxel_size, int32_t k,
                                   float* cov6, uint8_t* valid, far_stream_t stream) {
   if (n < 0 || n >= (int64_t(1) << 31) || !(voxel_size > 0.0) || k < 1 || k > 32 ||
@@ -676,45 +815,21 @@ far_status_t far_scan_covariances(const float* xyz, int64_t n, double voxel_size
     return FAR_E_INVALID;
   }
   if (n == 0) return FAR_OK;
-  hipStream_t st = S(stream);
-  Scratch scr(st);
-  Runs r;
-  FAR_TRY(build_runs(xyz, n, voxel_size, st, scr, r));
-  uint32_t h_cnt[4];
-  FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
-  FAR_HIP(hipStreamSynchronize(st));
-  if (h_cnt[1] > 0) {
-    set_error("far_scan_covariances: %u points have voxel keys outside [-2^20, 2^20)",
-              h_cnt[1]);
+  return scan_cov_impl(xyz, nullptr, 1, n, voxel_size, k, cov6, valid, S(stream),
+                       "far_scan_covariances");
+}
+
+far_status_t far_scan_covariances_batch(const float* xyz, const int64_t* offsets, int32_t S_,
+                                        int64_t n_total, double voxel_size, int32_t k,
+                                        float* cov6, uint8_t* valid, far_stream_t stream) {
+  if (S_ < 1 || !offsets || n_total < 0 || n_total >= (int64_t(1) << 31) ||
+      !(voxel_size > 0.0) || k < 1 || k > 32 || (n_total > 0 && (!xyz || !cov6 || !valid))) {
+    set_error("far_scan_covariances_batch: invalid argument");
     return FAR_E_INVALID;
   }
-  const int64_t n_seg = h_cnt[2];
-  const int64_t n_valid = n - h_cnt[0];
-  // non-finite points: zero covariance, invalid
-  FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
-  FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
-  if (n_valid == 0) return FAR_OK;
-  int log2_slots = ceil_log2(2 * n_seg);
-  if (log2_slots < 6) log2_slots = 6;
-  int64_t n_slots = int64_t(1) << log2_slots;
-  Slot* slots;
-  float4* sorted;
-  FAR_TRY(scr.get(&slots, size_t(n_slots)));
-  FAR_TRY(scr.get(&sorted, size_t(n_valid)));
-  FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
-  k_gather_sorted<<<blocks_for(n_valid), kT, 0, st>>>(xyz, n, r.vals, n_valid, sorted);
-  FAR_HIP(hipGetLastError());
-  k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
-                                                 r.keys, r.seg_start, n_seg);
-  FAR_HIP(hipGetLastError());
-  GridView g{slots, sorted, r.seg_start, r.seg_end, voxel_size, log2_slots,
-             uint32_t(n_slots - 1)};
-  return dispatch_k(k, [&](auto KK) -> far_status_t {
-    constexpr int K = decltype(KK)::value;
-    k_grid_cov<K><<<blocks_for(n_valid), kT, 0, st>>>(g, n_valid, n, k, cov6, valid);
-    FAR_HIP(hipGetLastError());
-    return FAR_OK;
-  });
+  if (n_total == 0) return FAR_OK;
+  return scan_cov_impl(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid, S(stream),
+                       "far_scan_covariances_batch");
 }
 
 far_status_t far_map_stats(far_map_t m, far_map_stats_t* out, far_stream_t stream) {

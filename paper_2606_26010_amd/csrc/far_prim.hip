@@ -176,7 +176,8 @@ far_status_t scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32
 
 far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                               uint32_t* vals_alt, int64_t n, int bits, hipStream_t st,
-                              Scratch& scr) {
+                              Scratch& scr, bool* in_alt) {
+  if (in_alt) *in_alt = false;
   if (n <= 1 || bits <= 0) return FAR_OK;
   int64_t nblocks = (n + kSortTile - 1) / kSortTile;
   uint32_t* hist = nullptr;
@@ -194,6 +195,10 @@ far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt
     FAR_HIP(hipGetLastError());
     uint64_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
+  }
+  if (in_alt) {
+    *in_alt = ka != keys;
+    return FAR_OK;
   }
   if (ka != keys) {
     FAR_HIP(hipMemcpyAsync(keys, ka, size_t(n) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));

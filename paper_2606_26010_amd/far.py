@@ -64,6 +64,10 @@ _SIGS = {
     "far_map_insert": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.POINTER(C.c_int64)]),
     "far_map_knn": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_double, _P, _P, _P, _P]),
     "far_scan_covariances": (C.c_int, [_P, C.c_int64, C.c_double, C.c_int32, _P, _P, _P]),
+    "far_scan_covariances_batch": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double,
+                                             C.c_int32, _P, _P, _P]),
+    "far_timing_enable": (C.c_int, [C.c_int32]),
+    "far_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "far_gicp_linearize": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                      C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.c_int32, _P, C.POINTER(far_lin_t), _P]),
@@ -178,6 +182,32 @@ def far_scan_covariances(xyz, voxel_size, k, stream=None):
                                       _dev(val, torch.uint8, "valid"), _stream(stream)),
            "far_scan_covariances")
     return cov, val
+
+
+def far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=None, stream=None):
+    p, n = _pts(xyz)
+    S = offsets.shape[0] - 1
+    if out is None:
+        cov = torch.empty((6, n), dtype=torch.float32, device=xyz.device)
+        val = torch.empty(n, dtype=torch.uint8, device=xyz.device)
+    else:
+        cov, val = out
+    _check(lib().far_scan_covariances_batch(p, _dev(offsets, torch.int64, "offsets"), S, n,
+                                            voxel_size, k, _dev(cov, torch.float32, "cov6"),
+                                            _dev(val, torch.uint8, "valid"), _stream(stream)),
+           "far_scan_covariances_batch")
+    return cov, val
+
+
+def far_timing_enable(on: bool):
+    _check(lib().far_timing_enable(1 if on else 0), "far_timing_enable")
+
+
+def far_timing_read(reset: bool = False):
+    ms, n = C.c_double(0), C.c_int64(0)
+    _check(lib().far_timing_read(C.byref(ms), C.byref(n), 1 if reset else 0),
+           "far_timing_read")
+    return ms.value, n.value
 
 
 def _lin_dict(lin: far_lin_t):

@@ -135,29 +135,52 @@ class Corridor:
     pole_height: float = 6.0
     pole_spacing: float = 20.0
     pole_inset: float = 3.0
+    pillar_spacing: float = 10.0   # wall pillars (0: none), jittered +-1.5 m
+    pillar_width: float = 1.0
+    pillar_depth: float = 0.6
     seed: int = 7
-    poles: np.ndarray = field(default=None, repr=False)  # [P, 2] centres
+    poles: np.ndarray = field(default=None, repr=False)    # [P, 2] centres
+    pillars: np.ndarray = field(default=None, repr=False)  # [Q, 4] x0, x1, y0, y1
 
     def __post_init__(self):
+        g = rng(self.seed)
         if self.poles is None:
-            g = rng(self.seed)
             xs = np.arange(self.pole_spacing / 2, self.length, self.pole_spacing)
             ys = self.half_width - self.pole_inset
             left = np.stack([xs + g.uniform(-2, 2, xs.size), np.full(xs.size, ys)], 1)
             right = np.stack([xs + g.uniform(-2, 2, xs.size), np.full(xs.size, -ys)], 1)
             self.poles = np.concatenate([left, right])
+        if self.pillars is None:
+            rows = []
+            if self.pillar_spacing > 0:
+                W, w, dp = self.half_width, self.pillar_width / 2, self.pillar_depth
+                for xc in np.arange(self.pillar_spacing / 2, self.length, self.pillar_spacing):
+                    a = xc + g.uniform(-1.5, 1.5)
+                    b = xc + g.uniform(-1.5, 1.5)
+                    rows.append((a - w, a + w, W - dp, W))
+                    rows.append((b - w, b + w, -W, -W + dp))
+            self.pillars = np.array(rows, dtype=np.float64).reshape(-1, 4)
+
+    def _pillar_face_areas(self):
+        H = self.wall_height
+        fw = (self.pillars[:, 1] - self.pillars[:, 0]) * H       # face toward the corridor
+        sd = (self.pillars[:, 3] - self.pillars[:, 2]) * H       # each side face
+        return fw, sd
 
     def surface_area(self):
+        fw, sd = self._pillar_face_areas()
         return (self.length * 2 * self.half_width + 2 * self.length * self.wall_height
-                + len(self.poles) * 2 * math.pi * self.pole_radius * self.pole_height)
+                + len(self.poles) * 2 * math.pi * self.pole_radius * self.pole_height
+                + float(np.sum(fw + 2 * sd)))
 
     def surface_samples(self, g: np.random.Generator, n: int) -> np.ndarray:
         L, W, H = self.length, self.half_width, self.wall_height
         pa = 2 * math.pi * self.pole_radius * self.pole_height
-        w = np.array([L * 2 * W, L * H, L * H, pa * len(self.poles)])
-        which = g.choice(4, size=n, p=w / w.sum())
+        fw, sd = self._pillar_face_areas()
+        w = np.array([L * 2 * W, L * H, L * H, pa * len(self.poles), float(np.sum(fw + 2 * sd))])
+        which = g.choice(5, size=n, p=w / w.sum())
         out = np.empty((3, n))
-        for j in range(4):
+        for j in range(5):
             idx = np.nonzero(which == j)[0]
             m = idx.size
             if not m:
@@ -168,12 +191,25 @@ class Corridor:
                 pts = _sample_rect(g, m, (0, W, 0), (L, 0, 0), (0, 0, H))
             elif j == 2:
                 pts = _sample_rect(g, m, (0, -W, 0), (L, 0, 0), (0, 0, H))
-            else:
+            elif j == 3:
                 k = g.integers(0, len(self.poles), size=m)
                 th = g.uniform(0, 2 * math.pi, size=m)
                 pts = np.stack([self.poles[k, 0] + self.pole_radius * np.cos(th),
                                 self.poles[k, 1] + self.pole_radius * np.sin(th),
                                 g.uniform(0, self.pole_height, size=m)])
+            else:
+                # pillar faces: the one toward the corridor and the two sides
+                areas = np.concatenate([fw, sd, sd])
+                f = g.choice(areas.size, size=m, p=areas / areas.sum())
+                q = len(self.pillars)
+                P = self.pillars[f % q]
+                u, z = g.uniform(size=m), g.uniform(0, H, size=m)
+                # toward-corridor face: y = inner side of the pillar
+                inner = np.where(P[:, 3] > 0, P[:, 2], P[:, 3])
+                x = np.where(f < q, P[:, 0] + u * (P[:, 1] - P[:, 0]),
+                             np.where(f < 2 * q, P[:, 0], P[:, 1]))
+                y = np.where(f < q, inner, P[:, 2] + u * (P[:, 3] - P[:, 2]))
+                pts = np.stack([x, y, z])
             out[:, idx] = pts
         return out.astype(np.float32)
 
@@ -193,6 +229,15 @@ class Corridor:
                 x, z = ox + t * dx, oz + t * dz
                 ok = (t > 0) & (x >= 0) & (x <= self.length) & (z >= 0) & (z <= self.wall_height)
                 best = np.where(ok & (t < best), t, best)
+            # axis-aligned pillar boxes (slab test in x and y, z in [0, H])
+            for x0, x1, y0, y1 in self.pillars[np.abs(self.pillars[:, 0] - ox) < max_range + 2]:
+                tx0, tx1 = (x0 - ox) / dx, (x1 - ox) / dx
+                ty0, ty1 = (y0 - oy) / dy, (y1 - oy) / dy
+                tmin = np.maximum(np.minimum(tx0, tx1), np.minimum(ty0, ty1))
+                tmax = np.minimum(np.maximum(tx0, tx1), np.maximum(ty0, ty1))
+                z = oz + tmin * dz
+                ok = (tmax >= tmin) & (tmin > 0) & (z >= 0) & (z <= self.wall_height)
+                best = np.where(ok & (tmin < best), tmin, best)
             near = self.poles[np.hypot(self.poles[:, 0] - ox, self.poles[:, 1] - oy)
                               < max_range + 1.0]
             a = dx * dx + dy * dy

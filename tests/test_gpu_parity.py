@@ -314,3 +314,23 @@ def test_map_stats_probe_lengths(far, tiny_pair):
     say("map stats", s)
     assert s["n_points"] == om.size and s["n_voxels"] == om.n_voxels
     assert s["load_factor"] <= 0.5 and 1.0 <= s["mean_probe"] < 4.0
+
+
+def test_scan_covariances_batch_parity(far, orc):
+    # overlapping scans of one scene: a batched call must keep them apart
+    scans = [synth.make_tiny(s, n_batches=1, n_source=n).source
+             for s, n in ((6, 1), (7, 3000), (8, 257), (9, 5000), (10, 1024))]
+    scans.insert(2, np.zeros((3, 0), np.float32))
+    bad = synth.random_cloud(11, 700, extent=2.0)
+    bad[0, ::50] = np.nan
+    scans.append(bad)
+    sizes = [s.shape[1] for s in scans]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cov, val = far.far_scan_covariances_batch(dev(np.concatenate(scans, 1)), dev(offs), 1.0, 5)
+    cov, val = host(cov), host(val)
+    for s, sc in enumerate(scans):
+        if sc.shape[1] == 0:
+            continue
+        oc, ov = orc.scan_covariances(np.ascontiguousarray(sc), 1.0, 5)
+        np.testing.assert_array_equal(val[offs[s]:offs[s + 1]], ov)
+        np.testing.assert_allclose(cov[:, offs[s]:offs[s + 1]], oc, rtol=2e-6, atol=1e-6)

@@ -23,13 +23,15 @@
 namespace far {
 namespace {
 
-constexpr int kTile = 256;
+constexpr int kTile = 256;     // points per tile = threads per linearisation block
 constexpr int kVals = 29;     // 21 H + 6 b + cost + count
 constexpr int kStride = 32;   // partial row stride (doubles)
 
 struct Params {
   double r2;        // min(tau, v)^2
   double kappa2;
+  double inv_v;     // 1 / v
+  int32_t v_pow2;   // v is a power of two (1/v exact)
   double eps;
   int32_t max_iters;
   int32_t recenter;
@@ -140,9 +142,9 @@ __device__ inline uint32_t spread10(uint32_t x) {
   return x;
 }
 
-__device__ inline uint32_t quant10(float x, double v) {
-  double q = floor(double(x) / v) + 512.0;
-  q = q < 0.0 ? 0.0 : (q > 1023.0 ? 1023.0 : q);
+__device__ inline uint32_t quant8(float x, double v) {
+  double q = floor(double(x) / v) + 128.0;
+  q = q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q);
   return uint32_t(q);
 }
 
@@ -157,21 +159,29 @@ __global__ __launch_bounds__(256) void k_order_keys(const float* src, int64_t n,
     if (offsets[mid] <= i) lo = mid; else hi = mid;
   }
   float x = src[i], y = src[n + i], z = src[2 * n + i];
-  uint32_t code = (1u << 30) - 1u;
+  uint32_t code = (1u << 24) - 1u;
   if (isfinite(x) && isfinite(y) && isfinite(z))
-    code = spread10(quant10(x, v)) | (spread10(quant10(y, v)) << 1) |
-           (spread10(quant10(z, v)) << 2);
-  keys[i] = (uint64_t(lo) << 30) | code;
+    code = spread10(quant8(x, v)) | (spread10(quant8(y, v)) << 1) |
+           (spread10(quant8(z, v)) << 2);
+  keys[i] = (uint64_t(lo) << 24) | code;
   vals[i] = uint32_t(i);
 }
 
+__global__ __launch_bounds__(256) void k_invert(const uint32_t* perm, int64_t n,
+                                                uint32_t* inv) {
+  int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (m < n) inv[perm[m]] = uint32_t(m);
+}
+
+// Pack in key order: read the caller's SoA arrays in their own order
+// (coalesced) and write each point's 40 bytes to its sorted position.
 __global__ __launch_bounds__(256) void k_pack(const float* src, const float* cov6,
                                               const uint8_t* valid, int64_t n,
-                                              const uint32_t* perm, float4* A, float4* B,
+                                              const uint32_t* inv, float4* A, float4* B,
                                               float2* C) {
-  int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (m >= n) return;
-  uint32_t i = perm[m];
+  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint32_t m = inv[i];
   A[m] = make_float4(src[i], src[n + i], src[2 * n + i], __int_as_float(int32_t(i)));
   bool ok = valid[i] != 0;
   B[m] = make_float4(ok ? cov6[i] : -1.0f, cov6[n + i], cov6[2 * n + i], cov6[3 * n + i]);
@@ -266,42 +276,69 @@ __device__ inline void gicp_term(double px, double py, double pz, float4 r, floa
 }
 
 // ---------------------------------------------------------------- linearise
-// One 256-thread block per tile of 256 locality-ordered points, persistent
-// over tiles.  The tiles are split into eight contiguous ranges, one per XCD
-// (blocks are dealt to the eight XCDs round-robin), so neighbouring tiles -
-// which share map voxels - meet in the same L2.
+// One block of kTile threads per tile of kTile locality-ordered points (one
+// point per lane).  Blocks are dealt to the eight XCDs round-robin; block b
+// takes tile (b mod 8) * chunk + b / 8 so that each XCD works through one
+// contiguous range of tiles and neighbouring tiles - which share map voxels -
+// meet in the same L2.
 //
-// Per tile: every lane transforms its point (FP64, no FMA) and takes its map
-// voxel key; the block forms the key box of the tile grown by one voxel.  If
-// the box has at most kBoxMax cells and holds at most kLdsPts map points, the
-// block probes the hash table once per cell, prefix-sums the counts into a
-// dense local voxel table and copies the points into LDS; every lane then
-// searches its 27-voxel neighbourhood in LDS.  Otherwise the lanes search the
-// global map directly.  Both give the same nearest point: the same voxels'
-// points, the same FP64 squared distances, the same (d2, id) ranking.
-constexpr int kBoxMax = 1024;
-constexpr int kLdsPts = 1024;
+// Nearest-neighbour search per lane (exact, ranked by (d2, id)): the own
+// voxel first, then every neighbour voxel whose conservative lower-bound
+// distance can still beat the current best.  The needed neighbours are kept
+// as a bit mask and visited in lockstep - each lane takes its own next
+// needed neighbour in the same step - so a wave does as many voxel visits as
+// its busiest lane needs, not one per offset any lane needs.
+__device__ inline double lb2_of(const double* gl, const double* gh, int ox, int oy, int oz) {
+  double s2 = 0.0;
+  s2 += ox < 0 ? gl[0] * gl[0] : (ox > 0 ? gh[0] * gh[0] : 0.0);
+  s2 += oy < 0 ? gl[1] * gl[1] : (oy > 0 ? gh[1] * gh[1] : 0.0);
+  s2 += oz < 0 ? gl[2] * gl[2] : (oz > 0 ? gh[2] * gh[2] : 0.0);
+  return s2;
+}
 
-__device__ inline int block_exscan_int(int v, int* lds, int* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int x = v;
+__device__ inline void nn_lockstep(const MapView& m, double px, double py, double pz,
+                                   int64_t kx, int64_t ky, int64_t kz, double r2,
+                                   TopK<1>& top) {
+  top.init();
+  const double v = m.v, slack = 1e-7 * v;
+  const double gl[3] = {fmax(px - double(kx) * v - slack, 0.0),
+                        fmax(py - double(ky) * v - slack, 0.0),
+                        fmax(pz - double(kz) * v - slack, 0.0)};
+  const double gh[3] = {fmax(double(kx + 1) * v - px - slack, 0.0),
+                        fmax(double(ky + 1) * v - py - slack, 0.0),
+                        fmax(double(kz + 1) * v - pz - slack, 0.0)};
+  int32_t cnt;
+  int32_t vox = map_find(m, kx, ky, kz, &cnt);
+  if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, px, py, pz, r2, top);
+  uint32_t need = 0;
+  {
+    const double bnd = fmin(r2, top.bound());
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
+    for (int q = 1; q < 27; ++q) {
+      const int code = kNbrOrder[q];
+      if (lb2_of(gl, gh, code / 9 - 1, (code / 3) % 3 - 1, code % 3 - 1) <= bnd)
+        need |= 1u << q;
+    }
   }
-  if (lane == 63) lds[wave] = x;
-  __syncthreads();
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kTile / 64; ++w) {
-    int s = lds[w];
-    pre += (w < wave) ? s : 0;
-    tot += s;
+  while (need) {
+    const int q = __builtin_ctz(need);
+    need &= need - 1;
+    const int code = kNbrOrder[q];
+    const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+    if (lb2_of(gl, gh, ox, oy, oz) > fmin(r2, top.bound())) continue;
+    vox = map_find(m, kx + ox, ky + oy, kz + oz, &cnt);
+    if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, px, py, pz, r2, top);
   }
-  __syncthreads();
-  *total = tot;
-  return pre + x - v;
+}
+
+// Voxel index with an exact multiply when 1/v is exact (power-of-two v),
+// else the division; both give floor(x / v) exactly as the FP64 quotient.
+__device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool pow2,
+                                        int64_t* k) {
+  const double f = floor(pow2 ? x * inv_v : x / v);
+  if (!(f >= -double(kKeyBias) && f < double(kKeyBias))) return false;
+  *k = int64_t(f);
+  return true;
 }
 
 template <class Real>
@@ -312,149 +349,62 @@ __global__ __launch_bounds__(kTile) void k_linearize(
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
     int32_t* __restrict__ corr) {
-  __shared__ double red[kTile / 64][kVals];
-  __shared__ int s_box[6];
-  __shared__ int s_start[kBoxMax + 1];
-  __shared__ int s_vox[kBoxMax];
-  __shared__ float4 s_pts[kLdsPts];
-  __shared__ int s_scan[kTile / 64];
+  constexpr int kWaves = kTile / 64;
+  __shared__ double red[kWaves][kVals];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double v = m.v;
-
-  const int64_t per = gridDim.x >> 3;
   const int64_t chunk = (n_tiles + 7) >> 3;
-  const int64_t t_begin = int64_t(blockIdx.x & 7) * chunk;
-  const int64_t t_end = t_begin + chunk < n_tiles ? t_begin + chunk : n_tiles;
-  for (int64_t t = t_begin + (blockIdx.x >> 3); t < t_end; t += per) {
-    const int32_t s = tile_scan[t];
-    if (s < 0 || done[s]) continue;
-    const double* Ts = T + 16 * int64_t(s);
-    double R[9] = {Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]};
-    const double tx = Ts[3], ty = Ts[7], tz = Ts[11];
-    const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
-    const int64_t i = int64_t(tile_lo[t]) + tid;
+  const int64_t t = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (t >= n_tiles || (blockIdx.x >> 3) >= chunk) return;
+  const int32_t s = tile_scan[t];
+  if (s < 0 || done[s]) return;
+  const double* Ts = T + 16 * int64_t(s);
+  const double R[9] = {Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]};
+  const double tx = Ts[3], ty = Ts[7], tz = Ts[11];
+  const int64_t i = int64_t(tile_lo[t]) + tid;
+  const bool in_tile = i < int64_t(tile_hi[t]);
 
-    // transform and voxel key of this lane's point
-    bool have = false;
-    double px = 0, py = 0, pz = 0;
-    int64_t kx = 0, ky = 0, kz = 0;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < int64_t(tile_hi[t])) {
-      a = pA[i];
-      if (isfinite(a.x) && isfinite(a.y) && isfinite(a.z)) {
-        const double sx = a.x, sy = a.y, sz = a.z;
-        px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
-        py = ((R[3] * sx + R[4] * sy) + R[5] * sz) + ty;
-        pz = ((R[6] * sx + R[7] * sy) + R[8] * sz) + tz;
-        have = voxel_index(px, v, &kx) && voxel_index(py, v, &ky) && voxel_index(pz, v, &kz);
-      }
-    }
-    // key box of the tile
-    if (tid < 3) s_box[tid] = INT_MAX;
-    else if (tid < 6) s_box[tid] = INT_MIN;
-    __syncthreads();
-    if (have) {
-      atomicMin(&s_box[0], int(kx)); atomicMin(&s_box[1], int(ky)); atomicMin(&s_box[2], int(kz));
-      atomicMax(&s_box[3], int(kx)); atomicMax(&s_box[4], int(ky)); atomicMax(&s_box[5], int(kz));
-    }
-    __syncthreads();
-    const int bx0 = s_box[0] - 1, by0 = s_box[1] - 1, bz0 = s_box[2] - 1;
-    const int64_t dx = int64_t(s_box[3]) - bx0 + 2, dy = int64_t(s_box[4]) - by0 + 2,
-                  dz = int64_t(s_box[5]) - bz0 + 2;
-    const bool any = s_box[0] != INT_MAX;
-    const int64_t ncell64 = any ? dx * dy * dz : 0;
-    bool staged = any && ncell64 <= kBoxMax;
-    int total = 0;
-    if (staged) {
-      const int ncell = int(ncell64);
-      int cnt[kBoxMax / kTile];
+  Real acc[kVals];
 #pragma unroll
-      for (int q = 0; q < kBoxMax / kTile; ++q) {
-        const int c = tid * (kBoxMax / kTile) + q;
-        cnt[q] = 0;
-        if (c < ncell) {
-          const int cz_ = c % int(dz), cy_ = (c / int(dz)) % int(dy), cx_ = c / int(dz * dy);
-          const int32_t vox = map_find(m, bx0 + cx_, by0 + cy_, bz0 + cz_);
-          s_vox[c] = vox;
-          cnt[q] = vox >= 0 ? m.vox_count[vox] : 0;
+  for (int q = 0; q < kVals; ++q) acc[q] = Real(0);
+  int32_t match = -1;
+  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (in_tile) {
+    a = pA[i];
+    if (isfinite(a.x) && isfinite(a.y) && isfinite(a.z)) {
+      const double sx = a.x, sy = a.y, sz = a.z;
+      const double px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
+      const double py = ((R[3] * sx + R[4] * sy) + R[5] * sz) + ty;
+      const double pz = ((R[6] * sx + R[7] * sy) + R[8] * sz) + tz;
+      int64_t kx, ky, kz;
+      if (voxel_index_fast(px, m.v, prm.inv_v, prm.v_pow2, &kx) &&
+          voxel_index_fast(py, m.v, prm.inv_v, prm.v_pow2, &ky) &&
+          voxel_index_fast(pz, m.v, prm.inv_v, prm.v_pow2, &kz)) {
+        TopK<1> top;
+        nn_lockstep(m, px, py, pz, kx, ky, kz, prm.r2, top);
+        if (top.pos[0] >= 0) {
+          match = top.id[0];
+          const float4 r = m.vox_pts[top.pos[0]];
+          const float4 ca = m.cov[2 * int64_t(match)];
+          const float4 cb = m.cov[2 * int64_t(match) + 1];
+          gicp_term<Real>(px, py, pz, r, ca, cb, pB[i], pC[i], R, ctr[3 * s], ctr[3 * s + 1],
+                          ctr[3 * s + 2], prm.kappa2, acc);
         }
       }
-      int sum = 0;
-#pragma unroll
-      for (int q = 0; q < kBoxMax / kTile; ++q) sum += cnt[q];
-      int run = block_exscan_int(sum, s_scan, &total);
-#pragma unroll
-      for (int q = 0; q < kBoxMax / kTile; ++q) {
-        const int c = tid * (kBoxMax / kTile) + q;
-        if (c < ncell) s_start[c] = run;
-        run += cnt[q];
-      }
-      if (tid == 0) s_start[ncell] = total;
-      staged = total <= kLdsPts;          // block-uniform
-      __syncthreads();
-      if (staged) {
-        for (int e = tid; e < total; e += kTile) {
-          int lo = 0, hi = ncell;           // s_start[lo] <= e < s_start[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_start[mid] <= e) lo = mid; else hi = mid;
-          }
-          s_pts[e] = m.vox_pts[int64_t(s_vox[lo]) * m.nmax + (e - s_start[lo])];
-        }
-      }
-      __syncthreads();
     }
-
-    Real acc[kVals];
+    if (corr) corr[__float_as_int(a.w)] = match;
+  }
+  // wave sums (compensated in FP32), then the block's waves in FP64
 #pragma unroll
-    for (int q = 0; q < kVals; ++q) acc[q] = Real(0);
-    int32_t match = -1;
-    if (have) {
-      TopK<1> top;
-      float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (staged) {
-        top.init();
-        for (int q = 0; q < 27; ++q) {
-          const int code = kNbrOrder[q];
-          const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
-          const double bnd = fmin(prm.r2, top.bound());
-          if (voxel_lb2(px, py, pz, kx, ky, kz, ox, oy, oz, v) > bnd) continue;
-          const int c = ((int(kx) + ox - bx0) * int(dy) + (int(ky) + oy - by0)) * int(dz) +
-                        (int(kz) + oz - bz0);
-          const int e1 = s_start[c + 1];
-          for (int e = s_start[c]; e < e1; ++e) {
-            const float4 q4 = s_pts[e];
-            const double d = dist2(double(q4.x), double(q4.y), double(q4.z), px, py, pz);
-            if (d <= prm.r2) top.push(d, __float_as_int(q4.w), e);
-          }
-        }
-        if (top.pos[0] >= 0) r = s_pts[top.pos[0]];
-      } else {
-        map_knn_query<1>(m, px, py, pz, prm.r2, top);
-        if (top.pos[0] >= 0) r = m.vox_pts[top.pos[0]];
-      }
-      if (top.pos[0] >= 0) {
-        match = top.id[0];
-        const float4 ca = m.cov[2 * int64_t(match)];
-        const float4 cb = m.cov[2 * int64_t(match) + 1];
-        gicp_term<Real>(px, py, pz, r, ca, cb, pB[i], pC[i], R, cx, cy, cz, prm.kappa2, acc);
-      }
-    }
-    if (corr && i < int64_t(tile_hi[t])) corr[__float_as_int(a.w)] = match;
-    // wave sums (compensated in FP32), then the block's four waves in FP64
+  for (int q = 0; q < kVals; ++q) {
+    const double sv = wave_sum(acc[q]);
+    if (lane == 0) red[wave][q] = sv;
+  }
+  __syncthreads();
+  if (tid < kVals) {
+    double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < kVals; ++q) {
-      const double sv = wave_sum(acc[q]);
-      if (lane == 0) red[wave][q] = sv;
-    }
-    __syncthreads();
-    if (tid < kVals) {
-      double sum = 0.0;
-#pragma unroll
-      for (int w = 0; w < kTile / 64; ++w) sum += red[w][tid];
-      partial[t * kStride + tid] = sum;
-    }
-    __syncthreads();
+    for (int w = 0; w < kWaves; ++w) sum += red[w][tid];
+    partial[t * kStride + tid] = sum;
   }
 }
 
@@ -754,15 +704,15 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
     Scratch scr(st, w->arena, w->arena_cap);
     bool in_alt = false;
     FAR_TRY(radix_sort_pairs(w->okeys, w->ovals, w->okeys_alt, w->ovals_alt, j.n_total,
-                             30 + ceil_log2_i(j.S), st, scr, &in_alt));
-    k_pack<<<nb, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total,
-                               in_alt ? w->ovals_alt : w->ovals, w->pA, w->pB, w->pC);
+                             24 + ceil_log2_i(j.S), st, scr, &in_alt));
+    uint32_t* perm = in_alt ? w->ovals_alt : w->ovals;
+    uint32_t* inv = in_alt ? w->ovals : w->ovals_alt;
+    k_invert<<<nb, 256, 0, st>>>(perm, j.n_total, inv);
+    FAR_HIP(hipGetLastError());
+    k_pack<<<nb, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total, inv, w->pA, w->pB, w->pC);
     FAR_HIP(hipGetLastError());
   }
-  int64_t grid = ((max_tiles + 7) / 8) * 8;
-  const int64_t cap = int64_t(device_cu_count()) * 8;
-  if (grid > cap) grid = cap;
-  if (grid < 8) grid = 8;
+  const int64_t grid = ((max_tiles + 7) / 8) * 8;   // one block per tile
   const int iters = j.c_fixed ? 1 : j.prm.max_iters;
   const bool timed = timing().on;
   for (int it = 0; it < iters; ++it) {
@@ -853,6 +803,9 @@ Params make_params(const far_map_s* m, double tau, double kappa, double eps, int
   double r = tau < m->p.voxel_size ? tau : m->p.voxel_size;
   prm.r2 = r * r;
   prm.kappa2 = kappa * kappa;
+  int e2 = 0;
+  prm.v_pow2 = std::frexp(m->p.voxel_size, &e2) == 0.5 ? 1 : 0;
+  prm.inv_v = 1.0 / m->p.voxel_size;
   prm.eps = eps;
   prm.max_iters = max_iters;
   prm.recenter = recenter ? 1 : 0;

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/far.h"
+#include "far.h"
 
 namespace far {
 
@@ -61,7 +61,8 @@ __host__ __device__ inline uint32_t voxel_hash(int64_t kx, int64_t ky, int64_t k
 struct alignas(16) Slot {
   uint64_t key;   // kEmptyKey when free
   int32_t vox;    // compact voxel index
-  int32_t pad;
+  int32_t aux;    // map: points the voxel holds (mirror of vox_count), so one
+                  // 16-byte probe yields key, voxel and count; scan grid: scan id
 };
 
 // Device view of a map, passed by value to kernels.
@@ -78,13 +79,20 @@ struct MapView {
   uint32_t slot_mask;
 };
 
-__device__ inline int32_t map_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz) {
+// Voxel index of key (kx, ky, kz), or -1; *cnt receives its point count (0
+// when absent).
+__device__ inline int32_t map_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz,
+                                   int32_t* cnt) {
+  *cnt = 0;
   if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
   uint64_t key = pack_key(kx, ky, kz);
   uint32_t s = voxel_hash(kx, ky, kz, m.log2_slots);
   for (uint32_t probe = 0; probe <= m.slot_mask; ++probe) {
     Slot sl = m.slots[s];
-    if (sl.key == key) return sl.vox;
+    if (sl.key == key) {
+      *cnt = sl.aux;
+      return sl.vox;
+    }
     if (sl.key == kEmptyKey) return -1;
     s = (s + 1) & m.slot_mask;
   }
@@ -220,6 +228,7 @@ struct far_map_s {
   float4* cov = nullptr;
   float* pt_xyz = nullptr;
   int32_t* pt_loc = nullptr;
+  int32_t* vox_slot = nullptr;
   int64_t n_points = 0;
   int64_t n_voxels = 0;
   int device = 0;

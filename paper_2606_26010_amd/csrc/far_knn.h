@@ -64,6 +64,26 @@ __device__ inline bool voxel_index(double x, double v, int64_t* k) {
   return true;
 }
 
+// Rank the cnt points stored at pts[base ...] against q.  Loads are issued
+// four at a time so that they overlap instead of waiting one by one.
+template <int K>
+__device__ inline void scan_voxel_points(const float4* pts, int32_t base, int32_t cnt,
+                                         double qx, double qy, double qz, double r2,
+                                         TopK<K>& top) {
+  for (int32_t j = 0; j < cnt; j += 4) {
+    float4 p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j + u < cnt) p[u] = pts[base + j + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j + u < cnt) {
+        double d = dist2(double(p[u].x), double(p[u].y), double(p[u].z), qx, qy, qz);
+        if (d <= r2) top.push(d, __float_as_int(p[u].w), base + j + u);
+      }
+  }
+}
+
 // K nearest map points within sqrt(r2) of q over the 27-voxel neighbourhood,
 // skipping voxels whose conservative lower bound exceeds the current K-th
 // best (own voxel first, so the bound tightens early).
@@ -80,15 +100,10 @@ __device__ inline void map_knn_query(const MapView& m, double qx, double qy, dou
     int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
     double bnd = fmin(r2, top.bound());
     if (voxel_lb2(qx, qy, qz, kx, ky, kz, ox, oy, oz, m.v) > bnd) continue;
-    int32_t vox = map_find(m, kx + ox, ky + oy, kz + oz);
+    int32_t cnt;
+    int32_t vox = map_find(m, kx + ox, ky + oy, kz + oz, &cnt);
     if (vox < 0) continue;
-    int32_t cnt = m.vox_count[vox];
-    int32_t base = vox * m.nmax;
-    for (int32_t j = 0; j < cnt; ++j) {
-      float4 p = m.vox_pts[base + j];
-      double d = dist2(double(p.x), double(p.y), double(p.z), qx, qy, qz);
-      if (d <= r2) top.push(d, __float_as_int(p.w), base + j);
-    }
+    scan_voxel_points<K>(m.vox_pts, vox * m.nmax, cnt, qx, qy, qz, r2, top);
   }
 }
 

@@ -118,7 +118,8 @@ __global__ __launch_bounds__(kT) void k_seg_lookup(MapView m, const uint64_t* ke
     return;
   }
   uint64_t key = keys[seg_start[s]];
-  int32_t vox = map_find(m, key_x(key), key_y(key), key_z(key));
+  int32_t cnt;
+  int32_t vox = map_find(m, key_x(key), key_y(key), key_z(key), &cnt);
   seg_vox[s] = vox;
   is_new[s] = vox < 0 ? 1u : 0u;
 }
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kT) void k_seg_claim(Slot* slots, uint32_t slot_mas
                                                   const uint32_t* is_new,
                                                   const uint32_t* new_rank, int64_t n_seg,
                                                   int64_t n_vox_old, int32_t* seg_vox,
-                                                  uint64_t* vox_key) {
+                                                  uint64_t* vox_key, int32_t* vox_slot) {
   int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (s >= n_seg || !is_new[s]) return;
   uint64_t key = keys[seg_start[s]];
@@ -143,6 +144,8 @@ __global__ __launch_bounds__(kT) void k_seg_claim(Slot* slots, uint32_t slot_mas
                                        (unsigned long long)key);
     if (old == kEmptyKey) {
       slots[h].vox = vox;
+      slots[h].aux = 0;
+      vox_slot[vox] = int32_t(h);
       break;
     }
     h = (h + 1) & slot_mask;
@@ -223,20 +226,21 @@ __global__ __launch_bounds__(kT) void k_counts(int64_t n_seg, const int32_t* seg
                                                const uint32_t* seg_end,
                                                const uint32_t* acc_flag,
                                                const uint32_t* id_local, int64_t n_commit,
-                                               int32_t* vox_count) {
+                                               int32_t* vox_count, const int32_t* vox_slot,
+                                               Slot* slots) {
   int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (s >= n_seg) return;
   int32_t vox = seg_vox[s];
-  if (!truncated) {
-    vox_count[vox] = seg_newcount[s];
-    return;
-  }
-  int32_t c = vox_count[vox];
-  for (uint32_t j = seg_start[s]; j < seg_end[s]; ++j) {
-    uint32_t i = vals[j];
-    if (acc_flag[i] && int64_t(id_local[i]) < n_commit) ++c;
+  int32_t c = seg_newcount[s];
+  if (truncated) {
+    c = vox_count[vox];
+    for (uint32_t j = seg_start[s]; j < seg_end[s]; ++j) {
+      uint32_t i = vals[j];
+      if (acc_flag[i] && int64_t(id_local[i]) < n_commit) ++c;
+    }
   }
   vox_count[vox] = c;
+  slots[vox_slot[vox]].aux = c;
 }
 
 // Covariances of map points [id0, id1): k nearest within v on the map.
@@ -308,7 +312,7 @@ __device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, i
   uint32_t s = grid_hash(kx, ky, kz, sid, g.log2_slots);
   for (uint32_t probe = 0; probe <= g.slot_mask; ++probe) {
     Slot sl = g.slots[s];
-    if (sl.key == key && uint32_t(sl.pad) == sid) return sl.vox;
+    if (sl.key == key && uint32_t(sl.aux) == sid) return sl.vox;
     if (sl.key == kEmptyKey) return -1;
     s = (s + 1) & g.slot_mask;
   }
@@ -393,7 +397,7 @@ __global__ __launch_bounds__(kT) void k_grid_claim(Slot* slots, uint32_t slot_ma
                                        (unsigned long long)key);
     if (old == kEmptyKey) {
       slots[h].vox = int32_t(s);
-      slots[h].pad = int32_t(sc);
+      slots[h].aux = int32_t(sc);
       return;
     }
     h = (h + 1) & slot_mask;
@@ -607,6 +611,7 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   size_t b_cov = size_t(p.point_capacity) * 2 * sizeof(float4);
   size_t b_xyz = size_t(p.point_capacity) * 3 * sizeof(float);
   size_t b_loc = size_t(p.point_capacity) * sizeof(int32_t);
+  size_t b_vslot = size_t(m->voxel_cap) * sizeof(int32_t);
   if ((e = hipMalloc(&m->slots_d, b_slots)) != hipSuccess) return fail(e, "hipMalloc slots");
   if ((e = hipMalloc(&m->vox_count, b_cnt)) != hipSuccess) return fail(e, "hipMalloc counts");
   if ((e = hipMalloc(&m->vox_key, b_key)) != hipSuccess) return fail(e, "hipMalloc keys");
@@ -614,7 +619,8 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->cov, b_cov)) != hipSuccess) return fail(e, "hipMalloc cov");
   if ((e = hipMalloc(&m->pt_xyz, b_xyz)) != hipSuccess) return fail(e, "hipMalloc xyz");
   if ((e = hipMalloc(&m->pt_loc, b_loc)) != hipSuccess) return fail(e, "hipMalloc loc");
-  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_xyz + b_loc);
+  if ((e = hipMalloc(&m->vox_slot, b_vslot)) != hipSuccess) return fail(e, "hipMalloc vslot");
+  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_xyz + b_loc + b_vslot);
   if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipMemsetAsync(m->vox_count, 0, b_cnt, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "sync");
@@ -627,7 +633,8 @@ far_status_t far_map_destroy(far_map_t m) {
   hipError_t e = hipDeviceSynchronize();
   free_ws(m->ws);
   m->ws = nullptr;
-  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->pt_xyz, m->pt_loc};
+  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->pt_xyz,
+                  m->pt_loc, m->vox_slot};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -674,7 +681,7 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
   k_seg_claim<<<blocks_for(n_seg), kT, 0, st>>>(m->slots_d, uint32_t(m->slots - 1),
                                                 m->log2_slots, r.keys, r.seg_start, is_new,
                                                 new_rank, n_seg, m->n_voxels, seg_vox,
-                                                m->vox_key);
+                                                m->vox_key, m->vox_slot);
   FAR_HIP(hipGetLastError());
   uint32_t *acc_flag, *id_local, *acc_total;
   int32_t *acc_pos, *seg_newcount;
@@ -703,7 +710,8 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
   FAR_HIP(hipGetLastError());
   k_counts<<<blocks_for(n_seg), kT, 0, st>>>(n_seg, seg_vox, seg_newcount, truncated, r.vals,
                                              r.seg_start, r.seg_end, acc_flag, id_local,
-                                             n_commit, m->vox_count);
+                                             n_commit, m->vox_count, m->vox_slot,
+                                             m->slots_d);
   FAR_HIP(hipGetLastError());
   FAR_TRY(map_covariances(m->view(), m->cov, m->n_points, m->n_points + n_commit,
                           m->p.k_cov, st));

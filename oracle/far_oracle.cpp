@@ -677,4 +677,115 @@ void orc_touch_stats(const orc_map* m, const float* src, int64_t n,
   *n_points = pts;
 }
 
+
+// ---------------------------------------------------------------------------
+// Scan downsampling (part of the preprocessing in the runtime breakdown of
+// Sec. IV-B; the rule is not given, read as "first point in input order per
+// voxel").  A voxel seen for the first time keeps its point.
+// ---------------------------------------------------------------------------
+int orc_downsample(const float* xyz, int64_t n, double v, int64_t* keep, int64_t* n_keep) {
+  *n_keep = 0;
+  if (n < 0 || !(v > 0.0)) return 1;
+  for (int64_t i = 0; i < n; ++i) {
+    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    if (finite3(x, y, z) && !key_in_range(key_of(x, y, z, v))) return 1;
+  }
+  std::unordered_map<Key, int, KeyHash> seen;
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    if (!finite3(x, y, z)) continue;
+    if (seen.emplace(key_of(x, y, z, v), 1).second) keep[m++] = i;
+  }
+  *n_keep = m;
+  return 0;
+}
+
+// Rigid transform of a point set by a row-major 4x4 pose; each coordinate is
+// ((R_r0 sx + R_r1 sy) + R_r2 sz) + t_r in FP64, then rounded to float.
+void orc_transform(const float* xyz, int64_t n, const double T[16], float* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double s[3] = {xyz[i], xyz[n + i], xyz[2 * n + i]};
+    for (int r = 0; r < 3; ++r) {
+      double p = ((T[r * 4 + 0] * s[0] + T[r * 4 + 1] * s[1]) + T[r * 4 + 2] * s[2]) +
+                 T[r * 4 + 3];
+      out[r * n + i] = float(p);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive threshold (Sec. III-A.2 adapts the correspondence threshold and
+// the robust kernel's kappa to the motion, "analogous to" KISS-ICP).  Read as
+// the published KISS-ICP rule: the deviation of the estimate from the motion
+// prediction, measured as the largest displacement it causes within range
+// r_max (2 r_max sin(theta/2) for the rotation, plus the translation), is a
+// sample when it exceeds min_motion; sigma is the root mean square of the
+// samples (sigma0 before the first), the threshold 3 sigma and kappa sigma/3.
+// ---------------------------------------------------------------------------
+void orc_threshold_init(orc_threshold* s, double sigma0, double r_max, double min_motion) {
+  s->sigma0 = sigma0;
+  s->r_max = r_max;
+  s->min_motion = min_motion;
+  s->sse = 0.0;
+  s->n = 0;
+}
+
+double orc_threshold_update(orc_threshold* s, const double P[16], const double E[16]) {
+  // D = P^-1 E with P^-1 = [R^T, -R^T t]
+  double Pi[16] = {0};
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) Pi[i * 4 + j] = P[j * 4 + i];
+    Pi[i * 4 + 3] = -(P[0 * 4 + i] * P[3] + P[1 * 4 + i] * P[7] + P[2 * 4 + i] * P[11]);
+  }
+  Pi[15] = 1.0;
+  double D[16];
+  matmul4(Pi, E, D);
+  // rotation angle of D from its unit quaternion (Shepperd's method: build
+  // the largest of |w|, |x|, |y|, |z| from the diagonal, the rest from the
+  // off-diagonal sums and differences), theta = 2 atan2(|(x, y, z)|, |w|);
+  // unlike acos of the trace this keeps full precision for small angles
+  double tr = D[0] + D[5] + D[10];
+  double q[4];  // w, x, y, z
+  double d4[4] = {1.0 + tr, 1.0 + 2.0 * D[0] - tr, 1.0 + 2.0 * D[5] - tr, 1.0 + 2.0 * D[10] - tr};
+  int big = int(std::max_element(d4, d4 + 4) - d4);
+  double r = std::sqrt(d4[big]);  // = 2 |q_big|
+  if (big == 0) {
+    q[0] = 0.5 * r;
+    q[1] = (D[9] - D[6]) / (2.0 * r);
+    q[2] = (D[2] - D[8]) / (2.0 * r);
+    q[3] = (D[4] - D[1]) / (2.0 * r);
+  } else if (big == 1) {
+    q[1] = 0.5 * r;
+    q[0] = (D[9] - D[6]) / (2.0 * r);
+    q[2] = (D[1] + D[4]) / (2.0 * r);
+    q[3] = (D[2] + D[8]) / (2.0 * r);
+  } else if (big == 2) {
+    q[2] = 0.5 * r;
+    q[0] = (D[2] - D[8]) / (2.0 * r);
+    q[1] = (D[1] + D[4]) / (2.0 * r);
+    q[3] = (D[6] + D[9]) / (2.0 * r);
+  } else {
+    q[3] = 0.5 * r;
+    q[0] = (D[4] - D[1]) / (2.0 * r);
+    q[1] = (D[2] + D[8]) / (2.0 * r);
+    q[2] = (D[6] + D[9]) / (2.0 * r);
+  }
+  double theta = 2.0 * std::atan2(std::sqrt(q[1] * q[1] + q[2] * q[2] + q[3] * q[3]),
+                                  std::fabs(q[0]));
+  double dt = std::sqrt(D[3] * D[3] + D[7] * D[7] + D[11] * D[11]);
+  double dev = 2.0 * s->r_max * std::sin(theta / 2.0) + dt;
+  if (dev > s->min_motion) {
+    s->sse += dev * dev;
+    s->n += 1;
+  }
+  return dev;
+}
+
+void orc_threshold_get(const orc_threshold* s, double* tau, double* kappa) {
+  double sigma = s->n > 0 ? std::sqrt(s->sse / double(s->n)) : s->sigma0;
+  *tau = 3.0 * sigma;
+  *kappa = sigma / 3.0;
+}
+
 }  // extern "C"

@@ -80,6 +80,32 @@ void orc_regularize_cov(const double S[9], double out[9]);
 void orc_touch_stats(const orc_map* m, const float* src, int64_t n,
                      const double T[16], int64_t* n_voxels, int64_t* n_points);
 
+/* Voxel downsampling of a scan (the preprocessing named in the runtime
+ * breakdown of Sec. IV-B; reading: keep, for every voxel of edge v, the
+ * first point in input order).  keep [n] receives the kept input indices in
+ * increasing order and *n_keep their number; non-finite points are dropped.
+ * Returns 1 (and keeps nothing) when a finite point's key is out of range. */
+int orc_downsample(const float* xyz, int64_t n, double v, int64_t* keep, int64_t* n_keep);
+
+/* out = R s + t for every point, in FP64 with the fixed evaluation order
+ * ((R00 sx + R01 sy) + R02 sz) + tx, rounded to float.  SoA in and out. */
+void orc_transform(const float* xyz, int64_t n, const double T[16], float* out);
+
+/* Adaptive correspondence threshold (Sec. III-A.2: the outlier threshold and
+ * the Cauchy kappa adapt to the motion, following Vizzo et al., KISS-ICP).
+ * State: sum of squared model deviations above min_motion and their count. */
+typedef struct {
+  double sigma0, r_max, min_motion, sse;
+  int64_t n;
+} orc_threshold;
+void orc_threshold_init(orc_threshold* s, double sigma0, double r_max, double min_motion);
+/* Model deviation of T_est against T_pred: 2 r_max sin(theta/2) + |dt| of
+ * T_pred^-1 T_est; returns it and adds its square when above min_motion. */
+double orc_threshold_update(orc_threshold* s, const double T_pred[16], const double T_est[16]);
+/* sigma = sqrt(sse / n), or sigma0 before the first sample; tau = 3 sigma,
+ * kappa = sigma / 3. */
+void orc_threshold_get(const orc_threshold* s, double* tau, double* kappa);
+
 #ifdef __cplusplus
 }
 #endif

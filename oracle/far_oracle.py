@@ -32,6 +32,11 @@ def _opt(t):
     return _P
 
 
+class _ThresholdState(C.Structure):
+    _fields_ = [("sigma0", C.c_double), ("r_max", C.c_double), ("min_motion", C.c_double),
+                ("sse", C.c_double), ("n", C.c_int64)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -67,6 +72,15 @@ def lib():
         L.orc_regularize_cov.argtypes = [_f64p, _f64p]
         L.orc_touch_stats.argtypes = [C.c_void_p, _f32p, C.c_int64, _f64p,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.orc_downsample.argtypes = [_f32p, C.c_int64, C.c_double, _i64p,
+                                     C.POINTER(C.c_int64)]
+        L.orc_transform.argtypes = [_f32p, C.c_int64, _f64p, _f32p]
+        L.orc_threshold_init.argtypes = [C.POINTER(_ThresholdState), C.c_double, C.c_double,
+                                         C.c_double]
+        L.orc_threshold_update.restype = C.c_double
+        L.orc_threshold_update.argtypes = [C.POINTER(_ThresholdState), _f64p, _f64p]
+        L.orc_threshold_get.argtypes = [C.POINTER(_ThresholdState), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -218,3 +232,99 @@ def regularize_cov(S):
     out = np.zeros(9)
     lib().orc_regularize_cov(np.ascontiguousarray(S, dtype=np.float64).reshape(9), out)
     return out.reshape(3, 3)
+
+
+def downsample(xyz, v):
+    """Indices (increasing) of the first point of every voxel of edge v."""
+    a = _soa(xyz)
+    n = a.shape[1]
+    keep = np.zeros(max(n, 1), np.int64)
+    m = C.c_int64(0)
+    rc = lib().orc_downsample(a, n, v, keep, C.byref(m))
+    if rc:
+        raise OracleError(rc, "orc_downsample")
+    return keep[:m.value].copy()
+
+
+def transform(xyz, T):
+    a = _soa(xyz)
+    out = np.zeros_like(a)
+    lib().orc_transform(a, a.shape[1], np.ascontiguousarray(T, dtype=np.float64).reshape(16), out)
+    return out
+
+
+class Threshold:
+    """Adaptive correspondence threshold and Cauchy kappa (KISS-ICP rule)."""
+
+    def __init__(self, sigma0, r_max, min_motion=0.1):
+        self._s = _ThresholdState()
+        lib().orc_threshold_init(C.byref(self._s), sigma0, r_max, min_motion)
+
+    def update(self, T_pred, T_est):
+        return lib().orc_threshold_update(
+            C.byref(self._s), np.ascontiguousarray(T_pred, dtype=np.float64).reshape(16),
+            np.ascontiguousarray(T_est, dtype=np.float64).reshape(16))
+
+    def get(self):
+        tau, kappa = C.c_double(0), C.c_double(0)
+        lib().orc_threshold_get(C.byref(self._s), C.byref(tau), C.byref(kappa))
+        return tau.value, kappa.value
+
+    @property
+    def samples(self):
+        return self._s.n
+
+
+def _inv(T):
+    R, t = T[:3, :3], T[:3, 3]
+    out = np.eye(4)
+    out[:3, :3] = R.T
+    out[:3, 3] = -R.T @ t
+    return out
+
+
+def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing, k,
+             map_capacity, downsample_v, sigma0, r_max, min_motion=0.1, max_iters=10,
+             eps=0.0):
+    """Scan-to-submap odometry over a sequence (Sec. III-A: downsample, source
+    covariances, registration against the capped submap, insertion of the
+    registered scan), driven by the oracle's own steps.
+
+    Readings: the first scan is inserted at T_first; the motion prediction is
+    constant velocity, T_pred = T_prev (T_prev2^-1 T_prev), with the relative
+    motion v_first (the inertial prediction of the paper's filter) for the
+    second scan; the threshold and kappa come from Threshold before each
+    registration and the deviation of the estimate is added after it; the
+    registered, downsampled scan is inserted; once the map is full, inserting
+    stops (the map keeps what fit).  Returns per-scan dicts with the pose,
+    the prediction, tau, kappa, the align status and map sizes."""
+    m = Map(voxel_size, max_pts_per_voxel, min_spacing, k, point_capacity=map_capacity,
+            voxel_capacity=map_capacity)
+    thr = Threshold(sigma0, r_max, min_motion)
+    out, poses = [], []
+    full = False
+    for s, raw in enumerate(scans):
+        src = _soa(raw)[:, downsample(raw, downsample_v)]
+        rec = dict(n=src.shape[1])
+        if s == 0:
+            T = np.array(T_first, dtype=np.float64)
+            rec.update(T_pred=T.copy(), tau=None, kappa=None, status=0, iters=0)
+        else:
+            vel = v_first if s == 1 else _inv(poses[-2]) @ poses[-1]
+            T_pred = poses[-1] @ vel
+            tau, kappa = thr.get()
+            cov, val = scan_covariances(src, voxel_size, k)
+            r = m.align(src, cov.astype(np.float32), val, T_pred, tau, kappa,
+                        max_iters=max_iters, eps=eps)
+            T = r["T"] if r["status"] == 0 else T_pred
+            rec.update(T_pred=T_pred, tau=tau, kappa=kappa, status=r["status"],
+                       iters=r["iters"], n_inliers=r["n_inliers"], cost=r["cost"],
+                       deviation=thr.update(T_pred, T))
+        poses.append(T)
+        if not full:
+            rc, acc, _ = m.insert(transform(src, T), check=False)
+            full = rc == 2
+            rec["inserted"] = acc
+        rec.update(T=T, map_points=m.size, map_voxels=m.n_voxels)
+        out.append(rec)
+    return out, m

@@ -1,0 +1,120 @@
+"""Pins of the oracle's sequence-pipeline pieces: voxel downsampling, the
+rigid transform of a scan, the adaptive threshold (KISS-ICP rule) and the
+odometry loop that strings them together."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from paper_2606_26010_amd import synth
+
+
+def first_per_voxel(x, v):
+    """Plain definition: the first occurrence of every voxel key, via numpy."""
+    fin = np.all(np.isfinite(x), axis=0)
+    idx = np.nonzero(fin)[0]
+    keys = np.floor(x[:, idx].astype(np.float64).T / v).astype(np.int64)
+    _, first = np.unique(keys, axis=0, return_index=True)
+    return np.sort(idx[first])
+
+
+def test_downsample_is_first_point_per_voxel(orc):
+    g = np.random.default_rng(1)
+    x = g.uniform(-4, 4, (3, 30000)).astype(np.float32)
+    x[:, 5000:5100] = x[:, 100:200]                          # duplicates
+    x[:, 6000:6300] = (g.integers(-8, 8, (3, 300)) * 0.5).astype(np.float32)   # on faces
+    x[0, 7000:7010] = np.nan
+    x[2, 7010:7020] = np.inf
+    keep = orc.downsample(x, 0.5)
+    np.testing.assert_array_equal(keep, first_per_voxel(x, 0.5))
+    assert not np.isin(np.arange(7000, 7020), keep).any()
+
+
+def test_downsample_equals_cap_one_insert(orc):
+    g = np.random.default_rng(2)
+    x = g.uniform(-6, 6, (3, 20000)).astype(np.float32)
+    keep = orc.downsample(x, 0.5)
+    m = orc.Map(0.5, 1, 0.0, 1, point_capacity=1 << 16, voxel_capacity=1 << 16)
+    m.insert(x)
+    mx, _, _ = m.export()
+    np.testing.assert_array_equal(mx, x[:, keep])
+
+
+def test_downsample_edges(orc):
+    assert orc.downsample(np.zeros((3, 0), np.float32), 0.5).size == 0
+    np.testing.assert_array_equal(orc.downsample(np.zeros((3, 7), np.float32), 0.5), [0])
+    bad = np.zeros((3, 3), np.float32)
+    bad[1, 2] = 1e6                                          # key 2e6 > 2^20
+    with pytest.raises(orc.OracleError):
+        orc.downsample(bad, 0.5)
+
+
+def test_transform_rounding(orc):
+    g = np.random.default_rng(3)
+    x = g.uniform(-100, 100, (3, 5000)).astype(np.float32)
+    np.testing.assert_array_equal(orc.transform(x, np.eye(4)), x)
+    T = np.eye(4)
+    T[:3, 3] = (0.1, -7.25, 1e3 / 3)
+    np.testing.assert_array_equal(
+        orc.transform(x, T), (x.astype(np.float64) + T[:3, 3:4]).astype(np.float32))
+    T = synth.pose(Rotation.from_rotvec([0.3, -0.2, 1.1]).as_matrix(), (5.0, -3.0, 2.0))
+    ref = T[:3, :3] @ x.astype(np.float64) + T[:3, 3:4]
+    got = orc.transform(x, T)
+    ulp = np.spacing(np.abs(ref).astype(np.float32))
+    assert np.all(np.abs(got - ref) <= ulp)                 # one rounding to float
+
+
+def test_threshold_hand_sequence(orc):
+    t = orc.Threshold(1.0 / 3.0, 100.0, 0.1)
+    assert t.get() == pytest.approx((1.0, 1.0 / 9.0), rel=1e-15)
+    I = np.eye(4)
+
+    def trans(x, y, z):
+        T = np.eye(4)
+        T[:3, 3] = (x, y, z)
+        return T
+
+    # 5 cm deviation: below the minimum motion, no sample
+    assert t.update(I, trans(0.05, 0, 0)) == pytest.approx(0.05, abs=1e-15)
+    assert t.samples == 0 and t.get()[0] == pytest.approx(1.0, rel=1e-15)
+    # 0.5 m deviation: sigma = 0.5
+    assert t.update(I, trans(0.3, 0.4, 0)) == pytest.approx(0.5, abs=1e-15)
+    assert t.get() == pytest.approx((1.5, 0.5 / 3.0), rel=1e-14)
+    # deviation D = (rotation about z by 2 asin(1e-3), 0.1 m along z) applied
+    # on the right of a non-trivial prediction P: 2 * 100 * 1e-3 + 0.1 = 0.3
+    P = synth.pose(Rotation.from_euler("z", 30, degrees=True).as_matrix(), (5.0, -2.0, 1.0))
+    D = synth.pose(Rotation.from_euler("z", 2 * math.asin(1e-3)).as_matrix(), (0, 0, 0.1))
+    assert t.update(P, P @ D) == pytest.approx(0.3, abs=1e-9)
+    s = math.sqrt((0.25 + 0.09) / 2)
+    assert t.get() == pytest.approx((3 * s, s / 3), rel=1e-8)
+    assert t.samples == 2
+
+
+def test_odometry_short_sequence_tracks_ground_truth(orc):
+    c = synth.make_sequence(2, n_scans=6, lidar=synth.Lidar(beams=32, azimuths=512))
+    v1 = np.linalg.inv(c.poses[0]) @ c.poses[1]
+    out, m = orc.odometry(c.scans, c.poses[0], v1, c.voxel_size, c.max_pts_per_voxel,
+                          c.min_spacing, c.k, c.map_capacity, c.downsample, c.sigma0,
+                          c.r_max)
+    assert [r["status"] for r in out] == [0] * 6
+    assert all(out[i]["map_points"] > out[i - 1]["map_points"] for i in range(1, 6))
+    for r, T in zip(out, c.poses):
+        E = r["T"][:3, :3] @ T[:3, :3].T
+        ang = math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(E) - 1) / 2))))
+        assert np.linalg.norm(r["T"][:3, 3] - T[:3, 3]) < 0.1 and ang < 0.3
+
+
+@pytest.mark.parametrize("angle", [1e-7, 3e-4, 0.3, 2.0, 3.1, math.pi])
+def test_threshold_deviation_closed_form(orc, angle):
+    # rotation only: the deviation is exactly 2 r_max sin(theta / 2), at small
+    # angles and near pi (every quaternion branch) alike
+    g = np.random.default_rng(int(angle * 1e3) + 7)
+    for _ in range(5):
+        axis = g.normal(size=3)
+        axis /= np.linalg.norm(axis)
+        P = synth.pose(Rotation.from_rotvec(g.normal(size=3)).as_matrix(), g.normal(size=3))
+        D = synth.pose(Rotation.from_rotvec(axis * angle).as_matrix(), (0, 0, 0))
+        t = orc.Threshold(1.0, 50.0, 0.0)
+        want = 100.0 * math.sin(angle / 2)
+        assert t.update(P, P @ D) == pytest.approx(want, rel=1e-7, abs=1e-12)

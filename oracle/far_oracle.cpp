@@ -788,4 +788,181 @@ void orc_threshold_get(const orc_threshold* s, double* tau, double* kappa) {
   *kappa = sigma / 3.0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Differentiation of the GICP cost.  The cost is Eq. (4) with the Cauchy rho
+// of Eq. (5): sum_i rho(e2_i), e2_i = d_i^T M_i^-1 d_i, d_i = r_j(i) - p_i,
+// p_i = R s_i + t, M_i = Sigma_r + R Sigma_s,i R^T (or I, sparsity-aware
+// case).  Readings: the correspondences j(i) and Sigma_s are held fixed; R
+// enters both p and M, so the pose gradient carries the d M / d R term.
+// ---------------------------------------------------------------------------
+namespace {
+
+// M (both covariances valid) or I, and its inverse W.
+void m_and_w(const orc_map* m, const float* src_cov6, const uint8_t* src_valid, int64_t n,
+             int64_t i, int64_t j, const double R[9], double M[9], double W[9], double Ss[9],
+             bool* both) {
+  *both = src_valid[i] != 0 && m->valid[size_t(j)] != 0;
+  for (int t = 0; t < 9; ++t) Ss[t] = 0.0;
+  if (*both) {
+    const float* cr = &m->cov[size_t(j) * 6];
+    double Sr[9] = {cr[0], cr[1], cr[2], cr[1], cr[3], cr[4], cr[2], cr[4], cr[5]};
+    double cs[6];
+    for (int t = 0; t < 6; ++t) cs[t] = src_cov6[t * n + i];
+    double S9[9] = {cs[0], cs[1], cs[2], cs[1], cs[3], cs[4], cs[2], cs[4], cs[5]};
+    for (int t = 0; t < 9; ++t) Ss[t] = S9[t];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) s += R[a * 3 + k] * S9[k * 3 + l] * R[b * 3 + l];
+        M[a * 3 + b] = Sr[a * 3 + b] + s;
+      }
+  } else {
+    for (int t = 0; t < 9; ++t) M[t] = (t % 4 == 0) ? 1.0 : 0.0;
+  }
+  inv3(M, W);
+}
+
+}  // namespace
+
+int orc_cost_fixed(const orc_map* m, const double* src, const float* src_cov6,
+                   const uint8_t* src_valid, int64_t n, const double T[16], double kappa,
+                   const int32_t* corr, double* cost) {
+  if (n < 0 || !(kappa > 0.0)) return 1;
+  const double R[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};
+  const double k2 = kappa * kappa;
+  double total = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t j = corr[i];
+    if (j < 0) continue;
+    double s[3] = {src[i], src[n + i], src[2 * n + i]};
+    double p[3];
+    for (int a = 0; a < 3; ++a)
+      p[a] = R[a * 3] * s[0] + R[a * 3 + 1] * s[1] + R[a * 3 + 2] * s[2] + T[a * 4 + 3];
+    const Pt& q = m->g.pts[size_t(j)];
+    double d[3] = {q.x - p[0], q.y - p[1], q.z - p[2]};
+    double M[9], W[9], Ss[9];
+    bool both;
+    m_and_w(m, src_cov6, src_valid, n, i, j, R, M, W, Ss, &both);
+    double e2 = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) e2 += d[a] * W[a * 3 + b] * d[b];
+    total += 0.5 * k2 * std::log1p(e2 / k2);
+  }
+  *cost = total;
+  return 0;
+}
+
+// Gradient by the chain rule, per inlier (rho'(e2) = w/2 with the IRLS
+// weight w = kappa^2 / (kappa^2 + e2)):
+//   d e2 / d p = -2 u,  d e2 / d M = -u u^T,  u = W d;
+//   d cost / d t   = -w u
+//   d cost / d R   = -w u s^T  -  w u u^T R Sigma_s      (second term: M)
+//   d cost / d s_i = -w R^T u
+//   twist: d d / d delta = J = [[p - c]x, -I] gives w J^T u; the rotation
+//   part of delta also moves M by [e_k]x A - A [e_k]x (A = R Sigma_s R^T),
+//   adding (w/2) tr(-u u^T ([e_k]x A - A [e_k]x)) to component k.
+int orc_gradient(const orc_map* m, const float* src, const float* src_cov6,
+                 const uint8_t* src_valid, int64_t n, const double T[16], double tau,
+                 double kappa, const double c[3], double grad_T[12], double grad_twist[6],
+                 double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr) {
+  if (n < 0 || !(tau > 0.0) || !(kappa > 0.0)) return 1;
+  std::vector<int32_t> cj(size_t(n), -1);
+  {
+    double H[36], b[6], cst;
+    int64_t cnt;
+    int rc = orc_linearize(m, src, src_cov6, src_valid, n, T, tau, kappa, c, H, b, &cst, &cnt,
+                           cj.data(), nullptr);
+    if (rc) return rc;
+  }
+  const double R[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};
+  const double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
+  const double k2 = kappa * kappa;
+  std::vector<double> rows(size_t(n) * 19, 0.0);   // 12 grad_T, 6 twist, rho
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    if (grad_src)
+      for (int a = 0; a < 3; ++a) grad_src[a * n + i] = 0.0;
+    int64_t j = cj[size_t(i)];
+    if (j < 0) continue;
+    double s[3] = {src[i], src[n + i], src[2 * n + i]};
+    double p[3];
+    for (int a = 0; a < 3; ++a)
+      p[a] = ((R[a * 3] * s[0] + R[a * 3 + 1] * s[1]) + R[a * 3 + 2] * s[2]) + T[a * 4 + 3];
+    const Pt& q = m->g.pts[size_t(j)];
+    double d[3] = {q.x - p[0], q.y - p[1], q.z - p[2]};
+    double M[9], W[9], Ss[9];
+    bool both;
+    m_and_w(m, src_cov6, src_valid, n, i, j, R, M, W, Ss, &both);
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = W[a * 3] * d[0] + W[a * 3 + 1] * d[1] + W[a * 3 + 2] * d[2];
+    double e2 = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    double w = k2 / (k2 + e2);
+    double* row = &rows[size_t(i) * 19];
+    // d cost / d R and d cost / d t
+    double RS[9] = {0};   // R Sigma_s
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int k = 0; k < 3; ++k) RS[a * 3 + b] += R[a * 3 + k] * Ss[k * 3 + b];
+    double uRS[3] = {0};  // u^T R Sigma_s
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a) uRS[b] += u[a] * RS[a * 3 + b];
+    for (int a = 0; a < 3; ++a) {
+      for (int b = 0; b < 3; ++b) row[a * 4 + b] = -w * u[a] * s[b] - w * u[a] * uRS[b];
+      row[a * 4 + 3] = -w * u[a];
+    }
+    // twist: w J^T u, then the M term of the rotation part
+    double ax = p[0] - cc[0], ay = p[1] - cc[1], az = p[2] - cc[2];
+    double J[18] = {0.0, -az, ay, -1.0, 0.0, 0.0,
+                    az, 0.0, -ax, 0.0, -1.0, 0.0,
+                    -ay, ax, 0.0, 0.0, 0.0, -1.0};
+    for (int k = 0; k < 6; ++k)
+      row[12 + k] = w * (J[k] * u[0] + J[6 + k] * u[1] + J[12 + k] * u[2]);
+    if (both) {
+      double A[9] = {0};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          for (int k = 0; k < 3; ++k) A[a * 3 + b] += RS[a * 3 + k] * R[b * 3 + k];
+      for (int k = 0; k < 3; ++k) {
+        double E[9] = {0};   // [e_k]x
+        if (k == 0) { E[5] = -1; E[7] = 1; }
+        if (k == 1) { E[2] = 1; E[6] = -1; }
+        if (k == 2) { E[1] = -1; E[3] = 1; }
+        double dM[9];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            double x = 0.0;
+            for (int l = 0; l < 3; ++l) x += E[a * 3 + l] * A[l * 3 + b] - A[a * 3 + l] * E[l * 3 + b];
+            dM[a * 3 + b] = x;
+          }
+        double quad = 0.0;   // u^T dM u
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) quad += u[a] * dM[a * 3 + b] * u[b];
+        row[12 + k] += 0.5 * w * (-quad);
+      }
+    }
+    row[18] = 0.5 * k2 * std::log1p(e2 / k2);
+    if (grad_src)
+      for (int b = 0; b < 3; ++b)
+        grad_src[b * n + i] = -w * (R[0 * 3 + b] * u[0] + R[1 * 3 + b] * u[1] + R[2 * 3 + b] * u[2]);
+  }
+  double gT[12] = {0}, gw[6] = {0}, cs = 0.0;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (corr) corr[i] = cj[size_t(i)];
+    if (cj[size_t(i)] < 0) continue;
+    const double* row = &rows[size_t(i) * 19];
+    for (int t = 0; t < 12; ++t) gT[t] += row[t];
+    for (int t = 0; t < 6; ++t) gw[t] += row[12 + t];
+    cs += row[18];
+    ++cnt;
+  }
+  for (int t = 0; t < 12; ++t) grad_T[t] = gT[t];
+  for (int t = 0; t < 6; ++t) grad_twist[t] = gw[t];
+  *cost = cs;
+  *n_inliers = cnt;
+  return 0;
+}
+
 }  // extern "C"

@@ -106,6 +106,26 @@ double orc_threshold_update(orc_threshold* s, const double T_pred[16], const dou
  * kappa = sigma / 3. */
 void orc_threshold_get(const orc_threshold* s, double* tau, double* kappa);
 
+/* GICP cost (Eq. 4 with the Cauchy rho of Eq. 5) at pose T [16] for given
+ * correspondences corr [n] (-1 = none), with FP64 source points
+ * src [3][n] double; the rotation block of T is used as a free 3x3 matrix in
+ * p = R s + t and M = Sigma_r + R Sigma_s R^T (used for finite differences). */
+int orc_cost_fixed(const orc_map* m, const double* src, const float* src_cov6,
+                   const uint8_t* src_valid, int64_t n, const double T[16], double kappa,
+                   const int32_t* corr, double* cost);
+
+/* Gradient of the GICP cost at T, correspondences (nearest map point within
+ * min(tau, v), as orc_linearize) and Sigma_s held fixed:
+ *   grad_T [12]     d cost / d [R | t], row-major 3x4 (R as a free 3x3);
+ *   grad_twist [6]  d cost / d delta at delta = 0 for
+ *                   T(delta) = T_c Exp(delta) T_c^-1 T, delta = (omega, v);
+ *   grad_src [3][n] d cost / d s_i (double, or NULL);
+ *   cost, n_inliers; corr [n] or NULL receives the correspondences. */
+int orc_gradient(const orc_map* m, const float* src, const float* src_cov6,
+                 const uint8_t* src_valid, int64_t n, const double T[16], double tau,
+                 double kappa, const double c[3], double grad_T[12], double grad_twist[6],
+                 double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,11 @@ def lib():
         L.orc_regularize_cov.argtypes = [_f64p, _f64p]
         L.orc_touch_stats.argtypes = [C.c_void_p, _f32p, C.c_int64, _f64p,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.orc_cost_fixed.argtypes = [C.c_void_p, _f64p, _f32p, _u8p, C.c_int64, _f64p,
+                                     C.c_double, _i32p, C.POINTER(C.c_double)]
+        L.orc_gradient.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p, C.c_double,
+                                   C.c_double, _opt(_f64p), _f64p, _f64p, _opt(_f64p),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int64), _opt(_i32p)]
         L.orc_downsample.argtypes = [_f32p, C.c_int64, C.c_double, _i64p,
                                      C.POINTER(C.c_int64)]
         L.orc_transform.argtypes = [_f32p, C.c_int64, _f64p, _f32p]
@@ -188,6 +193,39 @@ class Map:
                              C.byref(cost), C.byref(cnt))
         return dict(status=rc, T=Tout.reshape(4, 4), iters=it.value, converged=conv.value,
                     H=H.reshape(6, 6), b=b, cost=cost.value, n_inliers=cnt.value)
+
+    def cost_fixed(self, src64, cov6, valid, T, kappa, corr):
+        """Cost at T (rotation block used as a free 3x3) with correspondences
+        corr fixed and FP64 source points src64 [3, n]."""
+        a = np.ascontiguousarray(src64, dtype=np.float64)
+        n = a.shape[1]
+        out = C.c_double(0)
+        rc = lib().orc_cost_fixed(self._h, a, np.ascontiguousarray(cov6, dtype=np.float32),
+                                  np.ascontiguousarray(valid, dtype=np.uint8), n,
+                                  np.ascontiguousarray(T, dtype=np.float64).reshape(16), kappa,
+                                  np.ascontiguousarray(corr, dtype=np.int32), C.byref(out))
+        if rc:
+            raise OracleError(rc, "orc_cost_fixed")
+        return out.value
+
+    def gradient(self, src, cov6, valid, T, tau, kappa, c=None, want_src=True):
+        """dict(grad_T [3, 4], grad_twist [6], grad_src [3, n] or None, cost,
+        n_inliers, corr)."""
+        a = _soa(src)
+        n = a.shape[1]
+        gT, gw = np.zeros(12), np.zeros(6)
+        gs = np.zeros((3, n)) if want_src else None
+        cost, cnt = C.c_double(0), C.c_int64(0)
+        corr = np.zeros(n, np.int32)
+        cc = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        rc = lib().orc_gradient(self._h, a, np.ascontiguousarray(cov6, dtype=np.float32),
+                                np.ascontiguousarray(valid, dtype=np.uint8), n,
+                                np.ascontiguousarray(T, dtype=np.float64).reshape(16), tau,
+                                kappa, cc, gT, gw, gs, C.byref(cost), C.byref(cnt), corr)
+        if rc:
+            raise OracleError(rc, "orc_gradient")
+        return dict(grad_T=gT.reshape(3, 4), grad_twist=gw, grad_src=gs, cost=cost.value,
+                    n_inliers=cnt.value, corr=corr)
 
     def touch_stats(self, src, T):
         a = _soa(src)

@@ -53,7 +53,7 @@ typedef enum {
 } far_status_t;
 
 typedef enum {
-  FAR_PREC_FP32 = 0,      /* FP32 per-point term, compensated FP32 wave sums */
+  FAR_PREC_FP32 = 0,      /* FP32 per-point term, FP64 sums                  */
   FAR_PREC_FP64 = 1       /* every per-point term and sum in FP64            */
 } far_precision_t;
 
@@ -185,6 +185,24 @@ far_status_t far_gicp_linearize(far_map_t map, const float* src, const float* co
                                 int32_t precision, int32_t* corr, far_lin_t* out,
                                 far_stream_t stream);
 
+/* Gradient of the GICP cost (Eq. 4 with the Cauchy rho of Eq. 5) at pose T
+ * [host], with each point's correspondence (nearest map point within
+ * min(tau, v), searched again here) and the source covariances held fixed;
+ * R enters both p = R s + t and M = Sigma_r + R Sigma_s R^T.
+ *   grad_T [host, 12]    d cost / d [R | t], row-major 3 x 4, R taken as a
+ *                        free 3 x 3 matrix;
+ *   grad_twist [host, 6] d cost / d delta at delta = 0 for the perturbation
+ *                        T(delta) = T_c Exp(delta) T_c^-1 T about c [host, 3]
+ *                        (NULL = origin), delta = (omega, v);
+ *   grad_src [dev, SoA 3 x n, or NULL]  d cost / d s_i (0 for outliers);
+ *   cost, n_inliers [host, or NULL].
+ * precision as for far_gicp_linearize.  Synchronises `stream`. */
+far_status_t far_gicp_gradient(far_map_t map, const float* src, const float* cov6,
+                               const uint8_t* valid, int64_t n, const double T[16],
+                               double tau, double kappa, const double c[3], int32_t precision,
+                               double grad_T[12], double grad_twist[6], float* grad_src,
+                               double* cost, int64_t* n_inliers, far_stream_t stream);
+
 /* Gauss-Newton align of one scan (Eq. 6): up to max_iters iterations of
  * linearise, solve H delta = -b by FP64 Cholesky, T <- T_c Exp(delta) T_c^-1 T
  * (T_c = translation by the linearisation centre), stopping when
@@ -220,6 +238,98 @@ far_status_t far_map_stats(far_map_t map, far_map_stats_t* out, far_stream_t str
  * N exceeds it (nothing written).  Synchronises. */
 far_status_t far_map_export(far_map_t map, float* xyz, float* cov6, uint8_t* valid,
                             int64_t capacity, int64_t* n_out, far_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Scan-to-submap odometry over a sequence (Sec. III-A: preprocessing,
+ * registration against the capped submap, insertion of the registered scan
+ * into the submap), with the adaptive threshold of Sec. III-A.2.
+ * ---------------------------------------------------------------------- */
+
+/* Voxel downsampling of a scan (the preprocessing of the runtime breakdown of
+ * Sec. IV-B; the rule is not given and is read as: for every voxel of edge v
+ * keep the first point in input order).  xyz [dev, SoA 3 x n]; out [dev, room
+ * for 3 x n floats, not aliasing xyz] receives the kept points in input order,
+ * SoA with row stride n_out; keep [dev, n, or NULL] their input indices;
+ * n_out [host].  Non-finite points are dropped.  Keys outside [-2^20, 2^20):
+ * FAR_E_INVALID, nothing written.  Synchronises `stream`. */
+far_status_t far_voxel_downsample(const float* xyz, int64_t n, double v, float* out,
+                                  int32_t* keep, int64_t* n_out, far_stream_t stream);
+
+/* Rigid transform of xyz [dev, SoA 3 x n] by T [host]: each coordinate is
+ * ((R_r0 x + R_r1 y) + R_r2 z) + t_r in FP64 without fused multiply-add,
+ * rounded to float, into out [dev, SoA 3 x n] (may alias xyz).  Asynchronous. */
+far_status_t far_transform_points(const float* xyz, int64_t n, const double T[16],
+                                  float* out, far_stream_t stream);
+
+/* Adaptive correspondence threshold tau and Cauchy scale kappa (Sec. III-A.2
+ * adapts both to the motion following Vizzo et al., KISS-ICP; read as its
+ * published rule).  The deviation of an estimate T_est from its motion
+ * prediction T_pred is the largest displacement D = T_pred^-1 T_est causes
+ * within range r_max: 2 r_max sin(theta/2) + |t_D| (theta = rotation angle
+ * of D).  Deviations above min_motion are samples; sigma = their root mean
+ * square (sigma0 before the first); tau = 3 sigma, kappa = sigma / 3.
+ * Host-only state, plain C, no device work. */
+typedef struct {
+  double sigma0, r_max, min_motion;
+  double sse;             /* sum of squared samples */
+  int64_t n_samples;
+} far_threshold_t;
+
+far_status_t far_threshold_init(far_threshold_t* s, double sigma0, double r_max,
+                                double min_motion);
+/* Adds the deviation of T_est [host] from T_pred [host] when above
+ * min_motion; deviation [host, or NULL] receives it. */
+far_status_t far_threshold_update(far_threshold_t* s, const double T_pred[16],
+                                  const double T_est[16], double* deviation);
+far_status_t far_threshold_get(const far_threshold_t* s, double* tau, double* kappa);
+
+typedef struct far_odometry_s* far_odometry_t;   /* opaque; owns scan buffers */
+
+typedef struct {
+  double downsample;      /* voxel edge of the scan downsample, > 0          */
+  double sigma0;          /* threshold sigma before the first sample          */
+  double r_max;           /* range of the deviation model (sensor max range)  */
+  double min_motion;      /* smallest deviation taken as a sample             */
+  int32_t max_iters;      /* Gauss-Newton iterations per scan, 1..64          */
+  double eps;             /* stop when ||delta|| <= eps                       */
+  int32_t precision;      /* far_precision_t                                  */
+} far_odometry_params_t;
+
+typedef struct {
+  int32_t status;         /* align status of the scan (FAR_OK for the first) */
+  int32_t iters;          /* Gauss-Newton iterations run                      */
+  int64_t n_raw;          /* points passed in                                 */
+  int64_t n_down;         /* points after the downsample                      */
+  int64_t n_inserted;     /* points the map accepted                          */
+  int32_t map_full;       /* the map reached its point capacity               */
+  int32_t reserved;
+  double tau, kappa;      /* threshold and Cauchy scale used (0 for the first)*/
+  double deviation;       /* deviation of the estimate from the prediction    */
+  double T_pred[16];      /* motion prediction (the initial guess)            */
+  far_lin_t last;         /* last linearisation of the align                  */
+} far_odometry_stats_t;
+
+/* An odometry over `map` (borrowed; it must outlive the odometry), whose
+ * voxel size and k_cov are used for the scan covariances.  The first scan is
+ * placed at T_first [host]; the second is predicted with the relative motion
+ * v_first [host] (NULL = identity: the inertial prediction of the paper's
+ * filter stands behind it), later ones with constant velocity
+ * T_pred = T_prev (T_prev2^-1 T_prev). */
+far_status_t far_odometry_create(far_map_t map, const far_odometry_params_t* params,
+                                 const double T_first[16], const double v_first[16],
+                                 far_odometry_t* out);
+/* One scan xyz [dev, SoA 3 x n, sensor frame]: downsample; for every scan but
+ * the first, covariances of the downsampled scan, tau and kappa from the
+ * threshold, align from T_pred, and the deviation added to the threshold (a
+ * failed align keeps T_pred and is reported in stats->status); then the
+ * downsampled scan, moved by the estimate, is inserted into the map until the
+ * map is full.  T_out [host] receives the estimate; stats [host, or NULL].
+ * Returns FAR_OK unless an argument, a key range or the HIP runtime fails.
+ * Synchronises `stream`. */
+far_status_t far_odometry_step(far_odometry_t od, const float* xyz, int64_t n,
+                               double T_out[16], far_odometry_stats_t* stats,
+                               far_stream_t stream);
+far_status_t far_odometry_destroy(far_odometry_t od);
 
 /* Instrumentation.  With timing on, every linearisation launch is bracketed
  * by HIP events recorded on the stream it runs on, and the align entry points

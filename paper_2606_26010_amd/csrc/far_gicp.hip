@@ -23,7 +23,9 @@
 namespace far {
 namespace {
 
-constexpr int kTile = 256;     // points per tile = threads per linearisation block
+constexpr int kBlock = 256;    // threads per linearisation block
+constexpr int kPerLane = 1;    // points per lane
+constexpr int kTile = kBlock * kPerLane;   // points per tile
 constexpr int kVals = 29;     // 21 H + 6 b + cost + count
 constexpr int kStride = 32;   // partial row stride (doubles)
 
@@ -96,32 +98,29 @@ __global__ __launch_bounds__(256) void k_init(int32_t S, const double* T, const 
 }
 
 // ---------------------------------------------------------------- reduction
-__device__ inline void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float bp = s - a;
-  e = (a - (s - bp)) + (b - bp);
-}
-
-// Wave-wide sum of one value per lane; FP32 values are combined with TwoSum
-// so the carried error terms make the wave sum nearly exact.
-__device__ inline double wave_sum(float v) {
-  float s = v, c = 0.0f;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    float so = __shfl_xor(s, o, 64);
-    float co = __shfl_xor(c, o, 64);
-    float t, e;
-    two_sum(s, so, t, e);
-    s = t;
-    c = (c + co) + e;
-  }
-  return double(s) + double(c);
+// Wave-wide sum of one value per lane, carried in FP64 (an FP32 per-point
+// term is widened first, which is at least as accurate as a compensated FP32
+// sum and takes one add per level instead of a TwoSum).
+// The four in-row levels use DPP lane swaps (quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror, row_mirror: each pairs a lane with a partner
+// holding the other half of its group), the two cross-row levels shuffles.
+// Partners add the same two values, so every lane ends with the same sum.
+template <int kCtrl>
+__device__ inline double dpp_partner(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += dpp_partner<0xB1>(v);
+  v += dpp_partner<0x4E>(v);
+  v += dpp_partner<0x141>(v);
+  v += dpp_partner<0x140>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
 }
+__device__ inline double wave_sum(float v) { return wave_sum(double(v)); }
 
 // ---------------------------------------------------------------- locality
 // Before the iterations every point is given a locality key (scan id, then
@@ -196,14 +195,22 @@ __global__ __launch_bounds__(256) void k_pack(const float* src, const float* cov
 //   J = [[a]x, -I]: H += w J^T W J (21 upper entries), b += w J^T W d,
 //   cost += rho, count += 1
 template <class Real>
-__device__ inline void gicp_term(double px, double py, double pz, float4 r, float4 ca,
-                                 float4 cb, float4 sB, float2 sC, const double* R, double cx,
-                                 double cy, double cz, double kappa2, Real* acc) {
-  const Real d0 = Real(double(r.x) - px), d1 = Real(double(r.y) - py),
-             d2 = Real(double(r.z) - pz);
-  const Real a0 = Real(px - cx), a1 = Real(py - cy), a2 = Real(pz - cz);
+struct Core {
+  Real W00, W01, W02, W11, W12, W22;   // W = M^-1 (symmetric)
+  Real g0, g1, g2;                     // u = W d
+  Real w, rho;
+  bool both;                           // M carries both covariances
+};
+
+// The part shared by the linearisation and the gradient: M, W = M^-1,
+// u = W d, e2 = d^T u, the Cauchy weight and cost.
+template <class Real>
+__device__ inline Core<Real> gicp_core(Real d0, Real d1, Real d2, float4 ca, float4 cb,
+                                       float4 sB, float2 sC, const double* R, double kappa2) {
+  Core<Real> c;
   Real M00, M01, M02, M11, M12, M22;
-  if (sB.x >= 0.0f && cb.z != 0.0f) {
+  c.both = sB.x >= 0.0f && cb.z != 0.0f;
+  if (c.both) {
     const Real q00 = sB.x, q01 = sB.y, q02 = sB.z, q11 = sB.w, q12 = sC.x, q22 = sC.y;
     const Real r00 = Real(R[0]), r01 = Real(R[1]), r02 = Real(R[2]);
     const Real r10 = Real(R[3]), r11 = Real(R[4]), r12 = Real(R[5]);
@@ -236,15 +243,28 @@ __device__ inline void gicp_term(double px, double py, double pz, float4 r, floa
   const Real A12 = M01 * M02 - M00 * M12;
   const Real A22 = M00 * M11 - M01 * M01;
   const Real inv_det = Real(1) / (M00 * A00 + M01 * A01 + M02 * A02);
-  const Real W00 = A00 * inv_det, W01 = A01 * inv_det, W02 = A02 * inv_det;
-  const Real W11 = A11 * inv_det, W12 = A12 * inv_det, W22 = A22 * inv_det;
-  const Real g0 = W00 * d0 + W01 * d1 + W02 * d2;
-  const Real g1 = W01 * d0 + W11 * d1 + W12 * d2;
-  const Real g2 = W02 * d0 + W12 * d1 + W22 * d2;
-  const Real e2 = d0 * g0 + d1 * g1 + d2 * g2;
+  c.W00 = A00 * inv_det; c.W01 = A01 * inv_det; c.W02 = A02 * inv_det;
+  c.W11 = A11 * inv_det; c.W12 = A12 * inv_det; c.W22 = A22 * inv_det;
+  c.g0 = c.W00 * d0 + c.W01 * d1 + c.W02 * d2;
+  c.g1 = c.W01 * d0 + c.W11 * d1 + c.W12 * d2;
+  c.g2 = c.W02 * d0 + c.W12 * d1 + c.W22 * d2;
+  const Real e2 = d0 * c.g0 + d1 * c.g1 + d2 * c.g2;
   const Real k2 = Real(kappa2);
-  const Real w = k2 / (k2 + e2);
-  const Real rho = Real(0.5) * k2 * log1p(e2 / k2);
+  c.w = k2 / (k2 + e2);
+  c.rho = Real(0.5) * k2 * log1p(e2 / k2);
+  return c;
+}
+
+template <class Real>
+__device__ inline void gicp_term(double px, double py, double pz, float4 r, float4 ca,
+                                 float4 cb, float4 sB, float2 sC, const double* R, double cx,
+                                 double cy, double cz, double kappa2, Real* acc) {
+  const Real d0 = Real(double(r.x) - px), d1 = Real(double(r.y) - py),
+             d2 = Real(double(r.z) - pz);
+  const Real a0 = Real(px - cx), a1 = Real(py - cy), a2 = Real(pz - cz);
+  const Core<Real> c = gicp_core<Real>(d0, d1, d2, ca, cb, sB, sC, R, kappa2);
+  const Real W00 = c.W00, W01 = c.W01, W02 = c.W02, W11 = c.W11, W12 = c.W12, W22 = c.W22;
+  const Real g0 = c.g0, g1 = c.g1, g2 = c.g2, w = c.w, rho = c.rho;
   // Columns of A = [a]x: A0 = (0, a2, -a1), A1 = (-a2, 0, a0), A2 = (a1, -a0, 0);
   // B = W A column by column.  H_rr[p][q] = A_p . B_q, H_rt[p][q] = -B[q][p],
   // H_tt = W; b = (A_p . g, -g).
@@ -275,6 +295,46 @@ __device__ inline void gicp_term(double px, double py, double pz, float4 r, floa
   acc[v++] = Real(1);
 }
 
+// One term of the gradient of the cost (correspondence and Sigma_s fixed),
+// with u = W d and w the Cauchy weight (rho'(e2) = w / 2):
+//   d cost / d t = -w u,   d cost / d R = -w u q^T,  q = s + Sigma_s R^T u
+//   (the Sigma_s part from M = Sigma_r + R Sigma_s R^T; q = s when M = I),
+//   d cost / d s = -w R^T u.
+// acc: the 3x4 gradient of [R | t] row-major, then rho and a count.
+template <class Real>
+__device__ inline void grad_term(double px, double py, double pz, float4 s, float4 r, float4 ca,
+                                 float4 cb, float4 sB, float2 sC, const double* R,
+                                 double kappa2, Real* acc, Real* gs) {
+  const Real d0 = Real(double(r.x) - px), d1 = Real(double(r.y) - py),
+             d2 = Real(double(r.z) - pz);
+  const Core<Real> c = gicp_core<Real>(d0, d1, d2, ca, cb, sB, sC, R, kappa2);
+  const Real u0 = c.g0, u1 = c.g1, u2 = c.g2;
+  // v = R^T u
+  const Real v0 = Real(R[0]) * u0 + Real(R[3]) * u1 + Real(R[6]) * u2;
+  const Real v1 = Real(R[1]) * u0 + Real(R[4]) * u1 + Real(R[7]) * u2;
+  const Real v2 = Real(R[2]) * u0 + Real(R[5]) * u1 + Real(R[8]) * u2;
+  Real q0 = Real(s.x), q1 = Real(s.y), q2 = Real(s.z);
+  if (c.both) {
+    q0 += Real(sB.x) * v0 + Real(sB.y) * v1 + Real(sB.z) * v2;
+    q1 += Real(sB.y) * v0 + Real(sB.w) * v1 + Real(sC.x) * v2;
+    q2 += Real(sB.z) * v0 + Real(sC.x) * v1 + Real(sC.y) * v2;
+  }
+  const Real nw = -c.w;
+  const Real wu[3] = {nw * u0, nw * u1, nw * u2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[4 * a + 0] = wu[a] * q0;
+    acc[4 * a + 1] = wu[a] * q1;
+    acc[4 * a + 2] = wu[a] * q2;
+    acc[4 * a + 3] = wu[a];
+  }
+  acc[12] = c.rho;
+  acc[13] = Real(1);
+  gs[0] = nw * v0;
+  gs[1] = nw * v1;
+  gs[2] = nw * v2;
+}
+
 // ---------------------------------------------------------------- linearise
 // One block of kTile threads per tile of kTile locality-ordered points (one
 // point per lane).  Blocks are dealt to the eight XCDs round-robin; block b
@@ -288,46 +348,45 @@ __device__ inline void gicp_term(double px, double py, double pz, float4 r, floa
 // as a bit mask and visited in lockstep - each lane takes its own next
 // needed neighbour in the same step - so a wave does as many voxel visits as
 // its busiest lane needs, not one per offset any lane needs.
-__device__ inline double lb2_of(const double* gl, const double* gh, int ox, int oy, int oz) {
-  double s2 = 0.0;
-  s2 += ox < 0 ? gl[0] * gl[0] : (ox > 0 ? gh[0] * gh[0] : 0.0);
-  s2 += oy < 0 ? gl[1] * gl[1] : (oy > 0 ? gh[1] * gh[1] : 0.0);
-  s2 += oz < 0 ? gl[2] * gl[2] : (oz > 0 ? gh[2] * gh[2] : 0.0);
-  return s2;
-}
-
+// Exact nearest map point within sqrt(r2) of one lane's point, ranked by
+// (d2, id): the own voxel first, then every neighbour voxel whose
+// conservative lower-bound distance can still beat the current best.  The
+// needed neighbours are kept as a bit mask and visited in lockstep - each
+// lane takes its own next needed neighbour in the same step - so a wave does
+// as many voxel visits as its busiest lane needs, not one per offset that
+// any lane needs.
 __device__ inline void nn_lockstep(const MapView& m, double px, double py, double pz,
                                    int64_t kx, int64_t ky, int64_t kz, double r2,
                                    TopK<1>& top) {
   top.init();
   const double v = m.v, slack = 1e-7 * v;
-  const double gl[3] = {fmax(px - double(kx) * v - slack, 0.0),
-                        fmax(py - double(ky) * v - slack, 0.0),
-                        fmax(pz - double(kz) * v - slack, 0.0)};
-  const double gh[3] = {fmax(double(kx + 1) * v - px - slack, 0.0),
-                        fmax(double(ky + 1) * v - py - slack, 0.0),
-                        fmax(double(kz + 1) * v - pz - slack, 0.0)};
+  double gl2[3], gh2[3];
+  {
+    const double l0 = fmax(px - double(kx) * v - slack, 0.0), h0 = fmax(double(kx + 1) * v - px - slack, 0.0);
+    const double l1 = fmax(py - double(ky) * v - slack, 0.0), h1 = fmax(double(ky + 1) * v - py - slack, 0.0);
+    const double l2 = fmax(pz - double(kz) * v - slack, 0.0), h2 = fmax(double(kz + 1) * v - pz - slack, 0.0);
+    gl2[0] = l0 * l0; gh2[0] = h0 * h0;
+    gl2[1] = l1 * l1; gh2[1] = h1 * h1;
+    gl2[2] = l2 * l2; gh2[2] = h2 * h2;
+  }
+  Query q = make_query(px, py, pz, r2);
   int32_t cnt;
   int32_t vox = map_find(m, kx, ky, kz, &cnt);
-  if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, px, py, pz, r2, top);
+  if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
   uint32_t need = 0;
   {
     const double bnd = fmin(r2, top.bound());
 #pragma unroll
-    for (int q = 1; q < 27; ++q) {
-      const int code = kNbrOrder[q];
-      if (lb2_of(gl, gh, code / 9 - 1, (code / 3) % 3 - 1, code % 3 - 1) <= bnd)
-        need |= 1u << q;
-    }
+    for (int rank = 1; rank < 27; ++rank)
+      if (lb2_of(gl2, gh2, nbr_code(rank)) <= bnd) need |= 1u << rank;
   }
   while (need) {
-    const int q = __builtin_ctz(need);
+    const int rank = __builtin_ctz(need);
     need &= need - 1;
-    const int code = kNbrOrder[q];
-    const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
-    if (lb2_of(gl, gh, ox, oy, oz) > fmin(r2, top.bound())) continue;
-    vox = map_find(m, kx + ox, ky + oy, kz + oz, &cnt);
-    if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, px, py, pz, r2, top);
+    const int code = nbr_code(rank);
+    if (lb2_of(gl2, gh2, code) > fmin(r2, top.bound())) continue;
+    vox = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
+    if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
   }
 }
 
@@ -341,16 +400,20 @@ __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool p
   return true;
 }
 
-template <class Real>
-__global__ __launch_bounds__(kTile) void k_linearize(
+// kGrad selects the gradient of the cost instead of H, b: 14 sums (the 3x4
+// gradient of [R | t], cost, count) and, when grad_src is given, each
+// point's source gradient written SoA at its original index (n_src apart).
+template <class Real, bool kGrad>
+__global__ __launch_bounds__(kBlock) void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
     const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
-    int32_t* __restrict__ corr) {
-  constexpr int kWaves = kTile / 64;
-  __shared__ double red[kWaves][kVals];
+    int32_t* __restrict__ corr, float* __restrict__ grad_src, int64_t n_src) {
+  constexpr int kWaves = kBlock / 64;
+  constexpr int kNV = kGrad ? 14 : kVals;
+  __shared__ double red[kWaves][kNV];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t chunk = (n_tiles + 7) >> 3;
   const int64_t t = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
@@ -360,47 +423,76 @@ __global__ __launch_bounds__(kTile) void k_linearize(
   const double* Ts = T + 16 * int64_t(s);
   const double R[9] = {Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]};
   const double tx = Ts[3], ty = Ts[7], tz = Ts[11];
-  const int64_t i = int64_t(tile_lo[t]) + tid;
-  const bool in_tile = i < int64_t(tile_hi[t]);
+  const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
+  const int64_t lo = tile_lo[t], hi = tile_hi[t];
 
-  Real acc[kVals];
+  Real acc[kNV];
 #pragma unroll
-  for (int q = 0; q < kVals; ++q) acc[q] = Real(0);
-  int32_t match = -1;
-  float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (in_tile) {
-    a = pA[i];
-    if (isfinite(a.x) && isfinite(a.y) && isfinite(a.z)) {
-      const double sx = a.x, sy = a.y, sz = a.z;
-      const double px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
-      const double py = ((R[3] * sx + R[4] * sy) + R[5] * sz) + ty;
-      const double pz = ((R[6] * sx + R[7] * sy) + R[8] * sz) + tz;
-      int64_t kx, ky, kz;
-      if (voxel_index_fast(px, m.v, prm.inv_v, prm.v_pow2, &kx) &&
-          voxel_index_fast(py, m.v, prm.inv_v, prm.v_pow2, &ky) &&
-          voxel_index_fast(pz, m.v, prm.inv_v, prm.v_pow2, &kz)) {
-        TopK<1> top;
-        nn_lockstep(m, px, py, pz, kx, ky, kz, prm.r2, top);
-        if (top.pos[0] >= 0) {
-          match = top.id[0];
-          const float4 r = m.vox_pts[top.pos[0]];
-          const float4 ca = m.cov[2 * int64_t(match)];
-          const float4 cb = m.cov[2 * int64_t(match) + 1];
-          gicp_term<Real>(px, py, pz, r, ca, cb, pB[i], pC[i], R, ctr[3 * s], ctr[3 * s + 1],
-                          ctr[3 * s + 2], prm.kappa2, acc);
-        }
-      }
+  for (int q = 0; q < kNV; ++q) acc[q] = Real(0);
+#pragma unroll
+  for (int u = 0; u < kPerLane; ++u) {
+    const int64_t i = lo + int64_t(u) * kBlock + tid;
+    const bool in_tile = i < hi;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 sB = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 sC = make_float2(0.f, 0.f);
+    if (in_tile) {
+      a = pA[i];
+      sB = pB[i];
+      sC = pC[i];
     }
-    if (corr) corr[__float_as_int(a.w)] = match;
+    // p = R s + t in FP64 (FMA-free), and its map voxel key
+    bool have = in_tile && isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+    double px = 0.0, py = 0.0, pz = 0.0;
+    int64_t kx = 0, ky = 0, kz = 0;
+    if (have) {
+      const double sx = a.x, sy = a.y, sz = a.z;
+      px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
+      py = ((R[3] * sx + R[4] * sy) + R[5] * sz) + ty;
+      pz = ((R[6] * sx + R[7] * sy) + R[8] * sz) + tz;
+      have = voxel_index_fast(px, m.v, prm.inv_v, prm.v_pow2, &kx) &&
+             voxel_index_fast(py, m.v, prm.inv_v, prm.v_pow2, &ky) &&
+             voxel_index_fast(pz, m.v, prm.inv_v, prm.v_pow2, &kz);
+    }
+    TopK<1> top;
+    top.init();
+    if (have) {
+      if (m.fine_ok)
+        knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
+                     [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
+                       return fine_find(m, a0, a1, a2, n);
+                     },
+                     top);
+      else nn_lockstep(m, px, py, pz, kx, ky, kz, prm.r2, top);
+    }
+    int32_t match = -1;
+    Real gs[3] = {Real(0), Real(0), Real(0)};
+    if (have && top.pos[0] >= 0) {
+      match = top.id[0];
+      const float4 r = m.fine_ok ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
+      const float4 ca = m.cov[2 * int64_t(match)];
+      const float4 cb = m.cov[2 * int64_t(match) + 1];
+      if constexpr (kGrad)
+        grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, R, prm.kappa2, acc, gs);
+      else
+        gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, R, cx, cy, cz, prm.kappa2, acc);
+    }
+    if (corr && in_tile) corr[__float_as_int(a.w)] = match;
+    if (kGrad && grad_src && in_tile) {
+      const int64_t o = __float_as_int(a.w);
+      grad_src[o] = float(gs[0]);
+      grad_src[n_src + o] = float(gs[1]);
+      grad_src[2 * n_src + o] = float(gs[2]);
+    }
   }
-  // wave sums (compensated in FP32), then the block's waves in FP64
+  // wave sums in FP64, then the block's waves
 #pragma unroll
-  for (int q = 0; q < kVals; ++q) {
+  for (int q = 0; q < kNV; ++q) {
     const double sv = wave_sum(acc[q]);
     if (lane == 0) red[wave][q] = sv;
   }
   __syncthreads();
-  if (tid < kVals) {
+  if (tid < kNV) {
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) sum += red[w][tid];
@@ -556,6 +648,27 @@ __global__ __launch_bounds__(256) void k_reduce_solve(int32_t S, const int32_t* 
   }
 }
 
+// Sum of the 14 gradient partials of one scan's tiles in tile order (eight
+// interleaved groups, then the groups in order, as k_reduce_solve).
+__global__ __launch_bounds__(256) void k_reduce_grad(const int32_t* begin,
+                                                     const double* partial, double* out) {
+  __shared__ double part[8][14];
+  const int g = threadIdx.x >> 5, v = threadIdx.x & 31;
+  if (v < 14) {
+    double acc = 0.0;
+    const int32_t t1 = begin[1];
+    for (int32_t t = begin[0] + g; t < t1; t += 8) acc += partial[int64_t(t) * kStride + v];
+    part[g][v] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < 14) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += part[q][threadIdx.x];
+    out[threadIdx.x] = acc;
+  }
+}
+
 }  // namespace
 
 // Kernel timing instrumentation (far_timing_enable / far_timing_read).
@@ -589,6 +702,7 @@ struct AlignWS {
   double* T = nullptr;          // single-scan path
   double* cfix = nullptr;       // fixed centre (linearize)
   far_align_stats_t* stats = nullptr;   // single-scan path
+  double* gsum = nullptr;       // gradient sums
   // locality-ordered packed source and its sort buffers
   float4* pA = nullptr;
   float4* pB = nullptr;
@@ -613,7 +727,7 @@ void free_ws(AlignWS* w) {
   if (!w) return;
   if (w->exec) (void)hipGraphExecDestroy(w->exec);
   void* ptrs[] = {w->tile_scan, w->tile_lo, w->tile_hi, w->begin, w->bad, w->done, w->ctr,
-                  w->partial, w->offsets, w->T, w->cfix, w->stats, w->pA, w->pB, w->pC,
+                  w->partial, w->offsets, w->T, w->cfix, w->stats, w->gsum, w->pA, w->pB, w->pC,
                   w->okeys, w->okeys_alt, w->ovals, w->ovals_alt, w->arena};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -657,6 +771,7 @@ far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, int64_t n, Al
   FAR_HIP(hipMalloc(&w->T, 16 * sizeof(double)));
   FAR_HIP(hipMalloc(&w->cfix, 3 * sizeof(double)));
   FAR_HIP(hipMalloc(&w->stats, sizeof(far_align_stats_t)));
+  FAR_HIP(hipMalloc(&w->gsum, kStride * sizeof(double)));
   FAR_HIP(hipMalloc(&w->pA, nc * sizeof(float4)));
   FAR_HIP(hipMalloc(&w->pB, nc * sizeof(float4)));
   FAR_HIP(hipMalloc(&w->pC, nc * sizeof(float2)));
@@ -683,6 +798,8 @@ struct Job {
   int32_t* corr;
   Params prm;
   int32_t precision;
+  double* gsum = nullptr;      // non-null: one gradient pass (single scan), sums here
+  float* grad_src = nullptr;   // gradient pass: per-point source gradient or null
 };
 
 // Enqueue the whole job (init, locality packing, iterations) on st.  Nothing
@@ -713,6 +830,20 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
     FAR_HIP(hipGetLastError());
   }
   const int64_t grid = ((max_tiles + 7) / 8) * 8;   // one block per tile
+  if (j.gsum) {
+    if (j.precision == FAR_PREC_FP64)
+      k_linearize<double, true><<<unsigned(grid), kBlock, 0, st>>>(
+          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
+          w->ctr, w->done, j.prm, w->partial, j.corr, j.grad_src, j.n_total);
+    else
+      k_linearize<float, true><<<unsigned(grid), kBlock, 0, st>>>(
+          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
+          w->ctr, w->done, j.prm, w->partial, j.corr, j.grad_src, j.n_total);
+    FAR_HIP(hipGetLastError());
+    k_reduce_grad<<<1, 256, 0, st>>>(w->begin, w->partial, j.gsum);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  }
   const int iters = j.c_fixed ? 1 : j.prm.max_iters;
   const bool timed = timing().on;
   for (int it = 0; it < iters; ++it) {
@@ -723,13 +854,13 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
       FAR_HIP(hipEventRecord(ev0, st));
     }
     if (j.precision == FAR_PREC_FP64)
-      k_linearize<double><<<unsigned(grid), kTile, 0, st>>>(
+      k_linearize<double, false><<<unsigned(grid), kBlock, 0, st>>>(
           mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
-          w->ctr, w->done, j.prm, w->partial, j.corr);
+          w->ctr, w->done, j.prm, w->partial, j.corr, nullptr, 0);
     else
-      k_linearize<float><<<unsigned(grid), kTile, 0, st>>>(
+      k_linearize<float, false><<<unsigned(grid), kBlock, 0, st>>>(
           mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
-          w->ctr, w->done, j.prm, w->partial, j.corr);
+          w->ctr, w->done, j.prm, w->partial, j.corr, nullptr, 0);
     FAR_HIP(hipGetLastError());
     if (timed) {
       FAR_HIP(hipEventRecord(ev1, st));
@@ -748,10 +879,13 @@ far_status_t run_job(far_map_s* m, const Job& j, hipStream_t st, bool use_graph)
   const int64_t max_tiles = (j.n_total + kTile - 1) / kTile + j.S;
   AlignWS* w = nullptr;
   FAR_TRY(ensure_ws(m, j.S, max_tiles, j.n_total, &w));
+  FAR_TRY(fine_build(m, st));  // the fine index of the current map (stream-ordered)
   (void)device_cu_count();   // query the device outside any capture
   if (!use_graph || st == nullptr || timing().on) return enqueue(m, w, j, max_tiles, st);
+  // the captured map view holds the fine-index flag: a graph captured with a
+  // different flag must not be replayed
   const void* key[10] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
-                         m->vox_pts, nullptr};
+                         m->vox_pts, reinterpret_cast<const void*>(intptr_t(m->fine_ok))};
   bool same = w->exec && w->key_n == j.n_total && w->key_S == j.S &&
               w->key_prec == j.precision && memcmp(w->key, key, sizeof(key)) == 0 &&
               memcmp(&w->key_prm, &j.prm, sizeof(Params)) == 0;
@@ -849,6 +983,57 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
   FAR_HIP(hipMemcpyAsync(&hs, w->stats, sizeof(hs), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipStreamSynchronize(st));
   lin_from_stats(hs, out);
+  return FAR_OK;
+}
+
+far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
+                               const uint8_t* valid, int64_t n, const double T[16], double tau,
+                               double kappa, const double c[3], int32_t precision,
+                               double grad_T[12], double grad_twist[6], float* grad_src,
+                               double* cost, int64_t* n_inliers, far_stream_t stream) {
+  if (!m || !T || !grad_T || !grad_twist || n < 0 || n >= (int64_t(1) << 31) ||
+      !(tau > 0.0) || !(kappa > 0.0) || (n > 0 && (!src || !cov6 || !valid)) ||
+      (precision != FAR_PREC_FP32 && precision != FAR_PREC_FP64)) {
+    set_error("far_gicp_gradient: invalid argument");
+    return FAR_E_INVALID;
+  }
+  for (int q = 0; q < 12; ++q) grad_T[q] = 0.0;
+  for (int q = 0; q < 6; ++q) grad_twist[q] = 0.0;
+  if (cost) *cost = 0.0;
+  if (n_inliers) *n_inliers = 0;
+  if (n == 0) return FAR_OK;
+  hipStream_t st = S(stream);
+  AlignWS* w = nullptr;
+  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, n, &w));
+  int64_t offs[2] = {0, n};
+  const double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
+  FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
+  FAR_HIP(hipMemcpyAsync(w->T, T, 16 * sizeof(double), hipMemcpyHostToDevice, st));
+  FAR_HIP(hipMemcpyAsync(w->cfix, cc, sizeof(cc), hipMemcpyHostToDevice, st));
+  Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, nullptr,
+        make_params(m, tau, kappa, 0.0, 1, 0), precision};
+  j.gsum = w->gsum;
+  j.grad_src = grad_src;
+  FAR_TRY(run_job(m, j, st, false));
+  double g[14];
+  FAR_HIP(hipMemcpyAsync(g, w->gsum, sizeof(g), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  for (int q = 0; q < 12; ++q) grad_T[q] = g[q];
+  // twist about c: dR = [w]x R, dt = [w]x (t - c) + v, so the rotation part
+  // is the axial vector of A - A^T with A = R G_R^T + (t - c) G_t^T
+  double A[9];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) {
+      double x = 0.0;
+      for (int l = 0; l < 3; ++l) x += T[4 * r + l] * g[4 * q + l];
+      A[3 * r + q] = x + (T[4 * r + 3] - cc[r]) * g[4 * q + 3];
+    }
+  grad_twist[0] = A[5] - A[7];
+  grad_twist[1] = A[6] - A[2];
+  grad_twist[2] = A[1] - A[3];
+  for (int q = 0; q < 3; ++q) grad_twist[3 + q] = g[4 * q + 3];
+  if (cost) *cost = g[12];
+  if (n_inliers) *n_inliers = int64_t(g[13]);
   return FAR_OK;
 }
 

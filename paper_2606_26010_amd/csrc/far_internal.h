@@ -77,7 +77,34 @@ struct MapView {
   int32_t nmax;
   int32_t log2_slots;
   uint32_t slot_mask;
+  // fine search index (cells of v/2): points sorted by cell, cell -> run
+  const float4* fine_pts;     // [n_points]: x, y, z, id bits
+  const Slot* fine_slots;     // key, vox = run start, aux = run length
+  uint32_t fine_mask;
+  int32_t fine_log2;
+  int32_t fine_ok;            // index built for the current map contents
+  double fc;                  // fine cell edge (v / 2, a power of two)
+  double inv_fc;
 };
+
+// Run [start, start + *cnt) of fine cell (kx, ky, kz) in fine_pts, or -1.
+__device__ inline int32_t fine_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz,
+                                    int32_t* cnt) {
+  *cnt = 0;
+  if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
+  const uint64_t key = pack_key(kx, ky, kz);
+  uint32_t s = voxel_hash(kx, ky, kz, m.fine_log2);
+  for (uint32_t probe = 0; probe <= m.fine_mask; ++probe) {
+    const Slot sl = m.fine_slots[s];
+    if (sl.key == key) {
+      *cnt = sl.aux;
+      return sl.vox;
+    }
+    if (sl.key == kEmptyKey) return -1;
+    s = (s + 1) & m.fine_mask;
+  }
+  return -1;
+}
 
 // Voxel index of key (kx, ky, kz), or -1; *cnt receives its point count (0
 // when absent).
@@ -88,7 +115,7 @@ __device__ inline int32_t map_find(const MapView& m, int64_t kx, int64_t ky, int
   uint64_t key = pack_key(kx, ky, kz);
   uint32_t s = voxel_hash(kx, ky, kz, m.log2_slots);
   for (uint32_t probe = 0; probe <= m.slot_mask; ++probe) {
-    Slot sl = m.slots[s];
+    const Slot sl = m.slots[s];
     if (sl.key == key) {
       *cnt = sl.aux;
       return sl.vox;
@@ -229,6 +256,12 @@ struct far_map_s {
   float* pt_xyz = nullptr;
   int32_t* pt_loc = nullptr;
   int32_t* vox_slot = nullptr;
+  // fine search index, rebuilt lazily after the map changes
+  float4* fine_pts = nullptr;
+  far::Slot* fine_slots = nullptr;
+  int64_t fine_nslots = 0;
+  int fine_log2 = 0;
+  bool fine_ok = false;
   int64_t n_points = 0;
   int64_t n_voxels = 0;
   int device = 0;
@@ -246,6 +279,20 @@ struct far_map_s {
     m.nmax = p.max_pts_per_voxel;
     m.log2_slots = log2_slots;
     m.slot_mask = uint32_t(slots - 1);
+    m.fine_pts = fine_pts;
+    m.fine_slots = fine_slots;
+    m.fine_mask = uint32_t(fine_nslots - 1);
+    m.fine_log2 = fine_log2;
+    m.fine_ok = fine_ok ? 1 : 0;
+    m.fc = 0.5 * p.voxel_size;
+    m.inv_fc = 1.0 / m.fc;
     return m;
   }
 };
+
+namespace far {
+// Build the fine search index of the map if it is stale (stream-ordered;
+// no-op when the voxel edge is not a power of two or a point lies outside
+// the fine key range, in which case searches use the voxels).
+far_status_t fine_build(far_map_s* m, hipStream_t st);
+}  // namespace far

@@ -64,12 +64,46 @@ __device__ inline bool voxel_index(double x, double v, int64_t* k) {
   return true;
 }
 
+// A query with an FP32 screen.  Every candidate's squared distance is first
+// formed in FP32 from the query rounded to FP32; only candidates whose FP32
+// value is within the screen bound get the exact FP64 evaluation that decides.
+//
+// The screen is conservative: with D = q - fl32(p) exactly, |D - d| <= delta,
+// delta = 2^-24 (|px| + |py| + |pz|) (rounding of p to FP32), and the FP32
+// subtraction and fused sum of squares add at most a factor (1 + 2^-24)^5.
+// So any candidate with exact d2 <= B has FP32 value
+// <= (sqrt(B) + delta)^2 (1 + 2^-24)^5, which screen_bound over-estimates
+// (margin m = 2 delta, then a factor 1 + 2^-19 before rounding to FP32).
+struct Query {
+  double x, y, z;
+  float fx, fy, fz;
+  double m;
+  float bound_f;
+};
+
+__device__ inline float screen_bound(double B, double m) {
+  const double s = sqrt(B) + m;
+  return float(s * s * (1.0 + 0x1p-19));
+}
+
+__device__ inline Query make_query(double x, double y, double z, double r2) {
+  Query q;
+  q.x = x;
+  q.y = y;
+  q.z = z;
+  q.fx = float(x);
+  q.fy = float(y);
+  q.fz = float(z);
+  q.m = 0x1p-23 * (fabs(x) + fabs(y) + fabs(z)) + 1e-30;
+  q.bound_f = screen_bound(r2, q.m);
+  return q;
+}
+
 // Rank the cnt points stored at pts[base ...] against q.  Loads are issued
 // four at a time so that they overlap instead of waiting one by one.
 template <int K>
 __device__ inline void scan_voxel_points(const float4* pts, int32_t base, int32_t cnt,
-                                         double qx, double qy, double qz, double r2,
-                                         TopK<K>& top) {
+                                         Query& q, double r2, TopK<K>& top) {
   for (int32_t j = 0; j < cnt; j += 4) {
     float4 p[4];
 #pragma unroll
@@ -78,8 +112,16 @@ __device__ inline void scan_voxel_points(const float4* pts, int32_t base, int32_
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (j + u < cnt) {
-        double d = dist2(double(p[u].x), double(p[u].y), double(p[u].z), qx, qy, qz);
-        if (d <= r2) top.push(d, __float_as_int(p[u].w), base + j + u);
+        const float dx = p[u].x - q.fx, dy = p[u].y - q.fy, dz = p[u].z - q.fz;
+        const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        if (d2f <= q.bound_f) {
+          const double d = dist2(double(p[u].x), double(p[u].y), double(p[u].z), q.x, q.y, q.z);
+          const int32_t id = __float_as_int(p[u].w);
+          if (d <= r2 && rank_less(d, id, top.d[K - 1], top.id[K - 1])) {
+            top.push(d, id, base + j + u);
+            q.bound_f = screen_bound(fmin(r2, top.bound()), q.m);
+          }
+        }
       }
   }
 }
@@ -95,6 +137,7 @@ __device__ inline void map_knn_query(const MapView& m, double qx, double qy, dou
   if (!voxel_index(qx, m.v, &kx) || !voxel_index(qy, m.v, &ky) ||
       !voxel_index(qz, m.v, &kz))
     return;
+  Query q = make_query(qx, qy, qz, r2);
   for (int t = 0; t < 27; ++t) {
     int code = kNbrOrder[t];
     int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
@@ -103,8 +146,100 @@ __device__ inline void map_knn_query(const MapView& m, double qx, double qy, dou
     int32_t cnt;
     int32_t vox = map_find(m, kx + ox, ky + oy, kz + oz, &cnt);
     if (vox < 0) continue;
-    scan_voxel_points<K>(m.vox_pts, vox * m.nmax, cnt, qx, qy, qz, r2, top);
+    scan_voxel_points<K>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
   }
+}
+
+// Neighbour offsets in visiting order (faces, edges, corners), packed five
+// bits per entry as code = (ox+1)*9 + (oy+1)*3 + (oz+1): ranks 1-12, 13-24,
+// 25-26 in three words.
+__device__ inline int nbr_code(int rank) {
+  constexpr uint64_t w0 = (uint64_t(4) << 0) | (uint64_t(22) << 5) | (uint64_t(10) << 10) |
+                          (uint64_t(16) << 15) | (uint64_t(12) << 20) | (uint64_t(14) << 25) |
+                          (uint64_t(1) << 30) | (uint64_t(3) << 35) | (uint64_t(5) << 40) |
+                          (uint64_t(7) << 45) | (uint64_t(9) << 50) | (uint64_t(11) << 55);
+  constexpr uint64_t w1 = (uint64_t(15) << 0) | (uint64_t(17) << 5) | (uint64_t(19) << 10) |
+                          (uint64_t(21) << 15) | (uint64_t(23) << 20) | (uint64_t(25) << 25) |
+                          (uint64_t(0) << 30) | (uint64_t(2) << 35) | (uint64_t(6) << 40) |
+                          (uint64_t(8) << 45) | (uint64_t(18) << 50) | (uint64_t(20) << 55);
+  constexpr uint64_t w2 = (uint64_t(24) << 0) | (uint64_t(26) << 5);
+  const int r = rank - 1;
+  const uint64_t w = r < 12 ? w0 : (r < 24 ? w1 : w2);
+  const int sh = 5 * (r < 12 ? r : (r < 24 ? r - 12 : r - 24));
+  return int((w >> sh) & 31u);
+}
+
+__device__ inline double lb2_of(const double* gl2, const double* gh2, int code) {
+  const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+  return (ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0)) + (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0)) +
+         (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0));
+}
+
+// Exact K nearest points within sqrt(r2) of p over a grid of cells of edge
+// c, with r <= range * c (range 1 or 2): every such point lies within
+// `range` cells per axis of p's own cell.  Visits the own cell, then the 26
+// cells around it - each lane keeps the ones it still needs (lower bound <=
+// current K-th best) as a bit mask and takes its own next one in lockstep -
+// then, when range is 2 and the K-th best can still be beaten there, the 98
+// cells two away.  find(kx, ky, kz, &cnt) gives the start of the cell's run
+// in pts (or -1) and its length.
+template <int K, class Find>
+__device__ inline void knn_cells(double px, double py, double pz, double c, double inv_c,
+                                 bool pow2, bool range2, double r2, const float4* pts,
+                                 Find find, TopK<K>& top) {
+  top.init();
+  const double fx = floor(pow2 ? px * inv_c : px / c), fy = floor(pow2 ? py * inv_c : py / c),
+               fz = floor(pow2 ? pz * inv_c : pz / c);
+  const double lim = double(kKeyBias);
+  if (!(fx >= -lim && fx < lim && fy >= -lim && fy < lim && fz >= -lim && fz < lim)) return;
+  const int64_t kx = int64_t(fx), ky = int64_t(fy), kz = int64_t(fz);
+  const double slack = 1e-7 * c;
+  double gl[3], gh[3], gl2[3], gh2[3];
+  gl[0] = fmax(px - fx * c - slack, 0.0); gh[0] = fmax((fx + 1.0) * c - px - slack, 0.0);
+  gl[1] = fmax(py - fy * c - slack, 0.0); gh[1] = fmax((fy + 1.0) * c - py - slack, 0.0);
+  gl[2] = fmax(pz - fz * c - slack, 0.0); gh[2] = fmax((fz + 1.0) * c - pz - slack, 0.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gl2[a] = gl[a] * gl[a];
+    gh2[a] = gh[a] * gh[a];
+  }
+  Query q = make_query(px, py, pz, r2);
+  int32_t cnt;
+  int32_t st = find(kx, ky, kz, &cnt);
+  if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+  uint32_t need = 0;
+  {
+    const double bnd = fmin(r2, top.bound());
+#pragma unroll
+    for (int rank = 1; rank < 27; ++rank)
+      if (lb2_of(gl2, gh2, nbr_code(rank)) <= bnd) need |= 1u << rank;
+  }
+  while (need) {
+    const int rank = __builtin_ctz(need);
+    need &= need - 1;
+    const int code = nbr_code(rank);
+    if (lb2_of(gl2, gh2, code) > fmin(r2, top.bound())) continue;
+    st = find(kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
+    if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+  }
+  if (!range2) return;
+  // cells two away along some axis lie at least one cell beyond a face
+  const double far_lb2 =
+      fmin(fmin(fmin((gl[0] + c) * (gl[0] + c), (gh[0] + c) * (gh[0] + c)),
+                fmin((gl[1] + c) * (gl[1] + c), (gh[1] + c) * (gh[1] + c))),
+           fmin((gl[2] + c) * (gl[2] + c), (gh[2] + c) * (gh[2] + c)));
+  if (far_lb2 > fmin(r2, top.bound())) return;
+  for (int ox = -2; ox <= 2; ++ox)
+    for (int oy = -2; oy <= 2; ++oy)
+      for (int oz = -2; oz <= 2; ++oz) {
+        if (ox > -2 && ox < 2 && oy > -2 && oy < 2 && oz > -2 && oz < 2) continue;
+        const double g0 = ox < 0 ? gl[0] + (ox == -2 ? c : 0.0) : (ox > 0 ? gh[0] + (ox == 2 ? c : 0.0) : 0.0);
+        const double g1 = oy < 0 ? gl[1] + (oy == -2 ? c : 0.0) : (oy > 0 ? gh[1] + (oy == 2 ? c : 0.0) : 0.0);
+        const double g2 = oz < 0 ? gl[2] + (oz == -2 ? c : 0.0) : (oz > 0 ? gh[2] + (oz == 2 ? c : 0.0) : 0.0);
+        if ((g0 * g0 + g1 * g1) + g2 * g2 > fmin(r2, top.bound())) continue;
+        st = find(kx + ox, ky + oy, kz + oz, &cnt);
+        if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+      }
 }
 
 // Regularised covariance (Eq. 1) of the first k entries of a neighbour list.

@@ -92,6 +92,52 @@ __global__ __launch_bounds__(kT) void k_heads(const uint64_t* keys, int64_t n,
   head[j] = (k != kEmptyKey && (j == 0 || keys[j - 1] != k)) ? 1u : 0u;
 }
 
+// ---------------------------------------------------------------- downsample
+// Keep flags of the first point (in input order) of every voxel: after the
+// stable sort every input index appears once in vals and a run's head holds
+// its smallest index, so writing head[j] to flag[vals[j]] sets every flag.
+__global__ __launch_bounds__(kT) void k_ds_flags(const uint32_t* vals, const uint32_t* head,
+                                                 int64_t n, uint32_t* flag) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  flag[vals[j]] = head[j];
+}
+
+// Compaction of the kept points in input order, SoA with row stride n_out.
+__global__ __launch_bounds__(kT) void k_ds_scatter(const float* xyz, int64_t n,
+                                                   const uint32_t* flag, const uint32_t* pos,
+                                                   int64_t n_out, float* out, int32_t* keep) {
+  int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  int64_t o = pos[i];
+  out[o] = xyz[i];
+  out[n_out + o] = xyz[n + i];
+  out[2 * n_out + o] = xyz[2 * n + i];
+  if (keep) keep[o] = int32_t(i);
+}
+
+// ---------------------------------------------------------------- transform
+struct Rigid {
+  double r[12];  // rows of [R | t]
+};
+
+// out = R s + t per point, FP64 in the order ((R_r0 x + R_r1 y) + R_r2 z) + t_r
+// (no contraction: the file is built with -ffp-contract=off), rounded to float.
+// Every thread reads its point before writing it, so out may alias xyz.
+__global__ __launch_bounds__(kT) void k_transform(const float* xyz, int64_t n, Rigid T,
+                                                  float* out) {
+  int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+  float o[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    o[r] = float(((T.r[4 * r] * x + T.r[4 * r + 1] * y) + T.r[4 * r + 2] * z) + T.r[4 * r + 3]);
+  out[i] = o[0];
+  out[n + i] = o[1];
+  out[2 * n + i] = o[2];
+}
+
 // Segment bounds: seg_start[s] and seg_end[s] for every run s.
 __global__ __launch_bounds__(kT) void k_seg_bounds(const uint64_t* keys, int64_t n,
                                                    const uint32_t* head,
@@ -295,7 +341,10 @@ struct GridView {
   const uint32_t* sid;        // scan id per sorted position (NULL: one scan)
   const uint32_t* seg_start;
   const uint32_t* seg_end;
-  double v;
+  double v;          // neighbourhood radius (the voxel edge)
+  double c;          // grid cell edge (v / 2 when v is a power of two, else v)
+  double inv_c;
+  int32_t pow2;
   int32_t log2_slots;
   uint32_t slot_mask;
 };
@@ -311,7 +360,7 @@ __device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, i
   uint64_t key = pack_key(kx, ky, kz);
   uint32_t s = grid_hash(kx, ky, kz, sid, g.log2_slots);
   for (uint32_t probe = 0; probe <= g.slot_mask; ++probe) {
-    Slot sl = g.slots[s];
+    const Slot sl = g.slots[s];
     if (sl.key == key && uint32_t(sl.aux) == sid) return sl.vox;
     if (sl.key == kEmptyKey) return -1;
     s = (s + 1) & g.slot_mask;
@@ -415,26 +464,18 @@ __global__ __launch_bounds__(kT) void k_grid_cov(GridView g, int64_t n, int32_t 
   const uint32_t sc = g.sid ? g.sid[j] : 0u;
   float4 me = g.sorted[j];
   double qx = me.x, qy = me.y, qz = me.z;
-  double r2 = g.v * g.v;
   TopK<K> top;
-  top.init();
-  int64_t kx, ky, kz;
-  voxel_index(qx, g.v, &kx);
-  voxel_index(qy, g.v, &ky);
-  voxel_index(qz, g.v, &kz);
-  for (int t = 0; t < 27; ++t) {
-    int code = kNbrOrder[t];
-    int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
-    double bnd = fmin(r2, top.bound());
-    if (voxel_lb2(qx, qy, qz, kx, ky, kz, ox, oy, oz, g.v) > bnd) continue;
-    int32_t s = grid_find(g, kx + ox, ky + oy, kz + oz, sc);
-    if (s < 0) continue;
-    for (uint32_t c = g.seg_start[s]; c < g.seg_end[s]; ++c) {
-      float4 p = g.sorted[c];
-      double d = dist2(double(p.x), double(p.y), double(p.z), qx, qy, qz);
-      if (d <= r2) top.push(d, __float_as_int(p.w), int32_t(c));
-    }
-  }
+  knn_cells<K>(qx, qy, qz, g.c, g.inv_c, g.pow2 != 0, g.c < g.v, g.v * g.v, g.sorted,
+               [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
+                 const int32_t s = grid_find(g, a0, a1, a2, sc);
+                 if (s < 0) {
+                   *n = 0;
+                   return int32_t(-1);
+                 }
+                 *n = int32_t(g.seg_end[s] - g.seg_start[s]);
+                 return int32_t(g.seg_start[s]);
+               },
+               top);
   double c6[6] = {0, 0, 0, 0, 0, 0};
   bool ok = top.found() >= k;
   if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
@@ -478,6 +519,57 @@ __global__ __launch_bounds__(kT) void k_export(const float4* cov, const float* p
     cov6[5 * N + i] = b.y;
   }
   if (valid) valid[i] = b.z != 0.0f ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- fine index
+// Fine cell key of every map point (cells of v/2, exact: v is a power of
+// two); a key outside the 21-bit range is counted and disables the index.
+__global__ __launch_bounds__(kT) void k_fine_keys(const float* pt_xyz, int64_t point_cap,
+                                                  int64_t n, double inv_fc, uint64_t* keys,
+                                                  uint32_t* vals, uint32_t* counters) {
+  int64_t id = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (id >= n) return;
+  const double x = pt_xyz[id], y = pt_xyz[point_cap + id], z = pt_xyz[2 * point_cap + id];
+  const double fx = floor(x * inv_fc), fy = floor(y * inv_fc), fz = floor(z * inv_fc);
+  const double lim = double(kKeyBias);
+  uint64_t key = kEmptyKey;
+  if (fx >= -lim && fx < lim && fy >= -lim && fy < lim && fz >= -lim && fz < lim)
+    key = pack_key(int64_t(fx), int64_t(fy), int64_t(fz));
+  else
+    atomicAdd(&counters[1], 1u);
+  keys[id] = key;
+  vals[id] = uint32_t(id);
+}
+
+__global__ __launch_bounds__(kT) void k_fine_fill(const float* pt_xyz, int64_t point_cap,
+                                                  int64_t n, const uint32_t* vals,
+                                                  float4* fine_pts) {
+  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t id = vals[j];
+  fine_pts[j] = make_float4(pt_xyz[id], pt_xyz[point_cap + id], pt_xyz[2 * point_cap + id],
+                            __int_as_float(int32_t(id)));
+}
+
+__global__ __launch_bounds__(kT) void k_fine_claim(Slot* slots, uint32_t slot_mask,
+                                                   int log2_slots, const uint64_t* keys,
+                                                   const uint32_t* seg_start,
+                                                   const uint32_t* seg_end, int64_t n_seg) {
+  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  const uint64_t key = keys[seg_start[s]];
+  uint32_t h = voxel_hash(key_x(key), key_y(key), key_z(key), log2_slots);
+  for (uint32_t probe = 0; probe <= slot_mask; ++probe) {
+    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[h].key),
+                                       (unsigned long long)kEmptyKey,
+                                       (unsigned long long)key);
+    if (old == kEmptyKey) {
+      slots[h].vox = int32_t(seg_start[s]);
+      slots[h].aux = int32_t(seg_end[s] - seg_start[s]);
+      return;
+    }
+    h = (h + 1) & slot_mask;
+  }
 }
 
 template <class F>
@@ -548,6 +640,50 @@ far_status_t map_covariances(const MapView& m, float4* cov_out, int64_t id0, int
   });
 }
 
+far_status_t fine_build(far_map_s* m, hipStream_t st) {
+  if (m->fine_ok || m->n_points == 0) return FAR_OK;
+  int e2 = 0;
+  if (std::frexp(m->p.voxel_size, &e2) != 0.5) return FAR_OK;   // not a power of two
+  const int64_t n = m->n_points;
+  Scratch scr(st);
+  uint64_t *keys, *keys_alt;
+  uint32_t *vals, *vals_alt, *head, *head_scan, *seg_start, *seg_end, *counters;
+  FAR_TRY(scr.get(&keys, size_t(n)));
+  FAR_TRY(scr.get(&keys_alt, size_t(n)));
+  FAR_TRY(scr.get(&vals, size_t(n)));
+  FAR_TRY(scr.get(&vals_alt, size_t(n)));
+  FAR_TRY(scr.get(&head, size_t(n)));
+  FAR_TRY(scr.get(&head_scan, size_t(n)));
+  FAR_TRY(scr.get(&seg_start, size_t(n)));
+  FAR_TRY(scr.get(&seg_end, size_t(n)));
+  FAR_TRY(scr.get(&counters, 4));
+  FAR_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
+  const double inv_fc = 2.0 / m->p.voxel_size;
+  k_fine_keys<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->p.point_capacity, n, inv_fc, keys,
+                                            vals, counters);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(radix_sort_pairs(keys, vals, keys_alt, vals_alt, n, kKeyBits, st, scr));
+  k_heads<<<blocks_for(n), kT, 0, st>>>(keys, n, head);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(head, head_scan, n, counters + 2, st, scr));
+  k_seg_bounds<<<blocks_for(n), kT, 0, st>>>(keys, n, head, head_scan, seg_start, seg_end);
+  FAR_HIP(hipGetLastError());
+  uint32_t h_cnt[4];
+  FAR_HIP(hipMemcpyAsync(h_cnt, counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  if (h_cnt[1] > 0) return FAR_OK;                    // out of the fine key range
+  const int64_t n_seg = h_cnt[2];
+  FAR_HIP(hipMemsetAsync(m->fine_slots, 0xFF, size_t(m->fine_nslots) * sizeof(Slot), st));
+  k_fine_claim<<<blocks_for(n_seg), kT, 0, st>>>(m->fine_slots, uint32_t(m->fine_nslots - 1),
+                                                 m->fine_log2, keys, seg_start, seg_end, n_seg);
+  FAR_HIP(hipGetLastError());
+  k_fine_fill<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->p.point_capacity, n, vals,
+                                            m->fine_pts);
+  FAR_HIP(hipGetLastError());
+  m->fine_ok = true;
+  return FAR_OK;
+}
+
 }  // namespace far
 
 using namespace far;
@@ -612,6 +748,11 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   size_t b_xyz = size_t(p.point_capacity) * 3 * sizeof(float);
   size_t b_loc = size_t(p.point_capacity) * sizeof(int32_t);
   size_t b_vslot = size_t(m->voxel_cap) * sizeof(int32_t);
+  m->fine_log2 = ceil_log2(2 * p.point_capacity);
+  if (m->fine_log2 < 10) m->fine_log2 = 10;
+  m->fine_nslots = int64_t(1) << m->fine_log2;
+  size_t b_fpts = size_t(p.point_capacity) * sizeof(float4);
+  size_t b_fslots = size_t(m->fine_nslots) * sizeof(Slot);
   if ((e = hipMalloc(&m->slots_d, b_slots)) != hipSuccess) return fail(e, "hipMalloc slots");
   if ((e = hipMalloc(&m->vox_count, b_cnt)) != hipSuccess) return fail(e, "hipMalloc counts");
   if ((e = hipMalloc(&m->vox_key, b_key)) != hipSuccess) return fail(e, "hipMalloc keys");
@@ -620,7 +761,10 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->pt_xyz, b_xyz)) != hipSuccess) return fail(e, "hipMalloc xyz");
   if ((e = hipMalloc(&m->pt_loc, b_loc)) != hipSuccess) return fail(e, "hipMalloc loc");
   if ((e = hipMalloc(&m->vox_slot, b_vslot)) != hipSuccess) return fail(e, "hipMalloc vslot");
-  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_xyz + b_loc + b_vslot);
+  if ((e = hipMalloc(&m->fine_pts, b_fpts)) != hipSuccess) return fail(e, "hipMalloc fine");
+  if ((e = hipMalloc(&m->fine_slots, b_fslots)) != hipSuccess) return fail(e, "hipMalloc fine");
+  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_xyz + b_loc + b_vslot + b_fpts +
+                     b_fslots);
   if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipMemsetAsync(m->vox_count, 0, b_cnt, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "sync");
@@ -634,7 +778,7 @@ far_status_t far_map_destroy(far_map_t m) {
   free_ws(m->ws);
   m->ws = nullptr;
   void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->pt_xyz,
-                  m->pt_loc, m->vox_slot};
+                  m->pt_loc, m->vox_slot, m->fine_pts, m->fine_slots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -654,6 +798,7 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
   Scratch scr(st);
   Runs r;
   FAR_TRY(build_runs(xyz, n, m->p.voxel_size, st, scr, r));
+  m->fine_ok = false;
   MapView mv = m->view();
   int32_t* seg_vox;
   uint32_t *is_new, *new_rank;
@@ -749,9 +894,23 @@ far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, doub
 static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
                                   int64_t n, double voxel_size, int32_t k, float* cov6,
                                   uint8_t* valid, hipStream_t st, const char* who) {
+  // grid cells of v/2 when v is a power of two (every neighbour within v is
+  // then at most two cells away per axis and the cells hold fewer points),
+  // else cells of v; points outside the finer key range fall back to v
+  int e2 = 0;
+  double cell = std::frexp(voxel_size, &e2) == 0.5 ? 0.5 * voxel_size : voxel_size;
   Scratch scr(st);
   Runs r;
-  FAR_TRY(build_runs(xyz, n, voxel_size, st, scr, r));
+  FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
+  if (cell < voxel_size) {
+    uint32_t oor = 0;
+    FAR_HIP(hipMemcpyAsync(&oor, r.counters + 1, sizeof(oor), hipMemcpyDeviceToHost, st));
+    FAR_HIP(hipStreamSynchronize(st));
+    if (oor > 0) {
+      cell = voxel_size;
+      FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
+    }
+  }
   uint64_t* keys = r.keys;
   uint32_t* vals = r.vals;
   uint32_t* sid = nullptr;
@@ -805,8 +964,9 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
   k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
                                                  keys, sid, r.seg_start, n_seg);
   FAR_HIP(hipGetLastError());
-  GridView g{slots, sorted, keys, sid, r.seg_start, r.seg_end, voxel_size, log2_slots,
-             uint32_t(n_slots - 1)};
+  GridView g{slots,     sorted,       keys, sid, r.seg_start, r.seg_end, voxel_size, cell,
+             1.0 / cell, cell < voxel_size ? 1 : (std::frexp(voxel_size, &e2) == 0.5 ? 1 : 0),
+             log2_slots, uint32_t(n_slots - 1)};
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
     k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, n, k, cov6, valid);
@@ -838,6 +998,64 @@ far_status_t far_scan_covariances_batch(const float* xyz, const int64_t* offsets
   if (n_total == 0) return FAR_OK;
   return scan_cov_impl(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid, S(stream),
                        "far_scan_covariances_batch");
+}
+
+far_status_t far_voxel_downsample(const float* xyz, int64_t n, double v, float* out,
+                                  int32_t* keep, int64_t* n_out, far_stream_t stream) {
+  if (n_out) *n_out = 0;
+  if (!n_out || n < 0 || n >= (int64_t(1) << 31) || !(v > 0.0) || !std::isfinite(v) ||
+      (n > 0 && (!xyz || !out)) || (n > 0 && out == xyz)) {
+    set_error("far_voxel_downsample: invalid argument");
+    return FAR_E_INVALID;
+  }
+  if (n == 0) return FAR_OK;
+  hipStream_t st = S(stream);
+  Scratch scr(st);
+  Runs r;
+  FAR_TRY(build_runs(xyz, n, v, st, scr, r));
+  uint32_t *flag, *pos, *total;
+  FAR_TRY(scr.get(&flag, size_t(n)));
+  FAR_TRY(scr.get(&pos, size_t(n)));
+  FAR_TRY(scr.get(&total, 1));
+  k_ds_flags<<<blocks_for(n), kT, 0, st>>>(r.vals, r.head, n, flag);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(flag, pos, n, total, st, scr));
+  uint32_t h[2];
+  FAR_HIP(hipMemcpyAsync(&h[0], r.counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipMemcpyAsync(&h[1], total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  if (h[0] > 0) {
+    set_error("far_voxel_downsample: %u points have voxel keys outside [-2^20, 2^20)", h[0]);
+    return FAR_E_INVALID;
+  }
+  const int64_t m = h[1];
+  if (m > 0) {
+    k_ds_scatter<<<blocks_for(n), kT, 0, st>>>(xyz, n, flag, pos, m, out, keep);
+    FAR_HIP(hipGetLastError());
+  }
+  FAR_HIP(hipStreamSynchronize(st));
+  *n_out = m;
+  return FAR_OK;
+}
+
+far_status_t far_transform_points(const float* xyz, int64_t n, const double T[16], float* out,
+                                  far_stream_t stream) {
+  if (n < 0 || !T || (n > 0 && (!xyz || !out))) {
+    set_error("far_transform_points: invalid argument");
+    return FAR_E_INVALID;
+  }
+  Rigid R;
+  for (int i = 0; i < 12; ++i) {
+    R.r[i] = T[i];
+    if (!std::isfinite(T[i])) {
+      set_error("far_transform_points: non-finite pose");
+      return FAR_E_INVALID;
+    }
+  }
+  if (n == 0) return FAR_OK;
+  k_transform<<<blocks_for(n), kT, 0, S(stream)>>>(xyz, n, R, out);
+  FAR_HIP(hipGetLastError());
+  return FAR_OK;
 }
 
 far_status_t far_map_stats(far_map_t m, far_map_stats_t* out, far_stream_t stream) {

@@ -51,6 +51,24 @@ class far_map_stats_t(C.Structure):
                 ("bytes_device", C.c_int64)]
 
 
+class far_threshold_t(C.Structure):
+    _fields_ = [("sigma0", C.c_double), ("r_max", C.c_double), ("min_motion", C.c_double),
+                ("sse", C.c_double), ("n_samples", C.c_int64)]
+
+
+class far_odometry_params_t(C.Structure):
+    _fields_ = [("downsample", C.c_double), ("sigma0", C.c_double), ("r_max", C.c_double),
+                ("min_motion", C.c_double), ("max_iters", C.c_int32), ("eps", C.c_double),
+                ("precision", C.c_int32)]
+
+
+class far_odometry_stats_t(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("n_raw", C.c_int64),
+                ("n_down", C.c_int64), ("n_inserted", C.c_int64), ("map_full", C.c_int32),
+                ("reserved", C.c_int32), ("tau", C.c_double), ("kappa", C.c_double),
+                ("deviation", C.c_double), ("T_pred", C.c_double * 16), ("last", far_lin_t)]
+
+
 STATS_DTYPE = np.dtype([("iters", np.int32), ("converged", np.int32), ("status", np.int32),
                         ("reserved", np.int32), ("H", np.float64, (36,)),
                         ("b", np.float64, (6,)), ("cost", np.float64),
@@ -71,6 +89,10 @@ _SIGS = {
     "far_gicp_linearize": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                      C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.c_int32, _P, C.POINTER(far_lin_t), _P]),
+    "far_gicp_gradient": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
+                                    C.c_double, C.c_double, C.POINTER(C.c_double), C.c_int32,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), _P,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int64), _P]),
     "far_gicp_align": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                  C.POINTER(far_align_params_t), C.POINTER(C.c_double),
                                  C.POINTER(far_align_stats_t), _P]),
@@ -78,6 +100,21 @@ _SIGS = {
                                        C.POINTER(far_align_params_t), _P, _P]),
     "far_map_stats": (C.c_int, [_P, C.POINTER(far_map_stats_t), _P]),
     "far_map_export": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
+    "far_voxel_downsample": (C.c_int, [_P, C.c_int64, C.c_double, _P, _P,
+                                       C.POINTER(C.c_int64), _P]),
+    "far_transform_points": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_double), _P, _P]),
+    "far_threshold_init": (C.c_int, [C.POINTER(far_threshold_t), C.c_double, C.c_double,
+                                     C.c_double]),
+    "far_threshold_update": (C.c_int, [C.POINTER(far_threshold_t), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "far_threshold_get": (C.c_int, [C.POINTER(far_threshold_t), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
+    "far_odometry_create": (C.c_int, [_P, C.POINTER(far_odometry_params_t),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(_P)]),
+    "far_odometry_step": (C.c_int, [_P, _P, C.c_int64, C.POINTER(C.c_double),
+                                    C.POINTER(far_odometry_stats_t), _P]),
+    "far_odometry_destroy": (C.c_int, [_P]),
     "far_status_str": (C.c_char_p, [C.c_int]),
     "far_last_error": (C.c_char_p, []),
 }
@@ -231,6 +268,25 @@ def far_gicp_linearize(h, src, cov6, valid, T, tau, kappa, c=None, precision=FAR
     return d
 
 
+def far_gicp_gradient(h, src, cov6, valid, T, tau, kappa, c=None, precision=FAR_PREC_FP32,
+                      want_src=True, stream=None):
+    """dict(grad_T [3, 4], grad_twist [6], grad_src [3, n] device tensor or None,
+    cost, n_inliers)."""
+    p, n = _pts(src, "src")
+    gs = torch.empty((3, max(n, 1)), dtype=torch.float32, device=src.device) if want_src else None
+    gT, gw = (C.c_double * 12)(), (C.c_double * 6)()
+    cost, cnt = C.c_double(0), C.c_int64(0)
+    cc = None if c is None else (C.c_double * 3)(*[float(x) for x in c])
+    _check(lib().far_gicp_gradient(h, p, _dev(cov6, torch.float32, "cov6"),
+                                   _dev(valid, torch.uint8, "valid"), n, _mat4(T), tau, kappa,
+                                   cc, precision, gT, gw, _dev(gs, torch.float32, "grad_src"),
+                                   C.byref(cost), C.byref(cnt), _stream(stream)),
+           "far_gicp_gradient")
+    return dict(grad_T=np.array(gT[:]).reshape(3, 4), grad_twist=np.array(gw[:]),
+                grad_src=None if gs is None else gs[:, :n], cost=cost.value,
+                n_inliers=cnt.value)
+
+
 def align_params(tau, kappa, max_iters=10, eps=1e-6, recenter=1, precision=FAR_PREC_FP32):
     return far_align_params_t(tau, kappa, max_iters, eps, recenter, precision)
 
@@ -322,6 +378,9 @@ class Map:
     def linearize(self, *a, **kw):
         return far_gicp_linearize(self.h, *a, **kw)
 
+    def gradient(self, *a, **kw):
+        return far_gicp_gradient(self.h, *a, **kw)
+
     def align(self, *a, **kw):
         return far_gicp_align(self.h, *a, **kw)
 
@@ -333,3 +392,116 @@ class Map:
 
     def export(self, stream=None):
         return far_map_export(self.h, stream=stream)
+
+
+def far_voxel_downsample(xyz, v, want_keep=False, stream=None):
+    """Returns (points SoA [3, m] float32 on the device, kept indices or None)."""
+    p, n = _pts(xyz, "xyz")
+    out = torch.empty(3 * max(n, 1), dtype=torch.float32, device=xyz.device)
+    keep = torch.empty(max(n, 1), dtype=torch.int32, device=xyz.device) if want_keep else None
+    m = C.c_int64(0)
+    _check(lib().far_voxel_downsample(p, n, v, _dev(out, torch.float32, "out"),
+                                      _dev(keep, torch.int32, "keep"), C.byref(m),
+                                      _stream(stream)), "far_voxel_downsample")
+    m = m.value
+    pts = out[:3 * m].view(3, m)
+    return pts, (keep[:m] if want_keep else None)
+
+
+def far_transform_points(xyz, T, out=None, stream=None):
+    p, n = _pts(xyz, "xyz")
+    if out is None:
+        out = torch.empty_like(xyz)
+    _check(lib().far_transform_points(p, n, _mat4(T), _dev(out, torch.float32, "out"),
+                                      _stream(stream)), "far_transform_points")
+    return out
+
+
+def far_threshold_init(sigma0, r_max, min_motion=0.1):
+    s = far_threshold_t()
+    _check(lib().far_threshold_init(C.byref(s), sigma0, r_max, min_motion), "far_threshold_init")
+    return s
+
+
+def far_threshold_update(s: far_threshold_t, T_pred, T_est):
+    d = C.c_double(0)
+    _check(lib().far_threshold_update(C.byref(s), _mat4(T_pred), _mat4(T_est), C.byref(d)),
+           "far_threshold_update")
+    return d.value
+
+
+def far_threshold_get(s: far_threshold_t):
+    tau, kappa = C.c_double(0), C.c_double(0)
+    _check(lib().far_threshold_get(C.byref(s), C.byref(tau), C.byref(kappa)), "far_threshold_get")
+    return tau.value, kappa.value
+
+
+def far_odometry_create(map_h, T_first, v_first=None, downsample=0.5, sigma0=1.0 / 3.0,
+                        r_max=120.0, min_motion=0.1, max_iters=10, eps=5e-3,
+                        precision=FAR_PREC_FP32):
+    prm = far_odometry_params_t(downsample, sigma0, r_max, min_motion, max_iters, eps, precision)
+    h = C.c_void_p()
+    _check(lib().far_odometry_create(map_h, C.byref(prm), _mat4(T_first),
+                                     _mat4_or_none(v_first), C.byref(h)), "far_odometry_create")
+    return h
+
+
+def far_odometry_step(h, xyz, stream=None):
+    """One scan [3, n] float32 on the device -> (T 4x4 numpy, stats dict)."""
+    p, n = _pts(xyz, "xyz")
+    T = (C.c_double * 16)()
+    st = far_odometry_stats_t()
+    _check(lib().far_odometry_step(h, p, n, T, C.byref(st), _stream(stream)),
+           "far_odometry_step")
+    return np.array(T[:]).reshape(4, 4), _odo_dict(st)
+
+
+def far_odometry_destroy(h):
+    _check(lib().far_odometry_destroy(h), "far_odometry_destroy")
+
+
+def _mat4_or_none(T):
+    return None if T is None else _mat4(T)
+
+
+class Threshold:
+    """Adaptive threshold state (far_threshold_t), host-side."""
+
+    def __init__(self, sigma0, r_max, min_motion=0.1):
+        self.s = far_threshold_init(sigma0, r_max, min_motion)
+
+    def update(self, T_pred, T_est):
+        return far_threshold_update(self.s, T_pred, T_est)
+
+    def get(self):
+        return far_threshold_get(self.s)
+
+
+def _odo_dict(st: far_odometry_stats_t):
+    d = {f: getattr(st, f) for f, _ in far_odometry_stats_t._fields_
+         if f not in ("T_pred", "last", "reserved")}
+    d["T_pred"] = np.array(st.T_pred[:]).reshape(4, 4)
+    d.update(_lin_dict(st.last))
+    return d
+
+
+class Odometry:
+    """Owning wrapper of a far_odometry_t over a Map (which must outlive it)."""
+
+    def __init__(self, map_, T_first, v_first=None, **kw):
+        self.map = map_
+        self._h = far_odometry_create(map_.h, T_first, v_first, **kw)
+
+    def step(self, xyz, stream=None):
+        return far_odometry_step(self._h, xyz, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            far_odometry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

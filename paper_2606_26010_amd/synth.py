@@ -392,3 +392,115 @@ def random_cloud(seed: int, n: int, extent: float = 4.0, dup_frac: float = 0.0,
         dst = g.integers(0, n, size=nd)
         p[:, dst] = p[:, src]
     return np.ascontiguousarray(p)
+
+
+# ---------------------------------------------------------------------------
+# Precision stress: exact planes (near-degenerate neighbourhoods) and rough
+# surfaces, fine voxels
+# ---------------------------------------------------------------------------
+def make_diff(seed: int = 4, n_scans: int = 16, n_points: int = 32768,
+              map_points: int = 1_000_000) -> BatchCase:
+    """Differentiation workload: n_scans scans of exactly n_points points from
+    the spinning-LiDAR simulator against a map of map_points points (the
+    batched-scans scene and map recipe at these sizes)."""
+    return make_batch(seed, n_scans=n_scans, n_min=n_points, n_max=n_points,
+                      map_points=map_points, n_map_batches=4)
+
+
+@dataclass
+class PrecisionCase:
+    map_batches: list
+    map_capacity: int
+    scan: np.ndarray       # sensor frame, SoA float32 [3, n]
+    T_gt: np.ndarray
+    T0: np.ndarray
+    planar_frac: float
+    voxel_size: float = 0.25
+    max_pts_per_voxel: int = 30
+    min_spacing: float = 0.25 / math.sqrt(30.0)
+    k: int = 5
+    tau: float = 0.25
+    kappa: float = 0.25 / 9.0
+    max_iters: int = 10
+
+
+def _site_samples(g, n, size, planar):
+    """Area-uniform samples of a size x size site.  planar=True: the exact
+    planes (floor z = 0 and four 20 m facades) with N(0, 1e-5^2) noise;
+    planar=False: rough surfaces with N(0, 0.03^2) noise - a rolling terrain
+    patch, boxes and vertical cylinders."""
+    if planar:
+        w = np.array([size * size, 4 * size * 20.0])
+        which = g.choice(2, size=n, p=w / w.sum())
+        out = np.empty((3, n))
+        i0 = np.nonzero(which == 0)[0]
+        out[:, i0] = _sample_rect(g, i0.size, (0, 0, 0), (size, 0, 0), (0, size, 0))
+        i1 = np.nonzero(which == 1)[0]
+        side = g.integers(0, 4, i1.size)
+        u, h = g.uniform(0, size, i1.size), g.uniform(0, 20.0, i1.size)
+        out[0, i1] = np.where(side == 0, 0.0, np.where(side == 1, size, u))
+        out[1, i1] = np.where(side == 2, 0.0, np.where(side == 3, size, u))
+        out[2, i1] = h
+        return out + g.normal(scale=1e-5, size=out.shape)
+    gs = rng(11)  # fixed clutter layout
+    boxes = np.concatenate([gs.uniform(10, size - 10, (60, 2)), gs.uniform(1.5, 4.0, (60, 2)),
+                            gs.uniform(1.0, 6.0, (60, 1))], 1)
+    cyl = np.concatenate([gs.uniform(10, size - 10, (80, 2)), gs.uniform(0.3, 1.0, (80, 1)),
+                          gs.uniform(2.0, 8.0, (80, 1))], 1)
+    a_terr = (size / 2) ** 2
+    a_box = boxes[:, 2] * boxes[:, 3] + 2 * (boxes[:, 2] + boxes[:, 3]) * boxes[:, 4]
+    a_cyl = 2 * math.pi * cyl[:, 2] * cyl[:, 3]
+    w = np.array([a_terr, a_box.sum(), a_cyl.sum()])
+    which = g.choice(3, size=n, p=w / w.sum())
+    out = np.empty((3, n))
+    i = np.nonzero(which == 0)[0]
+    x, y = g.uniform(0, size / 2, i.size), g.uniform(size / 2, size, i.size)
+    out[:, i] = np.stack([x, y, 0.4 * np.sin(x / 3.0) * np.cos(y / 4.0) + 0.5])
+    i = np.nonzero(which == 1)[0]
+    b = boxes[g.choice(len(boxes), size=i.size, p=a_box / a_box.sum())]
+    face = g.integers(0, 5, i.size)
+    u, v = g.uniform(size=i.size), g.uniform(size=i.size)
+    x = np.where(face == 1, b[:, 0], np.where(face == 2, b[:, 0] + b[:, 2], b[:, 0] + u * b[:, 2]))
+    y = np.where(face == 3, b[:, 1], np.where(face == 4, b[:, 1] + b[:, 3], b[:, 1] + v * b[:, 3]))
+    z = np.where(face == 0, b[:, 4], v * b[:, 4])
+    out[:, i] = np.stack([x, y, z])
+    i = np.nonzero(which == 2)[0]
+    cc = cyl[g.choice(len(cyl), size=i.size, p=a_cyl / a_cyl.sum())]
+    th = g.uniform(0, 2 * math.pi, i.size)
+    out[:, i] = np.stack([cc[:, 0] + cc[:, 2] * np.cos(th), cc[:, 1] + cc[:, 2] * np.sin(th),
+                          g.uniform(0, 1, i.size) * cc[:, 3]])
+    return out + g.normal(scale=0.03, size=out.shape)
+
+
+def make_precision(seed: int = 5, map_points: int = 20_000_000, map_batch: int = 5_000_000,
+                   n_map_batches: int = 12, n_scan: int = 1_000_000, planar_frac: float = 0.3,
+                   site: float = 250.0, scan_radius: float = 40.0) -> PrecisionCase:
+    """Precision stress: map of fine voxels (v = 0.25 m, N_max = 30) over a
+    site of exact planes and rough clutter; one scan of n_scan points within
+    scan_radius of a sensor near a corner of the site, a fraction planar_frac
+    of them on the exact planes (near-degenerate neighbourhoods), moved by a
+    0.05 m / 0.25 deg initial offset from the ground truth."""
+    g = rng(seed)
+    batches = []
+    for b in range(n_map_batches):
+        gb = rng(seed * 1000 + 500 + b)
+        m_pl = int(map_batch * 0.5)
+        pts = np.concatenate([_site_samples(gb, m_pl, site, True),
+                              _site_samples(gb, map_batch - m_pl, site, False)], 1)
+        batches.append(pts[:, gb.permutation(pts.shape[1])].astype(np.float32))
+    centre = np.array([35.0, 35.0, 2.0])
+
+    def near(planar, want):
+        got = []
+        while sum(x.shape[1] for x in got) < want:
+            x = _site_samples(g, max(4 * want, 1000), site, planar)
+            got.append(x[:, np.linalg.norm(x[:2] - centre[:2, None], axis=0) < scan_radius])
+        return np.concatenate(got, 1)[:, :want]
+
+    n_pl = int(n_scan * planar_frac)
+    x = np.concatenate([near(True, n_pl), near(False, n_scan - n_pl)], 1)
+    x = x[:, g.permutation(x.shape[1])]
+    T_gt = pose(Rotation.from_euler("z", g.uniform(-math.pi, math.pi)).as_matrix(), centre)
+    scan_ = apply(pose_inverse(T_gt), x)
+    T0 = T_gt @ random_offset(g, 0.05, 0.25)
+    return PrecisionCase(batches, map_points, scan_, T_gt, T0, planar_frac)

@@ -57,3 +57,23 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.far_map_create(ctypes.byref(p), None, ctypes.byref(h)) == far.FAR_E_INVALID
     assert L.far_map_insert(None, None, 0, None, None, None) == far.FAR_E_INVALID
     assert L.far_map_knn(None, None, 0, 5, 1.0, None, None, None, None) == far.FAR_E_INVALID
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfar.so not built")
+def test_threshold_is_host_only_and_matches_oracle(orc):
+    # far_threshold_* is plain host arithmetic: checked here without a GPU
+    import numpy as np
+    from scipy.spatial.transform import Rotation
+    from paper_2606_26010_amd import far, synth
+    g = np.random.default_rng(4)
+    a, b = far.Threshold(1.0 / 3.0, 120.0, 0.1), orc.Threshold(1.0 / 3.0, 120.0, 0.1)
+    assert a.get() == b.get()
+    for i in range(40):
+        P = synth.pose(Rotation.from_rotvec(g.normal(size=3)).as_matrix(), g.normal(size=3) * 50)
+        D = synth.pose(Rotation.from_rotvec(g.normal(size=3) * 10 ** g.uniform(-6, -2)).as_matrix(),
+                       g.normal(size=3) * 10 ** g.uniform(-3, 0))
+        da, db = a.update(P, P @ D), b.update(P, P @ D)
+        assert abs(da - db) <= 1e-9 * max(1.0, db), (i, da, db)
+        assert a.get() == pytest.approx(b.get(), rel=1e-9)
+    with pytest.raises(far.FarError):
+        far.Threshold(0.0, 120.0)

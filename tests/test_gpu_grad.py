@@ -1,0 +1,132 @@
+"""Gradient of the GICP cost on the GPU against the oracle gradient: the
+tiny plain-GICP case and the differentiation workload (16 scans of 32,768
+points against a 1,000,000-point map), in FP32 and FP64, plus the
+torch.autograd binding."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_26010_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-4, 1: 1e-9}     # FP32 bulk, FP64 path: relative norms
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def check(g, o, prec, what):
+    tol = TOL[prec]
+    assert g["n_inliers"] == o["n_inliers"], what
+    assert g["cost"] == pytest.approx(o["cost"], rel=tol), what
+    assert rel(g["grad_T"], o["grad_T"]) <= tol, (what, rel(g["grad_T"], o["grad_T"]))
+    assert rel(g["grad_twist"], o["grad_twist"]) <= tol, (what, rel(g["grad_twist"], o["grad_twist"]))
+    gs, os_ = host(g["grad_src"]).astype(np.float64), o["grad_src"]
+    # outliers exactly zero on both sides (same correspondence sets)
+    np.testing.assert_array_equal(gs == 0, os_ == 0)
+    scale = np.linalg.norm(os_, axis=0)
+    err = np.linalg.norm(gs - os_, axis=0)
+    # the source gradient is stored as float32 in both modes: the FP64 path is
+    # held to float32 rounding (2^-24 per component), the FP32 bulk to 1e-3
+    lim = (1e-3 if prec == 0 else 1.2e-7) * scale + (1e-6 if prec == 0 else 1e-12) * scale.max()
+    assert np.all(err <= lim), (what, float((err / np.maximum(lim, 1e-300)).max()))
+
+
+@pytest.fixture(scope="module")
+def tiny(orc):
+    from paper_2606_26010_amd import far
+    c = synth.make_tiny(1)
+    gm = far.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, 1 << 16, 0, c.k)
+    om = orc.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.k)
+    for b in c.map_batches:
+        gm.insert(dev(b))
+        om.insert(b)
+    cov, val = orc.scan_covariances(c.source, c.voxel_size, c.k)
+    cov = cov.astype(np.float32)
+    yield far, c, gm, om, cov, val
+    gm.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_tiny(tiny, prec):
+    far, c, gm, om, cov, val = tiny
+    g = synth.rng(31)
+    for k in range(3):
+        T = c.T_gt @ synth.random_offset(g, 0.1, 1.0)
+        ctr = T[:3, 3] if k else None
+        o = om.gradient(c.source, cov, val, T, c.tau, c.kappa, c=ctr)
+        r = gm.gradient(dev(c.source), dev(cov), dev(val), T, c.tau, c.kappa, c=ctr,
+                        precision=prec)
+        check(r, o, prec, f"tiny pose {k}")
+
+
+def test_gradient_edge_cases(tiny):
+    far, c, gm, om, cov, val = tiny
+    empty = torch.zeros((3, 0), dtype=torch.float32).cuda()
+    r = gm.gradient(empty, torch.zeros((6, 0)).cuda(), torch.zeros(0, dtype=torch.uint8).cuda(),
+                    np.eye(4), c.tau, c.kappa)
+    assert r["n_inliers"] == 0 and not np.any(r["grad_T"])
+    far_T = np.eye(4)
+    far_T[:3, 3] = (500.0, 0.0, 0.0)                     # nothing within reach
+    r = gm.gradient(dev(c.source), dev(cov), dev(val), far_T, c.tau, c.kappa)
+    assert r["n_inliers"] == 0 and not np.any(r["grad_T"])
+    assert not torch.any(r["grad_src"])
+
+
+@pytest.fixture(scope="module")
+def diff(orc):
+    from paper_2606_26010_amd import far
+    c = synth.make_diff(4)
+    print(f"diff workload: {len(c.scans)} scans of {c.scans[0].shape[1]} points", flush=True)
+    gm = far.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.map_capacity,
+                 c.map_capacity, c.k)
+    om = orc.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.k,
+                 point_capacity=c.map_capacity, voxel_capacity=c.map_capacity)
+    for b in c.map_batches:
+        gs, ga = gm.insert(dev(b))
+        orc_rc, oa, _ = om.insert(b, check=False)
+        assert (gs, ga) == (orc_rc, oa)
+        if om.size >= c.map_capacity:
+            break
+    assert om.size == c.map_capacity
+    yield far, c, gm, om
+    gm.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_diff_workload(orc, diff, prec):
+    far, c, gm, om = diff
+    for s, scan in enumerate(c.scans):
+        cov, val = orc.scan_covariances(scan, c.voxel_size, c.k)
+        cov = cov.astype(np.float32)
+        T = c.T0[s]
+        o = om.gradient(scan, cov, val, T, c.tau, c.kappa, c=T[:3, 3])
+        r = gm.gradient(dev(scan), dev(cov), dev(val), T, c.tau, c.kappa, c=T[:3, 3],
+                        precision=prec)
+        check(r, o, prec, f"scan {s}")
+
+
+def test_autograd_matches_gradient_and_oracle(tiny):
+    far, c, gm, om, cov, val = tiny
+    from paper_2606_26010_amd.autograd import gicp_cost
+    T = c.T_gt @ synth.random_offset(synth.rng(33), 0.1, 1.0)
+    src = dev(c.source).requires_grad_(True)
+    Tt = torch.from_numpy(T.copy()).requires_grad_(True)
+    cost = gicp_cost(src, Tt, gm, dev(cov), dev(val), c.tau, c.kappa, far.FAR_PREC_FP64)
+    (2.0 * cost).backward()
+    o = om.gradient(c.source, cov, val, T, c.tau, c.kappa)
+    assert float(cost) == pytest.approx(o["cost"], rel=1e-9)
+    assert rel(Tt.grad.numpy()[:3], 2.0 * o["grad_T"]) <= 1e-9
+    assert not torch.any(Tt.grad[3])
+    assert rel(host(src.grad), 2.0 * o["grad_src"]) <= 1e-6

@@ -334,3 +334,72 @@ def test_scan_covariances_batch_parity(far, orc):
         oc, ov = orc.scan_covariances(np.ascontiguousarray(sc), 1.0, 5)
         np.testing.assert_array_equal(val[offs[s]:offs[s + 1]], ov)
         np.testing.assert_allclose(cov[:, offs[s]:offs[s + 1]], oc, rtol=2e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("k", [1, 5])
+def test_knn_parity_far_from_origin(far, orc, k):
+    # FP32 spacing at 1.2e5 m is ~8 mm: candidate screening in FP32 must still
+    # leave every exact FP64 decision (and tie) to the FP64 comparison
+    shift = np.array([[123456.5], [-65432.25], [1000.0]], np.float32)
+    cloud = (synth.random_cloud(31, 6000, extent=3.0, dup_frac=0.05) + shift).astype(np.float32)
+    q = np.concatenate([cloud[:, :500],
+                        (synth.random_cloud(32, 800, extent=3.5) + shift).astype(np.float32)], 1)
+    gm, om, _ = build_pair(far, orc, [cloud], 1.0, 32, 0.0, 5)
+    gi, gd, gn = gm.knn(dev(q), k, 1.0)
+    oi, od, on = om.knn(q, k, 1.0)
+    np.testing.assert_array_equal(host(gn), on)
+    np.testing.assert_array_equal(host(gi), oi)
+    np.testing.assert_array_equal(host(gd), np.where(oi >= 0, od, -1.0).astype(np.float32))
+    gm.close()
+
+
+def test_linearize_parity_far_from_origin(far, orc):
+    c = synth.make_tiny(7, n_batches=4, n_source=3000)
+    shift = np.array([[98765.25], [43210.5], [-250.0]], np.float32)
+    batches = [(b + shift).astype(np.float32) for b in c.map_batches]
+    gm, om, _ = build_pair(far, orc, batches, 1.0, 20, c.min_spacing, 5)
+    src = c.source
+    T = c.T_gt.copy()
+    T[:3, 3] += shift[:, 0]
+    ocov, oval = orc.scan_covariances(src, 1.0, 5)
+    ocov = ocov.astype(np.float32)
+    for prec in (0, 1):
+        g = gm.linearize(dev(src), dev(ocov), dev(oval), T, 1.0, 1 / 9, c=T[:3, 3],
+                         precision=prec, want_corr=True)
+        o = om.linearize(src, ocov, oval, T, 1.0, 1 / 9, c=T[:3, 3], want_corr=True)
+        np.testing.assert_array_equal(host(g["corr"]), o["corr"])
+        assert rel(g["H"], o["H"]) <= (1e-4 if prec == 0 else 1e-9)
+    gm.close()
+
+
+def test_linearize_parity_non_pow2_voxel(far, orc):
+    # v = 0.75 m is not a power of two: the search falls back to the voxels
+    c = synth.make_tiny(8, n_batches=4, n_source=3000)
+    gm, om, _ = build_pair(far, orc, c.map_batches, 0.75, 20, 0.2, 5)
+    ocov, oval = orc.scan_covariances(c.source, 0.75, 5)
+    ocov = ocov.astype(np.float32)
+    for tau in (0.75, 0.5):
+        g = gm.linearize(dev(c.source), dev(ocov), dev(oval), c.T_gt, tau, 0.1, want_corr=True)
+        o = om.linearize(c.source, ocov, oval, c.T_gt, tau, 0.1, want_corr=True)
+        np.testing.assert_array_equal(host(g["corr"]), o["corr"])
+        assert rel(g["H"], o["H"]) <= 1e-4 and rel(g["b"], o["b"]) <= 1e-4
+    gm.close()
+
+
+def test_linearize_after_insert_refreshes_search_index(far, orc):
+    c = synth.make_tiny(9, n_batches=6, n_source=4000)
+    gm, om, _ = build_pair(far, orc, c.map_batches[:2], c.voxel_size, 20, c.min_spacing, 5)
+    ocov, oval = orc.scan_covariances(c.source, 1.0, 5)
+    ocov = ocov.astype(np.float32)
+    src, cov, val = dev(c.source), dev(ocov), dev(oval)
+    for b in c.map_batches[2:]:
+        g = gm.linearize(src, cov, val, c.T_gt, 1.0, 1 / 9, want_corr=True)
+        o = om.linearize(c.source, ocov, oval, c.T_gt, 1.0, 1 / 9, want_corr=True)
+        np.testing.assert_array_equal(host(g["corr"]), o["corr"])
+        gm.insert(dev(b))
+        om.insert(b)
+    g = gm.linearize(src, cov, val, c.T_gt, 1.0, 1 / 9, want_corr=True)
+    o = om.linearize(c.source, ocov, oval, c.T_gt, 1.0, 1 / 9, want_corr=True)
+    np.testing.assert_array_equal(host(g["corr"]), o["corr"])
+    assert rel(g["H"], o["H"]) <= 1e-4
+    gm.close()

@@ -314,7 +314,8 @@ typedef struct {
  * placed at T_first [host]; the second is predicted with the relative motion
  * v_first [host] (NULL = identity: the inertial prediction of the paper's
  * filter stands behind it), later ones with constant velocity
- * T_pred = T_prev (T_prev2^-1 T_prev). */
+ * T_pred = T_prev (T_prev2^-1 T_prev), its rotation projected back onto
+ * SO(3). */
 far_status_t far_odometry_create(far_map_t map, const far_odometry_params_t* params,
                                  const double T_first[16], const double v_first[16],
                                  far_odometry_t* out);

@@ -321,6 +321,13 @@ def _inv(T):
     return out
 
 
+def _nearest_rotation(R):
+    """Closest rotation matrix in the Frobenius norm (SVD polar factor)."""
+    U, _, Vt = np.linalg.svd(R)
+    D = np.diag([1.0, 1.0, np.sign(np.linalg.det(U @ Vt))])
+    return U @ D @ Vt
+
+
 def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing, k,
              map_capacity, downsample_v, sigma0, r_max, min_motion=0.1, max_iters=10,
              eps=0.0):
@@ -329,9 +336,11 @@ def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing
     registered scan), driven by the oracle's own steps.
 
     Readings: the first scan is inserted at T_first; the motion prediction is
-    constant velocity, T_pred = T_prev (T_prev2^-1 T_prev), with the relative
-    motion v_first (the inertial prediction of the paper's filter) for the
-    second scan; the threshold and kappa come from Threshold before each
+    constant velocity, T_pred = T_prev (T_prev2^-1 T_prev) with its rotation
+    projected back onto SO(3) (without the projection the rounding error of
+    the rotation grows about 2.4x per scan through the predictor), and the
+    relative motion v_first (the inertial prediction of the paper's filter)
+    for the second scan; the threshold and kappa come from Threshold before each
     registration and the deviation of the estimate is added after it; the
     registered, downsampled scan is inserted; once the map is full, inserting
     stops (the map keeps what fit).  Returns per-scan dicts with the pose,
@@ -350,6 +359,7 @@ def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing
         else:
             vel = v_first if s == 1 else _inv(poses[-2]) @ poses[-1]
             T_pred = poses[-1] @ vel
+            T_pred[:3, :3] = _nearest_rotation(T_pred[:3, :3])
             tau, kappa = thr.get()
             cov, val = scan_covariances(src, voxel_size, k)
             r = m.align(src, cov.astype(np.float32), val, T_pred, tau, kappa,

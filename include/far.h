@@ -229,6 +229,51 @@ far_status_t far_gicp_align_batch(far_map_t map, const float* src, const int64_t
                                   const far_align_params_t* params,
                                   far_align_stats_t* stats, far_stream_t stream);
 
+/* Launch schedule of the linearisation on a map (the tile and probe schedule
+ * of the batched iteration).  tile: points per block and tile, 128, 256
+ * (default) or 512.  fine_cells: 1 = correspondence search over cells of
+ * v/2 through a second hash index of the map (built lazily after inserts;
+ * power-of-two v only, else ignored), 0 = over the 27 voxels (default).
+ * Both searches are exact; the tile changes only the rounding order of the
+ * FP64 sums. */
+typedef struct {
+  int32_t tile;
+  int32_t fine_cells;
+} far_schedule_t;
+
+far_status_t far_map_get_schedule(far_map_t map, far_schedule_t* out);
+far_status_t far_map_set_schedule(far_map_t map, const far_schedule_t* schedule);
+
+/* Autotuner: times far_gicp_align_batch on the caller's batch (same
+ * arguments; T [dev, S x 16] is read, never modified) under every schedule
+ * candidate - tiles 128, 256, 512, each with the 27-voxel search and, for a
+ * power-of-two v, the fine cells - taking the fastest of `reps` timed runs
+ * (after one untimed run) of each.  The fastest schedule is set on the map
+ * and written to best [host]; ms [host, 6 entries, or NULL] receives each
+ * candidate's time in the order listed (tile-major, voxel search first;
+ * -1 for a candidate not run).  Synchronises `stream`. */
+far_status_t far_autotune(far_map_t map, const float* src, const int64_t* offsets, int32_t S,
+                          int64_t n_total, const float* cov6, const uint8_t* valid,
+                          const double* T, const far_align_params_t* params, int32_t reps,
+                          far_schedule_t* best, double* ms, far_stream_t stream);
+
+/* Schedule of the scan covariance search (process-wide): a point whose own
+ * voxel holds at least dense_threshold points searches cells of v/2 (power-
+ * of-two v), others the 27 voxels; 0 = always the 27 voxels.  Default 32.
+ * Results are identical for every setting. */
+far_status_t far_set_covariance_schedule(int32_t dense_threshold);
+far_status_t far_get_covariance_schedule(int32_t* dense_threshold);
+
+/* Covariance autotuner: times far_scan_covariances_batch on the caller's
+ * batch for dense thresholds 0, 16, 32, 64 and 128 (fastest of `reps`
+ * timed runs after one untimed run each), sets the fastest and returns it in
+ * best [host]; ms [host, 5 entries, or NULL] the times.  cov6 and valid
+ * receive the covariances.  Synchronises `stream`. */
+far_status_t far_autotune_covariances(const float* xyz, const int64_t* offsets, int32_t S,
+                                      int64_t n_total, double voxel_size, int32_t k,
+                                      float* cov6, uint8_t* valid, int32_t reps, int32_t* best,
+                                      double* ms, far_stream_t stream);
+
 /* Occupancy and probe statistics of the map's hash table.  Synchronises. */
 far_status_t far_map_stats(far_map_t map, far_map_stats_t* out, far_stream_t stream);
 

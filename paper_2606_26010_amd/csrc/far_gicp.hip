@@ -23,9 +23,10 @@
 namespace far {
 namespace {
 
-constexpr int kBlock = 256;    // threads per linearisation block
-constexpr int kPerLane = 1;    // points per lane
-constexpr int kTile = kBlock * kPerLane;   // points per tile
+// Points per linearisation tile (= threads per block, one point per lane):
+// 128, 256 or 512, chosen per map (far_map_set_schedule / far_autotune).
+constexpr int kTileDefault = 256;
+constexpr int kTileMin = 128;
 constexpr int kVals = 29;     // 21 H + 6 b + cost + count
 constexpr int kStride = 32;   // partial row stride (doubles)
 
@@ -37,14 +38,15 @@ struct Params {
   double eps;
   int32_t max_iters;
   int32_t recenter;
+  int32_t fine_nn;  // correspondence search over the fine index (cells v/2)
 };
 
 // ---------------------------------------------------------------- tiles
 __global__ __launch_bounds__(256) void k_build_tiles(const int64_t* offsets, int32_t S,
                                                      int64_t n_total, int64_t max_tiles,
-                                                     int32_t* tile_scan, uint32_t* tile_lo,
-                                                     uint32_t* tile_hi, int32_t* begin,
-                                                     int32_t* bad) {
+                                                     int32_t tile, int32_t* tile_scan,
+                                                     uint32_t* tile_lo, uint32_t* tile_hi,
+                                                     int32_t* begin, int32_t* bad) {
   __shared__ int32_t s_total;
   __shared__ int32_t s_bad;
   if (threadIdx.x == 0) {
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(256) void k_build_tiles(const int64_t* offsets, int
     for (int32_t s = 0; s < S; ++s) {
       int64_t len = offsets[s + 1] - offsets[s];
       if (len < 0) b = 1;
-      acc += len > 0 ? (len + kTile - 1) / kTile : 0;
+      acc += len > 0 ? (len + tile - 1) / tile : 0;
       begin[s + 1] = int32_t(acc);
     }
     if (acc > max_tiles) b = 1;
@@ -71,8 +73,8 @@ __global__ __launch_bounds__(256) void k_build_tiles(const int64_t* offsets, int
   for (int32_t s = threadIdx.x; s < S; s += blockDim.x) {
     int64_t lo = offsets[s], hi = offsets[s + 1];
     for (int32_t t = begin[s]; t < begin[s + 1]; ++t) {
-      int64_t a = lo + int64_t(t - begin[s]) * kTile;
-      int64_t b = a + kTile < hi ? a + kTile : hi;
+      int64_t a = lo + int64_t(t - begin[s]) * tile;
+      int64_t b = a + tile < hi ? a + tile : hi;
       tile_scan[t] = s;
       tile_lo[t] = uint32_t(a);
       tile_hi[t] = uint32_t(b);
@@ -336,8 +338,8 @@ __device__ inline void grad_term(double px, double py, double pz, float4 s, floa
 }
 
 // ---------------------------------------------------------------- linearise
-// One block of kTile threads per tile of kTile locality-ordered points (one
-// point per lane).  Blocks are dealt to the eight XCDs round-robin; block b
+// One block of kB threads per tile of kB locality-ordered points (one point
+// per lane).  Blocks are dealt to the eight XCDs round-robin; block b
 // takes tile (b mod 8) * chunk + b / 8 so that each XCD works through one
 // contiguous range of tiles and neighbouring tiles - which share map voxels -
 // meet in the same L2.
@@ -403,15 +405,15 @@ __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool p
 // kGrad selects the gradient of the cost instead of H, b: 14 sums (the 3x4
 // gradient of [R | t], cost, count) and, when grad_src is given, each
 // point's source gradient written SoA at its original index (n_src apart).
-template <class Real, bool kGrad>
-__global__ __launch_bounds__(kBlock) void k_linearize(
+template <class Real, bool kGrad, int kB>
+__global__ __launch_bounds__(kB) void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
     const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
     int32_t* __restrict__ corr, float* __restrict__ grad_src, int64_t n_src) {
-  constexpr int kWaves = kBlock / 64;
+  constexpr int kWaves = kB / 64;
   constexpr int kNV = kGrad ? 14 : kVals;
   __shared__ double red[kWaves][kNV];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -429,9 +431,8 @@ __global__ __launch_bounds__(kBlock) void k_linearize(
   Real acc[kNV];
 #pragma unroll
   for (int q = 0; q < kNV; ++q) acc[q] = Real(0);
-#pragma unroll
-  for (int u = 0; u < kPerLane; ++u) {
-    const int64_t i = lo + int64_t(u) * kBlock + tid;
+  {
+    const int64_t i = lo + tid;
     const bool in_tile = i < hi;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 sB = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_linearize(
     TopK<1> top;
     top.init();
     if (have) {
-      if (m.fine_ok)
+      if (prm.fine_nn && m.fine_ok)
         knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
                      [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
                        return fine_find(m, a0, a1, a2, n);
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_linearize(
     Real gs[3] = {Real(0), Real(0), Real(0)};
     if (have && top.pos[0] >= 0) {
       match = top.id[0];
-      const float4 r = m.fine_ok ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
+      const float4 r = (prm.fine_nn && m.fine_ok) ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
       const float4 ca = m.cov[2 * int64_t(match)];
       const float4 cb = m.cov[2 * int64_t(match) + 1];
       if constexpr (kGrad)
@@ -721,6 +722,7 @@ struct AlignWS {
   Params key_prm{};
   int32_t key_prec = -1;
   int32_t key_S = -1;
+  int32_t key_tile = -1;
 };
 
 void free_ws(AlignWS* w) {
@@ -800,15 +802,40 @@ struct Job {
   int32_t precision;
   double* gsum = nullptr;      // non-null: one gradient pass (single scan), sums here
   float* grad_src = nullptr;   // gradient pass: per-point source gradient or null
+  int32_t tile = kTileDefault; // points per tile (the map's schedule)
 };
+
+// Launch of the linearisation (or gradient) kernel at the map's tile size.
+template <class Real, bool kGrad>
+far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapView& mv,
+                        const AlignWS* w, int64_t max_tiles, const Job& j) {
+  switch (tile) {
+#define FAR_LIN_CASE(B)                                                                   \
+  case B:                                                                                 \
+    k_linearize<Real, kGrad, B><<<unsigned(grid), B, 0, st>>>(                           \
+        mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
+        w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
+        j.n_total);                                                                       \
+    break;
+    FAR_LIN_CASE(128)
+    FAR_LIN_CASE(256)
+    FAR_LIN_CASE(512)
+#undef FAR_LIN_CASE
+    default:
+      set_error("internal: unsupported tile size %d", tile);
+      return FAR_E_INVALID;
+  }
+  FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
 
 // Enqueue the whole job (init, locality packing, iterations) on st.  Nothing
 // here allocates or clears memory, so it can be recorded into a graph.
 far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
                      hipStream_t st) {
   MapView mv = m->view();
-  k_build_tiles<<<1, 256, 0, st>>>(j.offsets, j.S, j.n_total, max_tiles, w->tile_scan,
-                                   w->tile_lo, w->tile_hi, w->begin, w->bad);
+  k_build_tiles<<<1, 256, 0, st>>>(j.offsets, j.S, j.n_total, max_tiles, j.tile,
+                                   w->tile_scan, w->tile_lo, w->tile_hi, w->begin, w->bad);
   FAR_HIP(hipGetLastError());
   k_init<<<(j.S + 255) / 256, 256, 0, st>>>(j.S, j.T, w->bad, j.prm.recenter, j.c_fixed,
                                             j.stats, w->done, w->ctr);
@@ -832,14 +859,9 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
   const int64_t grid = ((max_tiles + 7) / 8) * 8;   // one block per tile
   if (j.gsum) {
     if (j.precision == FAR_PREC_FP64)
-      k_linearize<double, true><<<unsigned(grid), kBlock, 0, st>>>(
-          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
-          w->ctr, w->done, j.prm, w->partial, j.corr, j.grad_src, j.n_total);
+      FAR_TRY((launch_lin<double, true>(j.tile, grid, st, mv, w, max_tiles, j)));
     else
-      k_linearize<float, true><<<unsigned(grid), kBlock, 0, st>>>(
-          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
-          w->ctr, w->done, j.prm, w->partial, j.corr, j.grad_src, j.n_total);
-    FAR_HIP(hipGetLastError());
+      FAR_TRY((launch_lin<float, true>(j.tile, grid, st, mv, w, max_tiles, j)));
     k_reduce_grad<<<1, 256, 0, st>>>(w->begin, w->partial, j.gsum);
     FAR_HIP(hipGetLastError());
     return FAR_OK;
@@ -854,14 +876,9 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
       FAR_HIP(hipEventRecord(ev0, st));
     }
     if (j.precision == FAR_PREC_FP64)
-      k_linearize<double, false><<<unsigned(grid), kBlock, 0, st>>>(
-          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
-          w->ctr, w->done, j.prm, w->partial, j.corr, nullptr, 0);
+      FAR_TRY((launch_lin<double, false>(j.tile, grid, st, mv, w, max_tiles, j)));
     else
-      k_linearize<float, false><<<unsigned(grid), kBlock, 0, st>>>(
-          mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,
-          w->ctr, w->done, j.prm, w->partial, j.corr, nullptr, 0);
-    FAR_HIP(hipGetLastError());
+      FAR_TRY((launch_lin<float, false>(j.tile, grid, st, mv, w, max_tiles, j)));
     if (timed) {
       FAR_HIP(hipEventRecord(ev1, st));
       std::lock_guard<std::mutex> lk(timing().mu);
@@ -874,12 +891,22 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
   return FAR_OK;
 }
 
+bool same_params(const Params& a, const Params& b) {
+  return a.r2 == b.r2 && a.kappa2 == b.kappa2 && a.inv_v == b.inv_v && a.v_pow2 == b.v_pow2 &&
+         a.eps == b.eps && a.max_iters == b.max_iters && a.recenter == b.recenter &&
+         a.fine_nn == b.fine_nn;
+}
+
 // Run a job, through a cached graph when the stream allows capture.
-far_status_t run_job(far_map_s* m, const Job& j, hipStream_t st, bool use_graph) {
-  const int64_t max_tiles = (j.n_total + kTile - 1) / kTile + j.S;
+far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph) {
+  Job j = j0;
+  j.tile = m->sched_tile;
+  j.prm.fine_nn = m->sched_fine;
+  const int64_t max_tiles = (j.n_total + j.tile - 1) / j.tile + j.S;
   AlignWS* w = nullptr;
   FAR_TRY(ensure_ws(m, j.S, max_tiles, j.n_total, &w));
-  FAR_TRY(fine_build(m, st));  // the fine index of the current map (stream-ordered)
+  // the fine index of the current map (stream-ordered), when it is used
+  if (j.prm.fine_nn) FAR_TRY(fine_build(m, st));
   (void)device_cu_count();   // query the device outside any capture
   if (!use_graph || st == nullptr || timing().on) return enqueue(m, w, j, max_tiles, st);
   // the captured map view holds the fine-index flag: a graph captured with a
@@ -887,8 +914,8 @@ far_status_t run_job(far_map_s* m, const Job& j, hipStream_t st, bool use_graph)
   const void* key[10] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
                          m->vox_pts, reinterpret_cast<const void*>(intptr_t(m->fine_ok))};
   bool same = w->exec && w->key_n == j.n_total && w->key_S == j.S &&
-              w->key_prec == j.precision && memcmp(w->key, key, sizeof(key)) == 0 &&
-              memcmp(&w->key_prm, &j.prm, sizeof(Params)) == 0;
+              w->key_prec == j.precision && w->key_tile == j.tile &&
+              memcmp(w->key, key, sizeof(key)) == 0 && same_params(w->key_prm, j.prm);
   if (!same) {
     // Capture only once an argument set repeats: a one-off call (e.g. a
     // different scan every time) launches directly and pays no capture.
@@ -920,6 +947,7 @@ far_status_t run_job(far_map_s* m, const Job& j, hipStream_t st, bool use_graph)
     w->key_S = j.S;
     w->key_prec = j.precision;
     w->key_prm = j.prm;
+    w->key_tile = j.tile;
   }
   FAR_HIP(hipGraphLaunch(w->exec, st));
   return FAR_OK;
@@ -934,6 +962,7 @@ bool params_ok(const far_align_params_t* p) {
 Params make_params(const far_map_s* m, double tau, double kappa, double eps, int32_t max_iters,
                    int32_t recenter) {
   Params prm;
+  memset(&prm, 0, sizeof(prm));
   double r = tau < m->p.voxel_size ? tau : m->p.voxel_size;
   prm.r2 = r * r;
   prm.kappa2 = kappa * kappa;
@@ -943,6 +972,7 @@ Params make_params(const far_map_s* m, double tau, double kappa, double eps, int
   prm.eps = eps;
   prm.max_iters = max_iters;
   prm.recenter = recenter ? 1 : 0;
+  prm.fine_nn = 0;
   return prm;
 }
 
@@ -970,7 +1000,7 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
   if (n == 0) return FAR_OK;
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
-  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, n, &w));
+  FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
   int64_t offs[2] = {0, n};
   double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
   FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
@@ -1004,7 +1034,7 @@ far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
   if (n == 0) return FAR_OK;
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
-  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, n, &w));
+  FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
   int64_t offs[2] = {0, n};
   const double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
   FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
@@ -1056,7 +1086,7 @@ far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
   }
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
-  FAR_TRY(ensure_ws(m, 1, (n + kTile - 1) / kTile + 1, n, &w));
+  FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
   int64_t offs[2] = {0, n};
   FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
   FAR_HIP(hipMemcpyAsync(w->T, T0, 16 * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1070,6 +1100,116 @@ far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
   FAR_HIP(hipStreamSynchronize(st));
   if (stats) *stats = hs;
   return far_status_t(hs.status);
+}
+
+far_status_t far_map_get_schedule(far_map_t m, far_schedule_t* out) {
+  if (!m || !out) {
+    set_error("far_map_get_schedule: null argument");
+    return FAR_E_INVALID;
+  }
+  out->tile = m->sched_tile;
+  out->fine_cells = m->sched_fine;
+  return FAR_OK;
+}
+
+far_status_t far_map_set_schedule(far_map_t m, const far_schedule_t* sc) {
+  if (!m || !sc || (sc->tile != 128 && sc->tile != 256 && sc->tile != 512) ||
+      (sc->fine_cells != 0 && sc->fine_cells != 1)) {
+    set_error("far_map_set_schedule: need tile 128, 256 or 512 and fine_cells 0 or 1");
+    return FAR_E_INVALID;
+  }
+  m->sched_tile = sc->tile;
+  m->sched_fine = sc->fine_cells;
+  return FAR_OK;
+}
+
+far_status_t far_autotune(far_map_t m, const float* src, const int64_t* offsets, int32_t S_,
+                          int64_t n_total, const float* cov6, const uint8_t* valid,
+                          const double* T, const far_align_params_t* params, int32_t reps,
+                          far_schedule_t* best, double* ms, far_stream_t stream) {
+  if (!m || !offsets || !T || !best || !params_ok(params) || S_ < 1 || n_total < 0 ||
+      n_total >= (int64_t(1) << 31) || reps < 1 || reps > 100 ||
+      (n_total > 0 && (!src || !cov6 || !valid))) {
+    set_error("far_autotune: invalid argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  const far_schedule_t saved{m->sched_tile, m->sched_fine};
+  int e2 = 0;
+  const bool pow2 = std::frexp(m->p.voxel_size, &e2) == 0.5;
+  double* Tw = nullptr;
+  far_align_stats_t* sw = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  far_status_t rs = FAR_OK;
+  double times[6];
+  far_schedule_t win = saved;
+  double win_ms = -1.0;
+  auto fail = [&](far_status_t s) {
+    rs = s;
+    return s;
+  };
+  do {
+    hipError_t e;
+    if ((e = hipMalloc(&Tw, size_t(S_) * 16 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&sw, size_t(S_) * sizeof(far_align_stats_t))) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+      fail(hip_fail(e, "far_autotune setup", __FILE__, __LINE__));
+      break;
+    }
+    const int32_t tiles[3] = {128, 256, 512};
+    for (int c = 0; c < 6 && rs == FAR_OK; ++c) {
+      times[c] = -1.0;
+      const far_schedule_t cand{tiles[c / 2], c % 2};
+      if (cand.fine_cells && !pow2) continue;
+      m->sched_tile = cand.tile;
+      m->sched_fine = cand.fine_cells;
+      double bestc = 1e300;
+      for (int r = 0; r <= reps && rs == FAR_OK; ++r) {
+        if ((e = hipMemcpyAsync(Tw, T, size_t(S_) * 16 * sizeof(double),
+                                hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+            (e = hipEventRecord(e0, st)) != hipSuccess) {
+          fail(hip_fail(e, "far_autotune", __FILE__, __LINE__));
+          break;
+        }
+        far_status_t a = far_gicp_align_batch(m, src, offsets, S_, n_total, cov6, valid, Tw,
+                                              params, sw, stream);
+        if (a != FAR_OK) {
+          fail(a);
+          break;
+        }
+        float t = 0.0f;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess ||
+            (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+          fail(hip_fail(e, "far_autotune timing", __FILE__, __LINE__));
+          break;
+        }
+        if (r > 0 && t < bestc) bestc = t;   // run 0 is untimed (first launch, capture)
+      }
+      if (rs != FAR_OK) break;
+      times[c] = bestc;
+      if (win_ms < 0.0 || bestc < win_ms) {
+        win_ms = bestc;
+        win = cand;
+      }
+    }
+  } while (false);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (Tw || sw) (void)hipStreamSynchronize(st);
+  if (Tw) (void)hipFree(Tw);
+  if (sw) (void)hipFree(sw);
+  if (rs != FAR_OK) {
+    m->sched_tile = saved.tile;
+    m->sched_fine = saved.fine_cells;
+    return rs;
+  }
+  m->sched_tile = win.tile;
+  m->sched_fine = win.fine_cells;
+  *best = win;
+  if (ms)
+    for (int c = 0; c < 6; ++c) ms[c] = times[c];
+  return FAR_OK;
 }
 
 far_status_t far_timing_enable(int32_t on) {

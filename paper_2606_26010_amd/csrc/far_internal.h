@@ -244,6 +244,8 @@ void free_ws(AlignWS* w);
 // Host-side map object.
 struct far_map_s {
   far_map_params_t p;
+  int32_t sched_tile = 256;   // linearisation tile (points per block)
+  int32_t sched_fine = 0;     // correspondence search over the fine index
   double dmin;
   int64_t slots;
   int log2_slots;

@@ -454,32 +454,46 @@ __global__ __launch_bounds__(kT) void k_grid_claim(Slot* slots, uint32_t slot_ma
 }
 
 // Covariance of every scan point from its k nearest points of the same scan
-// within v (processed in sorted order for locality; written at the original
-// index).  Non-finite points keep the zero covariance / invalid flag.
+// within v (processed in coarse-sorted order for locality; written at the
+// original index).  The search is exact either way; per point it takes the
+// fine grid (cells of v/2, up to two cells away, pruned by the current k-th
+// distance) when its own coarse voxel holds at least `dense` points - where
+// the k-th neighbour is close and the fine cells cut the candidates - and the
+// coarse grid (the 27 voxels) otherwise, where the finer cells would only
+// add probes.  Non-finite points keep the zero covariance / invalid flag.
 template <int K>
-__global__ __launch_bounds__(kT) void k_grid_cov(GridView g, int64_t n, int32_t k, float* cov6,
-                                                 uint8_t* valid) {
+__global__ __launch_bounds__(kT) void k_grid_cov(GridView gc, GridView gf, int32_t have_fine,
+                                                 int32_t dense, int64_t n, int32_t k,
+                                                 float* cov6, uint8_t* valid) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n || g.keys[j] == kEmptyKey) return;
-  const uint32_t sc = g.sid ? g.sid[j] : 0u;
-  float4 me = g.sorted[j];
-  double qx = me.x, qy = me.y, qz = me.z;
+  if (j >= n || gc.keys[j] == kEmptyKey) return;
+  const uint32_t sc = gc.sid ? gc.sid[j] : 0u;
+  const float4 me = gc.sorted[j];
+  const double qx = me.x, qy = me.y, qz = me.z;
+  const uint64_t own = gc.keys[j];
+  bool fine = false;
+  if (have_fine) {
+    const int32_t so = grid_find(gc, key_x(own), key_y(own), key_z(own), sc);
+    fine = so >= 0 && int32_t(gc.seg_end[so] - gc.seg_start[so]) >= dense;
+  }
   TopK<K> top;
+  const GridView& g = fine ? gf : gc;
   knn_cells<K>(qx, qy, qz, g.c, g.inv_c, g.pow2 != 0, g.c < g.v, g.v * g.v, g.sorted,
-               [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
+               [&](int64_t a0, int64_t a1, int64_t a2, int32_t* cnt) {
                  const int32_t s = grid_find(g, a0, a1, a2, sc);
                  if (s < 0) {
-                   *n = 0;
+                   *cnt = 0;
                    return int32_t(-1);
                  }
-                 *n = int32_t(g.seg_end[s] - g.seg_start[s]);
+                 *cnt = int32_t(g.seg_end[s] - g.seg_start[s]);
                  return int32_t(g.seg_start[s]);
                },
                top);
   double c6[6] = {0, 0, 0, 0, 0, 0};
-  bool ok = top.found() >= k;
-  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
-  int64_t i = __float_as_int(me.w);
+  const bool ok = top.found() >= k;
+  const float4* P = g.sorted;
+  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return P[pos]; }, c6);
+  const int64_t i = __float_as_int(me.w);
 #pragma unroll
   for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
   valid[i] = ok ? 1 : 0;
@@ -891,26 +905,15 @@ far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, doub
   });
 }
 
-static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
-                                  int64_t n, double voxel_size, int32_t k, float* cov6,
-                                  uint8_t* valid, hipStream_t st, const char* who) {
-  // grid cells of v/2 when v is a power of two (every neighbour within v is
-  // then at most two cells away per axis and the cells hold fewer points),
-  // else cells of v; points outside the finer key range fall back to v
-  int e2 = 0;
-  double cell = std::frexp(voxel_size, &e2) == 0.5 ? 0.5 * voxel_size : voxel_size;
-  Scratch scr(st);
+// Voxel grid of a batch of scans with cells of edge `cell` (points grouped by
+// scan, then by cell key): sorted points, runs and a hash of the runs.
+// *oor receives the number of points whose cell key is out of range (the
+// grid is then not built).
+static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t S_, int64_t n,
+                               double v, double cell, hipStream_t st, Scratch& scr,
+                               GridView* out, uint32_t* oor) {
   Runs r;
   FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
-  if (cell < voxel_size) {
-    uint32_t oor = 0;
-    FAR_HIP(hipMemcpyAsync(&oor, r.counters + 1, sizeof(oor), hipMemcpyDeviceToHost, st));
-    FAR_HIP(hipStreamSynchronize(st));
-    if (oor > 0) {
-      cell = voxel_size;
-      FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
-    }
-  }
   uint64_t* keys = r.keys;
   uint32_t* vals = r.vals;
   uint32_t* sid = nullptr;
@@ -943,17 +946,12 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
   uint32_t h_cnt[4];
   FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipStreamSynchronize(st));
-  if (h_cnt[1] > 0) {
-    set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, h_cnt[1]);
-    return FAR_E_INVALID;
-  }
+  *oor = h_cnt[1];
+  if (h_cnt[1] > 0) return FAR_OK;
   const int64_t n_seg = h_cnt[2];
-  FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
-  FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
-  if (n_seg == 0) return FAR_OK;
-  int log2_slots = ceil_log2(2 * n_seg);
+  int log2_slots = ceil_log2(2 * (n_seg > 0 ? n_seg : 1));
   if (log2_slots < 6) log2_slots = 6;
-  int64_t n_slots = int64_t(1) << log2_slots;
+  const int64_t n_slots = int64_t(1) << log2_slots;
   Slot* slots;
   float4* sorted;
   FAR_TRY(scr.get(&slots, size_t(n_slots)));
@@ -961,15 +959,48 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
   FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
   k_gather_sorted<<<blocks_for(n), kT, 0, st>>>(xyz, n, vals, sorted);
   FAR_HIP(hipGetLastError());
-  k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
-                                                 keys, sid, r.seg_start, n_seg);
-  FAR_HIP(hipGetLastError());
-  GridView g{slots,     sorted,       keys, sid, r.seg_start, r.seg_end, voxel_size, cell,
-             1.0 / cell, cell < voxel_size ? 1 : (std::frexp(voxel_size, &e2) == 0.5 ? 1 : 0),
-             log2_slots, uint32_t(n_slots - 1)};
+  if (n_seg > 0) {
+    k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
+                                                   keys, sid, r.seg_start, n_seg);
+    FAR_HIP(hipGetLastError());
+  }
+  int e2 = 0;
+  const int32_t pow2 = std::frexp(cell, &e2) == 0.5 ? 1 : 0;
+  *out = GridView{slots, sorted, keys, sid, r.seg_start, r.seg_end, v, cell, 1.0 / cell, pow2,
+                  log2_slots, uint32_t(n_slots - 1)};
+  return FAR_OK;
+}
+
+// Points per coarse voxel from which the covariance search switches to the
+// fine grid.
+static int32_t g_dense_threshold = 32;
+
+static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
+                                  int64_t n, double voxel_size, int32_t k, float* cov6,
+                                  uint8_t* valid, hipStream_t st, const char* who) {
+  Scratch scr(st);
+  GridView gc{}, gf{};
+  uint32_t oor = 0;
+  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &gc, &oor));
+  if (oor > 0) {
+    set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, oor);
+    return FAR_E_INVALID;
+  }
+  // the fine grid (cells of v/2, exact when v is a power of two); points
+  // outside its key range leave only the coarse search
+  int e2 = 0;
+  int32_t have_fine = 0;
+  const int32_t dense = g_dense_threshold;
+  if (std::frexp(voxel_size, &e2) == 0.5 && dense > 0) {
+    FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, 0.5 * voxel_size, st, scr, &gf, &oor));
+    have_fine = oor == 0 ? 1 : 0;
+  }
+  FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
+  FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
-    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, n, k, cov6, valid);
+    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(gc, have_fine ? gf : gc, have_fine, dense, n, k,
+                                                cov6, valid);
     FAR_HIP(hipGetLastError());
     return FAR_OK;
   });
@@ -1055,6 +1086,82 @@ far_status_t far_transform_points(const float* xyz, int64_t n, const double T[16
   if (n == 0) return FAR_OK;
   k_transform<<<blocks_for(n), kT, 0, S(stream)>>>(xyz, n, R, out);
   FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
+
+far_status_t far_set_covariance_schedule(int32_t dense_threshold) {
+  if (dense_threshold < 0) {
+    set_error("far_set_covariance_schedule: dense_threshold must be >= 0");
+    return FAR_E_INVALID;
+  }
+  g_dense_threshold = dense_threshold;
+  return FAR_OK;
+}
+
+far_status_t far_get_covariance_schedule(int32_t* dense_threshold) {
+  if (!dense_threshold) {
+    set_error("far_get_covariance_schedule: null argument");
+    return FAR_E_INVALID;
+  }
+  *dense_threshold = g_dense_threshold;
+  return FAR_OK;
+}
+
+far_status_t far_autotune_covariances(const float* xyz, const int64_t* offsets, int32_t S_,
+                                      int64_t n_total, double voxel_size, int32_t k,
+                                      float* cov6, uint8_t* valid, int32_t reps, int32_t* best,
+                                      double* ms, far_stream_t stream) {
+  if (!best || reps < 1 || reps > 100) {
+    set_error("far_autotune_covariances: invalid argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  const int32_t saved = g_dense_threshold;
+  const int32_t cands[5] = {0, 16, 32, 64, 128};
+  double times[5];
+  int32_t win = saved;
+  double win_ms = -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  far_status_t rs = FAR_OK;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+    rs = hip_fail(e, "far_autotune_covariances setup", __FILE__, __LINE__);
+  for (int c = 0; c < 5 && rs == FAR_OK; ++c) {
+    g_dense_threshold = cands[c];
+    double bestc = 1e300;
+    for (int r = 0; r <= reps && rs == FAR_OK; ++r) {
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) {
+        rs = hip_fail(e, "far_autotune_covariances", __FILE__, __LINE__);
+        break;
+      }
+      rs = far_scan_covariances_batch(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid,
+                                      stream);
+      if (rs != FAR_OK) break;
+      float t = 0.0f;
+      if ((e = hipEventRecord(e1, st)) != hipSuccess ||
+          (e = hipEventSynchronize(e1)) != hipSuccess ||
+          (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+        rs = hip_fail(e, "far_autotune_covariances timing", __FILE__, __LINE__);
+        break;
+      }
+      if (r > 0 && t < bestc) bestc = t;
+    }
+    times[c] = bestc;
+    if (rs == FAR_OK && (win_ms < 0.0 || bestc < win_ms)) {
+      win_ms = bestc;
+      win = cands[c];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rs != FAR_OK) {
+    g_dense_threshold = saved;
+    return rs;
+  }
+  g_dense_threshold = win;
+  *best = win;
+  if (ms)
+    for (int c = 0; c < 5; ++c) ms[c] = times[c];
   return FAR_OK;
 }
 

@@ -51,6 +51,10 @@ class far_map_stats_t(C.Structure):
                 ("bytes_device", C.c_int64)]
 
 
+class far_schedule_t(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("fine_cells", C.c_int32)]
+
+
 class far_threshold_t(C.Structure):
     _fields_ = [("sigma0", C.c_double), ("r_max", C.c_double), ("min_motion", C.c_double),
                 ("sse", C.c_double), ("n_samples", C.c_int64)]
@@ -115,6 +119,16 @@ _SIGS = {
     "far_odometry_step": (C.c_int, [_P, _P, C.c_int64, C.POINTER(C.c_double),
                                     C.POINTER(far_odometry_stats_t), _P]),
     "far_odometry_destroy": (C.c_int, [_P]),
+    "far_map_get_schedule": (C.c_int, [_P, C.POINTER(far_schedule_t)]),
+    "far_map_set_schedule": (C.c_int, [_P, C.POINTER(far_schedule_t)]),
+    "far_autotune": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P,
+                               C.POINTER(far_align_params_t), C.c_int32,
+                               C.POINTER(far_schedule_t), C.POINTER(C.c_double), _P]),
+    "far_set_covariance_schedule": (C.c_int, [C.c_int32]),
+    "far_get_covariance_schedule": (C.c_int, [C.POINTER(C.c_int32)]),
+    "far_autotune_covariances": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
+                                           _P, _P, C.c_int32, C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_double), _P]),
     "far_status_str": (C.c_char_p, [C.c_int]),
     "far_last_error": (C.c_char_p, []),
 }
@@ -392,6 +406,57 @@ class Map:
 
     def export(self, stream=None):
         return far_map_export(self.h, stream=stream)
+
+
+def far_map_get_schedule(h):
+    sc = far_schedule_t()
+    _check(lib().far_map_get_schedule(h, C.byref(sc)), "far_map_get_schedule")
+    return dict(tile=sc.tile, fine_cells=sc.fine_cells)
+
+
+def far_map_set_schedule(h, tile=256, fine_cells=0):
+    sc = far_schedule_t(tile, fine_cells)
+    _check(lib().far_map_set_schedule(h, C.byref(sc)), "far_map_set_schedule")
+
+
+def far_autotune(h, src, offsets, cov6, valid, T, params: far_align_params_t, reps=3,
+                 stream=None):
+    """Returns (best schedule dict, times in ms per candidate: tiles 128, 256,
+    512, each with the voxel search then the fine cells; -1 = not run)."""
+    p, n = _pts(src, "src")
+    S = offsets.shape[0] - 1
+    best = far_schedule_t()
+    ms = (C.c_double * 6)()
+    _check(lib().far_autotune(h, p, _dev(offsets, torch.int64, "offsets"), S, n,
+                              _dev(cov6, torch.float32, "cov6"), _dev(valid, torch.uint8, "valid"),
+                              _dev(T, torch.float64, "T"), C.byref(params), reps, C.byref(best),
+                              ms, _stream(stream)), "far_autotune")
+    return dict(tile=best.tile, fine_cells=best.fine_cells), list(ms)
+
+
+def far_set_covariance_schedule(dense_threshold):
+    _check(lib().far_set_covariance_schedule(dense_threshold), "far_set_covariance_schedule")
+
+
+def far_get_covariance_schedule():
+    v = C.c_int32(0)
+    _check(lib().far_get_covariance_schedule(C.byref(v)), "far_get_covariance_schedule")
+    return v.value
+
+
+def far_autotune_covariances(xyz, offsets, voxel_size, k, reps=3, stream=None):
+    """Returns (best dense threshold, times in ms for 0, 16, 32, 64, 128)."""
+    p, n = _pts(xyz, "xyz")
+    S = offsets.shape[0] - 1
+    cov = torch.empty((6, max(n, 1)), dtype=torch.float32, device=xyz.device)
+    val = torch.empty(max(n, 1), dtype=torch.uint8, device=xyz.device)
+    best = C.c_int32(0)
+    ms = (C.c_double * 5)()
+    _check(lib().far_autotune_covariances(p, _dev(offsets, torch.int64, "offsets"), S, n,
+                                          voxel_size, k, _dev(cov, torch.float32, "cov6"),
+                                          _dev(val, torch.uint8, "valid"), reps, C.byref(best),
+                                          ms, _stream(stream)), "far_autotune_covariances")
+    return best.value, list(ms)
 
 
 def far_voxel_downsample(xyz, v, want_keep=False, stream=None):

@@ -1,0 +1,126 @@
+"""Launch schedules and the autotuners: every linearisation schedule (tile
+128/256/512, voxel or fine-cell correspondence search) and every covariance
+dense threshold gives oracle parity (neighbours bit-exact; covariances
+identical across schedules), and the autotuners set the schedule they
+report."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_26010_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [(t, f) for t in (128, 256, 512) for f in (0, 1)]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def angle_deg(A, B):
+    E = A[:3, :3] @ B[:3, :3].T
+    s = np.array([E[2, 1] - E[1, 2], E[0, 2] - E[2, 0], E[1, 0] - E[0, 1]])
+    return math.degrees(math.atan2(0.5 * np.linalg.norm(s), 0.5 * (np.trace(E) - 1)))
+
+
+@pytest.fixture(scope="module")
+def small(orc):
+    from paper_2606_26010_amd import far
+    c = synth.make_batch(7, n_scans=6, n_min=3000, n_max=40000, map_points=300_000,
+                         map_batch=300_000, n_map_batches=2)
+    gm = far.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.map_capacity,
+                 c.map_capacity, c.k)
+    om = orc.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.k,
+                 point_capacity=c.map_capacity, voxel_capacity=c.map_capacity)
+    for b in c.map_batches:
+        gm.insert(dev(b))
+        om.insert(b, check=False)
+    covs = [orc.scan_covariances(s, c.voxel_size, c.k) for s in c.scans]
+    yield far, c, gm, om, covs
+    far.far_map_set_schedule(gm.h, 256, 0)
+    gm.close()
+
+
+@pytest.mark.parametrize("tile,fine", SCHEDULES)
+def test_schedule_linearize_and_align_parity(small, tile, fine):
+    far, c, gm, om, covs = small
+    far.far_map_set_schedule(gm.h, tile, fine)
+    assert far.far_map_get_schedule(gm.h) == dict(tile=tile, fine_cells=fine)
+    s = 1
+    cov, val = covs[s][0].astype(np.float32), covs[s][1]
+    src = c.scans[s]
+    o = om.linearize(src, cov, val, c.T0[s], c.tau, c.kappa, c=c.T0[s][:3, 3], want_corr=True)
+    for prec, tol in ((0, 1e-4), (1, 1e-9)):
+        g = gm.linearize(dev(src), dev(cov), dev(val), c.T0[s], c.tau, c.kappa,
+                         c=c.T0[s][:3, 3], precision=prec, want_corr=True)
+        np.testing.assert_array_equal(host(g["corr"]), o["corr"])
+        assert rel(g["H"], o["H"]) <= tol and rel(g["b"], o["b"]) <= tol
+    ref = om.align(src, cov, val, c.T0[s], c.tau, c.kappa, max_iters=c.max_iters, eps=0.0)
+    st, T, _ = gm.align(dev(src), dev(cov), dev(val), c.T0[s],
+                        far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0))
+    assert st == ref["status"] == 0
+    assert np.linalg.norm(T[:3, 3] - ref["T"][:3, 3]) <= 1e-3 and angle_deg(T, ref["T"]) <= 1e-2
+
+
+def test_autotune_sets_reported_schedule(small):
+    far, c, gm, om, covs = small
+    sizes = np.array([s.shape[1] for s in c.scans])
+    offs = dev(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    src = dev(np.concatenate(c.scans, 1))
+    cov = dev(np.concatenate([cv[0] for cv in covs], 1).astype(np.float32))
+    val = dev(np.concatenate([cv[1] for cv in covs]))
+    T0 = dev(np.stack([t.reshape(16) for t in c.T0]))
+    prm = far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0)
+    best, ms = far.far_autotune(gm.h, src, offs, cov, val, T0, prm, reps=2)
+    print("autotune", best, ["%.3f" % x for x in ms], flush=True)
+    assert far.far_map_get_schedule(gm.h) == best
+    assert len(ms) == 6 and all(x > 0 for x in ms)               # v = 1: all six run
+    assert ms[[128, 256, 512].index(best["tile"]) * 2 + best["fine_cells"]] == min(ms)
+    np.testing.assert_array_equal(host(T0), np.stack([t.reshape(16) for t in c.T0]))  # untouched
+    T = T0.clone()
+    stats = far.decode_stats(gm.align_batch(src, offs, cov, val, T, prm))
+    torch.cuda.synchronize()
+    s = 0
+    ref = om.align(c.scans[s], covs[s][0].astype(np.float32), covs[s][1], c.T0[s], c.tau,
+                   c.kappa, max_iters=c.max_iters, eps=0.0)
+    Tb = host(T)[s].reshape(4, 4)
+    assert stats["status"][s] == 0
+    assert np.linalg.norm(Tb[:3, 3] - ref["T"][:3, 3]) <= 1e-3 and angle_deg(Tb, ref["T"]) <= 1e-2
+
+
+def test_covariance_schedules_identical(small, orc):
+    far, c, gm, om, covs = small
+    sizes = np.array([s.shape[1] for s in c.scans])
+    offs = dev(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    src = dev(np.concatenate(c.scans, 1))
+    ocov = np.concatenate([cv[0] for cv in covs], 1)
+    oval = np.concatenate([cv[1] for cv in covs])
+    saved = far.far_get_covariance_schedule()
+    first = None
+    try:
+        for thr in (0, 1, 16, 32, 1 << 20):
+            far.far_set_covariance_schedule(thr)
+            cov, val = far.far_scan_covariances_batch(src, offs, c.voxel_size, c.k)
+            cov, val = host(cov), host(val)
+            np.testing.assert_array_equal(val, oval)
+            np.testing.assert_allclose(cov, ocov, rtol=2e-6, atol=1e-6)
+            if first is None:
+                first = cov
+            np.testing.assert_array_equal(cov, first)       # same neighbours, same sums
+        best, ms = far.far_autotune_covariances(src, offs, c.voxel_size, c.k, reps=2)
+        print("covariance autotune", best, ["%.3f" % x for x in ms], flush=True)
+        assert far.far_get_covariance_schedule() == best
+        assert best in (0, 16, 32, 64, 128) and ms[(0, 16, 32, 64, 128).index(best)] == min(ms)
+    finally:
+        far.far_set_covariance_schedule(saved)

@@ -75,9 +75,9 @@ def touched_voxels(map_keys_counts, scan_xyz, T, v):
     return packed[hit], counts[idx[hit]]
 
 
-def read_traffic(fp):
+def read_traffic(fp, tile):
     """HBM bytes per linearisation launch from the committed rocprofv3 --pmc
-    summary, if it was taken on the current kernel sources."""
+    summary, if it was taken on the current kernel sources at this tile."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -85,7 +85,7 @@ def read_traffic(fp):
         if "=" in line and not line.startswith("#"):
             a, b = line.split("=", 1)
             kv[a.strip()] = b.strip()
-    if kv.get("kernel_sources_sha256_16") != fp:
+    if kv.get("kernel_sources_sha256_16") != fp or kv.get("tile") != str(tile):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -266,7 +266,7 @@ def main():
         avg_launch_ms = lin_ms / max(lin_launches, 1)
         achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
         fp = kernel_fingerprint()
-        traffic = read_traffic(fp)
+        traffic = read_traffic(fp, tile)
         log(f"[bench] linearize: {lin_launches} launches, avg {avg_launch_ms * 1e3:.1f} us, "
             f"{bytes_per_launch / 1e6:.1f} MB algorithmic per launch, {achieved:.0f} GB/s")
 

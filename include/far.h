@@ -249,6 +249,7 @@ far_status_t far_map_set_schedule(far_map_t map, const far_schedule_t* schedule)
  * candidate - tiles 128, 256, 512, each with the 27-voxel search and, for a
  * power-of-two v, the fine cells - taking the fastest of `reps` timed runs
  * (after one untimed run) of each.  The fastest schedule is set on the map
+ * (the schedule already set stays unless a candidate is more than 2 % faster)
  * and written to best [host]; ms [host, 6 entries, or NULL] receives each
  * candidate's time in the order listed (tile-major, voxel search first;
  * -1 for a candidate not run).  Synchronises `stream`. */
@@ -259,15 +260,16 @@ far_status_t far_autotune(far_map_t map, const float* src, const int64_t* offset
 
 /* Schedule of the scan covariance search (process-wide): a point whose own
  * voxel holds at least dense_threshold points searches cells of v/2 (power-
- * of-two v), others the 27 voxels; 0 = always the 27 voxels.  Default 32.
+ * of-two v), others the 27 voxels; 0 = always the 27 voxels (default).
  * Results are identical for every setting. */
 far_status_t far_set_covariance_schedule(int32_t dense_threshold);
 far_status_t far_get_covariance_schedule(int32_t* dense_threshold);
 
 /* Covariance autotuner: times far_scan_covariances_batch on the caller's
  * batch for dense thresholds 0, 16, 32, 64 and 128 (fastest of `reps`
- * timed runs after one untimed run each), sets the fastest and returns it in
- * best [host]; ms [host, 5 entries, or NULL] the times.  cov6 and valid
+ * timed runs after one untimed run each), sets the fastest (the threshold
+ * already set stays unless a candidate is more than 2 % faster) and returns
+ * it in best [host]; ms [host, 5 entries, or NULL] the times.  cov6 and valid
  * receive the covariances.  Synchronises `stream`. */
 far_status_t far_autotune_covariances(const float* xyz, const int64_t* offsets, int32_t S,
                                       int64_t n_total, double voxel_size, int32_t k,

@@ -357,19 +357,33 @@ __device__ inline void grad_term(double px, double py, double pz, float4 s, floa
 // lane takes its own next needed neighbour in the same step - so a wave does
 // as many voxel visits as its busiest lane needs, not one per offset that
 // any lane needs.
+// Squared distance to a face as a float that never exceeds the FP64 value:
+// rounded down on conversion and shrunk by 2^-20, which also covers the
+// rounding of the (at most three-term) float sums of lb2_of_f.  Only used to
+// skip voxels, so a bound below the exact one costs a visit, never a result.
+__device__ inline float lb_down(double g2) {
+  return __double2float_rd(g2) * (1.0f - 0x1p-20f);
+}
+
+__device__ inline float lb2_of_f(const float* gl2, const float* gh2, int code) {
+  const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+  return (ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0f)) + (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0f)) +
+         (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0f));
+}
+
 __device__ inline void nn_lockstep(const MapView& m, double px, double py, double pz,
-                                   int64_t kx, int64_t ky, int64_t kz, double r2,
+                                   int32_t kx, int32_t ky, int32_t kz, double r2,
                                    TopK<1>& top) {
   top.init();
   const double v = m.v, slack = 1e-7 * v;
-  double gl2[3], gh2[3];
+  float gl2[3], gh2[3];
   {
     const double l0 = fmax(px - double(kx) * v - slack, 0.0), h0 = fmax(double(kx + 1) * v - px - slack, 0.0);
     const double l1 = fmax(py - double(ky) * v - slack, 0.0), h1 = fmax(double(ky + 1) * v - py - slack, 0.0);
     const double l2 = fmax(pz - double(kz) * v - slack, 0.0), h2 = fmax(double(kz + 1) * v - pz - slack, 0.0);
-    gl2[0] = l0 * l0; gh2[0] = h0 * h0;
-    gl2[1] = l1 * l1; gh2[1] = h1 * h1;
-    gl2[2] = l2 * l2; gh2[2] = h2 * h2;
+    gl2[0] = lb_down(l0 * l0); gh2[0] = lb_down(h0 * h0);
+    gl2[1] = lb_down(l1 * l1); gh2[1] = lb_down(h1 * h1);
+    gl2[2] = lb_down(l2 * l2); gh2[2] = lb_down(h2 * h2);
   }
   Query q = make_query(px, py, pz, r2);
   int32_t cnt;
@@ -380,13 +394,13 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
     const double bnd = fmin(r2, top.bound());
 #pragma unroll
     for (int rank = 1; rank < 27; ++rank)
-      if (lb2_of(gl2, gh2, nbr_code(rank)) <= bnd) need |= 1u << rank;
+      if (double(lb2_of_f(gl2, gh2, nbr_code(rank))) <= bnd) need |= 1u << rank;
   }
   while (need) {
     const int rank = __builtin_ctz(need);
     need &= need - 1;
     const int code = nbr_code(rank);
-    if (lb2_of(gl2, gh2, code) > fmin(r2, top.bound())) continue;
+    if (double(lb2_of_f(gl2, gh2, code)) > fmin(r2, top.bound())) continue;
     vox = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
     if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
   }
@@ -405,8 +419,13 @@ __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool p
 // kGrad selects the gradient of the cost instead of H, b: 14 sums (the 3x4
 // gradient of [R | t], cost, count) and, when grad_src is given, each
 // point's source gradient written SoA at its original index (n_src apart).
-template <class Real, bool kGrad, int kB>
-__global__ __launch_bounds__(kB) void k_linearize(
+// Waves per SIMD asked of the FP32 voxel-search instantiation: the kernel
+// waits on chains of dependent gathers, so occupancy is what hides them.
+constexpr int kMinWaves = 7;
+
+template <class Real, bool kGrad, int kB, bool kFine>
+__global__ __launch_bounds__(kB, (std::is_same<Real, float>::value && !kFine) ? kMinWaves : 1)
+void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
     const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
@@ -435,17 +454,11 @@ __global__ __launch_bounds__(kB) void k_linearize(
     const int64_t i = lo + tid;
     const bool in_tile = i < hi;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 sB = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 sC = make_float2(0.f, 0.f);
-    if (in_tile) {
-      a = pA[i];
-      sB = pB[i];
-      sC = pC[i];
-    }
+    if (in_tile) a = pA[i];
     // p = R s + t in FP64 (FMA-free), and its map voxel key
     bool have = in_tile && isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
     double px = 0.0, py = 0.0, pz = 0.0;
-    int64_t kx = 0, ky = 0, kz = 0;
+    int64_t kx = 0, ky = 0, kz = 0;   // within [-2^20, 2^20) once have holds
     if (have) {
       const double sx = a.x, sy = a.y, sz = a.z;
       px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
@@ -458,19 +471,24 @@ __global__ __launch_bounds__(kB) void k_linearize(
     TopK<1> top;
     top.init();
     if (have) {
-      if (prm.fine_nn && m.fine_ok)
+      if constexpr (kFine)
         knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
                      [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
                        return fine_find(m, a0, a1, a2, n);
                      },
                      top);
-      else nn_lockstep(m, px, py, pz, kx, ky, kz, prm.r2, top);
+      else
+        nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, top);
     }
     int32_t match = -1;
     Real gs[3] = {Real(0), Real(0), Real(0)};
     if (have && top.pos[0] >= 0) {
       match = top.id[0];
-      const float4 r = (prm.fine_nn && m.fine_ok) ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
+      const float4 r = kFine ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
+      // the source covariance is read only now: not holding it through the
+      // search keeps the register count (and so the occupancy) down
+      const float4 sB = pB[i];
+      const float2 sC = pC[i];
       const float4 ca = m.cov[2 * int64_t(match)];
       const float4 cb = m.cov[2 * int64_t(match) + 1];
       if constexpr (kGrad)
@@ -809,17 +827,22 @@ struct Job {
 template <class Real, bool kGrad>
 far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapView& mv,
                         const AlignWS* w, int64_t max_tiles, const Job& j) {
-  switch (tile) {
-#define FAR_LIN_CASE(B)                                                                   \
-  case B:                                                                                 \
-    k_linearize<Real, kGrad, B><<<unsigned(grid), B, 0, st>>>(                           \
+  // the fine-cell search only where the index exists for the current map
+  const bool fine = j.prm.fine_nn && mv.fine_ok;
+  switch (tile * 2 + (fine ? 1 : 0)) {
+#define FAR_LIN_CASE(B, F)                                                                \
+  case B * 2 + F:                                                                         \
+    k_linearize<Real, kGrad, B, F><<<unsigned(grid), B, 0, st>>>(                        \
         mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
         w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
         j.n_total);                                                                       \
     break;
-    FAR_LIN_CASE(128)
-    FAR_LIN_CASE(256)
-    FAR_LIN_CASE(512)
+    FAR_LIN_CASE(128, 0)
+    FAR_LIN_CASE(128, 1)
+    FAR_LIN_CASE(256, 0)
+    FAR_LIN_CASE(256, 1)
+    FAR_LIN_CASE(512, 0)
+    FAR_LIN_CASE(512, 1)
 #undef FAR_LIN_CASE
     default:
       set_error("internal: unsupported tile size %d", tile);
@@ -1123,6 +1146,8 @@ far_status_t far_map_set_schedule(far_map_t m, const far_schedule_t* sc) {
   return FAR_OK;
 }
 
+static int32_t tiles_of(int c) { return c / 2 == 0 ? 128 : (c / 2 == 1 ? 256 : 512); }
+
 far_status_t far_autotune(far_map_t m, const float* src, const int64_t* offsets, int32_t S_,
                           int64_t n_total, const float* cov6, const uint8_t* valid,
                           const double* T, const far_align_params_t* params, int32_t reps,
@@ -1204,6 +1229,12 @@ far_status_t far_autotune(far_map_t m, const float* src, const int64_t* offsets,
     m->sched_fine = saved.fine_cells;
     return rs;
   }
+  // the schedule in place stays unless a candidate beats it by more than 2 %
+  // (equivalent schedules would otherwise flip with timing noise)
+  for (int c = 0; c < 6; ++c)
+    if (tiles_of(c) == saved.tile && (c % 2) == saved.fine_cells && times[c] > 0.0 &&
+        times[c] <= 1.02 * win_ms)
+      win = saved;
   m->sched_tile = win.tile;
   m->sched_fine = win.fine_cells;
   *best = win;

@@ -973,7 +973,7 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
 
 // Points per coarse voxel from which the covariance search switches to the
 // fine grid.
-static int32_t g_dense_threshold = 32;
+static int32_t g_dense_threshold = 0;
 
 static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
                                   int64_t n, double voxel_size, int32_t k, float* cov6,
@@ -1158,6 +1158,9 @@ far_status_t far_autotune_covariances(const float* xyz, const int64_t* offsets, 
     g_dense_threshold = saved;
     return rs;
   }
+  // the threshold in place stays unless a candidate beats it by more than 2 %
+  for (int c = 0; c < 5; ++c)
+    if (cands[c] == saved && times[c] <= 1.02 * win_ms) win = saved;
   g_dense_threshold = win;
   *best = win;
   if (ms)

@@ -86,7 +86,7 @@ def test_autotune_sets_reported_schedule(small):
     print("autotune", best, ["%.3f" % x for x in ms], flush=True)
     assert far.far_map_get_schedule(gm.h) == best
     assert len(ms) == 6 and all(x > 0 for x in ms)               # v = 1: all six run
-    assert ms[[128, 256, 512].index(best["tile"]) * 2 + best["fine_cells"]] == min(ms)
+    assert ms[[128, 256, 512].index(best["tile"]) * 2 + best["fine_cells"]] <= 1.02 * min(ms)
     np.testing.assert_array_equal(host(T0), np.stack([t.reshape(16) for t in c.T0]))  # untouched
     T = T0.clone()
     stats = far.decode_stats(gm.align_batch(src, offs, cov, val, T, prm))
@@ -121,6 +121,7 @@ def test_covariance_schedules_identical(small, orc):
         best, ms = far.far_autotune_covariances(src, offs, c.voxel_size, c.k, reps=2)
         print("covariance autotune", best, ["%.3f" % x for x in ms], flush=True)
         assert far.far_get_covariance_schedule() == best
-        assert best in (0, 16, 32, 64, 128) and ms[(0, 16, 32, 64, 128).index(best)] == min(ms)
+        assert best in (0, 16, 32, 64, 128)
+        assert ms[(0, 16, 32, 64, 128).index(best)] <= 1.02 * min(ms)
     finally:
         far.far_set_covariance_schedule(saved)

@@ -242,6 +242,61 @@ __device__ inline void knn_cells(double px, double py, double pz, double c, doub
       }
 }
 
+// Squared face distance as a float that never exceeds the FP64 value:
+// rounded down and shrunk by 2^-20 (which also covers the rounding of the
+// float sums of up to three such terms).  Used only to skip cells.
+__device__ inline float lb_down_sq(double g) {
+  return __double2float_rd(g * g) * (1.0f - 0x1p-20f);
+}
+
+// Exact K nearest points within sqrt(r2) of p over a grid of cells of edge
+// c >= sqrt(r2) (the 27 cells around p's own cell hold every candidate),
+// with the visiting rule of knn_cells for range 1: own cell, then each
+// neighbour cell whose conservative lower bound can still beat the current
+// K-th best, taken in lockstep from a per-lane bit mask.  Bounds are kept as
+// floats and cell indices as 32-bit integers to save registers.
+template <int K, class Find>
+__device__ inline void knn_cells27(double px, double py, double pz, double c, double inv_c,
+                                   bool pow2, double r2, const float4* pts, Find find,
+                                   TopK<K>& top) {
+  top.init();
+  const double fx = floor(pow2 ? px * inv_c : px / c), fy = floor(pow2 ? py * inv_c : py / c),
+               fz = floor(pow2 ? pz * inv_c : pz / c);
+  const double lim = double(kKeyBias);
+  if (!(fx >= -lim && fx < lim && fy >= -lim && fy < lim && fz >= -lim && fz < lim)) return;
+  const int32_t kx = int32_t(fx), ky = int32_t(fy), kz = int32_t(fz);
+  const double slack = 1e-7 * c;
+  float gl2[3], gh2[3];
+  gl2[0] = lb_down_sq(fmax(px - fx * c - slack, 0.0)); gh2[0] = lb_down_sq(fmax((fx + 1.0) * c - px - slack, 0.0));
+  gl2[1] = lb_down_sq(fmax(py - fy * c - slack, 0.0)); gh2[1] = lb_down_sq(fmax((fy + 1.0) * c - py - slack, 0.0));
+  gl2[2] = lb_down_sq(fmax(pz - fz * c - slack, 0.0)); gh2[2] = lb_down_sq(fmax((fz + 1.0) * c - pz - slack, 0.0));
+  Query q = make_query(px, py, pz, r2);
+  int32_t cnt;
+  int32_t st = find(kx, ky, kz, &cnt);
+  if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+  auto lb = [&](int code) {
+    const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+    return double((ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0f)) +
+                  (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0f)) +
+                  (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0f)));
+  };
+  uint32_t need = 0;
+  {
+    const double bnd = fmin(r2, top.bound());
+#pragma unroll
+    for (int rank = 1; rank < 27; ++rank)
+      if (lb(nbr_code(rank)) <= bnd) need |= 1u << rank;
+  }
+  while (need) {
+    const int rank = __builtin_ctz(need);
+    need &= need - 1;
+    const int code = nbr_code(rank);
+    if (lb(code) > fmin(r2, top.bound())) continue;
+    st = find(kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
+    if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+  }
+}
+
 // Regularised covariance (Eq. 1) of the first k entries of a neighbour list.
 // Two-pass FP64 sample covariance with 1/k, C = S + 1e-3 I, and
 // Sigma = (C^-1 / ||C^-1||_F)^-1 = ||C^-1||_F C, where ||C^-1||_F is the

@@ -453,46 +453,130 @@ __global__ __launch_bounds__(kT) void k_grid_claim(Slot* slots, uint32_t slot_ma
   }
 }
 
-// Covariance of every scan point from its k nearest points of the same scan
-// within v (processed in coarse-sorted order for locality; written at the
-// original index).  The search is exact either way; per point it takes the
-// fine grid (cells of v/2, up to two cells away, pruned by the current k-th
-// distance) when its own coarse voxel holds at least `dense` points - where
-// the k-th neighbour is close and the fine cells cut the candidates - and the
-// coarse grid (the 27 voxels) otherwise, where the finer cells would only
-// add probes.  Non-finite points keep the zero covariance / invalid flag.
+// Squared face distance as a float never above the FP64 value (rounded
+// down, shrunk by 2^-20 to cover the float sums of three terms).
+__device__ inline float face_lb(double g) { return __double2float_rd(g * g) * (1.0f - 0x1p-20f); }
+
+// Covariances, one wave per grid run (the points of one scan in one voxel of
+// edge v).  All of a run's queries share one 27-voxel neighbourhood (every
+// point within v of them lies in it), so the wave looks the 26 neighbours up
+// once and walks each needed voxel's points at wave-uniform addresses, every
+// lane testing the same candidate against its own query; a voxel that no
+// lane's current k-th distance can reach is skipped.  Exact, like the
+// per-point search: ranking by (d2, id) over a superset of the candidates.
+// Runs are dealt to the XCDs in contiguous ranges, as the linearisation's
+// tiles are.  Only runs of at least `dense` points are taken: in sparse runs
+// most lanes would idle while the wave walks the neighbourhood.
 template <int K>
-__global__ __launch_bounds__(kT) void k_grid_cov(GridView gc, GridView gf, int32_t have_fine,
-                                                 int32_t dense, int64_t n, int32_t k,
+__global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg, int32_t dense,
+                                                      int64_t n, int32_t k, float* cov6,
+                                                      uint8_t* valid) {
+  __shared__ int32_t nb_start[27];
+  __shared__ int32_t nb_cnt[27];
+  const int64_t chunk = (n_seg + 7) >> 3;
+  const int64_t sg = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (sg >= n_seg || (blockIdx.x >> 3) >= chunk) return;
+  const int lane = threadIdx.x;
+  const uint32_t s0 = g.seg_start[sg], s1 = g.seg_end[sg];
+  if (int64_t(s1 - s0) < dense) return;   // sparse runs: the per-point search
+  const uint64_t key = g.keys[s0];
+  const uint32_t sc = g.sid ? g.sid[s0] : 0u;
+  const int64_t kx = key_x(key), ky = key_y(key), kz = key_z(key);
+  if (lane < 27) {
+    int32_t st = -1, cnt = 0;
+    if (lane == 13) {
+      st = int32_t(s0);
+      cnt = int32_t(s1 - s0);
+    } else {
+      const int32_t r = grid_find(g, kx + lane / 9 - 1, ky + (lane / 3) % 3 - 1, kz + lane % 3 - 1, sc);
+      if (r >= 0) {
+        st = int32_t(g.seg_start[r]);
+        cnt = int32_t(g.seg_end[r] - g.seg_start[r]);
+      }
+    }
+    nb_start[lane] = st;
+    nb_cnt[lane] = cnt;
+  }
+  __syncthreads();
+  const double v = g.v, r2 = v * v, slack = 1e-7 * v;
+  const double bx = double(kx) * v, by = double(ky) * v, bz = double(kz) * v;
+  for (uint32_t q0 = s0; q0 < s1; q0 += 64) {
+    const uint32_t j = q0 + uint32_t(lane);
+    const bool act = j < s1;
+    const float4 me = g.sorted[act ? j : s0];
+    const double qx = me.x, qy = me.y, qz = me.z;
+    float gl2[3], gh2[3];
+    gl2[0] = face_lb(fmax(qx - bx - slack, 0.0)); gh2[0] = face_lb(fmax(bx + v - qx - slack, 0.0));
+    gl2[1] = face_lb(fmax(qy - by - slack, 0.0)); gh2[1] = face_lb(fmax(by + v - qy - slack, 0.0));
+    gl2[2] = face_lb(fmax(qz - bz - slack, 0.0)); gh2[2] = face_lb(fmax(bz + v - qz - slack, 0.0));
+    Query q = make_query(qx, qy, qz, r2);
+    TopK<K> top;
+    top.init();
+    for (int rank = 0; rank < 27; ++rank) {
+      const int code = rank == 0 ? 13 : nbr_code(rank);
+      const int32_t cnt = __builtin_amdgcn_readfirstlane(nb_cnt[code]);
+      if (cnt == 0) continue;
+      bool need = act;
+      if (rank > 0) {
+        const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+        const float lb = (ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0f)) +
+                         (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0f)) +
+                         (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0f));
+        need = need && double(lb) <= fmin(r2, top.bound());
+      }
+      if (!__any(need)) continue;
+      const int32_t st = __builtin_amdgcn_readfirstlane(nb_start[code]);
+      scan_voxel_points<K>(g.sorted, st, cnt, q, r2, top);
+    }
+    if (act) {
+      double c6[6] = {0, 0, 0, 0, 0, 0};
+      const bool ok = top.found() >= k;
+      if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
+      const int64_t i = __float_as_int(me.w);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
+      valid[i] = ok ? 1 : 0;
+    }
+  }
+}
+
+// Covariance of every scan point from its k nearest points of the same scan
+// within v, one point per lane over the 27 voxels (processed in sorted order
+// for locality; written at the original index).  Points of runs with at
+// least `dense` points (dense > 0) are left to k_grid_cov_wave.  Non-finite
+// points keep the zero covariance / invalid flag.
+// Waves per SIMD asked of the per-point covariance search (latency-bound
+// gathers, as in the linearisation).
+constexpr int kCovMinWaves = 5;
+
+template <int K>
+__global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32_t dense, int64_t n, int32_t k,
                                                  float* cov6, uint8_t* valid) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n || gc.keys[j] == kEmptyKey) return;
-  const uint32_t sc = gc.sid ? gc.sid[j] : 0u;
-  const float4 me = gc.sorted[j];
+  if (j >= n || g.keys[j] == kEmptyKey) return;
+  const uint32_t sc = g.sid ? g.sid[j] : 0u;
+  const float4 me = g.sorted[j];
   const double qx = me.x, qy = me.y, qz = me.z;
-  const uint64_t own = gc.keys[j];
-  bool fine = false;
-  if (have_fine) {
-    const int32_t so = grid_find(gc, key_x(own), key_y(own), key_z(own), sc);
-    fine = so >= 0 && int32_t(gc.seg_end[so] - gc.seg_start[so]) >= dense;
+  if (dense > 0) {
+    const uint64_t own = g.keys[j];
+    const int32_t so = grid_find(g, key_x(own), key_y(own), key_z(own), sc);
+    if (so >= 0 && int32_t(g.seg_end[so] - g.seg_start[so]) >= dense) return;
   }
   TopK<K> top;
-  const GridView& g = fine ? gf : gc;
-  knn_cells<K>(qx, qy, qz, g.c, g.inv_c, g.pow2 != 0, g.c < g.v, g.v * g.v, g.sorted,
-               [&](int64_t a0, int64_t a1, int64_t a2, int32_t* cnt) {
-                 const int32_t s = grid_find(g, a0, a1, a2, sc);
-                 if (s < 0) {
-                   *cnt = 0;
-                   return int32_t(-1);
-                 }
-                 *cnt = int32_t(g.seg_end[s] - g.seg_start[s]);
-                 return int32_t(g.seg_start[s]);
-               },
-               top);
+  knn_cells27<K>(qx, qy, qz, g.c, g.inv_c, g.pow2 != 0, g.v * g.v, g.sorted,
+                 [&](int32_t a0, int32_t a1, int32_t a2, int32_t* cnt) {
+                   const int32_t s = grid_find(g, a0, a1, a2, sc);
+                   if (s < 0) {
+                     *cnt = 0;
+                     return int32_t(-1);
+                   }
+                   *cnt = int32_t(g.seg_end[s] - g.seg_start[s]);
+                   return int32_t(g.seg_start[s]);
+                 },
+                 top);
   double c6[6] = {0, 0, 0, 0, 0, 0};
   const bool ok = top.found() >= k;
-  const float4* P = g.sorted;
-  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return P[pos]; }, c6);
+  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
   const int64_t i = __float_as_int(me.w);
 #pragma unroll
   for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
@@ -911,7 +995,7 @@ far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, doub
 // grid is then not built).
 static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t S_, int64_t n,
                                double v, double cell, hipStream_t st, Scratch& scr,
-                               GridView* out, uint32_t* oor) {
+                               GridView* out, uint32_t* oor, int64_t* runs = nullptr) {
   Runs r;
   FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
   uint64_t* keys = r.keys;
@@ -949,6 +1033,7 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   *oor = h_cnt[1];
   if (h_cnt[1] > 0) return FAR_OK;
   const int64_t n_seg = h_cnt[2];
+  if (runs) *runs = n_seg;
   int log2_slots = ceil_log2(2 * (n_seg > 0 ? n_seg : 1));
   if (log2_slots < 6) log2_slots = 6;
   const int64_t n_slots = int64_t(1) << log2_slots;
@@ -971,37 +1056,35 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   return FAR_OK;
 }
 
-// Points per coarse voxel from which the covariance search switches to the
-// fine grid.
+// Points per voxel run from which the covariance search takes one wave per
+// run (k_grid_cov_wave) instead of one lane per point; 0 = never.
 static int32_t g_dense_threshold = 0;
 
 static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
                                   int64_t n, double voxel_size, int32_t k, float* cov6,
                                   uint8_t* valid, hipStream_t st, const char* who) {
   Scratch scr(st);
-  GridView gc{}, gf{};
+  GridView g{};
   uint32_t oor = 0;
-  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &gc, &oor));
+  int64_t n_seg = 0;
+  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor, &n_seg));
   if (oor > 0) {
     set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, oor);
     return FAR_E_INVALID;
   }
-  // the fine grid (cells of v/2, exact when v is a power of two); points
-  // outside its key range leave only the coarse search
-  int e2 = 0;
-  int32_t have_fine = 0;
   const int32_t dense = g_dense_threshold;
-  if (std::frexp(voxel_size, &e2) == 0.5 && dense > 0) {
-    FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, 0.5 * voxel_size, st, scr, &gf, &oor));
-    have_fine = oor == 0 ? 1 : 0;
-  }
   FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
   FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
+  if (n_seg == 0) return FAR_OK;
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
-    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(gc, have_fine ? gf : gc, have_fine, dense, n, k,
-                                                cov6, valid);
+    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, dense, n, k, cov6, valid);
     FAR_HIP(hipGetLastError());
+    if (dense > 0) {
+      const int64_t grid = ((n_seg + 7) / 8) * 8;
+      k_grid_cov_wave<K><<<unsigned(grid), 64, 0, st>>>(g, n_seg, dense, n, k, cov6, valid);
+      FAR_HIP(hipGetLastError());
+    }
     return FAR_OK;
   });
 }

@@ -343,13 +343,7 @@ __device__ inline void grad_term(double px, double py, double pz, float4 s, floa
 // takes tile (b mod 8) * chunk + b / 8 so that each XCD works through one
 // contiguous range of tiles and neighbouring tiles - which share map voxels -
 // meet in the same L2.
-//
-// Nearest-neighbour search per lane (exact, ranked by (d2, id)): the own
-// voxel first, then every neighbour voxel whose conservative lower-bound
-// distance can still beat the current best.  The needed neighbours are kept
-// as a bit mask and visited in lockstep - each lane takes its own next
-// needed neighbour in the same step - so a wave does as many voxel visits as
-// its busiest lane needs, not one per offset any lane needs.
+
 // Exact nearest map point within sqrt(r2) of one lane's point, ranked by
 // (d2, id): the own voxel first, then every neighbour voxel whose
 // conservative lower-bound distance can still beat the current best.  The
@@ -357,34 +351,38 @@ __device__ inline void grad_term(double px, double py, double pz, float4 s, floa
 // lane takes its own next needed neighbour in the same step - so a wave does
 // as many voxel visits as its busiest lane needs, not one per offset that
 // any lane needs.
-// Squared distance to a face as a float that never exceeds the FP64 value:
-// rounded down on conversion and shrunk by 2^-20, which also covers the
-// rounding of the (at most three-term) float sums of lb2_of_f.  Only used to
-// skip voxels, so a bound below the exact one costs a visit, never a result.
-__device__ inline float lb_down(double g2) {
-  return __double2float_rd(g2) * (1.0f - 0x1p-20f);
-}
-
-__device__ inline float lb2_of_f(const float* gl2, const float* gh2, int code) {
-  const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
-  return (ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0f)) + (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0f)) +
-         (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0f));
-}
+//
+// The lower bounds come from the point's offset inside its voxel, held as
+// three floats: the float rounding (at most 2^-24 v) is covered by the slack
+// of 1e-7 v, and the squared sums are shrunk by 2^-20, so a bound never
+// exceeds the exact distance to the voxel (a low bound costs a visit, never
+// a result).
+struct FaceOffsets {
+  float f[3];     // p - voxel corner, per axis, in [0, v)
+  float v, slack;
+  __device__ inline float lb2(int code) const {
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int o = a == 0 ? code / 9 - 1 : (a == 1 ? (code / 3) % 3 - 1 : code % 3 - 1);
+      const float g = o < 0 ? fmaxf(f[a] - slack, 0.0f) : (o > 0 ? fmaxf(v - f[a] - slack, 0.0f) : 0.0f);
+      s += g * g;
+    }
+    return s * (1.0f - 0x1p-20f);
+  }
+};
 
 __device__ inline void nn_lockstep(const MapView& m, double px, double py, double pz,
                                    int32_t kx, int32_t ky, int32_t kz, double r2,
                                    TopK<1>& top) {
   top.init();
-  const double v = m.v, slack = 1e-7 * v;
-  float gl2[3], gh2[3];
-  {
-    const double l0 = fmax(px - double(kx) * v - slack, 0.0), h0 = fmax(double(kx + 1) * v - px - slack, 0.0);
-    const double l1 = fmax(py - double(ky) * v - slack, 0.0), h1 = fmax(double(ky + 1) * v - py - slack, 0.0);
-    const double l2 = fmax(pz - double(kz) * v - slack, 0.0), h2 = fmax(double(kz + 1) * v - pz - slack, 0.0);
-    gl2[0] = lb_down(l0 * l0); gh2[0] = lb_down(h0 * h0);
-    gl2[1] = lb_down(l1 * l1); gh2[1] = lb_down(h1 * h1);
-    gl2[2] = lb_down(l2 * l2); gh2[2] = lb_down(h2 * h2);
-  }
+  const double v = m.v;
+  FaceOffsets fo;
+  fo.f[0] = float(px - double(kx) * v);
+  fo.f[1] = float(py - double(ky) * v);
+  fo.f[2] = float(pz - double(kz) * v);
+  fo.v = float(v);
+  fo.slack = float(1e-7 * v);
   Query q = make_query(px, py, pz, r2);
   int32_t cnt;
   int32_t vox = map_find(m, kx, ky, kz, &cnt);
@@ -394,13 +392,13 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
     const double bnd = fmin(r2, top.bound());
 #pragma unroll
     for (int rank = 1; rank < 27; ++rank)
-      if (double(lb2_of_f(gl2, gh2, nbr_code(rank))) <= bnd) need |= 1u << rank;
+      if (double(fo.lb2(nbr_code(rank))) <= bnd) need |= 1u << rank;
   }
   while (need) {
     const int rank = __builtin_ctz(need);
     need &= need - 1;
     const int code = nbr_code(rank);
-    if (double(lb2_of_f(gl2, gh2, code)) > fmin(r2, top.bound())) continue;
+    if (double(fo.lb2(code)) > fmin(r2, top.bound())) continue;
     vox = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
     if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
   }
@@ -445,13 +443,15 @@ void k_linearize(
   const double R[9] = {Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]};
   const double tx = Ts[3], ty = Ts[7], tz = Ts[11];
   const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
-  const int64_t lo = tile_lo[t], hi = tile_hi[t];
+  // 32-bit point indices (n < 2^31): one register each where they stay live
+  // across the search
+  const uint32_t lo = tile_lo[t], hi = tile_hi[t];
 
   Real acc[kNV];
 #pragma unroll
   for (int q = 0; q < kNV; ++q) acc[q] = Real(0);
   {
-    const int64_t i = lo + tid;
+    const uint32_t i = lo + uint32_t(tid);
     const bool in_tile = i < hi;
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
     if (in_tile) a = pA[i];
@@ -496,9 +496,9 @@ void k_linearize(
       else
         gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, R, cx, cy, cz, prm.kappa2, acc);
     }
-    if (corr && in_tile) corr[__float_as_int(a.w)] = match;
+    if (corr && in_tile) corr[__float_as_uint(a.w)] = match;
     if (kGrad && grad_src && in_tile) {
-      const int64_t o = __float_as_int(a.w);
+      const uint32_t o = __float_as_uint(a.w);
       grad_src[o] = float(gs[0]);
       grad_src[n_src + o] = float(gs[1]);
       grad_src[2 * n_src + o] = float(gs[2]);

@@ -72,18 +72,23 @@ __device__ inline bool voxel_index(double x, double v, int64_t* k) {
 // delta = 2^-24 (|px| + |py| + |pz|) (rounding of p to FP32), and the FP32
 // subtraction and fused sum of squares add at most a factor (1 + 2^-24)^5.
 // So any candidate with exact d2 <= B has FP32 value
-// <= (sqrt(B) + delta)^2 (1 + 2^-24)^5, which screen_bound over-estimates
-// (margin m = 2 delta, then a factor 1 + 2^-19 before rounding to FP32).
+// <= (sqrt(B) + delta)^2 (1 + 2^-24)^5, which screen_bound over-estimates:
+// it works in FP32 (no FP64 square root in the candidate loop), with margin
+// m >= 2 delta and factors that outweigh every rounding on the way - the
+// conversion of B and the square root (2^-23 each, covered by 1 + 2^-21
+// twice), the sum and the square (2^-24 each) and the (1 + 2^-24)^5 above
+// (all covered by 1 + 2^-19).  A floor of 2^-100 keeps distances that
+// underflow FP32 inside the screen.
 struct Query {
   double x, y, z;
   float fx, fy, fz;
-  double m;
+  float m;
   float bound_f;
 };
 
-__device__ inline float screen_bound(double B, double m) {
-  const double s = sqrt(B) + m;
-  return float(s * s * (1.0 + 0x1p-19));
+__device__ inline float screen_bound(double B, float m) {
+  const float s = sqrtf(float(B) * (1.0f + 0x1p-21f)) * (1.0f + 0x1p-21f) + m;
+  return fmaxf(s * s * (1.0f + 0x1p-19f), 0x1p-100f);
 }
 
 __device__ inline Query make_query(double x, double y, double z, double r2) {
@@ -94,7 +99,7 @@ __device__ inline Query make_query(double x, double y, double z, double r2) {
   q.fx = float(x);
   q.fy = float(y);
   q.fz = float(z);
-  q.m = 0x1p-23 * (fabs(x) + fabs(y) + fabs(z)) + 1e-30;
+  q.m = float(0x1p-23 * (fabs(x) + fabs(y) + fabs(z)) + 1e-30) * (1.0f + 0x1p-21f);
   q.bound_f = screen_bound(r2, q.m);
   return q;
 }

@@ -65,7 +65,7 @@ typedef struct {
   int32_t max_pts_per_voxel;  /* N_max in [1, 64]                             */
   double min_spacing;         /* < 0: v / sqrt(N_max); 0: off; > 0: metres    */
   int64_t point_capacity;     /* >= 1, < 2^31                                 */
-  int64_t voxel_capacity;     /* <= 0: = point_capacity                       */
+  int64_t voxel_capacity;     /* < 2^25; <= 0: min(point_capacity, 2^25 - 1)  */
   int32_t k_cov;              /* neighbours per covariance, [1, 32]           */
 } far_map_params_t;
 

@@ -385,8 +385,8 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
   fo.slack = float(1e-7 * v);
   Query q = make_query(px, py, pz, r2);
   int32_t cnt;
-  int32_t vox = map_find(m, kx, ky, kz, &cnt);
-  if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
+  const int32_t own = map_find(m, kx, ky, kz, &cnt);
+  if (own >= 0) scan_voxel_points<1>(m.vox_pts, own * m.nmax, cnt, q, r2, top);
   uint32_t need = 0;
   {
     const double bnd = fmin(r2, top.bound());
@@ -394,13 +394,25 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
     for (int rank = 1; rank < 27; ++rank)
       if (double(fo.lb2(nbr_code(rank))) <= bnd) need |= 1u << rank;
   }
+  // neighbours of an existing voxel come from its row of the neighbour table
+  // (absent ones cost nothing); a point outside the map's voxels probes
+  const uint32_t* row = own >= 0 ? m.vox_nbr + int64_t(own) * 26 : nullptr;
   while (need) {
     const int rank = __builtin_ctz(need);
     need &= need - 1;
     const int code = nbr_code(rank);
     if (double(fo.lb2(code)) > fmin(r2, top.bound())) continue;
-    vox = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
-    if (vox >= 0) scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
+    int32_t vox;
+    if (row) {
+      const uint32_t e = row[nbr_dir(code)];
+      if (e == kNbrNone) continue;
+      vox = int32_t(e >> kNbrCountBits);
+      cnt = int32_t(e & ((1u << kNbrCountBits) - 1u));
+    } else {
+      vox = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
+      if (vox < 0) continue;
+    }
+    scan_voxel_points<1>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
   }
 }
 

@@ -71,6 +71,7 @@ struct MapView {
   const int32_t* vox_count;     // [voxel_cap]
   const float4* vox_pts;        // [voxel_cap * nmax]: x, y, z, id (int bits)
   const float4* cov;            // [point_cap * 2]: (xx,xy,xz,yy), (yz,zz,valid,0)
+  const uint32_t* vox_nbr;      // [voxel_cap * 26]: neighbour voxel << 7 | its count
   const float* pt_xyz;          // [3][point_cap]
   int64_t point_cap;
   double v;
@@ -86,6 +87,14 @@ struct MapView {
   double fc;                  // fine cell edge (v / 2, a power of two)
   double inv_fc;
 };
+
+// Neighbour table of the map: for every voxel and each of its 26 neighbour
+// directions (code = (ox+1)*9 + (oy+1)*3 + (oz+1), code 13 = the voxel
+// itself left out), the neighbour's voxel index << 7 | its point count, or
+// kNbrNone when the neighbour voxel does not exist.
+constexpr uint32_t kNbrNone = 0xFFFFFFFFu;
+constexpr int kNbrCountBits = 7;
+__host__ __device__ inline int nbr_dir(int code) { return code < 13 ? code : code - 1; }
 
 // Run [start, start + *cnt) of fine cell (kx, ky, kz) in fine_pts, or -1.
 __device__ inline int32_t fine_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz,
@@ -255,6 +264,7 @@ struct far_map_s {
   uint64_t* vox_key = nullptr;
   float4* vox_pts = nullptr;
   float4* cov = nullptr;
+  uint32_t* vox_nbr = nullptr;
   float* pt_xyz = nullptr;
   int32_t* pt_loc = nullptr;
   int32_t* vox_slot = nullptr;
@@ -275,6 +285,7 @@ struct far_map_s {
     m.vox_count = vox_count;
     m.vox_pts = vox_pts;
     m.cov = cov;
+    m.vox_nbr = vox_nbr;
     m.pt_xyz = pt_xyz;
     m.point_cap = p.point_capacity;
     m.v = p.voxel_size;

@@ -18,6 +18,8 @@
 #include <mutex>
 #include <type_traits>
 
+#include <algorithm>
+
 #include "far_knn.h"
 
 namespace far {
@@ -287,6 +289,36 @@ __global__ __launch_bounds__(kT) void k_counts(int64_t n_seg, const int32_t* seg
   }
   vox_count[vox] = c;
   slots[vox_slot[vox]].aux = c;
+}
+
+// Neighbour table upkeep after an insert, one thread per touched voxel run:
+// the voxel's entry (index and new count) is written into the row of every
+// existing neighbour, and a new voxel's own row is filled from the hash.  An
+// entry is written only by the thread of the voxel it names or of the voxel
+// whose row it is, with the same (final) value, so the writes need no
+// ordering.
+__global__ __launch_bounds__(kT) void k_nbr_update(MapView m, int64_t n_seg, const int32_t* seg_vox,
+                                                   const uint32_t* is_new, const uint64_t* vox_key,
+                                                   const int32_t* vox_count, uint32_t* vox_nbr) {
+  const int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  const int32_t V = seg_vox[s];
+  const bool fresh = is_new[s] != 0;
+  const uint64_t key = vox_key[V];
+  const int64_t kx = key_x(key), ky = key_y(key), kz = key_z(key);
+  const uint32_t eV = (uint32_t(V) << kNbrCountBits) | uint32_t(vox_count[V]);
+  for (int code = 0; code < 27; ++code) {
+    if (code == 13) continue;
+    int32_t cN;
+    const int32_t N = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cN);
+    const int dir = nbr_dir(code), back = nbr_dir(26 - code);
+    if (N >= 0) {
+      vox_nbr[int64_t(N) * 26 + back] = eV;
+      if (fresh) vox_nbr[int64_t(V) * 26 + dir] = (uint32_t(N) << kNbrCountBits) | uint32_t(cN);
+    } else if (fresh) {
+      vox_nbr[int64_t(V) * 26 + dir] = kNbrNone;
+    }
+  }
 }
 
 // Covariances of map points [id0, id1): k nearest within v on the map.
@@ -817,10 +849,13 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
     set_error("far_map_create: parameter out of range");
     return FAR_E_INVALID;
   }
-  if (p.voxel_capacity <= 0) p.voxel_capacity = p.point_capacity;
-  if (p.voxel_capacity >= (int64_t(1) << 29) ||
+  // the neighbour table packs a voxel index into 25 bits
+  if (p.voxel_capacity <= 0)
+    p.voxel_capacity = std::min<int64_t>(p.point_capacity, (int64_t(1) << 25) - 1);
+  if (p.voxel_capacity >= (int64_t(1) << 25) ||
       p.voxel_capacity * p.max_pts_per_voxel >= (int64_t(1) << 31)) {
-    set_error("far_map_create: voxel_capacity * max_pts_per_voxel must stay below 2^31");
+    set_error("far_map_create: need voxel_capacity < 2^25 and voxel_capacity * "
+              "max_pts_per_voxel < 2^31");
     return FAR_E_INVALID;
   }
   hipStream_t st = S(stream);
@@ -843,6 +878,7 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   size_t b_key = size_t(m->voxel_cap) * sizeof(uint64_t);
   size_t b_pts = size_t(m->voxel_cap) * p.max_pts_per_voxel * sizeof(float4);
   size_t b_cov = size_t(p.point_capacity) * 2 * sizeof(float4);
+  size_t b_nbr = size_t(m->voxel_cap) * 26 * sizeof(uint32_t);
   size_t b_xyz = size_t(p.point_capacity) * 3 * sizeof(float);
   size_t b_loc = size_t(p.point_capacity) * sizeof(int32_t);
   size_t b_vslot = size_t(m->voxel_cap) * sizeof(int32_t);
@@ -856,12 +892,13 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->vox_key, b_key)) != hipSuccess) return fail(e, "hipMalloc keys");
   if ((e = hipMalloc(&m->vox_pts, b_pts)) != hipSuccess) return fail(e, "hipMalloc points");
   if ((e = hipMalloc(&m->cov, b_cov)) != hipSuccess) return fail(e, "hipMalloc cov");
+  if ((e = hipMalloc(&m->vox_nbr, b_nbr)) != hipSuccess) return fail(e, "hipMalloc nbr");
   if ((e = hipMalloc(&m->pt_xyz, b_xyz)) != hipSuccess) return fail(e, "hipMalloc xyz");
   if ((e = hipMalloc(&m->pt_loc, b_loc)) != hipSuccess) return fail(e, "hipMalloc loc");
   if ((e = hipMalloc(&m->vox_slot, b_vslot)) != hipSuccess) return fail(e, "hipMalloc vslot");
   if ((e = hipMalloc(&m->fine_pts, b_fpts)) != hipSuccess) return fail(e, "hipMalloc fine");
   if ((e = hipMalloc(&m->fine_slots, b_fslots)) != hipSuccess) return fail(e, "hipMalloc fine");
-  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_xyz + b_loc + b_vslot + b_fpts +
+  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_nbr + b_xyz + b_loc + b_vslot + b_fpts +
                      b_fslots);
   if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipMemsetAsync(m->vox_count, 0, b_cnt, st)) != hipSuccess) return fail(e, "memset");
@@ -875,7 +912,7 @@ far_status_t far_map_destroy(far_map_t m) {
   hipError_t e = hipDeviceSynchronize();
   free_ws(m->ws);
   m->ws = nullptr;
-  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->pt_xyz,
+  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->vox_nbr, m->pt_xyz,
                   m->pt_loc, m->vox_slot, m->fine_pts, m->fine_slots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -955,6 +992,9 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
                                              r.seg_start, r.seg_end, acc_flag, id_local,
                                              n_commit, m->vox_count, m->vox_slot,
                                              m->slots_d);
+  FAR_HIP(hipGetLastError());
+  k_nbr_update<<<blocks_for(n_seg), kT, 0, st>>>(m->view(), n_seg, seg_vox, is_new, m->vox_key,
+                                                 m->vox_count, m->vox_nbr);
   FAR_HIP(hipGetLastError());
   FAR_TRY(map_covariances(m->view(), m->cov, m->n_points, m->n_points + n_commit,
                           m->p.k_cov, st));

@@ -168,6 +168,13 @@ __global__ __launch_bounds__(256) void k_order_keys(const float* src, int64_t n,
   vals[i] = uint32_t(i);
 }
 
+// No previous correspondence yet (a kernel, not a memset: the align may be
+// captured into a graph).
+__global__ __launch_bounds__(256) void k_fill_none(int32_t* a, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) a[i] = -1;
+}
+
 __global__ __launch_bounds__(256) void k_invert(const uint32_t* perm, int64_t n,
                                                 uint32_t* inv) {
   int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -373,9 +380,18 @@ struct FaceOffsets {
 };
 
 __device__ inline void nn_lockstep(const MapView& m, double px, double py, double pz,
-                                   int32_t kx, int32_t ky, int32_t kz, double r2,
+                                   int32_t kx, int32_t ky, int32_t kz, double r2, int32_t seed,
                                    TopK<1>& top) {
   top.init();
+  // seed: the point's correspondence of the previous iteration (a position in
+  // vox_pts), evaluated exactly at the current pose.  It lies within r <= v,
+  // so inside the 27 voxels searched below: the result is unchanged, but the
+  // bound is tight before the first voxel and prunes most neighbour visits.
+  if (seed >= 0) {
+    const float4 sp = m.vox_pts[seed];
+    const double d = dist2(double(sp.x), double(sp.y), double(sp.z), px, py, pz);
+    if (d <= r2) top.push(d, __float_as_int(sp.w), seed);
+  }
   const double v = m.v;
   FaceOffsets fo;
   fo.f[0] = float(px - double(kx) * v);
@@ -384,6 +400,7 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
   fo.v = float(v);
   fo.slack = float(1e-7 * v);
   Query q = make_query(px, py, pz, r2);
+  q.bound_f = screen_bound(fmin(r2, top.bound()), q.m);
   int32_t cnt;
   const int32_t own = map_find(m, kx, ky, kz, &cnt);
   if (own >= 0) scan_voxel_points<1>(m.vox_pts, own * m.nmax, cnt, q, r2, top);
@@ -441,7 +458,8 @@ void k_linearize(
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
-    int32_t* __restrict__ corr, float* __restrict__ grad_src, int64_t n_src) {
+    int32_t* __restrict__ corr, float* __restrict__ grad_src, int64_t n_src,
+    int32_t* __restrict__ prev) {
   constexpr int kWaves = kB / 64;
   constexpr int kNV = kGrad ? 14 : kVals;
   __shared__ double red[kWaves][kNV];
@@ -490,8 +508,10 @@ void k_linearize(
                      },
                      top);
       else
-        nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, top);
+        nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
+                    prev ? prev[i] : -1, top);
     }
+    if (!kFine && prev && in_tile) prev[i] = have ? top.pos[0] : -1;
     int32_t match = -1;
     Real gs[3] = {Real(0), Real(0), Real(0)};
     if (have && top.pos[0] >= 0) {
@@ -738,6 +758,7 @@ struct AlignWS {
   float4* pA = nullptr;
   float4* pB = nullptr;
   float2* pC = nullptr;
+  int32_t* prev = nullptr;      // per packed point: previous correspondence (vox_pts position)
   uint64_t* okeys = nullptr;
   uint64_t* okeys_alt = nullptr;
   uint32_t* ovals = nullptr;
@@ -760,6 +781,7 @@ void free_ws(AlignWS* w) {
   if (w->exec) (void)hipGraphExecDestroy(w->exec);
   void* ptrs[] = {w->tile_scan, w->tile_lo, w->tile_hi, w->begin, w->bad, w->done, w->ctr,
                   w->partial, w->offsets, w->T, w->cfix, w->stats, w->gsum, w->pA, w->pB, w->pC,
+                  w->prev,
                   w->okeys, w->okeys_alt, w->ovals, w->ovals_alt, w->arena};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -807,6 +829,7 @@ far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, int64_t n, Al
   FAR_HIP(hipMalloc(&w->pA, nc * sizeof(float4)));
   FAR_HIP(hipMalloc(&w->pB, nc * sizeof(float4)));
   FAR_HIP(hipMalloc(&w->pC, nc * sizeof(float2)));
+  FAR_HIP(hipMalloc(&w->prev, nc * sizeof(int32_t)));
   FAR_HIP(hipMalloc(&w->okeys, nc * sizeof(uint64_t)));
   FAR_HIP(hipMalloc(&w->okeys_alt, nc * sizeof(uint64_t)));
   FAR_HIP(hipMalloc(&w->ovals, nc * sizeof(uint32_t)));
@@ -847,7 +870,7 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
     k_linearize<Real, kGrad, B, F><<<unsigned(grid), B, 0, st>>>(                        \
         mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
         w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
-        j.n_total);                                                                       \
+        j.n_total, kGrad ? nullptr : w->prev);                                            \
     break;
     FAR_LIN_CASE(128, 0)
     FAR_LIN_CASE(128, 1)
@@ -889,6 +912,8 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
     k_invert<<<nb, 256, 0, st>>>(perm, j.n_total, inv);
     FAR_HIP(hipGetLastError());
     k_pack<<<nb, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total, inv, w->pA, w->pB, w->pC);
+    FAR_HIP(hipGetLastError());
+    k_fill_none<<<nb, 256, 0, st>>>(w->prev, j.n_total);
     FAR_HIP(hipGetLastError());
   }
   const int64_t grid = ((max_tiles + 7) / 8) * 8;   // one block per tile

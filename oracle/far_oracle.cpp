@@ -965,4 +965,79 @@ int orc_gradient(const orc_map* m, const float* src, const float* src_cov6,
   return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Adaptive submap density (Sec. III-A.3): the cap follows the density of the
+// current scan near the sensor and decays linearly over range, never below
+// the k points a covariance needs.  The near range, the decay length and the
+// rounding are readings (the paper names none).
+// ---------------------------------------------------------------------------
+int orc_asmd_caps(const float* xs, const float* xm, int64_t n, double v, int32_t k,
+                  int32_t nmax, double r_near, double r_max, int32_t* caps,
+                  double* mean_near) {
+  if (n < 0 || !(v > 0.0) || k < 1 || nmax < k || !(r_near >= 0.0) || !(r_max > 0.0)) return 1;
+  std::unordered_map<Key, int, KeyHash> vox;
+  int64_t near = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double sx = xs[i], sy = xs[n + i], sz = xs[2 * n + i];
+    double mx = xm[i], my = xm[n + i], mz = xm[2 * n + i];
+    if (!finite3(sx, sy, sz) || !finite3(mx, my, mz)) continue;
+    if ((sx * sx + sy * sy) + sz * sz <= r_near * r_near) {
+      Key K = key_of(mx, my, mz, v);
+      if (!key_in_range(K)) return 1;
+      vox[K] = 1;
+      ++near;
+    }
+  }
+  double mean = vox.empty() ? double(nmax) : double(near) / double(vox.size());
+  if (mean_near) *mean_near = mean;
+  for (int64_t i = 0; i < n; ++i) {
+    double sx = xs[i], sy = xs[n + i], sz = xs[2 * n + i];
+    int32_t cap = k;
+    if (finite3(sx, sy, sz)) {
+      double r = std::sqrt((sx * sx + sy * sy) + sz * sz);
+      double c = std::floor(mean * (1.0 - r / r_max) + 0.5);
+      cap = c < double(k) ? k : (c > double(nmax) ? nmax : int32_t(c));
+    }
+    caps[i] = cap;
+  }
+  return 0;
+}
+
+// Eviction (Sec. III-A.3): remove the voxels farther than `radius` from c,
+// judged by the voxel centre, and rebuild the map from the surviving points
+// in id order.
+int orc_map_evict(orc_map* m, const double c[3], double radius, int64_t* n_removed) {
+  if (!(radius >= 0.0)) return 1;
+  const double v = m->g.v, r2 = radius * radius;
+  const int64_t N = int64_t(m->g.pts.size());
+  orc_map fresh;
+  fresh.g.v = v;
+  fresh.nmax = m->nmax;
+  fresh.dmin = m->dmin;
+  fresh.k_cov = m->k_cov;
+  fresh.point_cap = m->point_cap;
+  fresh.voxel_cap = m->voxel_cap;
+  int64_t removed = 0;
+  for (int64_t id = 0; id < N; ++id) {
+    const Pt& p = m->g.pts[size_t(id)];
+    Key K = key_of(p.x, p.y, p.z, v);
+    double dx = (double(K.x) + 0.5) * v - c[0];
+    double dy = (double(K.y) + 0.5) * v - c[1];
+    double dz = (double(K.z) + 0.5) * v - c[2];
+    if ((dx * dx + dy * dy) + dz * dz > r2) { ++removed; continue; }
+    int64_t nid = int64_t(fresh.g.pts.size());
+    fresh.g.vox[K].push_back(nid);
+    fresh.g.pts.push_back(p);
+    fresh.fx.push_back(m->fx[size_t(id)]);
+    fresh.fy.push_back(m->fy[size_t(id)]);
+    fresh.fz.push_back(m->fz[size_t(id)]);
+    for (int t = 0; t < 6; ++t) fresh.cov.push_back(m->cov[size_t(id) * 6 + t]);
+    fresh.valid.push_back(m->valid[size_t(id)]);
+  }
+  *m = std::move(fresh);
+  if (n_removed) *n_removed = removed;
+  return 0;
+}
+
 }  // extern "C"

@@ -126,6 +126,24 @@ int orc_gradient(const orc_map* m, const float* src, const float* src_cov6,
                  double kappa, const double c[3], double grad_T[12], double grad_twist[6],
                  double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr);
 
+/* Adaptive submap density (Sec. III-A.3, ASMD).  Reading (the paper gives
+ * no constants): the mean number of points per voxel of edge v over the
+ * finite points within r_near of the sensor, counted on their map-frame voxel
+ * keys (xyz_map), or nmax when there are none; each point's cap is
+ * clamp(floor(mean (1 - r_i / r_max) + 0.5), k, nmax), r_i its sensor range
+ * (xyz_sensor), in FP64 evaluated in that order.  caps [n]; *mean_near.
+ * Returns 1 on a bad argument. */
+int orc_asmd_caps(const float* xyz_sensor, const float* xyz_map, int64_t n, double v,
+                  int32_t k, int32_t nmax, double r_near, double r_max, int32_t* caps,
+                  double* mean_near);
+
+/* Submap eviction (Sec. III-A.3, last step): voxels whose centre
+ * ((key + 1/2) v) is farther than radius from c are removed, with their
+ * points; the surviving points keep their coordinates, covariances and
+ * relative order and are renumbered consecutively; voxels are rebuilt from
+ * the surviving points (empty voxels do not survive). */
+int orc_map_evict(orc_map* m, const double c[3], double radius, int64_t* n_removed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,9 @@ def lib():
         L.orc_gradient.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p, C.c_double,
                                    C.c_double, _opt(_f64p), _f64p, _f64p, _opt(_f64p),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int64), _opt(_i32p)]
+        L.orc_asmd_caps.argtypes = [_f32p, _f32p, C.c_int64, C.c_double, C.c_int32, C.c_int32,
+                                    C.c_double, C.c_double, _i32p, C.POINTER(C.c_double)]
+        L.orc_map_evict.argtypes = [C.c_void_p, _f64p, C.c_double, C.POINTER(C.c_int64)]
         L.orc_downsample.argtypes = [_f32p, C.c_int64, C.c_double, _i64p,
                                      C.POINTER(C.c_int64)]
         L.orc_transform.argtypes = [_f32p, C.c_int64, _f64p, _f32p]
@@ -227,6 +230,16 @@ class Map:
         return dict(grad_T=gT.reshape(3, 4), grad_twist=gw, grad_src=gs, cost=cost.value,
                     n_inliers=cnt.value, corr=corr)
 
+    def evict(self, center, radius):
+        """Remove voxels whose centre is farther than radius from center;
+        returns the number of points removed."""
+        out = C.c_int64(0)
+        rc = lib().orc_map_evict(self._h, np.ascontiguousarray(center, dtype=np.float64),
+                                 radius, C.byref(out))
+        if rc:
+            raise OracleError(rc, "orc_map_evict")
+        return out.value
+
     def touch_stats(self, src, T):
         a = _soa(src)
         T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
@@ -330,7 +343,7 @@ def _nearest_rotation(R):
 
 def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing, k,
              map_capacity, downsample_v, sigma0, r_max, min_motion=0.1, max_iters=10,
-             eps=0.0):
+             eps=0.0, asmd=False, r_near=20.0, evict_radius=0.0):
     """Scan-to-submap odometry over a sequence (Sec. III-A: downsample, source
     covariances, registration against the capped submap, insertion of the
     registered scan), driven by the oracle's own steps.
@@ -342,8 +355,10 @@ def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing
     relative motion v_first (the inertial prediction of the paper's filter)
     for the second scan; the threshold and kappa come from Threshold before each
     registration and the deviation of the estimate is added after it; the
-    registered, downsampled scan is inserted; once the map is full, inserting
-    stops (the map keeps what fit).  Returns per-scan dicts with the pose,
+    registered, downsampled scan is inserted (with the adaptive submap density
+    caps of asmd_caps when asmd is set); once the map is full, inserting stops
+    (the map keeps what fit); with evict_radius > 0 the voxels farther than it
+    from the estimate's position are then removed (Sec. III-A.3).  Returns per-scan dicts with the pose,
     the prediction, tau, kappa, the align status and map sizes."""
     m = Map(voxel_size, max_pts_per_voxel, min_spacing, k, point_capacity=map_capacity,
             voxel_capacity=map_capacity)
@@ -370,9 +385,28 @@ def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing
                        deviation=thr.update(T_pred, T))
         poses.append(T)
         if not full:
-            rc, acc, _ = m.insert(transform(src, T), check=False)
+            moved = transform(src, T)
+            caps = None
+            if asmd:
+                caps, rec["asmd_mean"] = asmd_caps(src, moved, voxel_size, k, max_pts_per_voxel,
+                                                   r_near, r_max)
+            rc, acc, _ = m.insert(moved, caps, check=False)
             full = rc == 2
             rec["inserted"] = acc
+        if evict_radius > 0:
+            rec["evicted"] = m.evict(T[:3, 3], evict_radius)
         rec.update(T=T, map_points=m.size, map_voxels=m.n_voxels)
         out.append(rec)
     return out, m
+
+
+def asmd_caps(xyz_sensor, xyz_map, v, k, nmax, r_near=20.0, r_max=120.0):
+    """Per-point insert caps of the adaptive submap density; (caps, mean)."""
+    a, b = _soa(xyz_sensor), _soa(xyz_map)
+    n = a.shape[1]
+    caps = np.zeros(max(n, 1), np.int32)
+    mean = C.c_double(0)
+    rc = lib().orc_asmd_caps(a, b, n, v, k, nmax, r_near, r_max, caps, C.byref(mean))
+    if rc:
+        raise OracleError(rc, "orc_asmd_caps")
+    return caps[:n], mean.value

@@ -311,6 +311,29 @@ far_status_t far_voxel_downsample(const float* xyz, int64_t n, double v, float* 
 far_status_t far_transform_points(const float* xyz, int64_t n, const double T[16],
                                   float* out, far_stream_t stream);
 
+/* Adaptive submap density (Sec. III-A.3, ASMD): per-point insert caps that
+ * follow the current scan's density near the sensor and decay over range
+ * (the paper gives no constants; reading): mean = points per voxel of edge v
+ * over the finite points within r_near of the sensor, counted on their
+ * map-frame voxels (nmax when there are none); cap_i = clamp(floor(mean
+ * (1 - r_i / r_max) + 0.5), k, nmax) with r_i the point's sensor range, in
+ * FP64 in that order.  xyz_sensor and xyz_map [dev, SoA 3 x n] are the same
+ * points in the sensor and the map frame; caps [dev, n] (non-finite points:
+ * k), to pass to far_map_insert; mean_near [host, or NULL].  Near keys
+ * outside [-2^20, 2^20): FAR_E_INVALID.  Synchronises `stream`. */
+far_status_t far_asmd_caps(const float* xyz_sensor, const float* xyz_map, int64_t n, double v,
+                           int32_t k, int32_t nmax, double r_near, double r_max, int32_t* caps,
+                           double* mean_near, far_stream_t stream);
+
+/* Submap eviction (Sec. III-A.3, last step): removes every voxel whose centre
+ * ((key + 1/2) v per axis) is farther than radius from c [host, 3], with its
+ * points; the surviving points keep their coordinates, covariances (not
+ * recomputed) and relative order and are renumbered 0..N'-1; the voxel
+ * structures are rebuilt from them (voxels left empty do not survive).
+ * n_removed [host, or NULL].  Synchronises `stream`. */
+far_status_t far_map_evict(far_map_t map, const double c[3], double radius,
+                           int64_t* n_removed, far_stream_t stream);
+
 /* Adaptive correspondence threshold tau and Cauchy scale kappa (Sec. III-A.2
  * adapts both to the motion following Vizzo et al., KISS-ICP; read as its
  * published rule).  The deviation of an estimate T_est from its motion
@@ -343,6 +366,9 @@ typedef struct {
   int32_t max_iters;      /* Gauss-Newton iterations per scan, 1..64          */
   double eps;             /* stop when ||delta|| <= eps                       */
   int32_t precision;      /* far_precision_t                                  */
+  int32_t asmd;           /* 1: insert with far_asmd_caps caps (ASMD)         */
+  double r_near;          /* ASMD near range, metres                          */
+  double evict_radius;    /* > 0: far_map_evict around the pose after insert  */
 } far_odometry_params_t;
 
 typedef struct {
@@ -353,6 +379,8 @@ typedef struct {
   int64_t n_inserted;     /* points the map accepted                          */
   int32_t map_full;       /* the map reached its point capacity               */
   int32_t reserved;
+  int64_t n_evicted;      /* map points removed by the eviction               */
+  double asmd_mean;       /* ASMD near-range mean points per voxel (0: off)   */
   double tau, kappa;      /* threshold and Cauchy scale used (0 for the first)*/
   double deviation;       /* deviation of the estimate from the prediction    */
   double T_pred[16];      /* motion prediction (the initial guess)            */
@@ -373,8 +401,10 @@ far_status_t far_odometry_create(far_map_t map, const far_odometry_params_t* par
  * the first, covariances of the downsampled scan, tau and kappa from the
  * threshold, align from T_pred, and the deviation added to the threshold (a
  * failed align keeps T_pred and is reported in stats->status); then the
- * downsampled scan, moved by the estimate, is inserted into the map until the
- * map is full.  T_out [host] receives the estimate; stats [host, or NULL].
+ * downsampled scan, moved by the estimate, is inserted into the map (with
+ * ASMD caps when params.asmd is set) until the map is full, and with
+ * params.evict_radius > 0 the voxels farther than it from the estimate's
+ * position are removed (Sec. III-A.3).  T_out [host] receives the estimate; stats [host, or NULL].
  * Returns FAR_OK unless an argument, a key range or the HIP runtime fails.
  * Synchronises `stream`. */
 far_status_t far_odometry_step(far_odometry_t od, const float* xyz, int64_t n,

@@ -321,6 +321,140 @@ __global__ __launch_bounds__(kT) void k_nbr_update(MapView m, int64_t n_seg, con
   }
 }
 
+// ---------------------------------------------------------------- ASMD
+// Near-range points of the scan (sensor range <= r_near) and the distinct
+// map-frame voxels they fall in, counted through a temporary hash set of
+// keys (counters: [0] near points, [1] distinct voxels, [2] out of range).
+__global__ __launch_bounds__(kT) void k_asmd_count(const float* xs, const float* xm, int64_t n,
+                                                   double v, double rn2, uint64_t* set,
+                                                   uint32_t set_mask, int set_log2,
+                                                   uint32_t* counters) {
+  const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  const double sx = xs[i], sy = xs[n + i], sz = xs[2 * n + i];
+  const double mx = xm[i], my = xm[n + i], mz = xm[2 * n + i];
+  if (!(isfinite(sx) && isfinite(sy) && isfinite(sz) && isfinite(mx) && isfinite(my) &&
+        isfinite(mz)))
+    return;
+  if ((sx * sx + sy * sy) + sz * sz > rn2) return;
+  int64_t kx, ky, kz;
+  if (!voxel_index(mx, v, &kx) || !voxel_index(my, v, &ky) || !voxel_index(mz, v, &kz)) {
+    atomicAdd(&counters[2], 1u);
+    return;
+  }
+  atomicAdd(&counters[0], 1u);
+  const uint64_t key = pack_key(kx, ky, kz);
+  uint32_t h = voxel_hash(kx, ky, kz, set_log2);
+  for (uint32_t probe = 0; probe <= set_mask; ++probe) {
+    const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&set[h]),
+                                             (unsigned long long)kEmptyKey,
+                                             (unsigned long long)key);
+    if (old == kEmptyKey) {
+      atomicAdd(&counters[1], 1u);
+      return;
+    }
+    if (old == key) return;
+    h = (h + 1) & set_mask;
+  }
+}
+
+// cap_i = clamp(floor(mean (1 - r_i / r_max) + 0.5), k, nmax), FP64 in this
+// order (no contraction); non-finite points get k.
+__global__ __launch_bounds__(kT) void k_asmd_caps(const float* xs, int64_t n, double mean,
+                                                  double r_max, int32_t k, int32_t nmax,
+                                                  int32_t* caps) {
+  const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  const double sx = xs[i], sy = xs[n + i], sz = xs[2 * n + i];
+  int32_t cap = k;
+  if (isfinite(sx) && isfinite(sy) && isfinite(sz)) {
+    const double r = sqrt((sx * sx + sy * sy) + sz * sz);
+    const double c = floor(mean * (1.0 - r / r_max) + 0.5);
+    cap = c < double(k) ? k : (c > double(nmax) ? nmax : int32_t(c));
+  }
+  caps[i] = cap;
+}
+
+// ---------------------------------------------------------------- eviction
+// Keep flag of every map point: its voxel centre within radius of c.
+__global__ __launch_bounds__(kT) void k_evict_keep(const float* pt_xyz, int64_t point_cap,
+                                                   int64_t n, double v, double cx, double cy,
+                                                   double cz, double r2, uint32_t* keep) {
+  const int64_t id = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (id >= n) return;
+  int64_t kx = 0, ky = 0, kz = 0;
+  (void)voxel_index(double(pt_xyz[id]), v, &kx);
+  (void)voxel_index(double(pt_xyz[point_cap + id]), v, &ky);
+  (void)voxel_index(double(pt_xyz[2 * point_cap + id]), v, &kz);
+  const double dx = (double(kx) + 0.5) * v - cx;
+  const double dy = (double(ky) + 0.5) * v - cy;
+  const double dz = (double(kz) + 0.5) * v - cz;
+  keep[id] = ((dx * dx + dy * dy) + dz * dz <= r2) ? 1u : 0u;
+}
+
+// Survivors, in id order, into compact SoA coordinates and covariances.
+__global__ __launch_bounds__(kT) void k_evict_gather(const float* pt_xyz, const float4* cov,
+                                                     int64_t point_cap, int64_t n,
+                                                     const uint32_t* keep, const uint32_t* nid,
+                                                     int64_t n_keep, float* xyz_out,
+                                                     float4* cov_out) {
+  const int64_t id = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (id >= n || !keep[id]) return;
+  const int64_t j = nid[id];
+  xyz_out[j] = pt_xyz[id];
+  xyz_out[n_keep + j] = pt_xyz[point_cap + id];
+  xyz_out[2 * n_keep + j] = pt_xyz[2 * point_cap + id];
+  cov_out[2 * j] = cov[2 * id];
+  cov_out[2 * j + 1] = cov[2 * id + 1];
+}
+
+__global__ __launch_bounds__(kT) void k_evict_store(const float* xyz, int64_t n_keep,
+                                                    int64_t point_cap, float* pt_xyz) {
+  const int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n_keep) return;
+  pt_xyz[j] = xyz[j];
+  pt_xyz[point_cap + j] = xyz[n_keep + j];
+  pt_xyz[2 * point_cap + j] = xyz[2 * n_keep + j];
+}
+
+// Every run of the rebuild is a new voxel, numbered in sorted key order.
+__global__ __launch_bounds__(kT) void k_all_new(int64_t n_seg, uint32_t* is_new,
+                                                uint32_t* rank) {
+  const int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  is_new[s] = 1u;
+  rank[s] = uint32_t(s);
+}
+
+// Place the sorted survivors: a run's points keep their (id) order.
+__global__ __launch_bounds__(kT) void k_bulk_place(const float* xyz, int64_t n,
+                                                   const uint64_t* keys, const uint32_t* vals,
+                                                   const uint32_t* head, const uint32_t* head_scan,
+                                                   const uint32_t* seg_start,
+                                                   const int32_t* seg_vox, int32_t nmax,
+                                                   float4* vox_pts, int32_t* pt_loc) {
+  const int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (j >= n || keys[j] == kEmptyKey) return;
+  const uint32_t s = head_scan[j] + head[j] - 1;
+  const int32_t pos = seg_vox[s] * nmax + int32_t(uint32_t(j) - seg_start[s]);
+  const uint32_t id = vals[j];
+  vox_pts[pos] = make_float4(xyz[id], xyz[n + id], xyz[2 * n + id], __int_as_float(int32_t(id)));
+  pt_loc[id] = pos;
+}
+
+__global__ __launch_bounds__(kT) void k_bulk_counts(int64_t n_seg, const uint32_t* seg_start,
+                                                    const uint32_t* seg_end,
+                                                    const int32_t* seg_vox,
+                                                    const int32_t* vox_slot, int32_t* vox_count,
+                                                    Slot* slots) {
+  const int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg) return;
+  const int32_t vox = seg_vox[s];
+  const int32_t c = int32_t(seg_end[s] - seg_start[s]);
+  vox_count[vox] = c;
+  slots[vox_slot[vox]].aux = c;
+}
+
 // Covariances of map points [id0, id1): k nearest within v on the map.
 template <int K>
 __global__ __launch_bounds__(kT) void k_map_cov(MapView m, float4* cov, int64_t id0,
@@ -1288,6 +1422,137 @@ far_status_t far_autotune_covariances(const float* xyz, const int64_t* offsets, 
   *best = win;
   if (ms)
     for (int c = 0; c < 5; ++c) ms[c] = times[c];
+  return FAR_OK;
+}
+
+far_status_t far_asmd_caps(const float* xyz_sensor, const float* xyz_map, int64_t n, double v,
+                           int32_t k, int32_t nmax, double r_near, double r_max, int32_t* caps,
+                           double* mean_near, far_stream_t stream) {
+  if (n < 0 || n >= (int64_t(1) << 31) || !(v > 0.0) || !std::isfinite(v) || k < 1 ||
+      nmax < k || nmax > 64 || !(r_near >= 0.0) || !(r_max > 0.0) ||
+      (n > 0 && (!xyz_sensor || !xyz_map || !caps))) {
+    set_error("far_asmd_caps: invalid argument");
+    return FAR_E_INVALID;
+  }
+  double mean = double(nmax);
+  if (n > 0) {
+    hipStream_t st = S(stream);
+    Scratch scr(st);
+    const int set_log2 = std::max(6, ceil_log2(2 * n));
+    const int64_t set_n = int64_t(1) << set_log2;
+    uint64_t* set;
+    uint32_t* counters;
+    FAR_TRY(scr.get(&set, size_t(set_n)));
+    FAR_TRY(scr.get(&counters, 3));
+    FAR_HIP(hipMemsetAsync(set, 0xFF, size_t(set_n) * sizeof(uint64_t), st));
+    FAR_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(uint32_t), st));
+    k_asmd_count<<<blocks_for(n), kT, 0, st>>>(xyz_sensor, xyz_map, n, v, r_near * r_near, set,
+                                               uint32_t(set_n - 1), set_log2, counters);
+    FAR_HIP(hipGetLastError());
+    uint32_t h[3];
+    FAR_HIP(hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, st));
+    FAR_HIP(hipStreamSynchronize(st));
+    if (h[2] > 0) {
+      set_error("far_asmd_caps: %u near points have voxel keys outside [-2^20, 2^20)", h[2]);
+      return FAR_E_INVALID;
+    }
+    if (h[1] > 0) mean = double(h[0]) / double(h[1]);
+    k_asmd_caps<<<blocks_for(n), kT, 0, st>>>(xyz_sensor, n, mean, r_max, k, nmax, caps);
+    FAR_HIP(hipGetLastError());
+  }
+  if (mean_near) *mean_near = mean;
+  return FAR_OK;
+}
+
+far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_t* n_removed,
+                           far_stream_t stream) {
+  if (n_removed) *n_removed = 0;
+  if (!m || !c || !(radius >= 0.0) || !std::isfinite(c[0]) || !std::isfinite(c[1]) ||
+      !std::isfinite(c[2])) {
+    set_error("far_map_evict: invalid argument");
+    return FAR_E_INVALID;
+  }
+  const int64_t n = m->n_points;
+  hipStream_t st = S(stream);
+  const double v = m->p.voxel_size;
+  if (n == 0) {
+    // only empty voxels can be held: drop them too (the map is rebuilt from
+    // its surviving points)
+    if (m->n_voxels > 0) {
+      FAR_HIP(hipMemsetAsync(m->slots_d, 0xFF, size_t(m->slots) * sizeof(Slot), st));
+      FAR_HIP(hipMemsetAsync(m->vox_count, 0, size_t(m->n_voxels) * sizeof(int32_t), st));
+      FAR_HIP(hipStreamSynchronize(st));
+      m->n_voxels = 0;
+      m->fine_ok = false;
+    }
+    return FAR_OK;
+  }
+  Scratch scr(st);
+  uint32_t *keep, *nid, *total;
+  FAR_TRY(scr.get(&keep, size_t(n)));
+  FAR_TRY(scr.get(&nid, size_t(n)));
+  FAR_TRY(scr.get(&total, 1));
+  k_evict_keep<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->p.point_capacity, n, v, c[0], c[1],
+                                             c[2], radius * radius, keep);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(keep, nid, n, total, st, scr));
+  uint32_t h_keep = 0;
+  FAR_HIP(hipMemcpyAsync(&h_keep, total, sizeof(h_keep), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  const int64_t n_keep = h_keep;
+  if (n_keep == n) return FAR_OK;
+  float* xyz;
+  float4* cv;
+  FAR_TRY(scr.get(&xyz, size_t(3 * std::max<int64_t>(n_keep, 1))));
+  FAR_TRY(scr.get(&cv, size_t(2 * std::max<int64_t>(n_keep, 1))));
+  k_evict_gather<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->cov, m->p.point_capacity, n, keep,
+                                               nid, n_keep, xyz, cv);
+  FAR_HIP(hipGetLastError());
+  // clear the voxel structures, then store the survivors and rebuild them
+  FAR_HIP(hipMemsetAsync(m->slots_d, 0xFF, size_t(m->slots) * sizeof(Slot), st));
+  FAR_HIP(hipMemsetAsync(m->vox_count, 0, size_t(m->n_voxels) * sizeof(int32_t), st));
+  m->n_points = 0;
+  m->n_voxels = 0;
+  m->fine_ok = false;
+  if (n_removed) *n_removed = n - n_keep;
+  if (n_keep == 0) {
+    FAR_HIP(hipStreamSynchronize(st));
+    return FAR_OK;
+  }
+  k_evict_store<<<blocks_for(n_keep), kT, 0, st>>>(xyz, n_keep, m->p.point_capacity, m->pt_xyz);
+  FAR_HIP(hipGetLastError());
+  FAR_HIP(hipMemcpyAsync(m->cov, cv, size_t(n_keep) * 2 * sizeof(float4),
+                         hipMemcpyDeviceToDevice, st));
+  Runs r;
+  FAR_TRY(build_runs(xyz, n_keep, v, st, scr, r));
+  uint32_t h_cnt[4];
+  FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  const int64_t n_seg = h_cnt[2];
+  int32_t* seg_vox;
+  uint32_t *is_new, *rank;
+  FAR_TRY(scr.get(&seg_vox, size_t(n_seg)));
+  FAR_TRY(scr.get(&is_new, size_t(n_seg)));
+  FAR_TRY(scr.get(&rank, size_t(n_seg)));
+  k_all_new<<<blocks_for(n_seg), kT, 0, st>>>(n_seg, is_new, rank);
+  FAR_HIP(hipGetLastError());
+  k_seg_claim<<<blocks_for(n_seg), kT, 0, st>>>(m->slots_d, uint32_t(m->slots - 1),
+                                                m->log2_slots, r.keys, r.seg_start, is_new, rank,
+                                                n_seg, 0, seg_vox, m->vox_key, m->vox_slot);
+  FAR_HIP(hipGetLastError());
+  k_bulk_place<<<blocks_for(n_keep), kT, 0, st>>>(xyz, n_keep, r.keys, r.vals, r.head,
+                                                  r.head_scan, r.seg_start, seg_vox,
+                                                  m->p.max_pts_per_voxel, m->vox_pts, m->pt_loc);
+  FAR_HIP(hipGetLastError());
+  k_bulk_counts<<<blocks_for(n_seg), kT, 0, st>>>(n_seg, r.seg_start, r.seg_end, seg_vox,
+                                                  m->vox_slot, m->vox_count, m->slots_d);
+  FAR_HIP(hipGetLastError());
+  k_nbr_update<<<blocks_for(n_seg), kT, 0, st>>>(m->view(), n_seg, seg_vox, is_new, m->vox_key,
+                                                 m->vox_count, m->vox_nbr);
+  FAR_HIP(hipGetLastError());
+  m->n_points = n_keep;
+  m->n_voxels = n_seg;
+  FAR_HIP(hipStreamSynchronize(st));
   return FAR_OK;
 }
 

@@ -85,16 +85,18 @@ struct far_odometry_s {
   float* moved = nullptr;    // the same points in the map frame
   float* cov = nullptr;      // SoA [6][cap]
   uint8_t* valid = nullptr;  // [cap]
+  int32_t* caps = nullptr;   // ASMD caps [cap]
 };
 
 namespace {
 
 void release(far_odometry_s* o) {
-  void* ptrs[] = {o->down, o->moved, o->cov, o->valid};
+  void* ptrs[] = {o->down, o->moved, o->cov, o->valid, o->caps};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   o->down = o->moved = o->cov = nullptr;
   o->valid = nullptr;
+  o->caps = nullptr;
   o->cap = 0;
 }
 
@@ -107,6 +109,7 @@ far_status_t reserve(far_odometry_s* o, int64_t n, hipStream_t st) {
   FAR_HIP(hipMalloc(&o->moved, size_t(cap) * 3 * sizeof(float)));
   FAR_HIP(hipMalloc(&o->cov, size_t(cap) * 6 * sizeof(float)));
   FAR_HIP(hipMalloc(&o->valid, size_t(cap)));
+  FAR_HIP(hipMalloc(&o->caps, size_t(cap) * sizeof(int32_t)));
   o->cap = cap;
   return FAR_OK;
 }
@@ -172,7 +175,8 @@ far_status_t far_odometry_create(far_map_t map, const far_odometry_params_t* par
   if (!map || !params || !T_first || !out || !finite16(T_first) ||
       (v_first && !finite16(v_first)) || !(params->downsample > 0.0) ||
       !std::isfinite(params->downsample) || params->max_iters < 1 || params->max_iters > 64 ||
-      !(params->eps >= 0.0) ||
+      !(params->eps >= 0.0) || !(params->r_near >= 0.0) || !(params->evict_radius >= 0.0) ||
+      (params->asmd != 0 && params->asmd != 1) ||
       (params->precision != FAR_PREC_FP32 && params->precision != FAR_PREC_FP64)) {
     far::set_error("far_odometry_create: invalid argument");
     return FAR_E_INVALID;
@@ -243,13 +247,25 @@ far_status_t far_odometry_step(far_odometry_t o, const float* xyz, int64_t n, do
   }
   if (!o->full && m > 0) {
     FAR_TRY(far_transform_points(o->down, m, T, o->moved, stream));
+    const int32_t* caps = nullptr;
+    if (o->p.asmd) {
+      const far_map_s* mp = o->map;
+      FAR_TRY(far_asmd_caps(o->down, o->moved, m, mp->p.voxel_size, mp->p.k_cov,
+                            mp->p.max_pts_per_voxel, o->p.r_near, o->p.r_max, o->caps,
+                            &sx.asmd_mean, stream));
+      caps = o->caps;
+    }
     int64_t acc = 0;
-    far_status_t s = far_map_insert(o->map, o->moved, m, nullptr, stream, &acc);
+    far_status_t s = far_map_insert(o->map, o->moved, m, caps, stream, &acc);
     if (s == FAR_E_CAPACITY)
       o->full = true;
     else if (s != FAR_OK)
       return s;
     sx.n_inserted = acc;
+  }
+  if (o->p.evict_radius > 0.0) {
+    const double c[3] = {T[3], T[7], T[11]};
+    FAR_TRY(far_map_evict(o->map, c, o->p.evict_radius, &sx.n_evicted, stream));
   }
   sx.map_full = o->full ? 1 : 0;
   std::memcpy(o->T_prev2, o->T_prev, sizeof(T));

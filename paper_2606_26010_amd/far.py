@@ -63,13 +63,15 @@ class far_threshold_t(C.Structure):
 class far_odometry_params_t(C.Structure):
     _fields_ = [("downsample", C.c_double), ("sigma0", C.c_double), ("r_max", C.c_double),
                 ("min_motion", C.c_double), ("max_iters", C.c_int32), ("eps", C.c_double),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("asmd", C.c_int32), ("r_near", C.c_double),
+                ("evict_radius", C.c_double)]
 
 
 class far_odometry_stats_t(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("n_raw", C.c_int64),
                 ("n_down", C.c_int64), ("n_inserted", C.c_int64), ("map_full", C.c_int32),
-                ("reserved", C.c_int32), ("tau", C.c_double), ("kappa", C.c_double),
+                ("reserved", C.c_int32), ("n_evicted", C.c_int64), ("asmd_mean", C.c_double),
+                ("tau", C.c_double), ("kappa", C.c_double),
                 ("deviation", C.c_double), ("T_pred", C.c_double * 16), ("last", far_lin_t)]
 
 
@@ -129,6 +131,10 @@ _SIGS = {
     "far_autotune_covariances": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
                                            _P, _P, C.c_int32, C.POINTER(C.c_int32),
                                            C.POINTER(C.c_double), _P]),
+    "far_asmd_caps": (C.c_int, [_P, _P, C.c_int64, C.c_double, C.c_int32, C.c_int32,
+                                C.c_double, C.c_double, _P, C.POINTER(C.c_double), _P]),
+    "far_map_evict": (C.c_int, [_P, C.POINTER(C.c_double), C.c_double, C.POINTER(C.c_int64),
+                                _P]),
     "far_status_str": (C.c_char_p, [C.c_int]),
     "far_last_error": (C.c_char_p, []),
 }
@@ -392,6 +398,9 @@ class Map:
     def linearize(self, *a, **kw):
         return far_gicp_linearize(self.h, *a, **kw)
 
+    def evict(self, center, radius, stream=None):
+        return far_map_evict(self.h, center, radius, stream)
+
     def gradient(self, *a, **kw):
         return far_gicp_gradient(self.h, *a, **kw)
 
@@ -406,6 +415,27 @@ class Map:
 
     def export(self, stream=None):
         return far_map_export(self.h, stream=stream)
+
+
+def far_asmd_caps(xyz_sensor, xyz_map, v, k, nmax, r_near=20.0, r_max=120.0, stream=None):
+    """(caps int32 device tensor [n], mean near-range points per voxel)."""
+    ps, n = _pts(xyz_sensor, "xyz_sensor")
+    pm, n2 = _pts(xyz_map, "xyz_map")
+    if n2 != n:
+        raise ValueError("xyz_sensor and xyz_map differ in size")
+    caps = torch.empty(max(n, 1), dtype=torch.int32, device=xyz_sensor.device)
+    mean = C.c_double(0)
+    _check(lib().far_asmd_caps(ps, pm, n, v, k, nmax, r_near, r_max,
+                               _dev(caps, torch.int32, "caps"), C.byref(mean), _stream(stream)),
+           "far_asmd_caps")
+    return caps[:n], mean.value
+
+
+def far_map_evict(h, center, radius, stream=None):
+    out = C.c_int64(0)
+    cc = (C.c_double * 3)(*[float(x) for x in center])
+    _check(lib().far_map_evict(h, cc, radius, C.byref(out), _stream(stream)), "far_map_evict")
+    return out.value
 
 
 def far_map_get_schedule(h):
@@ -503,8 +533,9 @@ def far_threshold_get(s: far_threshold_t):
 
 def far_odometry_create(map_h, T_first, v_first=None, downsample=0.5, sigma0=1.0 / 3.0,
                         r_max=120.0, min_motion=0.1, max_iters=10, eps=5e-3,
-                        precision=FAR_PREC_FP32):
-    prm = far_odometry_params_t(downsample, sigma0, r_max, min_motion, max_iters, eps, precision)
+                        precision=FAR_PREC_FP32, asmd=False, r_near=20.0, evict_radius=0.0):
+    prm = far_odometry_params_t(downsample, sigma0, r_max, min_motion, max_iters, eps, precision,
+                                1 if asmd else 0, r_near, evict_radius)
     h = C.c_void_p()
     _check(lib().far_odometry_create(map_h, C.byref(prm), _mat4(T_first),
                                      _mat4_or_none(v_first), C.byref(h)), "far_odometry_create")

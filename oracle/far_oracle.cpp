@@ -1040,4 +1040,73 @@ int orc_map_evict(orc_map* m, const double c[3], double radius, int64_t* n_remov
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Motion undistortion (Sec. III-A.1).  The velocity history is fitted by
+// ordinary least squares per twist component, centred on the mean sample
+// time; every point is then carried to the frame of the scan's last point
+// time by the exponential of the fitted twist integrated over [t_ref, t_i].
+// For a twist linear in time the integral is tau times its value at the
+// midpoint (t_i + t_ref) / 2.
+// ---------------------------------------------------------------------------
+void orc_fit_twist(const double* ts, const double* xi, int64_t m, double* tbar, double a[6],
+                   double b[6]) {
+  std::vector<int64_t> use;
+  for (int64_t j = 0; j < m; ++j) {
+    bool ok = std::isfinite(ts[j]);
+    for (int k = 0; k < 6; ++k) ok = ok && std::isfinite(xi[j * 6 + k]);
+    if (ok) use.push_back(j);
+  }
+  for (int k = 0; k < 6; ++k) a[k] = b[k] = 0.0;
+  *tbar = 0.0;
+  if (use.empty()) return;
+  double st = 0.0;
+  for (int64_t j : use) st += ts[j];
+  double tb = st / double(use.size());
+  double stt = 0.0;
+  for (int64_t j : use) stt += (ts[j] - tb) * (ts[j] - tb);
+  for (int k = 0; k < 6; ++k) {
+    double sy = 0.0;
+    for (int64_t j : use) sy += xi[j * 6 + k];
+    double mean = sy / double(use.size());
+    double sty = 0.0;
+    for (int64_t j : use) sty += (ts[j] - tb) * (xi[j * 6 + k] - mean);
+    a[k] = mean;
+    b[k] = stt > 0.0 ? sty / stt : 0.0;
+  }
+  *tbar = tb;
+}
+
+void orc_undistort(const float* xyz, const float* t, int64_t n, const double* ts,
+                   const double* xi, int64_t m, float* out, double* t_ref) {
+  double tb, a[6], b[6];
+  orc_fit_twist(ts, xi, m, &tb, a, b);
+  bool any = false;
+  double tr = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    if (std::isfinite(t[i]) && (!any || double(t[i]) > tr)) { tr = t[i]; any = true; }
+  *t_ref = any ? tr : std::nan("");
+  const float* X = xyz;
+  const float* Y = xyz + n;
+  const float* Z = xyz + 2 * n;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(t[i])) {
+      out[i] = X[i]; out[n + i] = Y[i]; out[2 * n + i] = Z[i];
+      continue;
+    }
+    double tau = double(t[i]) - tr;
+    double mid = (double(t[i]) + tr) / 2.0 - tb;
+    double phi[6];
+    for (int k = 0; k < 6; ++k) phi[k] = tau * (a[k] + b[k] * mid);
+    // orc_se3_exp takes (rotation, translation)
+    double d[6] = {phi[3], phi[4], phi[5], phi[0], phi[1], phi[2]};
+    double T[16];
+    orc_se3_exp(d, T);
+    double p[3] = {X[i], Y[i], Z[i]};
+    for (int r = 0; r < 3; ++r)
+      out[r * n + i] = float(((T[r * 4 + 0] * p[0] + T[r * 4 + 1] * p[1]) + T[r * 4 + 2] * p[2]) +
+                             T[r * 4 + 3]);
+  }
+}
+
 }  // extern "C"

@@ -144,6 +144,27 @@ int orc_asmd_caps(const float* xyz_sensor, const float* xyz_map, int64_t n, doub
  * the surviving points (empty voxels do not survive). */
 int orc_map_evict(orc_map* m, const double c[3], double radius, int64_t* n_removed);
 
+/* Motion model of a scan (Sec. III-A.1: a linear regression over the
+ * velocity history of the sensor fusion).  Reading: samples are body-frame
+ * twists xi = (vx, vy, vz, wx, wy, wz) at times ts; each component is fitted
+ * by least squares as a_k + b_k (t - tbar), tbar the mean sample time.
+ * Samples with a non-finite time or component are left out; with no sample
+ * left a = b = 0, with all times equal b = 0.  xi [m x 6, row-major]. */
+void orc_fit_twist(const double* ts, const double* xi, int64_t m, double* tbar, double a[6],
+                   double b[6]);
+
+/* Undistortion of a scan (Sec. III-A.1): every point is moved from the
+ * sensor frame of its own time t_i to that of the frame reference time
+ * t_ref = the largest finite point time.  Reading: the pose of the frame at
+ * t_i relative to the frame at t_ref is the SE(3) exponential of the fitted
+ * twist integrated from t_ref to t_i, tau (a + b ((t_i + t_ref) / 2 - tbar))
+ * with tau = t_i - t_ref (exact for a constant twist and for twists that
+ * keep one screw axis; otherwise the first term of its Magnus expansion).
+ * Points with a non-finite time are copied unchanged.  xyz, out [SoA 3 x n];
+ * t [n]; *t_ref (NaN when no time is finite). */
+void orc_undistort(const float* xyz, const float* t, int64_t n, const double* ts,
+                   const double* xi, int64_t m, float* out, double* t_ref);
+
 #ifdef __cplusplus
 }
 #endif

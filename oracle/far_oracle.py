@@ -80,6 +80,10 @@ def lib():
         L.orc_asmd_caps.argtypes = [_f32p, _f32p, C.c_int64, C.c_double, C.c_int32, C.c_int32,
                                     C.c_double, C.c_double, _i32p, C.POINTER(C.c_double)]
         L.orc_map_evict.argtypes = [C.c_void_p, _f64p, C.c_double, C.POINTER(C.c_int64)]
+        L.orc_fit_twist.argtypes = [_f64p, _f64p, C.c_int64, C.POINTER(C.c_double), _f64p,
+                                    _f64p]
+        L.orc_undistort.argtypes = [_f32p, _f32p, C.c_int64, _f64p, _f64p, C.c_int64, _f32p,
+                                    C.POINTER(C.c_double)]
         L.orc_downsample.argtypes = [_f32p, C.c_int64, C.c_double, _i64p,
                                      C.POINTER(C.c_int64)]
         L.orc_transform.argtypes = [_f32p, C.c_int64, _f64p, _f32p]
@@ -304,6 +308,39 @@ def transform(xyz, T):
     return out
 
 
+def _samples(ts, xi):
+    ts = np.ascontiguousarray(ts, dtype=np.float64).reshape(-1)
+    xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 6)
+    assert xi.shape[0] == ts.size
+    return (ts if ts.size else np.zeros(1)), (xi if ts.size else np.zeros((1, 6))), ts.size
+
+
+def fit_twist(ts, xi):
+    """Least-squares line per component of the velocity samples xi [m, 6]
+    (vx vy vz wx wy wz, body frame) at times ts [m]: (tbar, a, b) with
+    xi_k(t) ~ a_k + b_k (t - tbar)."""
+    ts, xi, m = _samples(ts, xi)
+    tb = C.c_double(0)
+    a, b = np.zeros(6), np.zeros(6)
+    lib().orc_fit_twist(ts, xi, m, C.byref(tb), a, b)
+    return tb.value, a, b
+
+
+def undistort(xyz, t, ts, xi):
+    """Points [3, n] taken at times t [n] moved into the sensor frame of the
+    largest finite point time, with the motion fitted to (ts, xi); returns
+    (points float32 [3, n], t_ref)."""
+    a = _soa(xyz)
+    n = a.shape[1]
+    tt = np.ascontiguousarray(t, dtype=np.float32).reshape(-1)
+    assert tt.size == n
+    ts, xi, m = _samples(ts, xi)
+    out = np.zeros_like(a)
+    tr = C.c_double(0)
+    lib().orc_undistort(a, tt if n else np.zeros(1, np.float32), n, ts, xi, m, out, C.byref(tr))
+    return out, tr.value
+
+
 class Threshold:
     """Adaptive correspondence threshold and Cauchy kappa (KISS-ICP rule)."""
 
@@ -343,7 +380,8 @@ def _nearest_rotation(R):
 
 def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing, k,
              map_capacity, downsample_v, sigma0, r_max, min_motion=0.1, max_iters=10,
-             eps=0.0, asmd=False, r_near=20.0, evict_radius=0.0):
+             eps=0.0, asmd=False, r_near=20.0, evict_radius=0.0, times=None, vel_t=None,
+             vel=None):
     """Scan-to-submap odometry over a sequence (Sec. III-A: downsample, source
     covariances, registration against the capped submap, insertion of the
     registered scan), driven by the oracle's own steps.
@@ -358,22 +396,28 @@ def odometry(scans, T_first, v_first, voxel_size, max_pts_per_voxel, min_spacing
     registered, downsampled scan is inserted (with the adaptive submap density
     caps of asmd_caps when asmd is set); once the map is full, inserting stops
     (the map keeps what fit); with evict_radius > 0 the voxels farther than it
-    from the estimate's position are then removed (Sec. III-A.3).  Returns per-scan dicts with the pose,
-    the prediction, tau, kappa, the align status and map sizes."""
+    from the estimate's position are then removed (Sec. III-A.3).  With per-point
+    times and velocity samples given (lists over the scans), each raw scan is
+    first undistorted to its last point time (Sec. III-A.1), so every pose is the
+    sensor's at that time.  Returns per-scan dicts with the pose, the prediction,
+    tau, kappa, the align status and map sizes."""
     m = Map(voxel_size, max_pts_per_voxel, min_spacing, k, point_capacity=map_capacity,
             voxel_capacity=map_capacity)
     thr = Threshold(sigma0, r_max, min_motion)
     out, poses = [], []
     full = False
     for s, raw in enumerate(scans):
+        rec = {}
+        if times is not None:
+            raw, rec["t_ref"] = undistort(raw, times[s], vel_t[s], vel[s])
         src = _soa(raw)[:, downsample(raw, downsample_v)]
-        rec = dict(n=src.shape[1])
+        rec["n"] = src.shape[1]
         if s == 0:
             T = np.array(T_first, dtype=np.float64)
             rec.update(T_pred=T.copy(), tau=None, kappa=None, status=0, iters=0)
         else:
-            vel = v_first if s == 1 else _inv(poses[-2]) @ poses[-1]
-            T_pred = poses[-1] @ vel
+            motion = v_first if s == 1 else _inv(poses[-2]) @ poses[-1]
+            T_pred = poses[-1] @ motion
             T_pred[:3, :3] = _nearest_rotation(T_pred[:3, :3])
             tau, kappa = thr.get()
             cov, val = scan_covariances(src, voxel_size, k)

@@ -214,8 +214,10 @@ class Corridor:
         return out.astype(np.float32)
 
     def cast(self, origin: np.ndarray, dirs: np.ndarray, max_range: float) -> np.ndarray:
-        """First-hit distance of rays origin + t*dir (dirs [3, m], unit); inf = none."""
+        """First-hit distance of rays origin + t*dir (dirs [3, m], unit); inf = none.
+        origin is one point [3] or one per ray [3, m]."""
         ox, oy, oz = origin
+        lo, hi = np.min(ox), np.max(ox)
         dx, dy, dz = dirs
         best = np.full(dirs.shape[1], np.inf)
         with np.errstate(divide="ignore", invalid="ignore"):
@@ -230,7 +232,8 @@ class Corridor:
                 ok = (t > 0) & (x >= 0) & (x <= self.length) & (z >= 0) & (z <= self.wall_height)
                 best = np.where(ok & (t < best), t, best)
             # axis-aligned pillar boxes (slab test in x and y, z in [0, H])
-            for x0, x1, y0, y1 in self.pillars[np.abs(self.pillars[:, 0] - ox) < max_range + 2]:
+            px = self.pillars[:, 0]
+            for x0, x1, y0, y1 in self.pillars[(px > lo - max_range - 2) & (px < hi + max_range + 2)]:
                 tx0, tx1 = (x0 - ox) / dx, (x1 - ox) / dx
                 ty0, ty1 = (y0 - oy) / dy, (y1 - oy) / dy
                 tmin = np.maximum(np.minimum(tx0, tx1), np.minimum(ty0, ty1))
@@ -238,8 +241,12 @@ class Corridor:
                 z = oz + tmin * dz
                 ok = (tmax >= tmin) & (tmin > 0) & (z >= 0) & (z <= self.wall_height)
                 best = np.where(ok & (tmin < best), tmin, best)
-            near = self.poles[np.hypot(self.poles[:, 0] - ox, self.poles[:, 1] - oy)
-                              < max_range + 1.0]
+            if np.ndim(ox) == 0:
+                near = self.poles[np.hypot(self.poles[:, 0] - ox, self.poles[:, 1] - oy)
+                                  < max_range + 1.0]
+            else:
+                cx = self.poles[:, 0]
+                near = self.poles[(cx > lo - max_range - 1.0) & (cx < hi + max_range + 1.0)]
             a = dx * dx + dy * dy
             for cx, cy in near:
                 fx, fy = ox - cx, oy - cy
@@ -286,15 +293,49 @@ def scan(scene: Corridor, lidar: Lidar, T_world_sensor: np.ndarray,
 
 
 def trajectory_pose(t: float, speed: float = 70.0, amp: float = 3.0,
-                    period: float = 8.0, height: float = 2.0, x0: float = 5.0) -> np.ndarray:
-    """Smooth path along the corridor: x = x0 + speed t, y = amp sin(2 pi t / period),
-    heading along the velocity."""
-    x = x0 + speed * t
+                    period: float = 8.0, height: float = 2.0, x0: float = 5.0,
+                    accel: float = 0.0) -> np.ndarray:
+    """Smooth path along the corridor: x = x0 + speed t + accel t^2 / 2,
+    y = amp sin(2 pi t / period), heading along the velocity."""
+    x = x0 + speed * t + 0.5 * accel * t * t
     y = amp * math.sin(2 * math.pi * t / period)
-    vx = speed
+    vx = speed + accel * t
     vy = amp * 2 * math.pi / period * math.cos(2 * math.pi * t / period)
     yaw = math.atan2(vy, vx)
     return pose(Rotation.from_euler("z", yaw).as_matrix(), (x, y, height))
+
+
+def trajectory_twist(t: float, speed: float = 70.0, amp: float = 3.0,
+                     period: float = 8.0, accel: float = 0.0) -> np.ndarray:
+    """Body-frame velocity (vx, vy, vz, wx, wy, wz) of trajectory_pose at time t,
+    from its derivatives: the heading follows the planar velocity, so the linear
+    part is (|v|, 0, 0) and the angular part (0, 0, d yaw / dt)."""
+    w = 2 * math.pi / period
+    vx, vy = speed + accel * t, amp * w * math.cos(w * t)
+    ax, ay = accel, -amp * w * w * math.sin(w * t)
+    return np.array([math.hypot(vx, vy), 0.0, 0.0, 0.0, 0.0,
+                     (vx * ay - vy * ax) / (vx * vx + vy * vy)])
+
+
+def scan_moving(scene: Corridor, lidar: Lidar, pose_at, t0: float, period: float,
+                g: np.random.Generator) -> tuple[np.ndarray, np.ndarray]:
+    """A spinning-LiDAR scan taken while the sensor moves: azimuth column j fires
+    at t0 + period j / azimuths from the pose pose_at(time), and each return is
+    expressed in the sensor frame of its own firing time.  Returns the points
+    [3, n] float32 and their times relative to t0 [n] float32, in firing order."""
+    d_s = lidar.directions()
+    B, A = lidar.beams, lidar.azimuths
+    tcol = period * np.arange(A) / A
+    Ts = [pose_at(t0 + tc) for tc in tcol]
+    R = np.stack([T[:3, :3] for T in Ts])                        # [A, 3, 3]
+    org = np.repeat(np.stack([T[:3, 3] for T in Ts]), B, axis=0).T   # [3, A B]
+    d_w = np.einsum("aij,jab->iab", R, d_s.reshape(3, A, B)).reshape(3, A * B)
+    rng_ = scene.cast(org, d_w, lidar.max_range)
+    rng_ = rng_ + g.normal(scale=lidar.range_noise, size=rng_.shape)
+    keep = np.isfinite(rng_) & (rng_ >= lidar.min_range) & (rng_ <= lidar.max_range)
+    keep &= g.uniform(size=rng_.shape) >= lidar.drop
+    times = np.repeat(tcol, B)[keep].astype(np.float32)
+    return (d_s[:, keep] * rng_[keep]).astype(np.float32), times
 
 
 @dataclass
@@ -323,6 +364,65 @@ def make_sequence(seed: int = 2, n_scans: int = 100, rate_hz: float = 10.0,
         poses.append(T)
         scans.append(scan(scene, lidar, T, rng(seed * 1000 + s)))
     return SequenceCase(scans, poses, scene)
+
+
+@dataclass
+class DeskewCase:
+    """A sequence scanned while moving: per scan the points in firing order,
+    their times, velocity samples on the same clock (relative to the scan's
+    start) and the ground-truth pose at each scan's last point time."""
+    scans: list
+    times: list          # [n] float32 per scan, seconds after the scan start
+    vel_t: list          # [m] float64 per scan, sample times on the same clock
+    vel: list            # [m, 6] float64 per scan, body-frame (vx vy vz wx wy wz)
+    poses: list          # pose at each scan's largest point time
+    starts: list         # scan start times (sequence clock)
+    traj: dict
+    scene: Corridor
+    voxel_size: float = 1.0
+    max_pts_per_voxel: int = 20
+    min_spacing: float = 1.0 / math.sqrt(20.0)
+    downsample: float = 0.5
+    k: int = 5
+    map_capacity: int = 2_000_000
+    sigma0: float = 1.0 / 3.0
+    r_max: float = 120.0
+
+
+RACING = dict(speed=70.0, amp=4.0, period=2.5, accel=5.0)
+
+
+def make_deskew(seed: int = 6, n_scans: int = 40, rate_hz: float = 10.0,
+                lidar: Lidar | None = None, imu_hz: float = 200.0,
+                noise_v: float = 0.05, noise_w: float = 0.002,
+                traj: dict | None = None) -> DeskewCase:
+    """Sequence along an accelerating, weaving racing line (70 m/s, 5 m/s^2,
+    +-4 m at 0.4 Hz): each scan spans one rotation period, so uncorrected
+    points are smeared by up to 7 m and 2 degrees.  Velocity samples at imu_hz
+    from 10 ms before the scan start to its end, with Gaussian noise (noise_v
+    m/s on the linear, noise_w rad/s on the angular part), stand in for the
+    sensor fusion's velocity history."""
+    lidar = lidar or Lidar()
+    traj = dict(RACING if traj is None else traj)
+    scene = Corridor()
+    period = 1.0 / rate_hz
+    pose_at = lambda t: trajectory_pose(t, **traj)
+    out = dict(scans=[], times=[], vel_t=[], vel=[], poses=[], starts=[])
+    for s in range(n_scans):
+        g = rng(seed * 1000 + s)
+        t0 = s * period
+        xyz, tt = scan_moving(scene, lidar, pose_at, t0, period, g)
+        vt = np.arange(-0.01, period + 1e-9, 1.0 / imu_hz)
+        v = np.stack([trajectory_twist(t0 + x, **traj) for x in vt])
+        v[:, :3] += g.normal(scale=noise_v, size=(vt.size, 3))
+        v[:, 3:] += g.normal(scale=noise_w, size=(vt.size, 3))
+        out["scans"].append(xyz)
+        out["times"].append(tt)
+        out["vel_t"].append(vt)
+        out["vel"].append(v)
+        out["poses"].append(pose_at(t0 + float(tt.max())))
+        out["starts"].append(t0)
+    return DeskewCase(traj=traj, scene=scene, **out)
 
 
 @dataclass

@@ -93,6 +93,110 @@ def read_traffic(fp, tile):
         return None
 
 
+def lib_ms(far, kinds, fn, reps):
+    """GPU time per call (ms) of fn() for each timing kind, from the events the
+    library records on its launch stream around its own device work."""
+    fn()
+    for k in kinds:
+        far.far_timing_read_kind(k, reset=True)
+    far.far_timing_enable(True)
+    try:
+        for _ in range(reps):
+            fn()
+    finally:
+        far.far_timing_enable(False)
+    return [far.far_timing_read_kind(k, reset=True)[0] / reps for k in kinds]
+
+
+def hbm_roofline(bytes_per_call, ms):
+    gbs = bytes_per_call / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "algorithmic_bytes": round(bytes_per_call)}
+
+
+def next_rows(far, synth, np, torch, dev, stream, gm, case, T_fin, cov, val, seed):
+    """Timings of the steps around the registration, each on its own input
+    (HIP events the library records on its launch stream around each call's
+    device work, averaged over repetitions):
+      undistort  64 racing scans (8 distinct moving-LiDAR scans used 8 times,
+                 each with its own time offset) in one batched call; per point
+                 16 B read (xyz, time) and 12 B written;
+      gradient   d cost / d (pose, points) of the largest scan at its aligned
+                 pose: the linearisation's bytes plus 12 B per point written;
+      asmd_caps  adaptive density caps of the same scan: 24 B read and 4 B
+                 written per point (the hash set of near voxels aside);
+      evict      removal of the voxels beyond 60 m of the first scan's pose
+                 from the map and the rebuild of its structures: the sum of
+                 its device phases between the call's host synchronisations
+                 (last: it changes the map)."""
+    rows = {}
+    c = synth.make_deskew(seed + 3, n_scans=8)
+    scans, times, vts, vels = [], [], [], []
+    for r in range(8):
+        for s in range(8):
+            scans.append(c.scans[s])
+            times.append(c.times[s] + np.float32(0.125 * r))
+            vts.append(c.vel_t[s] + 0.125 * r)
+            vels.append(c.vel[s])
+    offs = np.concatenate([[0], np.cumsum([x.shape[1] for x in scans])]).astype(np.int64)
+    voffs = np.concatenate([[0], np.cumsum([x.size for x in vts])]).astype(np.int64)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    x, t, o, vt, v, vo = (to(np.concatenate(scans, 1)), to(np.concatenate(times)), to(offs),
+                          to(np.concatenate(vts)), to(np.concatenate(vels)), to(voffs))
+    out = torch.empty_like(x)
+    n = int(offs[-1])
+    ms, ms_apply = lib_ms(far, (far.FAR_TIME_UNDISTORT, far.FAR_TIME_UNDISTORT_APPLY),
+                          lambda: far.far_undistort_batch(x, t, o, vt, v, vo, out=out), 20)
+    rows["undistort"] = {"scans": 64, "points": n, "ms": round(ms, 4),
+                         "points_per_s": round(n / (ms * 1e-3), 1),
+                         "roofline": hbm_roofline(28.0 * n + 56.0 * int(voffs[-1]), ms),
+                         "apply_kernel": {"kernel": "k_ud_apply", "ms": round(ms_apply, 4),
+                                          "roofline": hbm_roofline(28.0 * n, ms_apply)}}
+    del x, t, o, vt, v, vo, out
+
+    # gradient and ASMD caps on the largest scan of the batch
+    s = int(np.argmax([sc.shape[1] for sc in case.scans]))
+    a = int(sum(sc.shape[1] for sc in case.scans[:s]))
+    n = case.scans[s].shape[1]
+    src = to(case.scans[s])
+    cv, vl = cov[:, a:a + n].contiguous(), val[a:a + n].contiguous()
+    T = T_fin[s]
+    res = {}
+
+    def grad():
+        res["g"] = far.far_gicp_gradient(gm.h, src, cv, vl, T, case.tau, case.kappa, c=T[:3, 3])
+    ms, = lib_ms(far, (far.FAR_TIME_GRADIENT,), grad, 20)
+    mx, _, _ = gm.export()
+    mk = np.floor(mx.cpu().numpy().astype(np.float64) / case.voxel_size).astype(np.int64)
+    mp = ((mk[0] + (1 << 20)) << 42) | ((mk[1] + (1 << 20)) << 21) | (mk[2] + (1 << 20))
+    vk, vc = touched_voxels(np.unique(mp, return_counts=True), case.scans[s], T, case.voxel_size)
+    nb = 37.0 * n + 32.0 * res["g"]["n_inliers"] + 20.0 * vk.size + 16.0 * vc.sum() + 12.0 * n
+    rows["gradient"] = {"points": n, "inliers": res["g"]["n_inliers"], "ms": round(ms, 4),
+                        "points_per_s": round(n / (ms * 1e-3), 1),
+                        "roofline": hbm_roofline(float(nb), ms)}
+
+    moved = far.far_transform_points(src, T)
+    ms, = lib_ms(far, (far.FAR_TIME_ASMD,),
+                 lambda: far.far_asmd_caps(src, moved, case.voxel_size, case.k,
+                                           case.max_pts_per_voxel, 20.0, 120.0), 20)
+    rows["asmd_caps"] = {"points": n, "ms": round(ms, 4),
+                         "points_per_s": round(n / (ms * 1e-3), 1),
+                         "roofline": hbm_roofline(28.0 * n, ms)}
+
+    before = gm.stats()["n_points"]
+    ctr = case.T0[0][:3, 3]
+    far.far_timing_read_kind(far.FAR_TIME_EVICT, reset=True)
+    far.far_timing_enable(True)
+    try:
+        removed = gm.evict(ctr, 60.0)
+    finally:
+        far.far_timing_enable(False)
+    ms = far.far_timing_read_kind(far.FAR_TIME_EVICT, reset=True)[0]
+    rows["evict"] = {"map_points_before": before, "removed": removed, "radius_m": 60.0,
+                     "ms": round(ms, 4), "map_points_per_s": round(before / (ms * 1e-3), 1)}
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +213,8 @@ def main():
     ap.add_argument("--cpu-sample-scans", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default schedules instead of autotuning them on the batch")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the timings of undistortion, gradient, ASMD caps and eviction")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -301,6 +407,13 @@ def main():
 
         gt_err = [pose_err(T_gpu[s], case.T_gt[s]) for s in range(S)]
 
+        rows = None
+        if not args.no_rows:
+            t_rows = time.time()
+            rows = next_rows(far, synth, np, torch, dev, stream, gm, case, T_fin, cov, val,
+                             args.seed)
+            log(f"[bench] rows {time.time() - t_rows:.1f}s: {rows}")
+
         # ---------------- CPU oracle on a bounded sample of the same workload
         cpu = None
         oracle_err = None
@@ -368,6 +481,7 @@ def main():
         {"max_m": max(e[0] for e in oracle_err), "max_deg": max(e[1] for e in oracle_err),
          "scans": len(oracle_err)},
         "schedule": schedule,
+        "rows": rows,
         "map_build": {"seconds": round(t_map, 3), "candidates": inserted,
                       "mean_probe": mstats["mean_probe"], "max_probe": mstats["max_probe"],
                       "load_factor": mstats["load_factor"]},

@@ -311,6 +311,36 @@ far_status_t far_voxel_downsample(const float* xyz, int64_t n, double v, float* 
 far_status_t far_transform_points(const float* xyz, int64_t n, const double T[16],
                                   float* out, far_stream_t stream);
 
+/* Motion undistortion of one scan (Sec. III-A.1: the sensor's motion during
+ * the sweep is modelled by a linear regression over the velocity history of
+ * the sensor fusion, and each raw point is moved to the frame of the scan's
+ * final point time).  Readings: the velocity samples are body-frame twists
+ * vel [dev, m x 6 row-major: vx vy vz wx wy wz] at times vel_t [dev, m]
+ * (seconds, the clock of t); each component is fitted by least squares as
+ * a_k + b_k (time - tbar), tbar the mean sample time, leaving out samples with
+ * a non-finite entry (none left: no motion; one time only: b = 0).  The
+ * frame reference t_ref is the largest finite point time; point i at time
+ * t[i] is moved by the SE(3) exponential of the fitted twist integrated over
+ * [t_ref, t[i]], (t[i] - t_ref) xi((t[i] + t_ref) / 2), evaluated in FP64 and
+ * rounded to float.  Points with a non-finite time are copied unchanged.
+ * xyz, out [dev, SoA 3 x n; out may alias xyz]; t [dev, n, float seconds,
+ * e.g. relative to the scan start]; t_ref [dev, 1, or NULL] receives the
+ * reference time (NaN when no time is finite).  Asynchronous; no memset, so
+ * the launches may be captured in a graph. */
+far_status_t far_undistort(const float* xyz, const float* t, int64_t n, const double* vel_t,
+                           const double* vel, int32_t m, float* out, double* t_ref,
+                           far_stream_t stream);
+
+/* far_undistort for S scans in one pass: scan s holds points
+ * [offsets[s], offsets[s+1]) of xyz, t and out (SoA 3 x n_total) and
+ * velocity samples [vel_offsets[s], vel_offsets[s+1]) of vel_t and vel;
+ * offsets and vel_offsets [dev, S+1] int64, non-decreasing from 0, with
+ * offsets[S] = n_total; t_ref [dev, S, or NULL]. */
+far_status_t far_undistort_batch(const float* xyz, const float* t, const int64_t* offsets,
+                                 int32_t S, int64_t n_total, const double* vel_t,
+                                 const double* vel, const int64_t* vel_offsets, float* out,
+                                 double* t_ref, far_stream_t stream);
+
 /* Adaptive submap density (Sec. III-A.3, ASMD): per-point insert caps that
  * follow the current scan's density near the sensor and decay over range
  * (the paper gives no constants; reading): mean = points per voxel of edge v
@@ -412,13 +442,26 @@ far_status_t far_odometry_step(far_odometry_t od, const float* xyz, int64_t n,
                                far_stream_t stream);
 far_status_t far_odometry_destroy(far_odometry_t od);
 
-/* Instrumentation.  With timing on, every linearisation launch is bracketed
- * by HIP events recorded on the stream it runs on, and the align entry points
- * launch their kernels directly instead of through a graph.  far_timing_read
- * waits for the recorded launches and returns their summed kernel time (ms)
- * and count since the last reset (reset != 0 clears them after reading).
- * Process-wide; not meant for concurrent use from several threads. */
+/* Instrumentation.  With timing on, the device work of each kind below is
+ * bracketed by HIP events recorded on the stream it runs on (before any host
+ * synchronisation of the call), and the align entry points launch their
+ * kernels directly instead of through a graph.  far_timing_read_kind waits
+ * for the recorded intervals of one kind and returns their summed time (ms)
+ * and count since the last reset (reset != 0 clears them after reading);
+ * far_timing_read is the linearisation kind.  Process-wide; not meant for
+ * concurrent use from several threads. */
+typedef enum {
+  FAR_TIME_LINEARIZE = 0,        /* each linearisation launch of an align    */
+  FAR_TIME_UNDISTORT = 1,        /* each far_undistort(_batch) call          */
+  FAR_TIME_UNDISTORT_APPLY = 2,  /* its per-point kernel alone               */
+  FAR_TIME_GRADIENT = 3,         /* each far_gicp_gradient call              */
+  FAR_TIME_ASMD = 4,             /* each far_asmd_caps call                  */
+  FAR_TIME_EVICT = 5,            /* each far_map_evict call                  */
+  FAR_TIME_KINDS = 6
+} far_time_kind_t;
+
 far_status_t far_timing_enable(int32_t on);
+far_status_t far_timing_read_kind(int32_t kind, double* ms, int64_t* count, int32_t reset);
 far_status_t far_timing_read(double* linearize_ms, int64_t* launches, int32_t reset);
 
 const char* far_status_str(far_status_t s);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libfar.so")
-SOURCES = ["far_prim.hip", "far_map.hip", "far_gicp.hip", "far_odom.hip"]
+SOURCES = ["far_prim.hip", "far_map.hip", "far_gicp.hip", "far_odom.hip", "far_deskew.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

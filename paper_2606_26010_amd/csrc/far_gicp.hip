@@ -722,19 +722,6 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const int32_t* begin,
 
 }  // namespace
 
-// Kernel timing instrumentation (far_timing_enable / far_timing_read).
-struct Timing {
-  std::mutex mu;
-  bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  double ms = 0.0;
-  int64_t launches = 0;
-};
-Timing& timing() {
-  static Timing t;
-  return t;
-}
-
 // Device workspace of the align driver, owned by the map and reused (with its
 // captured graph) while the call arguments stay the same.
 struct AlignWS {
@@ -927,22 +914,13 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
     return FAR_OK;
   }
   const int iters = j.c_fixed ? 1 : j.prm.max_iters;
-  const bool timed = timing().on;
   for (int it = 0; it < iters; ++it) {
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (timed) {
-      FAR_HIP(hipEventCreate(&ev0));
-      FAR_HIP(hipEventCreate(&ev1));
-      FAR_HIP(hipEventRecord(ev0, st));
-    }
-    if (j.precision == FAR_PREC_FP64)
-      FAR_TRY((launch_lin<double, false>(j.tile, grid, st, mv, w, max_tiles, j)));
-    else
-      FAR_TRY((launch_lin<float, false>(j.tile, grid, st, mv, w, max_tiles, j)));
-    if (timed) {
-      FAR_HIP(hipEventRecord(ev1, st));
-      std::lock_guard<std::mutex> lk(timing().mu);
-      timing().pending.push_back({ev0, ev1});
+    {
+      TimedScope ts(FAR_TIME_LINEARIZE, st);
+      if (j.precision == FAR_PREC_FP64)
+        FAR_TRY((launch_lin<double, false>(j.tile, grid, st, mv, w, max_tiles, j)));
+      else
+        FAR_TRY((launch_lin<float, false>(j.tile, grid, st, mv, w, max_tiles, j)));
     }
     k_reduce_solve<<<unsigned(j.S), 256, 0, st>>>(j.S, w->begin, w->partial, j.T, w->ctr,
                                                   w->done, j.stats, j.prm, j.c_fixed ? 0 : 1);
@@ -968,7 +946,7 @@ far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph
   // the fine index of the current map (stream-ordered), when it is used
   if (j.prm.fine_nn) FAR_TRY(fine_build(m, st));
   (void)device_cu_count();   // query the device outside any capture
-  if (!use_graph || st == nullptr || timing().on) return enqueue(m, w, j, max_tiles, st);
+  if (!use_graph || st == nullptr || timing_on()) return enqueue(m, w, j, max_tiles, st);
   // the captured map view holds the fine-index flag: a graph captured with a
   // different flag must not be replayed
   const void* key[10] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
@@ -1097,14 +1075,17 @@ far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
   FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
   int64_t offs[2] = {0, n};
   const double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
-  FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
-  FAR_HIP(hipMemcpyAsync(w->T, T, 16 * sizeof(double), hipMemcpyHostToDevice, st));
-  FAR_HIP(hipMemcpyAsync(w->cfix, cc, sizeof(cc), hipMemcpyHostToDevice, st));
-  Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, nullptr,
-        make_params(m, tau, kappa, 0.0, 1, 0), precision};
-  j.gsum = w->gsum;
-  j.grad_src = grad_src;
-  FAR_TRY(run_job(m, j, st, false));
+  {
+    TimedScope ts(FAR_TIME_GRADIENT, st);
+    FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
+    FAR_HIP(hipMemcpyAsync(w->T, T, 16 * sizeof(double), hipMemcpyHostToDevice, st));
+    FAR_HIP(hipMemcpyAsync(w->cfix, cc, sizeof(cc), hipMemcpyHostToDevice, st));
+    Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, nullptr,
+          make_params(m, tau, kappa, 0.0, 1, 0), precision};
+    j.gsum = w->gsum;
+    j.grad_src = grad_src;
+    FAR_TRY(run_job(m, j, st, false));
+  }
   double g[14];
   FAR_HIP(hipMemcpyAsync(g, w->gsum, sizeof(g), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipStreamSynchronize(st));
@@ -1277,34 +1258,6 @@ far_status_t far_autotune(far_map_t m, const float* src, const int64_t* offsets,
   *best = win;
   if (ms)
     for (int c = 0; c < 6; ++c) ms[c] = times[c];
-  return FAR_OK;
-}
-
-far_status_t far_timing_enable(int32_t on) {
-  std::lock_guard<std::mutex> lk(timing().mu);
-  timing().on = on != 0;
-  return FAR_OK;
-}
-
-far_status_t far_timing_read(double* linearize_ms, int64_t* launches, int32_t reset) {
-  std::lock_guard<std::mutex> lk(timing().mu);
-  Timing& t = timing();
-  for (auto& pr : t.pending) {
-    FAR_HIP(hipEventSynchronize(pr.second));
-    float ms = 0.0f;
-    FAR_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
-    t.ms += ms;
-    t.launches += 1;
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
-  t.pending.clear();
-  if (linearize_ms) *linearize_ms = t.ms;
-  if (launches) *launches = t.launches;
-  if (reset) {
-    t.ms = 0.0;
-    t.launches = 0;
-  }
   return FAR_OK;
 }
 

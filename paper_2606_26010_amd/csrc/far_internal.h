@@ -30,6 +30,34 @@ far_status_t hip_fail(hipError_t e, const char* what, const char* file, int line
 
 inline hipStream_t S(far_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ---------------------------------------------------------------- timing
+// Event timing of selected launches (far_timing_enable / far_timing_read_kind).
+// A TimedScope records an event on the stream at construction and one at
+// destruction when timing is on; far_timing_read_kind sums the intervals.
+bool timing_on();
+void timing_push(int kind, hipEvent_t ev0, hipEvent_t ev1);
+
+struct TimedScope {
+  int kind;
+  hipStream_t st;
+  hipEvent_t ev0 = nullptr;
+  TimedScope(int k, hipStream_t s) : kind(k), st(s) {
+    if (timing_on() && hipEventCreate(&ev0) == hipSuccess) (void)hipEventRecord(ev0, st);
+  }
+  // Ends the interval early (before a host synchronisation of the call).
+  void stop() {
+    hipEvent_t ev1 = nullptr;
+    if (ev0 && hipEventCreate(&ev1) == hipSuccess && hipEventRecord(ev1, st) == hipSuccess)
+      timing_push(kind, ev0, ev1);
+    else if (ev0)
+      (void)hipEventDestroy(ev0);
+    ev0 = nullptr;
+  }
+  ~TimedScope() { stop(); }
+  TimedScope(const TimedScope&) = delete;
+  TimedScope& operator=(const TimedScope&) = delete;
+};
+
 // ---------------------------------------------------------------- keys
 // A voxel key is the triple floor(x / v) per axis; keys are limited to
 // [-2^20, 2^20) and packed as three 21-bit fields biased by 2^20 into the low

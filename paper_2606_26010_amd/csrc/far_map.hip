@@ -359,12 +359,15 @@ __global__ __launch_bounds__(kT) void k_asmd_count(const float* xs, const float*
 }
 
 // cap_i = clamp(floor(mean (1 - r_i / r_max) + 0.5), k, nmax), FP64 in this
-// order (no contraction); non-finite points get k.
-__global__ __launch_bounds__(kT) void k_asmd_caps(const float* xs, int64_t n, double mean,
-                                                  double r_max, int32_t k, int32_t nmax,
-                                                  int32_t* caps) {
+// order (no contraction); non-finite points get k.  mean = near points /
+// distinct near voxels from k_asmd_count's counters (nmax when none).
+__global__ __launch_bounds__(kT) void k_asmd_caps(const float* xs, int64_t n,
+                                                  const uint32_t* counters, double r_max,
+                                                  int32_t k, int32_t nmax, int32_t* caps) {
   const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (i >= n) return;
+  const double mean =
+      counters[1] > 0 ? double(counters[0]) / double(counters[1]) : double(nmax);
   const double sx = xs[i], sy = xs[n + i], sz = xs[2 * n + i];
   int32_t cap = k;
   if (isfinite(sx) && isfinite(sy) && isfinite(sz)) {
@@ -1444,11 +1447,16 @@ far_status_t far_asmd_caps(const float* xyz_sensor, const float* xyz_map, int64_
     uint32_t* counters;
     FAR_TRY(scr.get(&set, size_t(set_n)));
     FAR_TRY(scr.get(&counters, 3));
-    FAR_HIP(hipMemsetAsync(set, 0xFF, size_t(set_n) * sizeof(uint64_t), st));
-    FAR_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(uint32_t), st));
-    k_asmd_count<<<blocks_for(n), kT, 0, st>>>(xyz_sensor, xyz_map, n, v, r_near * r_near, set,
-                                               uint32_t(set_n - 1), set_log2, counters);
-    FAR_HIP(hipGetLastError());
+    {
+      TimedScope ts(FAR_TIME_ASMD, st);
+      FAR_HIP(hipMemsetAsync(set, 0xFF, size_t(set_n) * sizeof(uint64_t), st));
+      FAR_HIP(hipMemsetAsync(counters, 0, 3 * sizeof(uint32_t), st));
+      k_asmd_count<<<blocks_for(n), kT, 0, st>>>(xyz_sensor, xyz_map, n, v, r_near * r_near,
+                                                 set, uint32_t(set_n - 1), set_log2, counters);
+      FAR_HIP(hipGetLastError());
+      k_asmd_caps<<<blocks_for(n), kT, 0, st>>>(xyz_sensor, n, counters, r_max, k, nmax, caps);
+      FAR_HIP(hipGetLastError());
+    }
     uint32_t h[3];
     FAR_HIP(hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, st));
     FAR_HIP(hipStreamSynchronize(st));
@@ -1457,8 +1465,6 @@ far_status_t far_asmd_caps(const float* xyz_sensor, const float* xyz_map, int64_
       return FAR_E_INVALID;
     }
     if (h[1] > 0) mean = double(h[0]) / double(h[1]);
-    k_asmd_caps<<<blocks_for(n), kT, 0, st>>>(xyz_sensor, n, mean, r_max, k, nmax, caps);
-    FAR_HIP(hipGetLastError());
   }
   if (mean_near) *mean_near = mean;
   return FAR_OK;
@@ -1492,10 +1498,13 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   FAR_TRY(scr.get(&keep, size_t(n)));
   FAR_TRY(scr.get(&nid, size_t(n)));
   FAR_TRY(scr.get(&total, 1));
-  k_evict_keep<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->p.point_capacity, n, v, c[0], c[1],
-                                             c[2], radius * radius, keep);
-  FAR_HIP(hipGetLastError());
-  FAR_TRY(scan_exclusive(keep, nid, n, total, st, scr));
+  {
+    TimedScope ts(FAR_TIME_EVICT, st);
+    k_evict_keep<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->p.point_capacity, n, v, c[0],
+                                               c[1], c[2], radius * radius, keep);
+    FAR_HIP(hipGetLastError());
+    FAR_TRY(scan_exclusive(keep, nid, n, total, st, scr));
+  }
   uint32_t h_keep = 0;
   FAR_HIP(hipMemcpyAsync(&h_keep, total, sizeof(h_keep), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipStreamSynchronize(st));
@@ -1505,6 +1514,7 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   float4* cv;
   FAR_TRY(scr.get(&xyz, size_t(3 * std::max<int64_t>(n_keep, 1))));
   FAR_TRY(scr.get(&cv, size_t(2 * std::max<int64_t>(n_keep, 1))));
+  TimedScope ts2(FAR_TIME_EVICT, st);
   k_evict_gather<<<blocks_for(n), kT, 0, st>>>(m->pt_xyz, m->cov, m->p.point_capacity, n, keep,
                                                nid, n_keep, xyz, cv);
   FAR_HIP(hipGetLastError());
@@ -1516,6 +1526,7 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   m->fine_ok = false;
   if (n_removed) *n_removed = n - n_keep;
   if (n_keep == 0) {
+    ts2.stop();
     FAR_HIP(hipStreamSynchronize(st));
     return FAR_OK;
   }
@@ -1527,8 +1538,10 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   FAR_TRY(build_runs(xyz, n_keep, v, st, scr, r));
   uint32_t h_cnt[4];
   FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  ts2.stop();
   FAR_HIP(hipStreamSynchronize(st));
   const int64_t n_seg = h_cnt[2];
+  TimedScope ts3(FAR_TIME_EVICT, st);
   int32_t* seg_vox;
   uint32_t *is_new, *rank;
   FAR_TRY(scr.get(&seg_vox, size_t(n_seg)));
@@ -1552,6 +1565,7 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   FAR_HIP(hipGetLastError());
   m->n_points = n_keep;
   m->n_voxels = n_seg;
+  ts3.stop();
   FAR_HIP(hipStreamSynchronize(st));
   return FAR_OK;
 }

@@ -4,6 +4,10 @@
 // The insert needs a *stable* grouping of points by voxel key so that each
 // voxel's candidates are visited in input order (the sequential capped-insert
 // semantics); an LSD radix sort whose every pass is stable gives exactly that.
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "far_internal.h"
 
 namespace far {
@@ -207,4 +211,69 @@ far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt
   return FAR_OK;
 }
 
+// ---------------------------------------------------------------- timing
+namespace {
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[FAR_TIME_KINDS];
+  double ms[FAR_TIME_KINDS] = {};
+  int64_t count[FAR_TIME_KINDS] = {};
+};
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+}  // namespace
+
+bool timing_on() {
+  std::lock_guard<std::mutex> lk(timing().mu);
+  return timing().on;
+}
+
+void timing_push(int kind, hipEvent_t ev0, hipEvent_t ev1) {
+  std::lock_guard<std::mutex> lk(timing().mu);
+  timing().pending[kind].push_back({ev0, ev1});
+}
+
 }  // namespace far
+
+extern "C" {
+
+far_status_t far_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(far::timing().mu);
+  far::timing().on = on != 0;
+  return FAR_OK;
+}
+
+far_status_t far_timing_read_kind(int32_t kind, double* ms, int64_t* count, int32_t reset) {
+  if (kind < 0 || kind >= FAR_TIME_KINDS) {
+    far::set_error("far_timing_read_kind: kind %d out of range", kind);
+    return FAR_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(far::timing().mu);
+  far::Timing& t = far::timing();
+  for (auto& pr : t.pending[kind]) {
+    FAR_HIP(hipEventSynchronize(pr.second));
+    float e = 0.0f;
+    FAR_HIP(hipEventElapsedTime(&e, pr.first, pr.second));
+    t.ms[kind] += e;
+    t.count[kind] += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  t.pending[kind].clear();
+  if (ms) *ms = t.ms[kind];
+  if (count) *count = t.count[kind];
+  if (reset) {
+    t.ms[kind] = 0.0;
+    t.count[kind] = 0;
+  }
+  return FAR_OK;
+}
+
+far_status_t far_timing_read(double* linearize_ms, int64_t* launches, int32_t reset) {
+  return far_timing_read_kind(FAR_TIME_LINEARIZE, linearize_ms, launches, reset);
+}
+
+}  // extern "C"

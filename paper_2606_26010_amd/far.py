@@ -92,6 +92,8 @@ _SIGS = {
                                              C.c_int32, _P, _P, _P]),
     "far_timing_enable": (C.c_int, [C.c_int32]),
     "far_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
+    "far_timing_read_kind": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                       C.c_int32]),
     "far_gicp_linearize": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                      C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.c_int32, _P, C.POINTER(far_lin_t), _P]),
@@ -109,6 +111,9 @@ _SIGS = {
     "far_voxel_downsample": (C.c_int, [_P, C.c_int64, C.c_double, _P, _P,
                                        C.POINTER(C.c_int64), _P]),
     "far_transform_points": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_double), _P, _P]),
+    "far_undistort": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P]),
+    "far_undistort_batch": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
+                                      _P]),
     "far_threshold_init": (C.c_int, [C.POINTER(far_threshold_t), C.c_double, C.c_double,
                                      C.c_double]),
     "far_threshold_update": (C.c_int, [C.POINTER(far_threshold_t), C.POINTER(C.c_double),
@@ -258,6 +263,18 @@ def far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=None, stream=Non
 
 def far_timing_enable(on: bool):
     _check(lib().far_timing_enable(1 if on else 0), "far_timing_enable")
+
+
+FAR_TIME_LINEARIZE, FAR_TIME_UNDISTORT, FAR_TIME_UNDISTORT_APPLY = 0, 1, 2
+FAR_TIME_GRADIENT, FAR_TIME_ASMD, FAR_TIME_EVICT = 3, 4, 5
+
+
+def far_timing_read_kind(kind: int, reset: bool = False):
+    """(summed ms, count) of the event-timed intervals of one kind."""
+    ms, n = C.c_double(0), C.c_int64(0)
+    _check(lib().far_timing_read_kind(kind, C.byref(ms), C.byref(n), 1 if reset else 0),
+           "far_timing_read_kind")
+    return ms.value, n.value
 
 
 def far_timing_read(reset: bool = False):
@@ -510,6 +527,50 @@ def far_transform_points(xyz, T, out=None, stream=None):
     _check(lib().far_transform_points(p, n, _mat4(T), _dev(out, torch.float32, "out"),
                                       _stream(stream)), "far_transform_points")
     return out
+
+
+def _samples(vel_t, vel):
+    if vel_t.dim() != 1 or vel.dim() != 2 or vel.shape[1] != 6 or vel.shape[0] != vel_t.shape[0]:
+        raise ValueError("vel_t must be [m] and vel [m, 6]")
+    return (_dev(vel_t, torch.float64, "vel_t"), _dev(vel, torch.float64, "vel"),
+            vel_t.shape[0])
+
+
+def far_undistort(xyz, t, vel_t, vel, out=None, stream=None):
+    """Motion undistortion of one scan: (points [3, n] in the frame of the
+    scan's last point time, t_ref as a float64 device tensor [1])."""
+    p, n = _pts(xyz, "xyz")
+    if t.dim() != 1 or t.shape[0] != n:
+        raise ValueError("t must be [n]")
+    pt, pv, m = _samples(vel_t, vel)
+    if out is None:
+        out = torch.empty_like(xyz)
+    t_ref = torch.empty(1, dtype=torch.float64, device=xyz.device)
+    _check(lib().far_undistort(p, _dev(t, torch.float32, "t"), n, pt, pv, m,
+                               _dev(out, torch.float32, "out"), _dev(t_ref, torch.float64, "t_ref"),
+                               _stream(stream)), "far_undistort")
+    return out, t_ref
+
+
+def far_undistort_batch(xyz, t, offsets, vel_t, vel, vel_offsets, out=None, stream=None):
+    """far_undistort over S scans: (points [3, n_total], t_ref [S])."""
+    p, n = _pts(xyz, "xyz")
+    if t.dim() != 1 or t.shape[0] != n:
+        raise ValueError("t must be [n_total]")
+    S = offsets.shape[0] - 1
+    if vel_offsets.shape[0] != S + 1:
+        raise ValueError("offsets and vel_offsets differ in scan count")
+    pt, pv, _ = _samples(vel_t, vel)
+    if out is None:
+        out = torch.empty_like(xyz)
+    t_ref = torch.empty(max(S, 1), dtype=torch.float64, device=xyz.device)
+    _check(lib().far_undistort_batch(p, _dev(t, torch.float32, "t"),
+                                     _dev(offsets, torch.int64, "offsets"), S, n, pt, pv,
+                                     _dev(vel_offsets, torch.int64, "vel_offsets"),
+                                     _dev(out, torch.float32, "out"),
+                                     _dev(t_ref, torch.float64, "t_ref"), _stream(stream)),
+           "far_undistort_batch")
+    return out, t_ref[:S]
 
 
 def far_threshold_init(sigma0, r_max, min_motion=0.1):

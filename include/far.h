@@ -415,6 +415,7 @@ typedef struct {
   double deviation;       /* deviation of the estimate from the prediction    */
   double T_pred[16];      /* motion prediction (the initial guess)            */
   far_lin_t last;         /* last linearisation of the align                  */
+  double t_ref;           /* reference time of the undistorted scan (NaN: none)*/
 } far_odometry_stats_t;
 
 /* An odometry over `map` (borrowed; it must outlive the odometry), whose
@@ -440,6 +441,16 @@ far_status_t far_odometry_create(far_map_t map, const far_odometry_params_t* par
 far_status_t far_odometry_step(far_odometry_t od, const float* xyz, int64_t n,
                                double T_out[16], far_odometry_stats_t* stats,
                                far_stream_t stream);
+/* far_odometry_step on a raw scan taken while moving (Sec. III-A.1): the
+ * scan xyz [dev, SoA 3 x n] with per-point times t [dev, n] is first
+ * undistorted by far_undistort with the velocity samples vel_t [dev, m] and
+ * vel [dev, m x 6] into a buffer the odometry owns, so every pose is the
+ * sensor's at the scan's reference time (stats->t_ref).  Synchronises
+ * `stream`. */
+far_status_t far_odometry_step_timed(far_odometry_t od, const float* xyz, const float* t,
+                                     int64_t n, const double* vel_t, const double* vel,
+                                     int32_t m, double T_out[16], far_odometry_stats_t* stats,
+                                     far_stream_t stream);
 far_status_t far_odometry_destroy(far_odometry_t od);
 
 /* Instrumentation.  With timing on, the device work of each kind below is

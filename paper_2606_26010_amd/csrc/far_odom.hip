@@ -86,11 +86,42 @@ struct far_odometry_s {
   float* cov = nullptr;      // SoA [6][cap]
   uint8_t* valid = nullptr;  // [cap]
   int32_t* caps = nullptr;   // ASMD caps [cap]
+  int64_t raw_cap = 0;       // points the undistortion buffer holds
+  float* raw = nullptr;      // undistorted raw scan, SoA [3][raw_cap]
+  double* t_ref = nullptr;   // its reference time [1]
 };
 
 namespace {
 
 void release(far_odometry_s* o) {
+  void* ptrs[] = {o->down, o->moved, o->cov, o->valid, o->caps, o->raw, o->t_ref};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  o->down = o->moved = o->cov = nullptr;
+  o->valid = nullptr;
+  o->caps = nullptr;
+  o->cap = 0;
+  o->raw = nullptr;
+  o->t_ref = nullptr;
+  o->raw_cap = 0;
+}
+
+far_status_t reserve_raw(far_odometry_s* o, int64_t n, hipStream_t st) {
+  if (n <= o->raw_cap && o->t_ref) return FAR_OK;
+  FAR_HIP(hipStreamSynchronize(st));
+  if (o->raw) (void)hipFree(o->raw);
+  o->raw = nullptr;
+  o->raw_cap = 0;
+  const int64_t cap = std::max<int64_t>(n, 1024);
+  FAR_HIP(hipMalloc(&o->raw, size_t(cap) * 3 * sizeof(float)));
+  if (!o->t_ref) FAR_HIP(hipMalloc(&o->t_ref, sizeof(double)));
+  o->raw_cap = cap;
+  return FAR_OK;
+}
+
+far_status_t reserve(far_odometry_s* o, int64_t n, hipStream_t st) {
+  if (n <= o->cap) return FAR_OK;
+  FAR_HIP(hipStreamSynchronize(st));
   void* ptrs[] = {o->down, o->moved, o->cov, o->valid, o->caps};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -98,12 +129,6 @@ void release(far_odometry_s* o) {
   o->valid = nullptr;
   o->caps = nullptr;
   o->cap = 0;
-}
-
-far_status_t reserve(far_odometry_s* o, int64_t n, hipStream_t st) {
-  if (n <= o->cap) return FAR_OK;
-  FAR_HIP(hipStreamSynchronize(st));
-  release(o);
   int64_t cap = std::max<int64_t>(n, 1024);
   FAR_HIP(hipMalloc(&o->down, size_t(cap) * 3 * sizeof(float)));
   FAR_HIP(hipMalloc(&o->moved, size_t(cap) * 3 * sizeof(float)));
@@ -206,6 +231,7 @@ far_status_t far_odometry_step(far_odometry_t o, const float* xyz, int64_t n, do
   far_odometry_stats_t sx;
   std::memset(&sx, 0, sizeof(sx));
   sx.n_raw = n;
+  sx.t_ref = std::nan("");
   FAR_TRY(reserve(o, n, st));
   int64_t m = 0;
   if (n > 0) FAR_TRY(far_voxel_downsample(xyz, n, o->p.downsample, o->down, nullptr, &m, stream));
@@ -272,6 +298,28 @@ far_status_t far_odometry_step(far_odometry_t o, const float* xyz, int64_t n, do
   std::memcpy(o->T_prev, T, sizeof(T));
   o->steps += 1;
   std::memcpy(T_out, T, sizeof(T));
+  if (stats) *stats = sx;
+  return FAR_OK;
+}
+
+far_status_t far_odometry_step_timed(far_odometry_t o, const float* xyz, const float* t,
+                                     int64_t n, const double* vel_t, const double* vel,
+                                     int32_t m, double T_out[16], far_odometry_stats_t* stats,
+                                     far_stream_t stream) {
+  if (!o || !T_out || n < 0 || n >= (int64_t(1) << 31) || (n > 0 && (!xyz || !t)) || m < 0 ||
+      (m > 0 && (!vel_t || !vel))) {
+    far::set_error("far_odometry_step_timed: invalid argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = far::S(stream);
+  FAR_TRY(reserve_raw(o, n, st));
+  FAR_TRY(far_undistort(xyz, t, n, vel_t, vel, m, o->raw, o->t_ref, stream));
+  far_odometry_stats_t sx;
+  FAR_TRY(far_odometry_step(o, o->raw, n, T_out, &sx, stream));
+  double tr = std::nan("");
+  FAR_HIP(hipMemcpyAsync(&tr, o->t_ref, sizeof(tr), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  sx.t_ref = tr;
   if (stats) *stats = sx;
   return FAR_OK;
 }

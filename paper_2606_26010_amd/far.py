@@ -72,7 +72,8 @@ class far_odometry_stats_t(C.Structure):
                 ("n_down", C.c_int64), ("n_inserted", C.c_int64), ("map_full", C.c_int32),
                 ("reserved", C.c_int32), ("n_evicted", C.c_int64), ("asmd_mean", C.c_double),
                 ("tau", C.c_double), ("kappa", C.c_double),
-                ("deviation", C.c_double), ("T_pred", C.c_double * 16), ("last", far_lin_t)]
+                ("deviation", C.c_double), ("T_pred", C.c_double * 16), ("last", far_lin_t),
+                ("t_ref", C.c_double)]
 
 
 STATS_DTYPE = np.dtype([("iters", np.int32), ("converged", np.int32), ("status", np.int32),
@@ -125,6 +126,8 @@ _SIGS = {
                                       C.POINTER(_P)]),
     "far_odometry_step": (C.c_int, [_P, _P, C.c_int64, C.POINTER(C.c_double),
                                     C.POINTER(far_odometry_stats_t), _P]),
+    "far_odometry_step_timed": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, C.c_int32,
+                                          C.POINTER(C.c_double), _P, _P]),
     "far_odometry_destroy": (C.c_int, [_P]),
     "far_map_get_schedule": (C.c_int, [_P, C.POINTER(far_schedule_t)]),
     "far_map_set_schedule": (C.c_int, [_P, C.POINTER(far_schedule_t)]),
@@ -613,6 +616,22 @@ def far_odometry_step(h, xyz, stream=None):
     return np.array(T[:]).reshape(4, 4), _odo_dict(st)
 
 
+def far_odometry_step_timed(h, xyz, t, vel_t, vel, stream=None):
+    """One raw scan [3, n] with point times t [n] and velocity samples
+    (vel_t [m], vel [m, 6], float64), all on the device: undistorted, then
+    as far_odometry_step -> (T, stats dict with t_ref)."""
+    p, n = _pts(xyz, "xyz")
+    if t.dim() != 1 or t.shape[0] != n:
+        raise ValueError("t must be [n]")
+    pt, pv, m = _samples(vel_t, vel)
+    T = (C.c_double * 16)()
+    st = far_odometry_stats_t()
+    _check(lib().far_odometry_step_timed(h, p, _dev(t, torch.float32, "t"), n, pt, pv, m, T,
+                                         C.byref(st), _stream(stream)),
+           "far_odometry_step_timed")
+    return np.array(T[:]).reshape(4, 4), _odo_dict(st)
+
+
 def far_odometry_destroy(h):
     _check(lib().far_odometry_destroy(h), "far_odometry_destroy")
 
@@ -649,7 +668,11 @@ class Odometry:
         self.map = map_
         self._h = far_odometry_create(map_.h, T_first, v_first, **kw)
 
-    def step(self, xyz, stream=None):
+    def step(self, xyz, stream=None, times=None, vel_t=None, vel=None):
+        """One scan; with per-point times and velocity samples it is
+        undistorted first (far_odometry_step_timed)."""
+        if times is not None:
+            return far_odometry_step_timed(self._h, xyz, times, vel_t, vel, stream)
         return far_odometry_step(self._h, xyz, stream)
 
     def close(self):

@@ -196,3 +196,56 @@ def test_undistort_full_racing_batch(orc):
         o[:, a:b], otr = orc.undistort(scans[s], times[s], vts[s], vels[s])
         assert gtr[s] == otr, s
     assert_parity(g, o, "full racing batch")
+
+
+def angle_deg(A, B):
+    E = A[:3, :3] @ B[:3, :3].T
+    s = np.array([E[2, 1] - E[1, 2], E[0, 2] - E[2, 0], E[1, 0] - E[0, 1]])
+    return math.degrees(math.atan2(0.5 * np.linalg.norm(s), 0.5 * (np.trace(E) - 1)))
+
+
+@pytest.mark.timeout(900)
+def test_odometry_with_undistortion_matches_oracle(orc):
+    """30 scans of the racing line through the odometry, each undistorted on
+    the GPU first (far_odometry_step_timed): poses within the sequence bar
+    of the oracle's, reference times exact; and the motion-undistortion
+    ablation on the GPU (the same scans without it drift several times
+    farther from the trajectory)."""
+    from paper_2606_26010_amd import far
+    n = 30
+    c = synth.make_deskew(6, n_scans=n)
+    v1 = np.linalg.inv(c.poses[0]) @ c.poses[1]
+    kw = dict(max_iters=10, eps=0.0)
+    ref, _ = orc.odometry(c.scans, c.poses[0], v1, c.voxel_size, c.max_pts_per_voxel,
+                          c.min_spacing, c.k, c.map_capacity, c.downsample, c.sigma0, c.r_max,
+                          times=c.times, vel_t=c.vel_t, vel=c.vel, **kw)
+    drift = {}
+    for deskew in (True, False):
+        gm = far.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.map_capacity,
+                     c.map_capacity, c.k)
+        od = far.Odometry(gm, c.poses[0], v1, downsample=c.downsample, sigma0=c.sigma0,
+                          r_max=c.r_max, **kw)
+        worst = (0.0, 0.0)
+        err = 0.0
+        for s in range(n):
+            if deskew:
+                T, st = od.step(dev(c.scans[s]), times=dev(c.times[s]), vel_t=dev(c.vel_t[s]),
+                                vel=dev(c.vel[s]))
+                r = ref[s]
+                assert st["t_ref"] == r["t_ref"], s
+                assert st["n_down"] == r["n"] and st["status"] == r["status"], s
+                dt = float(np.linalg.norm(T[:3, 3] - r["T"][:3, 3]))
+                da = angle_deg(T, r["T"])
+                worst = (max(worst[0], dt), max(worst[1], da))
+                assert dt <= 1e-3 and da <= 1e-2, (s, dt, da)
+            else:
+                T, st = od.step(dev(c.scans[s]))
+                assert math.isnan(st["t_ref"])
+            err = max(err, float(np.linalg.norm(T[:3, 3] - c.poses[s][:3, 3])))
+        drift[deskew] = err
+        if deskew:
+            say(f"odometry with undistortion vs oracle: worst {worst[0]:.2e} m, {worst[1]:.2e} deg")
+        od.close()
+        gm.close()
+    say(f"drift from the trajectory: undistorted {drift[True]:.3f} m, raw {drift[False]:.3f} m")
+    assert drift[True] <= 0.2 and drift[True] <= 0.25 * drift[False]

@@ -121,9 +121,10 @@ def next_rows(far, synth, np, torch, dev, stream, gm, case, T_fin, cov, val, see
       undistort  64 racing scans (8 distinct moving-LiDAR scans used 8 times,
                  each with its own time offset) in one batched call; per point
                  16 B read (xyz, time) and 12 B written;
-      gradient   d cost / d (pose, points) of the largest scan at its aligned
-                 pose: the linearisation's bytes plus 12 B per point written;
-      asmd_caps  adaptive density caps of the same scan: 24 B read and 4 B
+      gradient   d cost / d (pose, points) of every scan of the batch at its
+                 aligned pose in one batched call: the linearisation's bytes
+                 plus 12 B per point written (and the largest scan alone);
+      asmd_caps  adaptive density caps of the largest scan: 24 B read and 4 B
                  written per point (the hash set of near voxels aside);
       evict      removal of the voxels beyond 60 m of the first scan's pose
                  from the map and the rebuild of its structures: the sum of
@@ -154,26 +155,47 @@ def next_rows(far, synth, np, torch, dev, stream, gm, case, T_fin, cov, val, see
                                           "roofline": hbm_roofline(28.0 * n, ms_apply)}}
     del x, t, o, vt, v, vo, out
 
-    # gradient and ASMD caps on the largest scan of the batch
-    s = int(np.argmax([sc.shape[1] for sc in case.scans]))
-    a = int(sum(sc.shape[1] for sc in case.scans[:s]))
-    n = case.scans[s].shape[1]
-    src = to(case.scans[s])
-    cv, vl = cov[:, a:a + n].contiguous(), val[a:a + n].contiguous()
-    T = T_fin[s]
-    res = {}
-
-    def grad():
-        res["g"] = far.far_gicp_gradient(gm.h, src, cv, vl, T, case.tau, case.kappa, c=T[:3, 3])
-    ms, = lib_ms(far, (far.FAR_TIME_GRADIENT,), grad, 20)
+    # gradient of the whole batch at the aligned poses (one batched call), and
+    # of its largest scan alone
     mx, _, _ = gm.export()
     mk = np.floor(mx.cpu().numpy().astype(np.float64) / case.voxel_size).astype(np.int64)
     mp = ((mk[0] + (1 << 20)) << 42) | ((mk[1] + (1 << 20)) << 21) | (mk[2] + (1 << 20))
-    vk, vc = touched_voxels(np.unique(mp, return_counts=True), case.scans[s], T, case.voxel_size)
-    nb = 37.0 * n + 32.0 * res["g"]["n_inliers"] + 20.0 * vk.size + 16.0 * vc.sum() + 12.0 * n
-    rows["gradient"] = {"points": n, "inliers": res["g"]["n_inliers"], "ms": round(ms, 4),
-                        "points_per_s": round(n / (ms * 1e-3), 1),
+    keys_counts = np.unique(mp, return_counts=True)
+    S = len(case.scans)
+    sizes = np.array([sc.shape[1] for sc in case.scans], np.int64)
+    offs_b = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    src_b, o_b = to(np.concatenate(case.scans, 1)), to(offs_b)
+    T_b = to(np.stack([T_fin[k].reshape(16) for k in range(S)]))
+    ctr_b = to(np.stack([T_fin[k][:3, 3] for k in range(S)]))
+    res = {}
+
+    def grad_batch():
+        res["b"] = far.far_gicp_gradient_batch(gm.h, src_b, o_b, cov, val, T_b, case.tau,
+                                               case.kappa, c=ctr_b)
+    ms, = lib_ms(far, (far.FAR_TIME_GRADIENT,), grad_batch, 20)
+    inl = int(res["b"]["n_inliers"].sum())
+    vox = [touched_voxels(keys_counts, case.scans[k], T_fin[k], case.voxel_size)
+           for k in range(S)]
+    vk = np.concatenate([x[0] for x in vox])
+    vc = np.concatenate([x[1] for x in vox])
+    uk, ui = np.unique(vk, return_index=True)
+    N = int(offs_b[-1])
+    nb = 37.0 * N + 32.0 * inl + 20.0 * uk.size + 16.0 * vc[ui].sum() + 12.0 * N
+    rows["gradient"] = {"scans": S, "points": N, "inliers": inl, "ms": round(ms, 4),
+                        "points_per_s": round(N / (ms * 1e-3), 1),
                         "roofline": hbm_roofline(float(nb), ms)}
+
+    s = int(np.argmax(sizes))
+    a, n = int(offs_b[s]), int(sizes[s])
+    src = to(case.scans[s])
+    cv, vl = cov[:, a:a + n].contiguous(), val[a:a + n].contiguous()
+    T = T_fin[s]
+
+    def grad():
+        res["g"] = far.far_gicp_gradient(gm.h, src, cv, vl, T, case.tau, case.kappa, c=T[:3, 3])
+    ms1, = lib_ms(far, (far.FAR_TIME_GRADIENT,), grad, 20)
+    rows["gradient_one_scan"] = {"points": n, "ms": round(ms1, 4),
+                                 "points_per_s": round(n / (ms1 * 1e-3), 1)}
 
     moved = far.far_transform_points(src, T)
     ms, = lib_ms(far, (far.FAR_TIME_ASMD,),

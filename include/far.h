@@ -203,6 +203,22 @@ far_status_t far_gicp_gradient(far_map_t map, const float* src, const float* cov
                                double grad_T[12], double grad_twist[6], float* grad_src,
                                double* cost, int64_t* n_inliers, far_stream_t stream);
 
+/* far_gicp_gradient for S scans in one pass: scan s holds points
+ * [offsets[s], offsets[s+1]) of src [dev, SoA 3 x n_total], cov6 [dev, SoA
+ * 6 x n_total] and valid [dev, n_total] (offsets [dev, S+1] int64,
+ * non-decreasing, offsets[0] = 0, offsets[S] = n_total) at pose T [dev,
+ * S x 16]; c [dev, S x 3, or NULL = origins] the twist centres.  Outputs
+ * [dev]: grad_T [S x 12], grad_twist [S x 6], grad_src [SoA 3 x n_total, or
+ * NULL], cost [S, or NULL], n_inliers [S, or NULL].  Each scan's values are
+ * the bits far_gicp_gradient gives for it alone when the tile schedule
+ * matches.  Malformed offsets give zero outputs.  Asynchronous. */
+far_status_t far_gicp_gradient_batch(far_map_t map, const float* src, const int64_t* offsets,
+                                     int32_t S, int64_t n_total, const float* cov6,
+                                     const uint8_t* valid, const double* T, const double* c,
+                                     double tau, double kappa, int32_t precision,
+                                     double* grad_T, double* grad_twist, float* grad_src,
+                                     double* cost, int64_t* n_inliers, far_stream_t stream);
+
 /* Gauss-Newton align of one scan (Eq. 6): up to max_iters iterations of
  * linearise, solve H delta = -b by FP64 Cholesky, T <- T_c Exp(delta) T_c^-1 T
  * (T_c = translation by the linearisation centre), stopping when
@@ -235,7 +251,8 @@ far_status_t far_gicp_align_batch(far_map_t map, const float* src, const int64_t
  * v/2 through a second hash index of the map (built lazily after inserts;
  * power-of-two v only, else ignored), 0 = over the 27 voxels (default).
  * Both searches are exact; the tile changes only the rounding order of the
- * FP64 sums. */
+ * FP64 sums.  A job with fewer tiles than two per compute unit at the map's
+ * tile (a single scan of about 100k points) runs at tile 128. */
 typedef struct {
   int32_t tile;
   int32_t fine_cells;

@@ -42,44 +42,73 @@ struct Params {
 };
 
 // ---------------------------------------------------------------- tiles
-__global__ __launch_bounds__(256) void k_build_tiles(const int64_t* offsets, int32_t S,
-                                                     int64_t n_total, int64_t max_tiles,
-                                                     int32_t tile, int32_t* tile_scan,
-                                                     uint32_t* tile_lo, uint32_t* tile_hi,
-                                                     int32_t* begin, int32_t* bad) {
-  __shared__ int32_t s_total;
-  __shared__ int32_t s_bad;
-  if (threadIdx.x == 0) {
-    int32_t b = (offsets[0] != 0 || offsets[S] != n_total) ? 1 : 0;
-    int64_t acc = 0;
-    begin[0] = 0;
-    for (int32_t s = 0; s < S; ++s) {
-      int64_t len = offsets[s + 1] - offsets[s];
-      if (len < 0) b = 1;
-      acc += len > 0 ? (len + tile - 1) / tile : 0;
-      begin[s + 1] = int32_t(acc);
-    }
-    if (acc > max_tiles) b = 1;
-    if (b)
-      for (int32_t s = 0; s <= S; ++s) begin[s] = 0;
-    s_total = b ? 0 : int32_t(acc);
-    s_bad = b;
-    *bad = b;
+// Tile table of a job in two launches: k_tile_begin takes the per-scan tile
+// counts into begin[] (one lane; S is small) and flags a malformed offsets
+// array; k_tile_fill then writes one tile per lane (tile_scan -1 past the
+// last tile), finding its scan by bisection of begin[] in LDS.
+__global__ __launch_bounds__(64) void k_tile_begin(const int64_t* offsets, int32_t S,
+                                                   int64_t n_total, int64_t max_tiles,
+                                                   int32_t tile, int32_t* begin, int32_t* bad) {
+  if (threadIdx.x != 0) return;
+  int32_t b = (offsets[0] != 0 || offsets[S] != n_total) ? 1 : 0;
+  int64_t acc = 0;
+  begin[0] = 0;
+  for (int32_t s = 0; s < S; ++s) {
+    int64_t len = offsets[s + 1] - offsets[s];
+    if (len < 0) b = 1;
+    acc += len > 0 ? (len + tile - 1) / tile : 0;
+    begin[s + 1] = int32_t(acc);
   }
+  if (acc > max_tiles) b = 1;
+  if (b)
+    for (int32_t s = 0; s <= S; ++s) begin[s] = 0;
+  *bad = b;
+}
+
+constexpr int kTileLdsScans = 2048;
+
+__global__ __launch_bounds__(256) void k_tile_fill(const int64_t* offsets, int32_t S,
+                                                   int64_t max_tiles, int32_t tile,
+                                                   const int32_t* begin, int32_t* tile_scan,
+                                                   uint32_t* tile_lo, uint32_t* tile_hi) {
+  __shared__ int32_t s_begin[kTileLdsScans + 1];
+  const bool lds = S <= kTileLdsScans;
+  if (lds)
+    for (int32_t s = threadIdx.x; s <= S; s += blockDim.x) s_begin[s] = begin[s];
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < max_tiles; t += blockDim.x)
-    if (t >= s_total) tile_scan[t] = -1;
-  if (s_bad) return;
-  for (int32_t s = threadIdx.x; s < S; s += blockDim.x) {
-    int64_t lo = offsets[s], hi = offsets[s + 1];
-    for (int32_t t = begin[s]; t < begin[s + 1]; ++t) {
-      int64_t a = lo + int64_t(t - begin[s]) * tile;
-      int64_t b = a + tile < hi ? a + tile : hi;
-      tile_scan[t] = s;
-      tile_lo[t] = uint32_t(a);
-      tile_hi[t] = uint32_t(b);
-    }
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= max_tiles) return;
+  const int32_t* bg = lds ? s_begin : begin;
+  if (t >= bg[S]) {
+    tile_scan[t] = -1;
+    return;
   }
+  // the scan s with begin[s] <= t < begin[s + 1]
+  int32_t lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (bg[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int64_t a = offsets[lo] + (t - bg[lo]) * int64_t(tile);
+  const int64_t e = offsets[lo + 1];
+  tile_scan[t] = lo;
+  tile_lo[t] = uint32_t(a);
+  tile_hi[t] = uint32_t(a + tile < e ? a + tile : e);
+}
+
+// Offsets {0, n}, pose and fixed centre of a one-scan job, passed by value
+// (no host copy to stage).
+struct SingleArgs {
+  int64_t n;
+  double T[16];
+  double c[3];
+};
+
+__global__ void k_set_single(SingleArgs a, int64_t* offsets, double* T, double* cfix) {
+  const int i = threadIdx.x;
+  if (i < 16) T[i] = a.T[i];
+  if (i < 3 && cfix) cfix[i] = a.c[i];
+  if (i < 2) offsets[i] = i == 0 ? 0 : a.n;
 }
 
 // Per-scan state reset: not done, zero stats, linearisation centre.
@@ -699,16 +728,44 @@ __global__ __launch_bounds__(256) void k_reduce_solve(int32_t S, const int32_t* 
   }
 }
 
-// Sum of the 14 gradient partials of one scan's tiles in tile order (eight
-// interleaved groups, then the groups in order, as k_reduce_solve).
+// Twist gradient about c from the gradient g of [R | t] (row-major 3 x 4)
+// at pose T: with dR = [w]x R and dt = [w]x (t - c) + v, the rotation part
+// is the axial vector of A - A^T for A = R G_R^T + (t - c) G_t^T and the
+// translation part is G_t.  Shared by the host (one scan) and the batched
+// reduction so that both give the same bits.
+__host__ __device__ inline void twist_from_grad(const double* g, const double* T,
+                                                const double* c, double* tw) {
+  double A[9];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) {
+      double x = 0.0;
+      for (int l = 0; l < 3; ++l) x += T[4 * r + l] * g[4 * q + l];
+      A[3 * r + q] = x + (T[4 * r + 3] - c[r]) * g[4 * q + 3];
+    }
+  tw[0] = A[5] - A[7];
+  tw[1] = A[6] - A[2];
+  tw[2] = A[1] - A[3];
+  for (int q = 0; q < 3; ++q) tw[3 + q] = g[4 * q + 3];
+}
+
+// One block per scan: the sum of the 14 gradient partials of the scan's
+// tiles in tile order (eight interleaved groups, then the groups in order,
+// as k_reduce_solve) into out[14 s ..]; with gT given also the per-scan
+// outputs of the batched gradient (grad_T, the twist about c[3 s ..] or the
+// origin, cost, inliers).
 __global__ __launch_bounds__(256) void k_reduce_grad(const int32_t* begin,
-                                                     const double* partial, double* out) {
+                                                     const double* partial, double* out,
+                                                     const double* T, const double* c,
+                                                     double* gT, double* gtw, double* cost,
+                                                     int64_t* n_inl) {
   __shared__ double part[8][14];
+  __shared__ double sum[14];
+  const int s = blockIdx.x;
   const int g = threadIdx.x >> 5, v = threadIdx.x & 31;
   if (v < 14) {
     double acc = 0.0;
-    const int32_t t1 = begin[1];
-    for (int32_t t = begin[0] + g; t < t1; t += 8) acc += partial[int64_t(t) * kStride + v];
+    const int32_t t1 = begin[s + 1];
+    for (int32_t t = begin[s] + g; t < t1; t += 8) acc += partial[int64_t(t) * kStride + v];
     part[g][v] = acc;
   }
   __syncthreads();
@@ -716,7 +773,18 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const int32_t* begin,
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc += part[q][threadIdx.x];
-    out[threadIdx.x] = acc;
+    out[14 * int64_t(s) + threadIdx.x] = acc;
+    sum[threadIdx.x] = acc;
+  }
+  if (!gT) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double zero[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 12; ++q) gT[12 * int64_t(s) + q] = sum[q];
+    twist_from_grad(sum, T + 16 * int64_t(s), c ? c + 3 * int64_t(s) : zero,
+                    gtw + 6 * int64_t(s));
+    if (cost) cost[s] = sum[12];
+    if (n_inl) n_inl[s] = int64_t(sum[13]);
   }
 }
 
@@ -840,8 +908,14 @@ struct Job {
   int32_t* corr;
   Params prm;
   int32_t precision;
-  double* gsum = nullptr;      // non-null: one gradient pass (single scan), sums here
+  double* gsum = nullptr;      // non-null: one gradient pass, 14 sums per scan here
   float* grad_src = nullptr;   // gradient pass: per-point source gradient or null
+  // batched gradient outputs (per scan; null for the one-scan path)
+  const double* g_c = nullptr;
+  double* g_T = nullptr;
+  double* g_tw = nullptr;
+  double* g_cost = nullptr;
+  int64_t* g_n = nullptr;
   int32_t tile = kTileDefault; // points per tile (the map's schedule)
 };
 
@@ -879,8 +953,11 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
 far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
                      hipStream_t st) {
   MapView mv = m->view();
-  k_build_tiles<<<1, 256, 0, st>>>(j.offsets, j.S, j.n_total, max_tiles, j.tile,
-                                   w->tile_scan, w->tile_lo, w->tile_hi, w->begin, w->bad);
+  k_tile_begin<<<1, 64, 0, st>>>(j.offsets, j.S, j.n_total, max_tiles, j.tile, w->begin,
+                                 w->bad);
+  FAR_HIP(hipGetLastError());
+  k_tile_fill<<<unsigned((max_tiles + 255) / 256), 256, 0, st>>>(
+      j.offsets, j.S, max_tiles, j.tile, w->begin, w->tile_scan, w->tile_lo, w->tile_hi);
   FAR_HIP(hipGetLastError());
   k_init<<<(j.S + 255) / 256, 256, 0, st>>>(j.S, j.T, w->bad, j.prm.recenter, j.c_fixed,
                                             j.stats, w->done, w->ctr);
@@ -909,7 +986,8 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
       FAR_TRY((launch_lin<double, true>(j.tile, grid, st, mv, w, max_tiles, j)));
     else
       FAR_TRY((launch_lin<float, true>(j.tile, grid, st, mv, w, max_tiles, j)));
-    k_reduce_grad<<<1, 256, 0, st>>>(w->begin, w->partial, j.gsum);
+    k_reduce_grad<<<unsigned(j.S), 256, 0, st>>>(w->begin, w->partial, j.gsum, j.T, j.g_c,
+                                                  j.g_T, j.g_tw, j.g_cost, j.g_n);
     FAR_HIP(hipGetLastError());
     return FAR_OK;
   }
@@ -939,6 +1017,11 @@ bool same_params(const Params& a, const Params& b) {
 far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph) {
   Job j = j0;
   j.tile = m->sched_tile;
+  // a job too small to give every CU two blocks at the map's tile (one scan
+  // of ~100k points) runs at the smallest tile: twice the blocks to hide
+  // the search latency
+  if (j.tile > kTileMin && (j.n_total + j.tile - 1) / j.tile < 2 * int64_t(device_cu_count()))
+    j.tile = kTileMin;
   j.prm.fine_nn = m->sched_fine;
   const int64_t max_tiles = (j.n_total + j.tile - 1) / j.tile + j.S;
   AlignWS* w = nullptr;
@@ -1023,6 +1106,21 @@ using namespace far;
 
 extern "C" {
 
+const double kOrigin[3] = {0.0, 0.0, 0.0};
+
+// Writes a one-scan job's offsets, pose and (with_c) fixed centre into the
+// workspace by a kernel argument.
+far_status_t set_single(AlignWS* w, int64_t n, const double T[16], const double c[3],
+                        bool with_c, hipStream_t st) {
+  SingleArgs a;
+  a.n = n;
+  memcpy(a.T, T, sizeof(a.T));
+  memcpy(a.c, c, sizeof(a.c));
+  k_set_single<<<1, 64, 0, st>>>(a, w->offsets, w->T, with_c ? w->cfix : nullptr);
+  FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
+
 far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6,
                                 const uint8_t* valid, int64_t n, const double T[16],
                                 double tau, double kappa, const double c[3],
@@ -1039,11 +1137,7 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
   FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
-  int64_t offs[2] = {0, n};
-  double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
-  FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
-  FAR_HIP(hipMemcpyAsync(w->T, T, 16 * sizeof(double), hipMemcpyHostToDevice, st));
-  FAR_HIP(hipMemcpyAsync(w->cfix, cc, sizeof(cc), hipMemcpyHostToDevice, st));
+  FAR_TRY(set_single(w, n, T, c ? c : kOrigin, true, st));
   Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, corr,
         make_params(m, tau, kappa, 0.0, 1, 0), precision};
   FAR_TRY(run_job(m, j, st, false));
@@ -1073,13 +1167,10 @@ far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
   FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
-  int64_t offs[2] = {0, n};
   const double cc[3] = {c ? c[0] : 0.0, c ? c[1] : 0.0, c ? c[2] : 0.0};
   {
     TimedScope ts(FAR_TIME_GRADIENT, st);
-    FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
-    FAR_HIP(hipMemcpyAsync(w->T, T, 16 * sizeof(double), hipMemcpyHostToDevice, st));
-    FAR_HIP(hipMemcpyAsync(w->cfix, cc, sizeof(cc), hipMemcpyHostToDevice, st));
+    FAR_TRY(set_single(w, n, T, cc, true, st));
     Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, nullptr,
           make_params(m, tau, kappa, 0.0, 1, 0), precision};
     j.gsum = w->gsum;
@@ -1090,22 +1181,42 @@ far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
   FAR_HIP(hipMemcpyAsync(g, w->gsum, sizeof(g), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipStreamSynchronize(st));
   for (int q = 0; q < 12; ++q) grad_T[q] = g[q];
-  // twist about c: dR = [w]x R, dt = [w]x (t - c) + v, so the rotation part
-  // is the axial vector of A - A^T with A = R G_R^T + (t - c) G_t^T
-  double A[9];
-  for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < 3; ++q) {
-      double x = 0.0;
-      for (int l = 0; l < 3; ++l) x += T[4 * r + l] * g[4 * q + l];
-      A[3 * r + q] = x + (T[4 * r + 3] - cc[r]) * g[4 * q + 3];
-    }
-  grad_twist[0] = A[5] - A[7];
-  grad_twist[1] = A[6] - A[2];
-  grad_twist[2] = A[1] - A[3];
-  for (int q = 0; q < 3; ++q) grad_twist[3 + q] = g[4 * q + 3];
+  twist_from_grad(g, T, cc, grad_twist);
   if (cost) *cost = g[12];
   if (n_inliers) *n_inliers = int64_t(g[13]);
   return FAR_OK;
+}
+
+far_status_t far_gicp_gradient_batch(far_map_t m, const float* src, const int64_t* offsets,
+                                     int32_t S_, int64_t n_total, const float* cov6,
+                                     const uint8_t* valid, const double* T, const double* c,
+                                     double tau, double kappa, int32_t precision,
+                                     double* grad_T, double* grad_twist, float* grad_src,
+                                     double* cost, int64_t* n_inliers, far_stream_t stream) {
+  if (!m || !offsets || !T || !grad_T || !grad_twist || S_ < 1 || n_total < 0 ||
+      n_total >= (int64_t(1) << 31) || !(tau > 0.0) || !(kappa > 0.0) ||
+      (n_total > 0 && (!src || !cov6 || !valid)) ||
+      (precision != FAR_PREC_FP32 && precision != FAR_PREC_FP64)) {
+    set_error("far_gicp_gradient_batch: invalid argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  Scratch scr(st);
+  far_align_stats_t* sts;
+  double* gsum;
+  FAR_TRY(scr.get(&sts, size_t(S_)));
+  FAR_TRY(scr.get(&gsum, size_t(S_) * 14));
+  TimedScope ts(FAR_TIME_GRADIENT, st);
+  Job j{src, offsets, S_, n_total, cov6, valid, const_cast<double*>(T), sts, nullptr, nullptr,
+        make_params(m, tau, kappa, 0.0, 1, 0), precision};
+  j.gsum = gsum;
+  j.grad_src = grad_src;
+  j.g_c = c;
+  j.g_T = grad_T;
+  j.g_tw = grad_twist;
+  j.g_cost = cost;
+  j.g_n = n_inliers;
+  return run_job(m, j, st, false);
 }
 
 far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
@@ -1128,9 +1239,7 @@ far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
   hipStream_t st = S(stream);
   AlignWS* w = nullptr;
   FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
-  int64_t offs[2] = {0, n};
-  FAR_HIP(hipMemcpyAsync(w->offsets, offs, sizeof(offs), hipMemcpyHostToDevice, st));
-  FAR_HIP(hipMemcpyAsync(w->T, T0, 16 * sizeof(double), hipMemcpyHostToDevice, st));
+  FAR_TRY(set_single(w, n, T0, kOrigin, false, st));
   Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, nullptr, nullptr,
         make_params(m, params->tau, params->kappa, params->eps, params->max_iters,
                     params->recenter),

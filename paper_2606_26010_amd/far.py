@@ -112,6 +112,9 @@ _SIGS = {
     "far_voxel_downsample": (C.c_int, [_P, C.c_int64, C.c_double, _P, _P,
                                        C.POINTER(C.c_int64), _P]),
     "far_transform_points": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_double), _P, _P]),
+    "far_gicp_gradient_batch": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P, _P,
+                                          C.c_double, C.c_double, C.c_int32, _P, _P, _P, _P,
+                                          _P, _P]),
     "far_undistort": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P]),
     "far_undistort_batch": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
                                       _P]),
@@ -424,6 +427,9 @@ class Map:
     def gradient(self, *a, **kw):
         return far_gicp_gradient(self.h, *a, **kw)
 
+    def gradient_batch(self, *a, **kw):
+        return far_gicp_gradient_batch(self.h, *a, **kw)
+
     def align(self, *a, **kw):
         return far_gicp_align(self.h, *a, **kw)
 
@@ -537,6 +543,31 @@ def _samples(vel_t, vel):
         raise ValueError("vel_t must be [m] and vel [m, 6]")
     return (_dev(vel_t, torch.float64, "vel_t"), _dev(vel, torch.float64, "vel"),
             vel_t.shape[0])
+
+
+def far_gicp_gradient_batch(h, src, offsets, cov6, valid, T, tau, kappa, c=None,
+                            precision=FAR_PREC_FP32, want_src=True, stream=None):
+    """Batched gradient, all on the device: dict(grad_T [S, 3, 4], grad_twist
+    [S, 6], grad_src [3, n] or None, cost [S], n_inliers [S]) as tensors."""
+    p, n = _pts(src, "src")
+    S = offsets.shape[0] - 1
+    if T.shape != (S, 16) and T.shape != (S, 4, 4):
+        raise ValueError("T must be [S, 16] or [S, 4, 4]")
+    dv = src.device
+    gT = torch.empty((S, 12), dtype=torch.float64, device=dv)
+    gw = torch.empty((S, 6), dtype=torch.float64, device=dv)
+    cost = torch.empty(S, dtype=torch.float64, device=dv)
+    cnt = torch.empty(S, dtype=torch.int64, device=dv)
+    gs = torch.empty((3, max(n, 1)), dtype=torch.float32, device=dv) if want_src else None
+    _check(lib().far_gicp_gradient_batch(
+        h, p, _dev(offsets, torch.int64, "offsets"), S, n, _dev(cov6, torch.float32, "cov6"),
+        _dev(valid, torch.uint8, "valid"), _dev(T, torch.float64, "T"),
+        _dev(c, torch.float64, "c"), tau, kappa, precision, _dev(gT, torch.float64, "grad_T"),
+        _dev(gw, torch.float64, "grad_twist"), _dev(gs, torch.float32, "grad_src"),
+        _dev(cost, torch.float64, "cost"), _dev(cnt, torch.int64, "n_inliers"), _stream(stream)),
+        "far_gicp_gradient_batch")
+    return dict(grad_T=gT.view(S, 3, 4), grad_twist=gw, grad_src=None if gs is None else gs[:, :n],
+                cost=cost, n_inliers=cnt)
 
 
 def far_undistort(xyz, t, vel_t, vel, out=None, stream=None):

@@ -130,3 +130,53 @@ def test_autograd_matches_gradient_and_oracle(tiny):
     assert rel(Tt.grad.numpy()[:3], 2.0 * o["grad_T"]) <= 1e-9
     assert not torch.any(Tt.grad[3])
     assert rel(host(src.grad), 2.0 * o["grad_src"]) <= 1e-6
+
+
+def batch_inputs(orc, c):
+    sizes = [s.shape[1] for s in c.scans]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    covs = [orc.scan_covariances(s, c.voxel_size, c.k) for s in c.scans]
+    cov = np.concatenate([cv[0] for cv in covs], 1).astype(np.float32)
+    val = np.concatenate([cv[1] for cv in covs])
+    return offs, covs, cov, val
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_batch_matches_oracle(orc, diff, prec):
+    """All 16 scans in one batched call against the oracle, scan by scan."""
+    far, c, gm, om = diff
+    offs, covs, cov, val = batch_inputs(orc, c)
+    T = np.stack([t.reshape(16) for t in c.T0])
+    ctr = np.stack([t[:3, 3] for t in c.T0])
+    r = gm.gradient_batch(dev(np.concatenate(c.scans, 1)), dev(offs), dev(cov), dev(val), dev(T),
+                          c.tau, c.kappa, c=dev(ctr), precision=prec)
+    for s, scan in enumerate(c.scans):
+        o = om.gradient(scan, covs[s][0].astype(np.float32), covs[s][1], c.T0[s], c.tau, c.kappa,
+                        c=c.T0[s][:3, 3])
+        g = dict(grad_T=host(r["grad_T"][s]), grad_twist=host(r["grad_twist"][s]),
+                 cost=float(r["cost"][s]), n_inliers=int(r["n_inliers"][s]),
+                 grad_src=r["grad_src"][:, offs[s]:offs[s + 1]])
+        check(g, o, prec, f"batch scan {s}")
+
+
+def test_gradient_batch_equals_single(orc, diff):
+    """At one tile size for both, each scan of the batch gets exactly the
+    bits of its own one-scan call (origin as the twist centre)."""
+    far, c, gm, om = diff
+    offs, covs, cov, val = batch_inputs(orc, c)
+    T = np.stack([t.reshape(16) for t in c.T0])
+    far.far_map_set_schedule(gm.h, 128, 0)
+    try:
+        r = gm.gradient_batch(dev(np.concatenate(c.scans, 1)), dev(offs), dev(cov), dev(val),
+                              dev(T), c.tau, c.kappa)
+        for s, scan in enumerate(c.scans):
+            g = gm.gradient(dev(scan), dev(covs[s][0].astype(np.float32)), dev(covs[s][1]),
+                            c.T0[s], c.tau, c.kappa)
+            np.testing.assert_array_equal(host(r["grad_T"][s]), g["grad_T"])
+            np.testing.assert_array_equal(host(r["grad_twist"][s]), g["grad_twist"])
+            assert float(r["cost"][s]) == g["cost"] and int(r["n_inliers"][s]) == g["n_inliers"]
+            np.testing.assert_array_equal(host(r["grad_src"][:, offs[s]:offs[s + 1]]),
+                                          host(g["grad_src"]))
+    finally:
+        far.far_map_set_schedule(gm.h, 256, 0)

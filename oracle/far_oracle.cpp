@@ -468,7 +468,9 @@ int orc_cholesky_solve6(const double H[36], const double b[6], double x[6]) {
 //  - Eq. (3): d_i = r_i - p_i.
 //  - Eq. (4): M = Sigma_r + R Sigma_s R^T, W = M^-1, e2 = d^T W d.
 //    Sparsity-aware case: if either covariance is invalid, Sigma_r = I and
-//    Sigma_s = 0, i.e. M = I (point-to-point).
+//    Sigma_s = 0, i.e. M = I (point-to-point).  With sparsity_aware = 0 (the
+//    ablation of Table III, standard GICP) such a pair is dropped instead:
+//    no correspondence, no term, not an inlier.
 //  - Eq. (5), Cauchy kernel on the Mahalanobis norm e = sqrt(e2):
 //    rho = kappa^2/2 ln(1 + e2/kappa^2), IRLS weight w = kappa^2/(kappa^2+e2).
 //  - Jacobian of d with respect to a left perturbation about the centre c,
@@ -480,7 +482,7 @@ int orc_linearize(const orc_map* m, const float* src, const float* src_cov6,
                   const uint8_t* src_valid, int64_t n, const double T[16],
                   double tau, double kappa, const double c[3], double H[36],
                   double b[6], double* cost, int64_t* n_inliers, int32_t* corr,
-                  double* detail) {
+                  double* detail, int32_t sparsity_aware) {
   if (n < 0 || !(tau > 0.0) || !(kappa > 0.0)) return 1;
   const double R00 = T[0], R01 = T[1], R02 = T[2], tx = T[3];
   const double R10 = T[4], R11 = T[5], R12 = T[6], ty = T[7];
@@ -508,6 +510,7 @@ int orc_linearize(const orc_map* m, const float* src, const float* src_cov6,
     knn(m->g, px, py, pz, 1, r, nb);
     if (nb.empty()) continue;
     int64_t j = nb[0].second;
+    if (!sparsity_aware && !(src_valid[i] != 0 && m->valid[size_t(j)] != 0)) continue;
     rowj[size_t(i)] = int32_t(j);
     const Pt& q = m->g.pts[size_t(j)];
     double d[3] = {q.x - px, q.y - py, q.z - pz};
@@ -619,7 +622,7 @@ int orc_align(const orc_map* m, const float* src, const float* src_cov6,
               double tau, double kappa, int32_t max_iters, double eps,
               int32_t recenter, double T_out[16], int32_t* iters,
               int32_t* converged, double H[36], double b[6], double* cost,
-              int64_t* n_inliers) {
+              int64_t* n_inliers, int32_t sparsity_aware) {
   if (max_iters < 1) return 1;
   double T[16];
   std::memcpy(T, T0, sizeof(T));
@@ -630,7 +633,7 @@ int orc_align(const orc_map* m, const float* src, const float* src_cov6,
     double c[3] = {0.0, 0.0, 0.0};
     if (recenter) { c[0] = T[3]; c[1] = T[7]; c[2] = T[11]; }
     int rc = orc_linearize(m, src, src_cov6, src_valid, n, T, tau, kappa, c, H,
-                           b, cost, n_inliers, nullptr, nullptr);
+                           b, cost, n_inliers, nullptr, nullptr, sparsity_aware);
     if (rc) { status = rc; break; }
     if (*n_inliers < 6) { status = 5; break; }
     double nb[6], delta[6];
@@ -866,14 +869,15 @@ int orc_cost_fixed(const orc_map* m, const double* src, const float* src_cov6,
 int orc_gradient(const orc_map* m, const float* src, const float* src_cov6,
                  const uint8_t* src_valid, int64_t n, const double T[16], double tau,
                  double kappa, const double c[3], double grad_T[12], double grad_twist[6],
-                 double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr) {
+                 double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr,
+                 int32_t sparsity_aware) {
   if (n < 0 || !(tau > 0.0) || !(kappa > 0.0)) return 1;
   std::vector<int32_t> cj(size_t(n), -1);
   {
     double H[36], b[6], cst;
     int64_t cnt;
     int rc = orc_linearize(m, src, src_cov6, src_valid, n, T, tau, kappa, c, H, b, &cst, &cnt,
-                           cj.data(), nullptr);
+                           cj.data(), nullptr, sparsity_aware);
     if (rc) return rc;
   }
   const double R[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};

@@ -51,13 +51,15 @@ int orc_scan_covariances(const float* xyz, int64_t n, double v, int32_t k,
 /* One linearisation at pose T about centre c (NULL = origin).
  * src_cov6 is float SoA [6][n] (the stored precision).
  * Outputs: H [36] row-major, b [6], cost, inlier count; optional per-point
+ * sparsity_aware: 1 = a pair lacking a covariance enters with M = I
+ * (Sec. III-A.2), 0 = such a pair is dropped (standard GICP).
  * correspondence ids corr [n] (-1 = none) and per-point detail rows
  * detail [n][22] = (p[3], r[3], W[9], w, rho, e2, pad...) or NULL. */
 int orc_linearize(const orc_map* m, const float* src, const float* src_cov6,
                   const uint8_t* src_valid, int64_t n, const double T[16],
                   double tau, double kappa, const double c[3],
                   double H[36], double b[6], double* cost, int64_t* n_inliers,
-                  int32_t* corr, double* detail);
+                  int32_t* corr, double* detail, int32_t sparsity_aware);
 
 /* Gauss-Newton align.  Returns status; writes T_out, iterations, converged and
  * the last linearisation. */
@@ -66,7 +68,7 @@ int orc_align(const orc_map* m, const float* src, const float* src_cov6,
               double tau, double kappa, int32_t max_iters, double eps,
               int32_t recenter, double T_out[16], int32_t* iters,
               int32_t* converged, double H[36], double b[6], double* cost,
-              int64_t* n_inliers);
+              int64_t* n_inliers, int32_t sparsity_aware);
 
 /* Building blocks exposed for pinning. */
 void orc_voxel_keys(const float* xyz, int64_t n, double v, int64_t* keys3);
@@ -124,7 +126,8 @@ int orc_cost_fixed(const orc_map* m, const double* src, const float* src_cov6,
 int orc_gradient(const orc_map* m, const float* src, const float* src_cov6,
                  const uint8_t* src_valid, int64_t n, const double T[16], double tau,
                  double kappa, const double c[3], double grad_T[12], double grad_twist[6],
-                 double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr);
+                 double* grad_src, double* cost, int64_t* n_inliers, int32_t* corr,
+                 int32_t sparsity_aware);
 
 /* Adaptive submap density (Sec. III-A.3, ASMD).  Reading (the paper gives
  * no constants): the mean number of points per voxel of edge v over the

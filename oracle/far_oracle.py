@@ -61,11 +61,12 @@ def lib():
         L.orc_linearize.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p,
                                     C.c_double, C.c_double, _opt(_f64p), _f64p, _f64p,
                                     C.POINTER(C.c_double), C.POINTER(C.c_int64),
-                                    _opt(_i32p), _opt(_f64p)]
+                                    _opt(_i32p), _opt(_f64p), C.c_int32]
         L.orc_align.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p,
                                 C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                 _f64p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                _f64p, _f64p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+                                _f64p, _f64p, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                C.c_int32]
         L.orc_voxel_keys.argtypes = [_f32p, C.c_int64, C.c_double, _i64p]
         L.orc_se3_exp.argtypes = [_f64p, _f64p]
         L.orc_cholesky_solve6.argtypes = [_f64p, _f64p, _f64p]
@@ -76,7 +77,8 @@ def lib():
                                      C.c_double, _i32p, C.POINTER(C.c_double)]
         L.orc_gradient.argtypes = [C.c_void_p, _f32p, _f32p, _u8p, C.c_int64, _f64p, C.c_double,
                                    C.c_double, _opt(_f64p), _f64p, _f64p, _opt(_f64p),
-                                   C.POINTER(C.c_double), C.POINTER(C.c_int64), _opt(_i32p)]
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int64), _opt(_i32p),
+                                   C.c_int32]
         L.orc_asmd_caps.argtypes = [_f32p, _f32p, C.c_int64, C.c_double, C.c_int32, C.c_int32,
                                     C.c_double, C.c_double, _i32p, C.POINTER(C.c_double)]
         L.orc_map_evict.argtypes = [C.c_void_p, _f64p, C.c_double, C.POINTER(C.c_int64)]
@@ -163,7 +165,9 @@ class Map:
         return idx, d2, cnt
 
     def linearize(self, src, cov6, valid, T, tau, kappa, c=None, want_corr=False,
-                  want_detail=False):
+                  want_detail=False, sa=True):
+        """One linearisation; sa=False drops pairs lacking a covariance instead
+        of the sparsity-aware point-to-point term."""
         a = _soa(src)
         n = a.shape[1]
         cov = np.ascontiguousarray(cov6, dtype=np.float32)
@@ -175,7 +179,7 @@ class Map:
         corr = np.zeros(n, np.int32) if want_corr else None
         det = np.zeros((n, 18)) if want_detail else None
         rc = lib().orc_linearize(self._h, a, cov, val, n, T, tau, kappa, cc, H, b,
-                                 C.byref(cost), C.byref(cnt), corr, det)
+                                 C.byref(cost), C.byref(cnt), corr, det, 1 if sa else 0)
         if rc:
             raise OracleError(rc, "orc_linearize")
         out = dict(H=H.reshape(6, 6), b=b, cost=cost.value, n_inliers=cnt.value)
@@ -185,7 +189,8 @@ class Map:
             out["detail"] = det
         return out
 
-    def align(self, src, cov6, valid, T0, tau, kappa, max_iters=10, eps=1e-6, recenter=1):
+    def align(self, src, cov6, valid, T0, tau, kappa, max_iters=10, eps=1e-6, recenter=1,
+              sa=True):
         a = _soa(src)
         n = a.shape[1]
         cov = np.ascontiguousarray(cov6, dtype=np.float32)
@@ -197,7 +202,7 @@ class Map:
         cost, cnt = C.c_double(0), C.c_int64(0)
         rc = lib().orc_align(self._h, a, cov, val, n, T0, tau, kappa, max_iters, eps,
                              recenter, Tout, C.byref(it), C.byref(conv), H, b,
-                             C.byref(cost), C.byref(cnt))
+                             C.byref(cost), C.byref(cnt), 1 if sa else 0)
         return dict(status=rc, T=Tout.reshape(4, 4), iters=it.value, converged=conv.value,
                     H=H.reshape(6, 6), b=b, cost=cost.value, n_inliers=cnt.value)
 
@@ -215,7 +220,7 @@ class Map:
             raise OracleError(rc, "orc_cost_fixed")
         return out.value
 
-    def gradient(self, src, cov6, valid, T, tau, kappa, c=None, want_src=True):
+    def gradient(self, src, cov6, valid, T, tau, kappa, c=None, want_src=True, sa=True):
         """dict(grad_T [3, 4], grad_twist [6], grad_src [3, n] or None, cost,
         n_inliers, corr)."""
         a = _soa(src)
@@ -228,7 +233,8 @@ class Map:
         rc = lib().orc_gradient(self._h, a, np.ascontiguousarray(cov6, dtype=np.float32),
                                 np.ascontiguousarray(valid, dtype=np.uint8), n,
                                 np.ascontiguousarray(T, dtype=np.float64).reshape(16), tau,
-                                kappa, cc, gT, gw, gs, C.byref(cost), C.byref(cnt), corr)
+                                kappa, cc, gT, gw, gs, C.byref(cost), C.byref(cnt), corr,
+                                1 if sa else 0)
         if rc:
             raise OracleError(rc, "orc_gradient")
         return dict(grad_T=gT.reshape(3, 4), grad_twist=gw, grad_src=gs, cost=cost.value,

@@ -57,6 +57,15 @@ typedef enum {
   FAR_PREC_FP64 = 1       /* every per-point term and sum in FP64            */
 } far_precision_t;
 
+/* Option bit OR-ed into a precision argument (far_gicp_linearize,
+ * far_gicp_gradient, far_gicp_gradient_batch) or field (far_align_params_t,
+ * far_odometry_params_t).  FAR_OPT_NO_SA turns the sparsity-aware case of
+ * Sec. III-A.2 off: a correspondence whose source or map covariance is
+ * invalid is dropped like an outlier (no term, not an inlier, corr -1)
+ * instead of entering as a point-to-point term with M = I; the ablation the
+ * paper reports in Table III. */
+enum { FAR_OPT_NO_SA = 0x100 };
+
 /* Map parameters (Sec. III-A.2: voxel edge v, at most N_max "regularly
  * spaced" points per voxel; covariances from k neighbours).  Capacities are
  * fixed at create; the map never grows. */

@@ -39,6 +39,7 @@ struct Params {
   int32_t max_iters;
   int32_t recenter;
   int32_t fine_nn;  // correspondence search over the fine index (cells v/2)
+  int32_t sa_off;   // drop pairs with an invalid covariance (no sparsity-aware term)
 };
 
 // ---------------------------------------------------------------- tiles
@@ -544,18 +545,23 @@ void k_linearize(
     int32_t match = -1;
     Real gs[3] = {Real(0), Real(0), Real(0)};
     if (have && top.pos[0] >= 0) {
-      match = top.id[0];
+      const int32_t id = top.id[0];
       const float4 r = kFine ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
       // the source covariance is read only now: not holding it through the
       // search keeps the register count (and so the occupancy) down
       const float4 sB = pB[i];
       const float2 sC = pC[i];
-      const float4 ca = m.cov[2 * int64_t(match)];
-      const float4 cb = m.cov[2 * int64_t(match) + 1];
-      if constexpr (kGrad)
-        grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, R, prm.kappa2, acc, gs);
-      else
-        gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, R, cx, cy, cz, prm.kappa2, acc);
+      const float4 ca = m.cov[2 * int64_t(id)];
+      const float4 cb = m.cov[2 * int64_t(id) + 1];
+      // without the sparsity-aware case a pair lacking either covariance is
+      // dropped like an outlier
+      if (!prm.sa_off || (sB.x >= 0.0f && cb.z != 0.0f)) {
+        match = id;
+        if constexpr (kGrad)
+          grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, R, prm.kappa2, acc, gs);
+        else
+          gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, R, cx, cy, cz, prm.kappa2, acc);
+      }
     }
     if (corr && in_tile) corr[__float_as_uint(a.w)] = match;
     if (kGrad && grad_src && in_tile) {
@@ -1010,7 +1016,7 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
 bool same_params(const Params& a, const Params& b) {
   return a.r2 == b.r2 && a.kappa2 == b.kappa2 && a.inv_v == b.inv_v && a.v_pow2 == b.v_pow2 &&
          a.eps == b.eps && a.max_iters == b.max_iters && a.recenter == b.recenter &&
-         a.fine_nn == b.fine_nn;
+         a.fine_nn == b.fine_nn && a.sa_off == b.sa_off;
 }
 
 // Run a job, through a cached graph when the stream allows capture.
@@ -1074,16 +1080,24 @@ far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph
   return FAR_OK;
 }
 
+// A precision argument: far_precision_t, optionally with FAR_OPT_NO_SA.
+bool precision_ok(int32_t p) {
+  const int32_t base = p & ~int32_t(FAR_OPT_NO_SA);
+  return base == FAR_PREC_FP32 || base == FAR_PREC_FP64;
+}
+int32_t precision_of(int32_t p) { return p & ~int32_t(FAR_OPT_NO_SA); }
+
 bool params_ok(const far_align_params_t* p) {
   return p && p->tau > 0.0 && std::isfinite(p->tau) && p->kappa > 0.0 &&
          std::isfinite(p->kappa) && p->max_iters >= 1 && p->max_iters <= 64 &&
-         p->eps >= 0.0 && (p->precision == FAR_PREC_FP32 || p->precision == FAR_PREC_FP64);
+         p->eps >= 0.0 && precision_ok(p->precision);
 }
 
 Params make_params(const far_map_s* m, double tau, double kappa, double eps, int32_t max_iters,
-                   int32_t recenter) {
+                   int32_t recenter, int32_t precision) {
   Params prm;
   memset(&prm, 0, sizeof(prm));
+  prm.sa_off = (precision & FAR_OPT_NO_SA) ? 1 : 0;
   double r = tau < m->p.voxel_size ? tau : m->p.voxel_size;
   prm.r2 = r * r;
   prm.kappa2 = kappa * kappa;
@@ -1128,7 +1142,7 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
                                 far_stream_t stream) {
   if (!m || !T || !out || n < 0 || n >= (int64_t(1) << 31) || !(tau > 0.0) ||
       !(kappa > 0.0) || (n > 0 && (!src || !cov6 || !valid)) ||
-      (precision != FAR_PREC_FP32 && precision != FAR_PREC_FP64)) {
+      !precision_ok(precision)) {
     set_error("far_gicp_linearize: invalid argument");
     return FAR_E_INVALID;
   }
@@ -1139,7 +1153,7 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
   FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
   FAR_TRY(set_single(w, n, T, c ? c : kOrigin, true, st));
   Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, corr,
-        make_params(m, tau, kappa, 0.0, 1, 0), precision};
+        make_params(m, tau, kappa, 0.0, 1, 0, precision), precision_of(precision)};
   FAR_TRY(run_job(m, j, st, false));
   far_align_stats_t hs;
   FAR_HIP(hipMemcpyAsync(&hs, w->stats, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -1155,7 +1169,7 @@ far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
                                double* cost, int64_t* n_inliers, far_stream_t stream) {
   if (!m || !T || !grad_T || !grad_twist || n < 0 || n >= (int64_t(1) << 31) ||
       !(tau > 0.0) || !(kappa > 0.0) || (n > 0 && (!src || !cov6 || !valid)) ||
-      (precision != FAR_PREC_FP32 && precision != FAR_PREC_FP64)) {
+      !precision_ok(precision)) {
     set_error("far_gicp_gradient: invalid argument");
     return FAR_E_INVALID;
   }
@@ -1172,7 +1186,7 @@ far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,
     TimedScope ts(FAR_TIME_GRADIENT, st);
     FAR_TRY(set_single(w, n, T, cc, true, st));
     Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, nullptr,
-          make_params(m, tau, kappa, 0.0, 1, 0), precision};
+          make_params(m, tau, kappa, 0.0, 1, 0, precision), precision_of(precision)};
     j.gsum = w->gsum;
     j.grad_src = grad_src;
     FAR_TRY(run_job(m, j, st, false));
@@ -1196,7 +1210,7 @@ far_status_t far_gicp_gradient_batch(far_map_t m, const float* src, const int64_
   if (!m || !offsets || !T || !grad_T || !grad_twist || S_ < 1 || n_total < 0 ||
       n_total >= (int64_t(1) << 31) || !(tau > 0.0) || !(kappa > 0.0) ||
       (n_total > 0 && (!src || !cov6 || !valid)) ||
-      (precision != FAR_PREC_FP32 && precision != FAR_PREC_FP64)) {
+      !precision_ok(precision)) {
     set_error("far_gicp_gradient_batch: invalid argument");
     return FAR_E_INVALID;
   }
@@ -1208,7 +1222,7 @@ far_status_t far_gicp_gradient_batch(far_map_t m, const float* src, const int64_
   FAR_TRY(scr.get(&gsum, size_t(S_) * 14));
   TimedScope ts(FAR_TIME_GRADIENT, st);
   Job j{src, offsets, S_, n_total, cov6, valid, const_cast<double*>(T), sts, nullptr, nullptr,
-        make_params(m, tau, kappa, 0.0, 1, 0), precision};
+        make_params(m, tau, kappa, 0.0, 1, 0, precision), precision_of(precision)};
   j.gsum = gsum;
   j.grad_src = grad_src;
   j.g_c = c;
@@ -1242,8 +1256,8 @@ far_status_t far_gicp_align(far_map_t m, const float* src, const float* cov6,
   FAR_TRY(set_single(w, n, T0, kOrigin, false, st));
   Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, nullptr, nullptr,
         make_params(m, params->tau, params->kappa, params->eps, params->max_iters,
-                    params->recenter),
-        params->precision};
+                    params->recenter, params->precision),
+        precision_of(params->precision)};
   FAR_TRY(run_job(m, j, st, true));
   FAR_HIP(hipMemcpyAsync(T_out, w->T, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipMemcpyAsync(&hs, w->stats, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -1383,8 +1397,8 @@ far_status_t far_gicp_align_batch(far_map_t m, const float* src, const int64_t* 
   hipStream_t st = S(stream);
   Job j{src, offsets, S_, n_total, cov6, valid, T, stats, nullptr, nullptr,
         make_params(m, params->tau, params->kappa, params->eps, params->max_iters,
-                    params->recenter),
-        params->precision};
+                    params->recenter, params->precision),
+        precision_of(params->precision)};
   return run_job(m, j, st, true);
 }
 

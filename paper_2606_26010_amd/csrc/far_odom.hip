@@ -202,7 +202,8 @@ far_status_t far_odometry_create(far_map_t map, const far_odometry_params_t* par
       !std::isfinite(params->downsample) || params->max_iters < 1 || params->max_iters > 64 ||
       !(params->eps >= 0.0) || !(params->r_near >= 0.0) || !(params->evict_radius >= 0.0) ||
       (params->asmd != 0 && params->asmd != 1) ||
-      (params->precision != FAR_PREC_FP32 && params->precision != FAR_PREC_FP64)) {
+      ((params->precision & ~int32_t(FAR_OPT_NO_SA)) != FAR_PREC_FP32 &&
+       (params->precision & ~int32_t(FAR_OPT_NO_SA)) != FAR_PREC_FP64)) {
     far::set_error("far_odometry_create: invalid argument");
     return FAR_E_INVALID;
   }

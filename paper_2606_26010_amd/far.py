@@ -20,6 +20,7 @@ _lib = None
 FAR_OK, FAR_E_INVALID, FAR_E_CAPACITY, FAR_E_HIP, FAR_E_NOT_PD, FAR_E_FEW_CORR, \
     FAR_E_UNSUPPORTED = range(7)
 FAR_PREC_FP32, FAR_PREC_FP64 = 0, 1
+FAR_OPT_NO_SA = 0x100
 
 
 class far_map_params_t(C.Structure):
@@ -330,8 +331,11 @@ def far_gicp_gradient(h, src, cov6, valid, T, tau, kappa, c=None, precision=FAR_
                 n_inliers=cnt.value)
 
 
-def align_params(tau, kappa, max_iters=10, eps=1e-6, recenter=1, precision=FAR_PREC_FP32):
-    return far_align_params_t(tau, kappa, max_iters, eps, recenter, precision)
+def align_params(tau, kappa, max_iters=10, eps=1e-6, recenter=1, precision=FAR_PREC_FP32,
+                 sa=True):
+    """sa=False sets FAR_OPT_NO_SA (pairs lacking a covariance are dropped)."""
+    return far_align_params_t(tau, kappa, max_iters, eps, recenter,
+                              precision | (0 if sa else FAR_OPT_NO_SA))
 
 
 def far_gicp_align(h, src, cov6, valid, T0, params: far_align_params_t, stream=None):

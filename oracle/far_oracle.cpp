@@ -104,6 +104,77 @@ void regularize(const double S_hat[9], double Sigma[9]) {
   inv3(Cn, Sigma);
 }
 
+// Plane regularisation after Segal et al. (the GICP paper the sparsity-aware
+// case cites), offered beside Eq. (1): the sample covariance's eigenvector n
+// of its smallest eigenvalue is taken as the surface normal and the point's
+// covariance becomes that of a plane of thickness eps, U diag(eps, 1, 1) U^T
+// = I + (eps - 1) n n^T, eps = 1e-3.  The eigenvectors come from the cyclic
+// Jacobi method on the 3x3 matrix: plane rotations J chosen to zero one
+// off-diagonal entry at a time, A <- J^T A J, V <- V J, until the
+// off-diagonal part vanishes (to rounding) or 50 sweeps; ties between
+// smallest eigenvalues take the lowest index.
+const double kPlaneEps = 1e-3;
+int g_cov_mode = 0;   // 0: Eq. (1); 1: plane regularisation
+
+void mat3_mul(const double A[9], const double B[9], double C[9]) {
+  double t[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double x = 0.0;
+      for (int l = 0; l < 3; ++l) x += A[i * 3 + l] * B[l * 3 + j];
+      t[i * 3 + j] = x;
+    }
+  std::memcpy(C, t, sizeof(t));
+}
+
+void jacobi3(const double S[9], double evals[3], double V[9]) {
+  double A[9];
+  std::memcpy(A, S, sizeof(A));
+  for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  double fro = 0.0;
+  for (int i = 0; i < 9; ++i) fro += A[i] * A[i];
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    if (off == 0.0 || off <= 1e-36 * fro) break;
+    const int P[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (auto& pq : P) {
+      const int p = pq[0], q = pq[1];
+      const double apq = A[p * 3 + q];
+      if (apq == 0.0) continue;
+      // tan of the rotation angle, the smaller root (|angle| <= pi/4)
+      const double theta = (A[q * 3 + q] - A[p * 3 + p]) / (2.0 * apq);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+      const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+      double J[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+      J[p * 3 + p] = c; J[q * 3 + q] = c;
+      J[p * 3 + q] = sn; J[q * 3 + p] = -sn;
+      double Jt[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Jt[i * 3 + j] = J[j * 3 + i];
+      double T1[9];
+      mat3_mul(Jt, A, T1);
+      mat3_mul(T1, J, A);
+      A[p * 3 + q] = A[q * 3 + p] = 0.0;   // zero by construction
+      mat3_mul(V, J, V);
+    }
+  }
+  evals[0] = A[0]; evals[1] = A[4]; evals[2] = A[8];
+}
+
+void plane_regularize(const double S_hat[9], double Sigma[9]) {
+  double ev[3], V[9];
+  jacobi3(S_hat, ev, V);
+  int m = 0;
+  for (int i = 1; i < 3; ++i)
+    if (ev[i] < ev[m]) m = i;
+  double n[3] = {V[0 * 3 + m], V[1 * 3 + m], V[2 * 3 + m]};
+  const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (double& x : n) x /= len;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      Sigma[i * 3 + j] = (i == j ? 1.0 : 0.0) + (kPlaneEps - 1.0) * n[i] * n[j];
+}
+
 // Sample covariance of k points, two passes (mean first, then the centred
 // outer products), normalised by 1/k.  The neighbourhood includes the point
 // itself (Sec. III-A.2: covariance from the k nearest neighbours).
@@ -175,7 +246,10 @@ bool point_covariance(const Grid& g, const Pt& p, int k, double out6[6]) {
   for (auto& e : nb) pts.push_back(g.pts[size_t(e.second)]);
   double S[9], Sig[9];
   covariance_of(pts, S);
-  regularize(S, Sig);
+  if (g_cov_mode == 1)
+    plane_regularize(S, Sig);
+  else
+    regularize(S, Sig);
   out6[0] = Sig[0]; out6[1] = Sig[1]; out6[2] = Sig[2];
   out6[3] = Sig[4]; out6[4] = Sig[5]; out6[5] = Sig[8];
   return true;
@@ -377,6 +451,16 @@ int orc_scan_covariances(const float* xyz, int64_t n, double v, int32_t k,
 }
 
 void orc_regularize_cov(const double S[9], double out[9]) { regularize(S, out); }
+
+void orc_plane_cov(const double S[9], double out[9]) { plane_regularize(S, out); }
+
+void orc_jacobi3(const double S[9], double evals[3], double V[9]) { jacobi3(S, evals, V); }
+
+int orc_set_cov_mode(int32_t mode) {
+  if (mode != 0 && mode != 1) return 1;
+  g_cov_mode = mode;
+  return 0;
+}
 
 void orc_voxel_keys(const float* xyz, int64_t n, double v, int64_t* keys3) {
   for (int64_t i = 0; i < n; ++i) {

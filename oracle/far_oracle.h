@@ -70,6 +70,17 @@ int orc_align(const orc_map* m, const float* src, const float* src_cov6,
               int32_t* converged, double H[36], double b[6], double* cost,
               int64_t* n_inliers, int32_t sparsity_aware);
 
+/* Covariance regularisation used by every covariance computed afterwards
+ * (map inserts and scan covariances): 0 = Eq. (1) (default), 1 = plane
+ * regularisation after Segal et al., I + (1e-3 - 1) n n^T with n the
+ * eigenvector of the smallest eigenvalue of the sample covariance (cyclic
+ * Jacobi, FP64).  Returns 1 on another mode.  Process-wide. */
+int orc_set_cov_mode(int32_t mode);
+void orc_plane_cov(const double S[9], double out[9]);
+/* Eigenvalues (diagonal order) and eigenvectors (columns of V) by cyclic
+ * Jacobi. */
+void orc_jacobi3(const double S[9], double evals[3], double V[9]);
+
 /* Building blocks exposed for pinning. */
 void orc_voxel_keys(const float* xyz, int64_t n, double v, int64_t* keys3);
 void orc_se3_exp(const double delta[6], double T[16]);

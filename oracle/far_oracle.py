@@ -71,6 +71,9 @@ def lib():
         L.orc_se3_exp.argtypes = [_f64p, _f64p]
         L.orc_cholesky_solve6.argtypes = [_f64p, _f64p, _f64p]
         L.orc_regularize_cov.argtypes = [_f64p, _f64p]
+        L.orc_plane_cov.argtypes = [_f64p, _f64p]
+        L.orc_jacobi3.argtypes = [_f64p, _f64p, _f64p]
+        L.orc_set_cov_mode.argtypes = [C.c_int32]
         L.orc_touch_stats.argtypes = [C.c_void_p, _f32p, C.c_int64, _f64p,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.orc_cost_fixed.argtypes = [C.c_void_p, _f64p, _f32p, _u8p, C.c_int64, _f64p,
@@ -293,6 +296,26 @@ def regularize_cov(S):
     out = np.zeros(9)
     lib().orc_regularize_cov(np.ascontiguousarray(S, dtype=np.float64).reshape(9), out)
     return out.reshape(3, 3)
+
+
+def plane_cov(S):
+    """Plane-regularised covariance of a 3x3 sample covariance."""
+    out = np.zeros(9)
+    lib().orc_plane_cov(np.ascontiguousarray(S, dtype=np.float64).reshape(9), out)
+    return out.reshape(3, 3)
+
+
+def jacobi3(S):
+    """(eigenvalues [3], eigenvectors as columns [3, 3]) by cyclic Jacobi."""
+    ev, V = np.zeros(3), np.zeros(9)
+    lib().orc_jacobi3(np.ascontiguousarray(S, dtype=np.float64).reshape(9), ev, V)
+    return ev, V.reshape(3, 3)
+
+
+def set_cov_mode(mode):
+    """0: Eq. (1) (default); 1: plane regularisation.  Process-wide."""
+    if lib().orc_set_cov_mode(int(mode)):
+        raise OracleError(1, "orc_set_cov_mode")
 
 
 def downsample(xyz, v):

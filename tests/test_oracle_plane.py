@@ -1,0 +1,129 @@
+"""Pins of the oracle's plane regularisation, the variant offered beside Eq. (1)
+(after Segal et al., whom the sparsity-aware paragraph of Sec. III-A.2
+cites): Sigma = I + (eps - 1) n n^T, eps = 1e-3, n the eigenvector of the
+smallest eigenvalue of the sample covariance, by cyclic Jacobi in FP64.
+
+Checked against numpy.linalg.eigh, closed forms for planes, lines and
+coincident points, the invariant spectrum {eps, 1, 1}, and brute-force
+neighbour sets through the scan covariances and the map insert."""
+import numpy as np
+import pytest
+
+from paper_2606_26010_amd import synth
+from tests.test_oracle_cov import six_to_mat
+from tests.test_oracle_map import brute_knn
+
+EPS = 1e-3
+
+
+@pytest.fixture
+def plane_mode(orc):
+    orc.set_cov_mode(1)
+    yield orc
+    orc.set_cov_mode(0)
+
+
+def plane_ref(S):
+    """I + (eps - 1) n n^T with n from numpy.linalg.eigh (ascending order)."""
+    lam, Q = np.linalg.eigh(S)
+    n = Q[:, 0]
+    return np.eye(3) + (EPS - 1.0) * np.outer(n, n), lam
+
+
+def random_spd(g, scale_lo=1e-6, scale_hi=2.0):
+    A = g.normal(size=(3, 9)) * g.uniform(scale_lo, scale_hi, size=(3, 1))
+    Q = synth.random_offset(g, 0.0, 180.0)[:3, :3]
+    return Q @ np.cov(A, bias=True) @ Q.T
+
+
+def test_jacobi_against_numpy(orc):
+    g = synth.rng(11)
+    mats = [random_spd(g) for _ in range(200)]
+    mats += [np.zeros((3, 3)), np.diag([3.0, 1.0, 2.0]), np.diag([1.0, 1.0, 1.0]),
+             np.full((3, 3), 0.5)]
+    for S in mats:
+        ev, V = orc.jacobi3(S)
+        nrm = max(np.linalg.norm(S), 1e-300)
+        np.testing.assert_allclose(np.sort(ev), np.linalg.eigvalsh(S), rtol=0, atol=1e-13 * nrm)
+        np.testing.assert_allclose(V.T @ V, np.eye(3), rtol=0, atol=1e-14)
+        np.testing.assert_allclose(S @ V, V * ev, rtol=0, atol=1e-13 * nrm)
+
+
+def test_plane_cov_against_numpy_and_spectrum(orc):
+    g = synth.rng(12)
+    checked = 0
+    for _ in range(300):
+        S = random_spd(g)
+        Sig = orc.plane_cov(S)
+        np.testing.assert_allclose(Sig, Sig.T, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(np.linalg.eigvalsh(Sig), [EPS, 1.0, 1.0], rtol=0, atol=1e-13)
+        ref, lam = plane_ref(S)
+        if lam[1] - lam[0] > 1e-6 * lam[2]:        # n unique up to sign
+            np.testing.assert_allclose(Sig, ref, rtol=0, atol=1e-9)
+            checked += 1
+    assert checked > 250
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_plane_closed_forms(orc, axis):
+    g = synth.rng(13)
+    # points on a plane through the origin with normal e_axis
+    pts = g.normal(size=(3, 12))
+    pts[axis] = 0.0
+    Sig = orc.plane_cov(np.cov(pts, bias=True))
+    want = np.eye(3)
+    want[axis, axis] = EPS
+    np.testing.assert_allclose(Sig, want, rtol=0, atol=1e-15)
+    # a tilted plane: the normal of its rotation
+    Q = synth.random_offset(g, 0.0, 70.0)[:3, :3]
+    n0 = Q[:, axis]
+    Sig = orc.plane_cov(np.cov(Q @ pts, bias=True))
+    np.testing.assert_allclose(Sig, np.eye(3) + (EPS - 1.0) * np.outer(n0, n0), rtol=0,
+                               atol=1e-12)
+
+
+def test_plane_degenerate_ties(orc):
+    # coincident points (S = 0) and a line along z: every smallest eigenvalue
+    # ties, no rotation happens, the lowest index wins: n = e_x
+    want = np.diag([EPS, 1.0, 1.0])
+    close = dict(rtol=0, atol=1e-15)
+    np.testing.assert_allclose(orc.plane_cov(np.zeros((3, 3))), want, **close)
+    np.testing.assert_allclose(orc.plane_cov(np.diag([0.0, 0.0, 2.0])), want, **close)
+    np.testing.assert_allclose(orc.plane_cov(np.diag([5.0, 0.0, 0.0])),
+                               np.diag([1.0, EPS, 1.0]), **close)
+
+
+@pytest.mark.parametrize("k,v", [(5, 1.0), (10, 1.0)])
+def test_scan_covariances_plane_mode(plane_mode, k, v):
+    orc = plane_mode
+    cloud = synth.random_cloud(61, 2500, extent=2.5, dup_frac=0.02, on_faces=0.2, v=v)
+    cov, valid = orc.scan_covariances(cloud, v, k)
+    orc.set_cov_mode(0)
+    _, valid0 = orc.scan_covariances(cloud, v, k)
+    orc.set_cov_mode(1)
+    np.testing.assert_array_equal(valid, valid0)         # validity does not change
+    idx, _, cnt = brute_knn(cloud, np.arange(cloud.shape[1]), cloud, k, v)
+    p64 = cloud.astype(np.float64)
+    checked = 0
+    for i in np.nonzero(valid)[0][::2]:
+        S = np.cov(p64[:, idx[i]], bias=True)
+        ref, lam = plane_ref(S)
+        got = six_to_mat(cov[:, i])
+        np.testing.assert_allclose(np.linalg.eigvalsh(got), [EPS, 1.0, 1.0], rtol=0, atol=1e-12)
+        if lam[1] - lam[0] > 1e-6 * max(lam[2], 1e-300):
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-8)
+            checked += 1
+    assert checked > 300
+    assert np.all(cov[:, valid == 0] == 0)
+
+
+def test_map_insert_plane_mode(plane_mode):
+    orc = plane_mode
+    v, k = 1.0, 5
+    cloud = synth.random_cloud(62, 3000, extent=2.0, v=v)
+    m = orc.Map(v, 1 << 20, 0.0, k)
+    m.insert(cloud)
+    xyz, cov, val = m.export()
+    ref, rv = orc.scan_covariances(xyz, v, k)
+    np.testing.assert_array_equal(val, rv)
+    np.testing.assert_array_equal(cov, ref.astype(np.float32))

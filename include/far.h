@@ -291,6 +291,19 @@ far_status_t far_autotune(far_map_t map, const float* src, const int64_t* offset
  * lane per point over the 27 voxels; 0 = one lane per point everywhere.
  * Default 0 (measured fastest on the batched workload).  Results are
  * identical for every setting. */
+/* Covariance regularisation of every covariance computed afterwards (map
+ * inserts and scan covariances; process-wide, default FAR_REG_EQ1).
+ * FAR_REG_EQ1: Eq. (1) of Sec. III-A.2.  FAR_REG_PLANE: the plane
+ * regularisation of Segal et al. (cited by the sparsity-aware paragraph),
+ * Sigma = I + (1e-3 - 1) n n^T with n the unit eigenvector of the smallest
+ * eigenvalue of the k-neighbour sample covariance (FP64 closed-form 3x3
+ * eigen-solve on the GPU; when the smallest eigenvalue is double, any unit
+ * vector of its eigenspace).  Validity (k neighbours within v) is the same
+ * in both modes.  Another mode: FAR_E_INVALID. */
+typedef enum { FAR_REG_EQ1 = 0, FAR_REG_PLANE = 1 } far_cov_reg_t;
+far_status_t far_set_covariance_regularisation(int32_t mode);
+far_status_t far_get_covariance_regularisation(int32_t* mode);
+
 far_status_t far_set_covariance_schedule(int32_t dense_threshold);
 far_status_t far_get_covariance_schedule(int32_t* dense_threshold);
 

@@ -302,12 +302,102 @@ __device__ inline void knn_cells27(double px, double py, double pz, double c, do
   }
 }
 
-// Regularised covariance (Eq. 1) of the first k entries of a neighbour list.
-// Two-pass FP64 sample covariance with 1/k, C = S + 1e-3 I, and
-// Sigma = (C^-1 / ||C^-1||_F)^-1 = ||C^-1||_F C, where ||C^-1||_F is the
-// Frobenius norm of the cofactor matrix over |det C|.
+// Plane regularisation after Segal et al., beside Eq. (1): I + (eps - 1) n n^T
+// with eps = 1e-3 and n the unit eigenvector of the smallest eigenvalue of the
+// sample covariance S, in FP64.  The smallest eigenvalue comes from the
+// trigonometric solution of the characteristic cubic of a symmetric 3x3; n is
+// the longest cross product of two rows of S - lambda I.  Degenerate cases:
+// S diagonal gives the axis of its smallest entry (ties: the lowest axis),
+// as a diagonalisation with no rotation does; when S - lambda I has rank one
+// or less (a double smallest eigenvalue) any unit vector orthogonal to its
+// largest row is an eigenvector, and one is taken.
+__device__ inline void plane_regularised(double s00, double s01, double s02, double s11,
+                                         double s12, double s22, double out[6]) {
+  double n0 = 1.0, n1 = 0.0, n2 = 0.0;
+  const double p1 = (s01 * s01 + s02 * s02) + s12 * s12;
+  if (p1 == 0.0) {
+    int a = 0;
+    double m = s00;
+    if (s11 < m) { a = 1; m = s11; }
+    if (s22 < m) a = 2;
+    n0 = a == 0 ? 1.0 : 0.0;
+    n1 = a == 1 ? 1.0 : 0.0;
+    n2 = a == 2 ? 1.0 : 0.0;
+  } else {
+    const double q = (s00 + s11 + s22) / 3.0;
+    const double b00 = s00 - q, b11 = s11 - q, b22 = s22 - q;
+    const double p2 = (b00 * b00 + b11 * b11 + b22 * b22) + 2.0 * p1;
+    const double p = sqrt(p2 / 6.0), ip = 1.0 / p;
+    const double c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip;
+    const double c01 = s01 * ip, c02 = s02 * ip, c12 = s12 * ip;
+    double r = 0.5 * ((c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02)) +
+                      c02 * (c01 * c12 - c11 * c02));
+    r = fmin(1.0, fmax(-1.0, r));
+    // eigenvalues q + 2 p cos(phi + 2 pi j / 3), phi = acos(r) / 3: j = 1 is
+    // the smallest
+    const double lam = q + 2.0 * p * cos(acos(r) / 3.0 + 2.0943951023931957);
+    // rows of S - lambda I and their pairwise cross products, selected with
+    // scalar compares (no dynamic indexing: the arrays stay in registers)
+    const double a0 = s00 - lam, a1 = s01, a2 = s02;
+    const double b0 = s01, b1 = s11 - lam, b2 = s12;
+    const double d0 = s02, d1 = s12, d2 = s22 - lam;
+    const double x0 = a1 * b2 - a2 * b1, x1 = a2 * b0 - a0 * b2, x2 = a0 * b1 - a1 * b0;
+    const double y0 = a1 * d2 - a2 * d1, y1 = a2 * d0 - a0 * d2, y2 = a0 * d1 - a1 * d0;
+    const double z0 = b1 * d2 - b2 * d1, z1 = b2 * d0 - b0 * d2, z2 = b0 * d1 - b1 * d0;
+    const double dx = (x0 * x0 + x1 * x1) + x2 * x2;
+    const double dy = (y0 * y0 + y1 * y1) + y2 * y2;
+    const double dz = (z0 * z0 + z1 * z1) + z2 * z2;
+    double c0 = x0, c1 = x1, c2 = x2, dm = dx;
+    if (dy > dm) { c0 = y0; c1 = y1; c2 = y2; dm = dy; }
+    if (dz > dm) { c0 = z0; c1 = z1; c2 = z2; dm = dz; }
+    const double f2 = (s00 * s00 + s11 * s11 + s22 * s22) + 2.0 * p1;   // |S|_F^2
+    if (dm > 1e-30 * f2 * f2) {
+      const double il = 1.0 / sqrt(dm);
+      n0 = c0 * il;
+      n1 = c1 * il;
+      n2 = c2 * il;
+    } else {
+      // rank <= 1: a unit vector orthogonal to the largest row w, as w x e_a
+      // with a the axis where |w| is smallest
+      const double na = (a0 * a0 + a1 * a1) + a2 * a2;
+      const double nb = (b0 * b0 + b1 * b1) + b2 * b2;
+      const double nd = (d0 * d0 + d1 * d1) + d2 * d2;
+      double w0 = a0, w1 = a1, w2 = a2, nw = na;
+      if (nb > nw) { w0 = b0; w1 = b1; w2 = b2; nw = nb; }
+      if (nd > nw) { w0 = d0; w1 = d1; w2 = d2; nw = nd; }
+      if (nw > 0.0) {
+        double t0, t1, t2;
+        if (fabs(w0) <= fabs(w1) && fabs(w0) <= fabs(w2)) {        // w x e_x
+          t0 = 0.0; t1 = w2; t2 = -w1;
+        } else if (fabs(w1) <= fabs(w2)) {                          // w x e_y
+          t0 = -w2; t1 = 0.0; t2 = w0;
+        } else {                                                    // w x e_z
+          t0 = w1; t1 = -w0; t2 = 0.0;
+        }
+        const double il = 1.0 / sqrt((t0 * t0 + t1 * t1) + t2 * t2);
+        n0 = t0 * il;
+        n1 = t1 * il;
+        n2 = t2 * il;
+      }
+    }
+  }
+  const double e = 1e-3 - 1.0;
+  out[0] = 1.0 + e * n0 * n0;
+  out[1] = e * n0 * n1;
+  out[2] = e * n0 * n2;
+  out[3] = 1.0 + e * n1 * n1;
+  out[4] = e * n1 * n2;
+  out[5] = 1.0 + e * n2 * n2;
+}
+
+// Regularised covariance of the first k entries of a neighbour list:
+// two-pass FP64 sample covariance with 1/k, then with reg = FAR_REG_EQ1
+// Eq. (1): C = S + 1e-3 I and Sigma = (C^-1 / ||C^-1||_F)^-1 = ||C^-1||_F C,
+// where ||C^-1||_F is the Frobenius norm of the cofactor matrix over
+// |det C|; with reg = FAR_REG_PLANE the plane regularisation above.
 template <int K, class Get>
-__device__ inline void regularised_cov(const TopK<K>& top, int k, Get get, double out[6]) {
+__device__ inline void regularised_cov(const TopK<K>& top, int k, Get get, double out[6],
+                                       int reg) {
   double mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
   for (int s = 0; s < K; ++s)
@@ -334,6 +424,11 @@ __device__ inline void regularised_cov(const TopK<K>& top, int k, Get get, doubl
       syz += dy * dz;
       szz += dz * dz;
     }
+  if (reg == FAR_REG_PLANE) {
+    plane_regularised(sxx * inv_k, sxy * inv_k, sxz * inv_k, syy * inv_k, syz * inv_k,
+                      szz * inv_k, out);
+    return;
+  }
   double c00 = sxx * inv_k + 1e-3, c01 = sxy * inv_k, c02 = sxz * inv_k;
   double c11 = syy * inv_k + 1e-3, c12 = syz * inv_k, c22 = szz * inv_k + 1e-3;
   double a00 = c11 * c22 - c12 * c12;

@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kT) void k_bulk_counts(int64_t n_seg, const uint32_
 // Covariances of map points [id0, id1): k nearest within v on the map.
 template <int K>
 __global__ __launch_bounds__(kT) void k_map_cov(MapView m, float4* cov, int64_t id0,
-                                                int64_t id1, int32_t k) {
+                                                int64_t id1, int32_t k, int32_t reg) {
   int64_t id = id0 + int64_t(blockIdx.x) * kT + threadIdx.x;
   if (id >= id1) return;
   double qx = m.pt_xyz[id], qy = m.pt_xyz[m.point_cap + id], qz = m.pt_xyz[2 * m.point_cap + id];
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(kT) void k_map_cov(MapView m, float4* cov, int64_t 
   map_knn_query<K>(m, qx, qy, qz, m.v * m.v, top);
   double c6[6] = {0, 0, 0, 0, 0, 0};
   bool ok = top.found() >= k;
-  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return m.vox_pts[pos]; }, c6);
+  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return m.vox_pts[pos]; }, c6, reg);
   cov[2 * id] = make_float4(float(c6[0]), float(c6[1]), float(c6[2]), float(c6[3]));
   cov[2 * id + 1] = make_float4(float(c6[4]), float(c6[5]), ok ? 1.0f : 0.0f, 0.0f);
 }
@@ -638,8 +638,8 @@ __device__ inline float face_lb(double g) { return __double2float_rd(g * g) * (1
 // most lanes would idle while the wave walks the neighbourhood.
 template <int K>
 __global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg, int32_t dense,
-                                                      int64_t n, int32_t k, float* cov6,
-                                                      uint8_t* valid) {
+                                                      int64_t n, int32_t k, int32_t reg,
+                                                      float* cov6, uint8_t* valid) {
   __shared__ int32_t nb_start[27];
   __shared__ int32_t nb_cnt[27];
   const int64_t chunk = (n_seg + 7) >> 3;
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg,
     if (act) {
       double c6[6] = {0, 0, 0, 0, 0, 0};
       const bool ok = top.found() >= k;
-      if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
+      if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6, reg);
       const int64_t i = __float_as_int(me.w);
 #pragma unroll
       for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
@@ -719,8 +719,9 @@ __global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg,
 constexpr int kCovMinWaves = 5;
 
 template <int K>
-__global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32_t dense, int64_t n, int32_t k,
-                                                 float* cov6, uint8_t* valid) {
+__global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32_t dense, int64_t n,
+                                                               int32_t k, int32_t reg,
+                                                               float* cov6, uint8_t* valid) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (j >= n || g.keys[j] == kEmptyKey) return;
   const uint32_t sc = g.sid ? g.sid[j] : 0u;
@@ -745,7 +746,7 @@ __global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32
                  top);
   double c6[6] = {0, 0, 0, 0, 0, 0};
   const bool ok = top.found() >= k;
-  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6);
+  if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6, reg);
   const int64_t i = __float_as_int(me.w);
 #pragma unroll
   for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
@@ -896,12 +897,16 @@ inline int ceil_log2(int64_t x) {
 
 }  // namespace
 
+// Covariance regularisation of every covariance computed from now on
+// (far_set_covariance_regularisation): FAR_REG_EQ1 or FAR_REG_PLANE.
+int32_t g_cov_reg = FAR_REG_EQ1;
+
 far_status_t map_covariances(const MapView& m, float4* cov_out, int64_t id0, int64_t id1,
                              int32_t k, hipStream_t st) {
   if (id1 <= id0) return FAR_OK;
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
-    k_map_cov<K><<<blocks_for(id1 - id0), kT, 0, st>>>(m, cov_out, id0, id1, k);
+    k_map_cov<K><<<blocks_for(id1 - id0), kT, 0, st>>>(m, cov_out, id0, id1, k, g_cov_reg);
     FAR_HIP(hipGetLastError());
     return FAR_OK;
   });
@@ -1255,11 +1260,12 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
   if (n_seg == 0) return FAR_OK;
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
-    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, dense, n, k, cov6, valid);
+    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, dense, n, k, g_cov_reg, cov6, valid);
     FAR_HIP(hipGetLastError());
     if (dense > 0) {
       const int64_t grid = ((n_seg + 7) / 8) * 8;
-      k_grid_cov_wave<K><<<unsigned(grid), 64, 0, st>>>(g, n_seg, dense, n, k, cov6, valid);
+      k_grid_cov_wave<K><<<unsigned(grid), 64, 0, st>>>(g, n_seg, dense, n, k, g_cov_reg,
+                                                        cov6, valid);
       FAR_HIP(hipGetLastError());
     }
     return FAR_OK;
@@ -1355,6 +1361,24 @@ far_status_t far_set_covariance_schedule(int32_t dense_threshold) {
     return FAR_E_INVALID;
   }
   g_dense_threshold = dense_threshold;
+  return FAR_OK;
+}
+
+far_status_t far_set_covariance_regularisation(int32_t mode) {
+  if (mode != FAR_REG_EQ1 && mode != FAR_REG_PLANE) {
+    set_error("far_set_covariance_regularisation: unknown mode %d", mode);
+    return FAR_E_INVALID;
+  }
+  g_cov_reg = mode;
+  return FAR_OK;
+}
+
+far_status_t far_get_covariance_regularisation(int32_t* mode) {
+  if (!mode) {
+    set_error("far_get_covariance_regularisation: null argument");
+    return FAR_E_INVALID;
+  }
+  *mode = g_cov_reg;
   return FAR_OK;
 }
 

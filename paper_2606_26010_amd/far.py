@@ -92,6 +92,8 @@ _SIGS = {
     "far_scan_covariances": (C.c_int, [_P, C.c_int64, C.c_double, C.c_int32, _P, _P, _P]),
     "far_scan_covariances_batch": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double,
                                              C.c_int32, _P, _P, _P]),
+    "far_set_covariance_regularisation": (C.c_int, [C.c_int32]),
+    "far_get_covariance_regularisation": (C.c_int, [C.POINTER(C.c_int32)]),
     "far_timing_enable": (C.c_int, [C.c_int32]),
     "far_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "far_timing_read_kind": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
@@ -266,6 +268,21 @@ def far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=None, stream=Non
                                             _dev(val, torch.uint8, "valid"), _stream(stream)),
            "far_scan_covariances_batch")
     return cov, val
+
+
+FAR_REG_EQ1, FAR_REG_PLANE = 0, 1
+
+
+def far_set_covariance_regularisation(mode: int):
+    _check(lib().far_set_covariance_regularisation(int(mode)),
+           "far_set_covariance_regularisation")
+
+
+def far_get_covariance_regularisation() -> int:
+    v = C.c_int32(0)
+    _check(lib().far_get_covariance_regularisation(C.byref(v)),
+           "far_get_covariance_regularisation")
+    return v.value
 
 
 def far_timing_enable(on: bool):

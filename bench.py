@@ -516,7 +516,7 @@ def main():
                       "load_factor": mstats["load_factor"]},
     }
     result["roofline"]["kernel"] = (f"k_linearize<{'double' if prec == far.FAR_PREC_FP64 else 'float'}"
-                                    f", false, {tile}>")
+                                    f", false, {tile}, false, false>")
     print(json.dumps(result), flush=True)
     gm.close()
 

@@ -480,7 +480,9 @@ __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool p
 // waits on chains of dependent gathers, so occupancy is what hides them.
 constexpr int kMinWaves = 7;
 
-template <class Real, bool kGrad, int kB, bool kFine>
+// kNoSA (the sparsity-aware case off) is a template parameter: a run-time
+// test in the match block costs the default path 8 %.
+template <class Real, bool kGrad, int kB, bool kFine, bool kNoSA>
 __global__ __launch_bounds__(kB, (std::is_same<Real, float>::value && !kFine) ? kMinWaves : 1)
 void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
@@ -555,7 +557,7 @@ void k_linearize(
       const float4 cb = m.cov[2 * int64_t(id) + 1];
       // without the sparsity-aware case a pair lacking either covariance is
       // dropped like an outlier
-      if (!prm.sa_off || (sB.x >= 0.0f && cb.z != 0.0f)) {
+      if (!kNoSA || (sB.x >= 0.0f && cb.z != 0.0f)) {
         match = id;
         if constexpr (kGrad)
           grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, R, prm.kappa2, acc, gs);
@@ -931,20 +933,26 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
                         const AlignWS* w, int64_t max_tiles, const Job& j) {
   // the fine-cell search only where the index exists for the current map
   const bool fine = j.prm.fine_nn && mv.fine_ok;
-  switch (tile * 2 + (fine ? 1 : 0)) {
-#define FAR_LIN_CASE(B, F)                                                                \
-  case B * 2 + F:                                                                         \
-    k_linearize<Real, kGrad, B, F><<<unsigned(grid), B, 0, st>>>(                        \
+  switch (tile * 4 + (fine ? 2 : 0) + (j.prm.sa_off ? 1 : 0)) {
+#define FAR_LIN_CASE(B, F, N)                                                             \
+  case B * 4 + F * 2 + N:                                                                 \
+    k_linearize<Real, kGrad, B, F, N><<<unsigned(grid), B, 0, st>>>(                     \
         mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
         w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
         j.n_total, kGrad ? nullptr : w->prev);                                            \
     break;
-    FAR_LIN_CASE(128, 0)
-    FAR_LIN_CASE(128, 1)
-    FAR_LIN_CASE(256, 0)
-    FAR_LIN_CASE(256, 1)
-    FAR_LIN_CASE(512, 0)
-    FAR_LIN_CASE(512, 1)
+    FAR_LIN_CASE(128, 0, 0)
+    FAR_LIN_CASE(128, 0, 1)
+    FAR_LIN_CASE(128, 1, 0)
+    FAR_LIN_CASE(128, 1, 1)
+    FAR_LIN_CASE(256, 0, 0)
+    FAR_LIN_CASE(256, 0, 1)
+    FAR_LIN_CASE(256, 1, 0)
+    FAR_LIN_CASE(256, 1, 1)
+    FAR_LIN_CASE(512, 0, 0)
+    FAR_LIN_CASE(512, 0, 1)
+    FAR_LIN_CASE(512, 1, 0)
+    FAR_LIN_CASE(512, 1, 1)
 #undef FAR_LIN_CASE
     default:
       set_error("internal: unsupported tile size %d", tile);

@@ -505,7 +505,10 @@ def main():
         "cpu_baseline": cpu,
         "single_scan_path": single,
         "pose_err_vs_gt": {"max_m": max(e[0] for e in gt_err),
-                           "max_deg": max(e[1] for e in gt_err)},
+                           "max_deg": max(e[1] for e in gt_err),
+                           "median_m": float(np.median([e[0] for e in gt_err])),
+                           "median_deg": float(np.median([e[1] for e in gt_err])),
+                           "scans_over_0.1m": int(sum(e[0] > 0.1 for e in gt_err))},
         "pose_err_vs_oracle": None if oracle_err is None else
         {"max_m": max(e[0] for e in oracle_err), "max_deg": max(e[1] for e in oracle_err),
          "scans": len(oracle_err)},

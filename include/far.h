@@ -514,6 +514,17 @@ far_status_t far_timing_enable(int32_t on);
 far_status_t far_timing_read_kind(int32_t kind, double* ms, int64_t* count, int32_t reset);
 far_status_t far_timing_read(double* linearize_ms, int64_t* launches, int32_t reset);
 
+/* Scratch memory.  The temporary device buffers of every call (sort
+ * buffers, grids, partial sums) come from one stream-ordered pool per device
+ * that keeps freed memory for the next call instead of returning it to the
+ * driver, so repeated calls map no new memory; the pool grows to the largest
+ * scratch a single call has needed.  far_scratch_release returns the unused
+ * part of every device's pool to the driver (buffers of calls still running
+ * stay); far_scratch_reserved gives the bytes the current device's pool
+ * holds (0 before its first use).  Both are safe at any time. */
+far_status_t far_scratch_release(void);
+far_status_t far_scratch_reserved(int64_t* bytes /* [host] */);
+
 const char* far_status_str(far_status_t s);
 const char* far_last_error(void);
 

@@ -201,6 +201,10 @@ static __constant__ int8_t kNbrOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1,  3,  5
                                             2,  6,  8, 18, 20, 24, 26};
 
 // ---------------------------------------------------------------- scratch
+// The stream-ordered pool of the current device that scratch comes from: one
+// per device, created on first use, keeping freed memory for later calls.
+far_status_t scratch_pool(hipMemPool_t* out);
+
 // Stream-ordered device scratch, freed when the guard leaves scope.
 // With an arena (a preallocated device buffer) it hands out 256-byte aligned
 // pieces of it instead, which is what code recorded into a graph needs.
@@ -232,8 +236,10 @@ struct Scratch {
       *out = reinterpret_cast<T*>(arena + at);
       return FAR_OK;
     }
+    hipMemPool_t pool;
+    FAR_TRY(scratch_pool(&pool));
     void* p = nullptr;
-    FAR_HIP(hipMallocAsync(&p, bytes, stream));
+    FAR_HIP(hipMallocFromPoolAsync(&p, bytes, pool, stream));
     ptrs.push_back(p);
     *out = static_cast<T*>(p);
     return FAR_OK;

@@ -567,6 +567,149 @@ __global__ __launch_bounds__(kT) void k_apply_perm(const uint32_t* perm, int64_t
   sid_out[m] = uint32_t(sid_key[m]);
 }
 
+// ---------------------------------------------------------------- compact grid keys
+// A batch's scan grid sorts its points by (scan, voxel key).  Keys limited to
+// the batch's own range per axis need few bits (a sensor-frame scan of 120 m
+// range at v = 1: 8 per axis), so one radix sort of (scan, kx - min, ky - min,
+// kz - min) replaces a 63-bit sort followed by a sort by scan: the same
+// order (both are lexicographic, stable on input order), in about half the
+// passes.  The range comes from a two-level reduction (no same-address
+// atomics); points without a finite, in-range key sort last in their scan.
+constexpr int kRangePts = 16;                // points per lane of the range pass
+
+__global__ __launch_bounds__(kT) void k_key_range(const float* xyz, int64_t n, double v,
+                                                  int32_t* part, uint32_t* part_oor) {
+  __shared__ int32_t s_r[kT / 64][6];
+  __shared__ uint32_t s_o[kT / 64];
+  int32_t r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  uint32_t oor = 0;
+  const int64_t base = int64_t(blockIdx.x) * (kT * kRangePts);
+  for (int j = 0; j < kRangePts; ++j) {
+    const int64_t i = base + j * kT + threadIdx.x;
+    if (i >= n) break;
+    const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
+    int64_t kx, ky, kz;
+    if (voxel_index(double(x), v, &kx) && voxel_index(double(y), v, &ky) &&
+        voxel_index(double(z), v, &kz)) {
+      r[0] = min(r[0], int32_t(kx)); r[3] = max(r[3], int32_t(kx));
+      r[1] = min(r[1], int32_t(ky)); r[4] = max(r[4], int32_t(ky));
+      r[2] = min(r[2], int32_t(kz)); r[5] = max(r[5], int32_t(kz));
+    } else {
+      ++oor;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    for (int a = 0; a < 3; ++a) {
+      r[a] = min(r[a], __shfl_xor(r[a], d));
+      r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], d));
+    }
+    oor += uint32_t(__shfl_xor(int(oor), d));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 6; ++a) s_r[w][a] = r[a];
+    s_o[w] = oor;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    int32_t x = s_r[0][threadIdx.x];
+    for (int q = 1; q < kT / 64; ++q)
+      x = threadIdx.x < 3 ? min(x, s_r[q][threadIdx.x]) : max(x, s_r[q][threadIdx.x]);
+    part[int64_t(blockIdx.x) * 6 + threadIdx.x] = x;
+  }
+  if (threadIdx.x == 6) {
+    uint32_t o = 0;
+    for (int q = 0; q < kT / 64; ++q) o += s_o[q];
+    part_oor[blockIdx.x] = o;
+  }
+}
+
+// One block: the partial ranges in order into out[0..5], their sum of
+// out-of-range counts into out[6].
+__global__ __launch_bounds__(kT) void k_key_range_final(const int32_t* part,
+                                                        const uint32_t* part_oor, int64_t nb,
+                                                        int32_t* out) {
+  __shared__ int32_t s_r[kT][6];
+  __shared__ uint32_t s_o[kT];
+  int32_t r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  uint32_t oor = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += kT) {
+    for (int a = 0; a < 3; ++a) {
+      r[a] = min(r[a], part[b * 6 + a]);
+      r[3 + a] = max(r[3 + a], part[b * 6 + 3 + a]);
+    }
+    oor += part_oor[b];
+  }
+  for (int a = 0; a < 6; ++a) s_r[threadIdx.x][a] = r[a];
+  s_o[threadIdx.x] = oor;
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    if (threadIdx.x == 6) {
+      uint32_t o = 0;
+      for (int q = 0; q < kT; ++q) o += s_o[q];
+      out[6] = int32_t(o);
+    } else {
+      int32_t x = s_r[0][threadIdx.x];
+      for (int q = 1; q < kT; ++q)
+        x = threadIdx.x < 3 ? min(x, s_r[q][threadIdx.x]) : max(x, s_r[q][threadIdx.x]);
+      out[threadIdx.x] = x;
+    }
+  }
+}
+
+struct CompactKey {
+  int32_t mx, my, mz;   // per-axis minimum
+  int32_t by, bz;       // bits of y and z
+  int32_t kb;           // key bits (x, y, z); 1 << kb marks an empty key
+};
+
+__global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n, double v,
+                                                     const int64_t* offsets, int32_t S,
+                                                     CompactKey ck, uint64_t* keys,
+                                                     uint32_t* vals) {
+  const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  int32_t s = 0;
+  if (offsets) {
+    int32_t lo = 0, hi = S;            // offsets[s] <= i < offsets[s+1]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (offsets[mid] <= i) lo = mid; else hi = mid;
+    }
+    s = lo;
+  }
+  uint64_t key = uint64_t(1) << ck.kb;
+  const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+  int64_t kx, ky, kz;
+  if (isfinite(x) && isfinite(y) && isfinite(z) && voxel_index(double(x), v, &kx) &&
+      voxel_index(double(y), v, &ky) && voxel_index(double(z), v, &kz))
+    key = (uint64_t(kx - ck.mx) << (ck.by + ck.bz)) | (uint64_t(ky - ck.my) << ck.bz) |
+          uint64_t(kz - ck.mz);
+  keys[i] = (uint64_t(s) << (ck.kb + 1)) | key;
+  vals[i] = uint32_t(i);
+}
+
+// Sorted compact keys back to full keys (kEmptyKey for the empty ones) and
+// scan ids.
+__global__ __launch_bounds__(kT) void k_keys_expand(const uint64_t* ckeys, int64_t n,
+                                                    CompactKey ck, uint64_t* keys,
+                                                    uint32_t* sid) {
+  const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t c = ckeys[i];
+  const uint64_t k = c & ((uint64_t(2) << ck.kb) - 1);
+  if (sid) sid[i] = uint32_t(c >> (ck.kb + 1));
+  if (k >> ck.kb) {
+    keys[i] = kEmptyKey;
+  } else {
+    const int64_t kx = int64_t(k >> (ck.by + ck.bz)) + ck.mx;
+    const int64_t ky = int64_t((k >> ck.bz) & ((uint64_t(1) << ck.by) - 1)) + ck.my;
+    const int64_t kz = int64_t(k & ((uint64_t(1) << ck.bz) - 1)) + ck.mz;
+    keys[i] = pack_key(kx, ky, kz);
+  }
+}
+
 __global__ __launch_bounds__(kT) void k_grid_heads(const uint64_t* keys, const uint32_t* sid,
                                                    int64_t n, uint32_t* head) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
@@ -1175,15 +1318,86 @@ far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, doub
 // scan, then by cell key): sorted points, runs and a hash of the runs.
 // *oor receives the number of points whose cell key is out of range (the
 // grid is then not built).
+// The runs of a scan grid sorted by (scan, key) through compact keys (see
+// k_key_range).  *used = false when the batch has no finite point or its key
+// range needs more than 62 bits with the scan id; *oor receives the points
+// whose keys leave [-2^20, 2^20) (nothing else is done then).
+static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets, int32_t S_,
+                                       int64_t n, double cell, hipStream_t st, Scratch& scr,
+                                       Runs& r, uint32_t** sid_out, bool* used, uint32_t* oor) {
+  *used = false;
+  *oor = 0;
+  const int64_t nb = (n + int64_t(kT) * kRangePts - 1) / (int64_t(kT) * kRangePts);
+  int32_t *part, *rng;
+  uint32_t* part_oor;
+  FAR_TRY(scr.get(&part, size_t(nb) * 6));
+  FAR_TRY(scr.get(&part_oor, size_t(nb)));
+  FAR_TRY(scr.get(&rng, 7));
+  k_key_range<<<unsigned(nb), kT, 0, st>>>(xyz, n, cell, part, part_oor);
+  FAR_HIP(hipGetLastError());
+  k_key_range_final<<<1, kT, 0, st>>>(part, part_oor, nb, rng);
+  FAR_HIP(hipGetLastError());
+  int32_t h[7];
+  FAR_HIP(hipMemcpyAsync(h, rng, sizeof(h), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  *oor = uint32_t(h[6]);
+  if (h[6] > 0 || h[0] > h[3]) return FAR_OK;
+  CompactKey ck;
+  ck.mx = h[0];
+  ck.my = h[1];
+  ck.mz = h[2];
+  const int bx = ceil_log2(int64_t(h[3]) - h[0] + 1);
+  ck.by = ceil_log2(int64_t(h[4]) - h[1] + 1);
+  ck.bz = ceil_log2(int64_t(h[5]) - h[2] + 1);
+  ck.kb = bx + ck.by + ck.bz;
+  const int bits = (S_ > 1 ? ceil_log2(S_) : 0) + ck.kb + 1;
+  if (bits > 62) return FAR_OK;
+  uint64_t *ckeys, *ckeys_alt;
+  uint32_t* vals_alt;
+  FAR_TRY(scr.get(&ckeys, size_t(n)));
+  FAR_TRY(scr.get(&ckeys_alt, size_t(n)));
+  FAR_TRY(scr.get(&r.keys, size_t(n)));
+  FAR_TRY(scr.get(&r.vals, size_t(n)));
+  FAR_TRY(scr.get(&vals_alt, size_t(n)));
+  FAR_TRY(scr.get(&r.head, size_t(n)));
+  FAR_TRY(scr.get(&r.head_scan, size_t(n)));
+  FAR_TRY(scr.get(&r.seg_start, size_t(n)));
+  FAR_TRY(scr.get(&r.seg_end, size_t(n)));
+  FAR_TRY(scr.get(&r.counters, 4));
+  uint32_t* sid = nullptr;
+  if (S_ > 1) FAR_TRY(scr.get(&sid, size_t(n)));
+  FAR_HIP(hipMemsetAsync(r.counters, 0, 4 * sizeof(uint32_t), st));
+  k_keys_compact<<<blocks_for(n), kT, 0, st>>>(xyz, n, cell, S_ > 1 ? offsets : nullptr, S_,
+                                                ck, ckeys, r.vals);
+  FAR_HIP(hipGetLastError());
+  bool alt = false;
+  FAR_TRY(radix_sort_pairs(ckeys, r.vals, ckeys_alt, vals_alt, n, bits, st, scr, &alt));
+  if (alt) r.vals = vals_alt;
+  k_keys_expand<<<blocks_for(n), kT, 0, st>>>(alt ? ckeys_alt : ckeys, n, ck, r.keys, sid);
+  FAR_HIP(hipGetLastError());
+  k_grid_heads<<<blocks_for(n), kT, 0, st>>>(r.keys, sid, n, r.head);
+  FAR_HIP(hipGetLastError());
+  FAR_TRY(scan_exclusive(r.head, r.head_scan, n, r.counters + 2, st, scr));
+  k_grid_bounds<<<blocks_for(n), kT, 0, st>>>(r.keys, sid, n, r.head, r.head_scan,
+                                              r.seg_start, r.seg_end);
+  FAR_HIP(hipGetLastError());
+  *sid_out = sid;
+  *used = true;
+  return FAR_OK;
+}
+
 static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t S_, int64_t n,
                                double v, double cell, hipStream_t st, Scratch& scr,
                                GridView* out, uint32_t* oor, int64_t* runs = nullptr) {
   Runs r;
-  FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
+  uint32_t* sid = nullptr;
+  bool compact = false;
+  FAR_TRY(build_runs_compact(xyz, offsets, S_, n, cell, st, scr, r, &sid, &compact, oor));
+  if (*oor > 0) return FAR_OK;
+  if (!compact) FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
   uint64_t* keys = r.keys;
   uint32_t* vals = r.vals;
-  uint32_t* sid = nullptr;
-  if (S_ > 1) {
+  if (S_ > 1 && !compact) {
     // second stable sort, by scan id, keeps the key order inside every scan
     uint64_t *sid_key, *sid_alt, *keys2;
     uint32_t *perm, *perm_alt, *vals2;
@@ -1212,8 +1426,10 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   uint32_t h_cnt[4];
   FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
   FAR_HIP(hipStreamSynchronize(st));
-  *oor = h_cnt[1];
-  if (h_cnt[1] > 0) return FAR_OK;
+  if (!compact) {
+    *oor = h_cnt[1];
+    if (h_cnt[1] > 0) return FAR_OK;
+  }
   const int64_t n_seg = h_cnt[2];
   if (runs) *runs = n_seg;
   int log2_slots = ceil_log2(2 * (n_seg > 0 ? n_seg : 1));

@@ -211,6 +211,52 @@ far_status_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt
   return FAR_OK;
 }
 
+// ---------------------------------------------------------------- scratch pool
+// A call's temporary buffers are allocated and freed on its stream.  The
+// device's default pool hands freed memory back to the driver at every
+// synchronisation (release threshold 0), so each call would map its scratch
+// afresh, which costs more than many of the kernels it serves.  The library's
+// own pool keeps what it has reserved (threshold unlimited) until
+// far_scratch_release: its footprint is the largest scratch any one call
+// has needed, far below the device memory of the workloads it serves.
+namespace {
+struct Pools {
+  std::mutex mu;
+  std::vector<hipMemPool_t> pool;   // per device id, null until first use
+};
+Pools& pools() {
+  static Pools p;
+  return p;
+}
+}  // namespace
+
+far_status_t scratch_pool(hipMemPool_t* out) {
+  *out = nullptr;
+  int dev = 0;
+  FAR_HIP(hipGetDevice(&dev));
+  Pools& P = pools();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (size_t(dev) >= P.pool.size()) P.pool.resize(size_t(dev) + 1, nullptr);
+  if (!P.pool[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t p = nullptr;
+    FAR_HIP(hipMemPoolCreate(&p, &props));
+    uint64_t keep = ~uint64_t(0);
+    const hipError_t e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) {
+      (void)hipMemPoolDestroy(p);
+      return hip_fail(e, "hipMemPoolSetAttribute(release threshold)", __FILE__, __LINE__);
+    }
+    P.pool[dev] = p;
+  }
+  *out = P.pool[dev];
+  return FAR_OK;
+}
+
 // ---------------------------------------------------------------- timing
 namespace {
 struct Timing {
@@ -239,6 +285,31 @@ void timing_push(int kind, hipEvent_t ev0, hipEvent_t ev1) {
 }  // namespace far
 
 extern "C" {
+
+far_status_t far_scratch_release(void) {
+  far::Pools& P = far::pools();
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (hipMemPool_t p : P.pool)
+    if (p) FAR_HIP(hipMemPoolTrimTo(p, 0));
+  return FAR_OK;
+}
+
+far_status_t far_scratch_reserved(int64_t* bytes) {
+  if (!bytes) {
+    far::set_error("far_scratch_reserved: invalid argument");
+    return FAR_E_INVALID;
+  }
+  *bytes = 0;
+  int dev = 0;
+  FAR_HIP(hipGetDevice(&dev));
+  far::Pools& P = far::pools();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (size_t(dev) >= P.pool.size() || !P.pool[dev]) return FAR_OK;
+  uint64_t v = 0;
+  FAR_HIP(hipMemPoolGetAttribute(P.pool[dev], hipMemPoolAttrReservedMemCurrent, &v));
+  *bytes = int64_t(v);
+  return FAR_OK;
+}
 
 far_status_t far_timing_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(far::timing().mu);

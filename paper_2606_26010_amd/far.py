@@ -95,6 +95,8 @@ _SIGS = {
     "far_set_covariance_regularisation": (C.c_int, [C.c_int32]),
     "far_get_covariance_regularisation": (C.c_int, [C.POINTER(C.c_int32)]),
     "far_timing_enable": (C.c_int, [C.c_int32]),
+    "far_scratch_release": (C.c_int, []),
+    "far_scratch_reserved": (C.c_int, [C.POINTER(C.c_int64)]),
     "far_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "far_timing_read_kind": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                        C.c_int32]),
@@ -282,6 +284,17 @@ def far_get_covariance_regularisation() -> int:
     v = C.c_int32(0)
     _check(lib().far_get_covariance_regularisation(C.byref(v)),
            "far_get_covariance_regularisation")
+    return v.value
+
+
+def far_scratch_release():
+    _check(lib().far_scratch_release(), "far_scratch_release")
+
+
+def far_scratch_reserved() -> int:
+    """Bytes the current device's scratch pool holds."""
+    v = C.c_int64(0)
+    _check(lib().far_scratch_reserved(C.byref(v)), "far_scratch_reserved")
     return v.value
 
 

@@ -154,6 +154,17 @@ __device__ inline double wave_sum(double v) {
 }
 __device__ inline double wave_sum(float v) { return wave_sum(double(v)); }
 
+// Wave sums of many FP32 values per lane through LDS (the FP32 kernels):
+// each lane stores its values as one column of a [value][lane] table whose
+// rows are padded to 65 words (no bank conflicts on the writes, at most two
+// lanes per bank on the reads); then four lanes per value each add sixteen
+// entries in lane order in FP64 and two DPP levels join the four quarters.
+// About 4 instructions per value instead of the 18 of a DPP/shuffle tree.
+// The order is fixed, so the sums are deterministic; a sum of 64 FP32 values
+// in FP64 is exact unless their binary exponents span more than 29.
+constexpr int kRedChunk = 16;   // values per pass: lanes 4v .. 4v+3 take value v
+constexpr int kRedRow = 65;     // words per table row
+
 // ---------------------------------------------------------------- locality
 // Before the iterations every point is given a locality key (scan id, then
 // the Morton code of its sensor-frame voxel) and the source is packed, in key
@@ -495,6 +506,7 @@ void k_linearize(
   constexpr int kWaves = kB / 64;
   constexpr int kNV = kGrad ? 14 : kVals;
   __shared__ double red[kWaves][kNV];
+  __shared__ float tbl[std::is_same<Real, float>::value ? kWaves : 1][kRedChunk * kRedRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t chunk = (n_tiles + 7) >> 3;
   const int64_t t = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
@@ -574,10 +586,32 @@ void k_linearize(
     }
   }
   // wave sums in FP64, then the block's waves
+  if constexpr (std::is_same<Real, float>::value) {
+    float* tb = tbl[wave];
+    const int v = lane >> 2, quarter = lane & 3;
 #pragma unroll
-  for (int q = 0; q < kNV; ++q) {
-    const double sv = wave_sum(acc[q]);
-    if (lane == 0) red[wave][q] = sv;
+    for (int c0 = 0; c0 < kNV; c0 += kRedChunk) {
+      if (c0 > 0) __syncthreads();   // the previous pass's reads are done
+#pragma unroll
+      for (int q = 0; q < kRedChunk; ++q)
+        if (c0 + q < kNV) tb[q * kRedRow + lane] = acc[c0 + q];
+      __syncthreads();
+      double sv = 0.0;
+      if (c0 + v < kNV) {
+        const float* row = tb + v * kRedRow + 16 * quarter;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sv += double(row[e]);
+      }
+      sv += dpp_partner<0xB1>(sv);
+      sv += dpp_partner<0x4E>(sv);
+      if (quarter == 0 && c0 + v < kNV) red[wave][c0 + v] = sv;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kNV; ++q) {
+      const double sv = wave_sum(acc[q]);
+      if (lane == 0) red[wave][q] = sv;
+    }
   }
   __syncthreads();
   if (tid < kNV) {

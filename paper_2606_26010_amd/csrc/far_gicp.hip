@@ -577,7 +577,14 @@ void k_linearize(
           gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, R, cx, cy, cz, prm.kappa2, acc);
       }
     }
-    if (corr && in_tile) corr[__float_as_uint(a.w)] = match;
+    if (corr && in_tile) {
+      // the original index is loaded again rather than kept across the
+      // search (it would be spilled there); the empty asm hides that the
+      // address is the one read before, so the load is not merged with it
+      uint32_t ia = i;
+      if constexpr (!kGrad) asm volatile("" : "+v"(ia));
+      corr[__float_as_uint(kGrad ? a.w : pA[ia].w)] = match;
+    }
     if (kGrad && grad_src && in_tile) {
       const uint32_t o = __float_as_uint(a.w);
       grad_src[o] = float(gs[0]);

@@ -205,14 +205,21 @@ static __constant__ int8_t kNbrOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1,  3,  5
 // per device, created on first use, keeping freed memory for later calls.
 far_status_t scratch_pool(hipMemPool_t* out);
 
-// Stream-ordered device scratch, freed when the guard leaves scope.
+// Stream-ordered device scratch, freed when the guard leaves scope.  Pieces
+// are cut from chunks of at least kScratchChunk bytes taken from the pool,
+// so a call with many temporary buffers makes a few pool requests (each
+// costs microseconds of host time) instead of one per buffer.
 // With an arena (a preallocated device buffer) it hands out 256-byte aligned
 // pieces of it instead, which is what code recorded into a graph needs.
+constexpr size_t kScratchChunk = size_t(64) << 20;
+
 struct Scratch {
   hipStream_t stream;
   std::vector<void*> ptrs;
   char* arena = nullptr;
   size_t arena_cap = 0, arena_used = 0;
+  char* chunk = nullptr;
+  size_t chunk_cap = 0, chunk_used = 0;
   explicit Scratch(hipStream_t s) : stream(s) {}
   Scratch(hipStream_t s, void* buf, size_t cap)
       : stream(s), arena(static_cast<char*>(buf)), arena_cap(cap) {}
@@ -236,11 +243,21 @@ struct Scratch {
       *out = reinterpret_cast<T*>(arena + at);
       return FAR_OK;
     }
+    const size_t at = (chunk_used + 255) & ~size_t(255);
+    if (chunk && at + bytes <= chunk_cap) {
+      chunk_used = at + bytes;
+      *out = reinterpret_cast<T*>(chunk + at);
+      return FAR_OK;
+    }
     hipMemPool_t pool;
     FAR_TRY(scratch_pool(&pool));
+    const size_t cap = bytes > kScratchChunk ? bytes : kScratchChunk;
     void* p = nullptr;
-    FAR_HIP(hipMallocFromPoolAsync(&p, bytes, pool, stream));
+    FAR_HIP(hipMallocFromPoolAsync(&p, cap, pool, stream));
     ptrs.push_back(p);
+    chunk = static_cast<char*>(p);
+    chunk_cap = cap;
+    chunk_used = bytes;
     *out = static_cast<T*>(p);
     return FAR_OK;
   }

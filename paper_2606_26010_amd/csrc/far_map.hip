@@ -856,7 +856,7 @@ __global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg,
 // within v, one point per lane over the 27 voxels (processed in sorted order
 // for locality; written at the original index).  Points of runs with at
 // least `dense` points (dense > 0) are left to k_grid_cov_wave.  Non-finite
-// points keep the zero covariance / invalid flag.
+// points get the zero covariance and the invalid flag.
 // Waves per SIMD asked of the per-point covariance search (latency-bound
 // gathers, as in the linearisation).
 constexpr int kCovMinWaves = 5;
@@ -866,9 +866,16 @@ __global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32
                                                                int32_t k, int32_t reg,
                                                                float* cov6, uint8_t* valid) {
   int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n || g.keys[j] == kEmptyKey) return;
-  const uint32_t sc = g.sid ? g.sid[j] : 0u;
+  if (j >= n) return;
   const float4 me = g.sorted[j];
+  if (g.keys[j] == kEmptyKey) {   // a non-finite point: zero covariance, invalid
+    const int64_t i = __float_as_int(me.w);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) cov6[t * n + i] = 0.0f;
+    valid[i] = 0;
+    return;
+  }
+  const uint32_t sc = g.sid ? g.sid[j] : 0u;
   const double qx = me.x, qy = me.y, qz = me.z;
   if (dense > 0) {
     const uint64_t own = g.keys[j];
@@ -1471,9 +1478,11 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
     return FAR_E_INVALID;
   }
   const int32_t dense = g_dense_threshold;
-  FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
-  FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
-  if (n_seg == 0) return FAR_OK;
+  if (n_seg == 0) {   // no finite point: every covariance zero, invalid
+    FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
+    FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
+    return FAR_OK;
+  }
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
     k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, dense, n, k, g_cov_reg, cov6, valid);

@@ -5,8 +5,9 @@ compact keys when the batch's key range packs into 62 bits, and otherwise by
 full keys and then by scan.  Both must give the oracle's covariances; the
 cases sit on either side of the limit (a batch spanning the whole key range,
 a scan at 2^20 voxels per axis, hundreds of scans); out-of-range keys are
-found by the range pass that picks the path, and rejected.  The scratch pool
-keeps its memory over repeated calls and gives it back on release."""
+found by the range pass that picks the path, and rejected.  Non-finite
+points get the zero result with the outputs starting as junk.  The scratch
+pool keeps its memory over repeated calls and gives it back on release."""
 import numpy as np
 import pytest
 import torch
@@ -125,3 +126,42 @@ def test_scratch_pool_keeps_and_releases(far):
     cov, val = far.far_scan_covariances(pts, 1.0, 5)     # and usable again
     torch.cuda.synchronize()
     assert far.far_scratch_reserved() > after and int(host(val).sum()) > 0
+
+
+@pytest.mark.parametrize("dense", [0, 16])
+def test_non_finite_points_get_the_zero_result(far, orc, dense):
+    """Every output is written, also where the input is not finite: the
+    outputs start as junk; a batch with scattered NaN / inf points and a scan
+    with no finite point at all (the whole result zero)."""
+    g = np.random.default_rng(29)
+    scans = [scene(30, 3000), scene(31, 500), scene(32, 800)]
+    for sc in scans[:2]:
+        m = g.uniform(size=sc.shape[1]) < 0.03
+        sc[0, m] = np.nan
+        sc[2, m[::-1]] = np.inf
+    scans[2][:] = np.nan
+    sizes = [s.shape[1] for s in scans]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(offs[-1])
+    cov = torch.full((6, n), 7.0, dtype=torch.float32, device="cuda")
+    val = torch.full((n,), 3, dtype=torch.uint8, device="cuda")
+    old = far.far_get_covariance_schedule()
+    far.far_set_covariance_schedule(dense)
+    try:
+        far.far_scan_covariances_batch(dev(np.concatenate(scans, 1)), dev(offs), 1.0, 5,
+                                       out=(cov, val))
+        c, v = host(cov), host(val)
+        for s, sc in enumerate(scans):
+            oc, ov = orc.scan_covariances(np.ascontiguousarray(sc), 1.0, 5)
+            np.testing.assert_array_equal(v[offs[s]:offs[s + 1]], ov)
+            np.testing.assert_allclose(c[:, offs[s]:offs[s + 1]], oc, rtol=2e-6, atol=1e-6)
+        bad = ~np.isfinite(np.concatenate(scans, 1)).all(axis=0)
+        assert bad.sum() > 900 and np.all(c[:, bad] == 0) and np.all(v[bad] == 0)
+        # one scan, nothing finite
+        cov1 = torch.full((6, 800), 7.0, dtype=torch.float32, device="cuda")
+        val1 = torch.full((800,), 3, dtype=torch.uint8, device="cuda")
+        far.far_scan_covariances_batch(dev(scans[2]), dev(np.array([0, 800], np.int64)), 1.0,
+                                       5, out=(cov1, val1))
+        assert np.all(host(cov1) == 0) and np.all(host(val1) == 0)
+    finally:
+        far.far_set_covariance_schedule(old)

@@ -447,10 +447,10 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
   if (own >= 0) scan_voxel_points<1>(m.vox_pts, own * m.nmax, cnt, q, r2, top);
   uint32_t need = 0;
   {
-    const double bnd = fmin(r2, top.bound());
+    const float bnd = f32_up(fmin(r2, top.bound()));
 #pragma unroll
     for (int rank = 1; rank < 27; ++rank)
-      if (double(fo.lb2(nbr_code(rank))) <= bnd) need |= 1u << rank;
+      if (fo.lb2(nbr_code(rank)) <= bnd) need |= 1u << rank;
   }
   // neighbours of an existing voxel come from its row of the neighbour table
   // (absent ones cost nothing); a point outside the map's voxels probes

@@ -247,6 +247,15 @@ __device__ inline void knn_cells(double px, double py, double pz, double c, doub
       }
 }
 
+// Smallest float not below d (d finite and non-negative): a float compared
+// with it keeps every case the comparison with d keeps and adds at most the
+// ties with the rounded value, which only adds visits to an exact search.
+__device__ inline float f32_up(double d) {
+  float f = float(d);
+  if (double(f) < d) f = __uint_as_float(__float_as_uint(f) + 1u);
+  return f;
+}
+
 // Squared face distance as a float that never exceeds the FP64 value:
 // rounded down and shrunk by 2^-20 (which also covers the rounding of the
 // float sums of up to three such terms).  Used only to skip cells.
@@ -287,10 +296,16 @@ __device__ inline void knn_cells27(double px, double py, double pz, double c, do
   };
   uint32_t need = 0;
   {
-    const double bnd = fmin(r2, top.bound());
+    const float bnd = f32_up(fmin(r2, top.bound()));
 #pragma unroll
-    for (int rank = 1; rank < 27; ++rank)
-      if (lb(nbr_code(rank)) <= bnd) need |= 1u << rank;
+    for (int rank = 1; rank < 27; ++rank) {
+      const int code = nbr_code(rank);
+      const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
+      const float s = (ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0f)) +
+                      (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0f)) +
+                      (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0f));
+      if (s <= bnd) need |= 1u << rank;
+    }
   }
   while (need) {
     const int rank = __builtin_ctz(need);

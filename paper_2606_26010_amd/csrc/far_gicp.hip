@@ -408,12 +408,15 @@ __device__ inline void grad_term(double px, double py, double pz, float4 s, floa
 struct FaceOffsets {
   float f[3];     // p - voxel corner, per axis, in [0, v)
   float v, slack;
+  // both gaps are formed and one is selected (the same value as forming
+  // only the selected one), so a run-time code costs selects, not branches
   __device__ inline float lb2(int code) const {
     float s = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int o = a == 0 ? code / 9 - 1 : (a == 1 ? (code / 3) % 3 - 1 : code % 3 - 1);
-      const float g = o < 0 ? fmaxf(f[a] - slack, 0.0f) : (o > 0 ? fmaxf(v - f[a] - slack, 0.0f) : 0.0f);
+      const float tl = f[a] - slack, th = v - f[a] - slack;
+      const float g = fmaxf(o < 0 ? tl : (o > 0 ? th : 0.0f), 0.0f);
       s += g * g;
     }
     return s * (1.0f - 0x1p-20f);

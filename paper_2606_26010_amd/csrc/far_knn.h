@@ -288,11 +288,16 @@ __device__ inline void knn_cells27(double px, double py, double pz, double c, do
   int32_t cnt;
   int32_t st = find(kx, ky, kz, &cnt);
   if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+  // two plain selects per axis (a nested conditional compiles to divergent
+  // branches for a run-time code); the value is the same
+  auto gap = [](int o, float lo, float hi) {
+    const float t = o < 0 ? lo : 0.0f;
+    return o > 0 ? hi : t;
+  };
   auto lb = [&](int code) {
     const int ox = code / 9 - 1, oy = (code / 3) % 3 - 1, oz = code % 3 - 1;
-    return double((ox < 0 ? gl2[0] : (ox > 0 ? gh2[0] : 0.0f)) +
-                  (oy < 0 ? gl2[1] : (oy > 0 ? gh2[1] : 0.0f)) +
-                  (oz < 0 ? gl2[2] : (oz > 0 ? gh2[2] : 0.0f)));
+    return double((gap(ox, gl2[0], gh2[0]) + gap(oy, gl2[1], gh2[1])) +
+                  gap(oz, gl2[2], gh2[2]));
   };
   uint32_t need = 0;
   {

@@ -284,13 +284,6 @@ far_status_t far_autotune(far_map_t map, const float* src, const int64_t* offset
                           const double* T, const far_align_params_t* params, int32_t reps,
                           far_schedule_t* best, double* ms, far_stream_t stream);
 
-/* Schedule of the scan covariance search (process-wide).  The points of a
- * voxel holding at least dense_threshold of its scan's points are searched
- * by one wave per voxel (the voxel's points share one 27-voxel
- * neighbourhood, walked once at wave-uniform addresses), the others one
- * lane per point over the 27 voxels; 0 = one lane per point everywhere.
- * Default 0 (measured fastest on the batched workload).  Results are
- * identical for every setting. */
 /* Covariance regularisation of every covariance computed afterwards (map
  * inserts and scan covariances; process-wide, default FAR_REG_EQ1).
  * FAR_REG_EQ1: Eq. (1) of Sec. III-A.2.  FAR_REG_PLANE: the plane
@@ -304,6 +297,13 @@ typedef enum { FAR_REG_EQ1 = 0, FAR_REG_PLANE = 1 } far_cov_reg_t;
 far_status_t far_set_covariance_regularisation(int32_t mode);
 far_status_t far_get_covariance_regularisation(int32_t* mode);
 
+/* Schedule of the scan covariance search (process-wide).  The points of a
+ * voxel holding at least dense_threshold of its scan's points are searched
+ * by one wave per voxel (the voxel's points share one 27-voxel
+ * neighbourhood, walked once at wave-uniform addresses), the others one
+ * lane per point over the 27 voxels; 0 = one lane per point everywhere.
+ * Default 0 (measured fastest on the batched workload).  Results are
+ * identical for every setting. */
 far_status_t far_set_covariance_schedule(int32_t dense_threshold);
 far_status_t far_get_covariance_schedule(int32_t* dense_threshold);
 

@@ -309,10 +309,10 @@ void orc_map_free(orc_map* m) { delete m; }
 int64_t orc_map_size(const orc_map* m) { return int64_t(m->g.pts.size()); }
 int64_t orc_map_nvoxels(const orc_map* m) { return int64_t(m->g.vox.size()); }
 
-// Capped insert (Sec. III-A.3: points enter their voxel "as long as the number
-// of points inside it is below" the cap; Sec. III-A.2: "regularly spaced"
-// points with a minimum spacing).  Semantics, taken as sequential in input
-// order:
+// Capped insert (Sec. III-A.3: a point enters its voxel only while the voxel
+// holds fewer points than its cap; Sec. III-A.2: the points of a voxel keep
+// a minimum spacing from each other).  Semantics, taken as sequential in
+// input order:
 //   for each finite point i in order, with K = key(p_i):
 //     accept iff count(K) < cap_i and, when dmin > 0, every point already in
 //     K (including points accepted earlier in this batch) is at squared

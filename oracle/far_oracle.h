@@ -51,10 +51,11 @@ int orc_scan_covariances(const float* xyz, int64_t n, double v, int32_t k,
 /* One linearisation at pose T about centre c (NULL = origin).
  * src_cov6 is float SoA [6][n] (the stored precision).
  * Outputs: H [36] row-major, b [6], cost, inlier count; optional per-point
- * sparsity_aware: 1 = a pair lacking a covariance enters with M = I
- * (Sec. III-A.2), 0 = such a pair is dropped (standard GICP).
  * correspondence ids corr [n] (-1 = none) and per-point detail rows
- * detail [n][22] = (p[3], r[3], W[9], w, rho, e2, pad...) or NULL. */
+ * detail [n][18] = (p[3], r[3], W[9], w, rho, e2), NaN for a point without
+ * a correspondence, or NULL.
+ * sparsity_aware: 1 = a pair lacking a covariance enters with M = I
+ * (Sec. III-A.2), 0 = such a pair is dropped (standard GICP). */
 int orc_linearize(const orc_map* m, const float* src, const float* src_cov6,
                   const uint8_t* src_valid, int64_t n, const double T[16],
                   double tau, double kappa, const double c[3],

@@ -494,6 +494,28 @@ def random_cloud(seed: int, n: int, extent: float = 4.0, dup_frac: float = 0.0,
     return np.ascontiguousarray(p)
 
 
+def line_cloud(seed: int, n_lines: int = 300, per_line: int = 12, extent: float = 8.0,
+               step: float = 0.125) -> np.ndarray:
+    """Points on straight lines (edges and thin poles in a scan): per line
+    per_line points step apart from a random start; two thirds of the lines
+    run along a coordinate axis with exactly representable coordinates, so
+    their neighbourhoods are exactly collinear (the sample covariance's
+    smallest eigenvalue is double), the rest along random directions."""
+    g = rng(seed)
+    out = []
+    for i in range(n_lines):
+        start = np.round(g.uniform(-extent, extent, size=3) * 8.0) / 8.0
+        if i % 3 != 2:
+            d = np.zeros(3)
+            d[i % 3] = 1.0
+        else:
+            d = g.normal(size=3)
+            d /= np.linalg.norm(d)
+        t = step * np.arange(per_line)
+        out.append(start[:, None] + d[:, None] * t[None, :])
+    return np.ascontiguousarray(np.concatenate(out, axis=1).astype(np.float32))
+
+
 # ---------------------------------------------------------------------------
 # Precision stress: exact planes (near-degenerate neighbourhoods) and rough
 # surfaces, fine voxels

@@ -2,10 +2,12 @@
 oracle's: validity bit-exact; each covariance within float rounding of the
 oracle's wherever the normal is unique (smallest eigenvalue separated from
 the next by more than 1e-4 of the largest, measured on the Eq. (1) output,
-which shares the sample covariance's eigenvectors); elsewhere the spectrum
-{1e-3, 1, 1} that every choice of normal gives.  Scan covariances (random
-cloud with coincident points and points on voxel faces, a LiDAR scan), map
-covariances through inserts, and a GICP align on plane covariances."""
+which shares the sample covariance's eigenvectors); elsewhere the normal
+must lie in the smallest eigenspace, and every valid point has the spectrum
+{1e-3, 1, 1}.  Scan covariances (random cloud with coincident points and
+points on voxel faces, a LiDAR scan, collinear neighbourhoods whose smallest
+eigenvalue is double), map covariances through inserts, and a GICP align on
+plane covariances."""
 import math
 
 import numpy as np
@@ -13,10 +15,15 @@ import pytest
 import torch
 
 from paper_2606_26010_amd import synth
+from tests.plane_check import assert_plane_parity as _check
 
 pytestmark = pytest.mark.gpu
 
 EPS = 1e-3
+
+
+def assert_plane_parity(g6, o6, eq1_6, valid, what):
+    return _check(g6, o6, eq1_6, valid, what, say=say)
 
 
 def dev(a):
@@ -29,28 +36,6 @@ def host(t):
 
 def say(*a):
     print(*a, flush=True)
-
-
-def mats(c6):
-    c = np.asarray(c6, dtype=np.float64)
-    return np.stack([np.stack([c[0], c[1], c[2]], -1), np.stack([c[1], c[3], c[4]], -1),
-                     np.stack([c[2], c[4], c[5]], -1)], -2)
-
-
-def assert_plane_parity(g6, o6, eq1_6, valid, what):
-    G, O, E = mats(g6), mats(o6), mats(eq1_6)
-    v = valid != 0
-    assert np.all(G[~v] == 0)
-    lam = np.linalg.eigvalsh(E[v])
-    unique = (lam[:, 1] - lam[:, 0]) > 1e-4 * lam[:, 2]
-    d = np.abs(G[v] - O[v]).max(axis=(1, 2))
-    assert np.all(d[unique] <= 2e-6), (what, float(d[unique].max()))
-    spec = np.linalg.eigvalsh(G[v])
-    np.testing.assert_allclose(spec, np.broadcast_to([EPS, 1.0, 1.0], spec.shape), rtol=0,
-                               atol=2e-6)
-    say(f"{what}: {v.sum()} valid, {unique.sum()} with a unique normal, "
-        f"max diff {float(d[unique].max()):.2e}")
-    assert unique.mean() > 0.9
 
 
 @pytest.fixture
@@ -67,7 +52,8 @@ def clouds():
     lid = synth.scan(synth.Corridor(), synth.Lidar(), synth.trajectory_pose(0.7), synth.rng(9))
     return {"random_faces_dups": synth.random_cloud(61, 20000, extent=6.0, dup_frac=0.02,
                                                     on_faces=0.2, v=1.0),
-            "lidar_scan": lid}
+            "lidar_scan": lid,
+            "collinear_lines": synth.line_cloud(62)}
 
 
 @pytest.mark.parametrize("name", list(clouds()))

@@ -127,3 +127,40 @@ def test_map_insert_plane_mode(plane_mode):
     ref, rv = orc.scan_covariances(xyz, v, k)
     np.testing.assert_array_equal(val, rv)
     np.testing.assert_array_equal(cov, ref.astype(np.float32))
+
+
+def test_parity_check_places_the_normal_in_the_smallest_eigenspace(plane_mode):
+    """The GPU parity check accepts any normal of a double smallest eigenvalue
+    but rejects one outside that eigenspace: on collinear neighbourhoods
+    (smallest eigenvalue double) the oracle's own covariances pass, and the
+    same covariances with the line direction planted as the normal fail."""
+    from tests.plane_check import assert_plane_parity, mats
+    orc = plane_mode
+    x = synth.line_cloud(62)
+    o6, val = orc.scan_covariances(x, 1.0, 5)
+    orc.set_cov_mode(0)
+    e6, _ = orc.scan_covariances(x, 1.0, 5)
+    orc.set_cov_mode(1)
+    n_unique, n_double = assert_plane_parity(o6, o6, e6, val, "oracle")
+    assert n_double > 100
+    # any other unit vector of the smallest eigenspace is accepted too
+    E = mats(e6)
+    v = np.nonzero(val)[0]
+    lam, Q = np.linalg.eigh(E[v])
+    double = (lam[:, 1] - lam[:, 0]) <= 1e-4 * lam[:, 2]
+    g = synth.rng(5)
+    a = g.uniform(0, 2 * np.pi, size=v.size)
+    n_alt = np.cos(a)[:, None] * Q[:, :, 0] + np.sin(a)[:, None] * Q[:, :, 1]
+    alt = o6.copy()
+    for t, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+        vals = (i == j) + (EPS - 1.0) * n_alt[:, i] * n_alt[:, j]
+        alt[t, v[double]] = vals[double]
+    assert_plane_parity(alt, o6, e6, val, "another normal of the eigenspace")
+    # the largest eigenvector planted as the normal must fail
+    bad = o6.copy()
+    nb = Q[:, :, 2]
+    for t, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+        vals = (i == j) + (EPS - 1.0) * nb[:, i] * nb[:, j]
+        bad[t, v[double]] = vals[double]
+    with pytest.raises(AssertionError):
+        assert_plane_parity(bad, o6, e6, val, "planted")

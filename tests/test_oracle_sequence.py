@@ -101,22 +101,216 @@ def test_nearest_rotation(orc):
         assert np.linalg.det(P) == pytest.approx(1.0, abs=1e-14)
 
 
-def test_odometry_sequence_tracks_ground_truth(orc):
+def _angle_deg(A, B):
+    E = A[:3, :3] @ B[:3, :3].T
+    return math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(E) - 1) / 2))))
+
+
+def _polar_rotation(M):
+    """Nearest rotation by Davenport's q-method (scipy's from_matrix), an
+    algorithm other than the oracle's SVD polar factor."""
+    return Rotation.from_matrix(M).as_matrix()
+
+
+def _deviation(T_pred, T_est, r_max):
+    """KISS-ICP model deviation of T_est from T_pred, written out with a
+    general inverse and scipy's rotation angle."""
+    D = np.linalg.inv(T_pred) @ T_est
+    theta = Rotation.from_matrix(D[:3, :3]).magnitude()
+    return 2.0 * r_max * math.sin(theta / 2.0) + float(np.linalg.norm(D[:3, 3]))
+
+
+def check_odometry_structure(orc, c, out, m, n, max_iters=10, eps=0.0, asmd=False,
+                             evict_radius=0.0, r_near=20.0, min_motion=0.1):
+    """Replay the scan-to-submap loop (Sec. III-A, III-A.3) from the records it
+    returned and check that each step consumed what the method says it does:
+
+    * the downsampled scan is the first point of every downsample voxel;
+    * the prediction of scan s >= 2 is T_{s-1} (T_{s-2}^-1 T_{s-1}) with its
+      rotation projected onto SO(3); scan 1 uses the given first motion;
+    * tau and kappa of scan s are 3 sigma and sigma / 3 of the deviations of
+      the estimates of scans 1..s-1 from their predictions (sigma0 before the
+      first sample), so the threshold is updated after the align;
+    * the align of scan s starts at the prediction, on the map that holds
+      scans 0..s-1 only, and returns the recorded estimate bit for bit;
+    * the map after scan s equals a fresh map fed every downsampled scan at
+      its returned estimate (sizes after every scan, the whole map at the
+      end), with the density caps and eviction when they are on.
+    """
+    v1 = np.linalg.inv(c.poses[0]) @ c.poses[1]
+    fm = orc.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.k,
+                 point_capacity=c.map_capacity, voxel_capacity=c.map_capacity)
+    samples, full = [], False
+    for s in range(n):
+        r = out[s]
+        raw = c.scans[s]
+        src = np.ascontiguousarray(raw[:, first_per_voxel(raw, c.downsample)])
+        assert r["n"] == src.shape[1], f"scan {s}: downsampled size"
+        if s == 0:
+            np.testing.assert_array_equal(r["T"], c.poses[0])
+        else:
+            if s == 1:
+                want = out[0]["T"] @ v1
+            else:
+                P1, P2 = out[s - 1]["T"], out[s - 2]["T"]
+                want = P1 @ (np.linalg.inv(P2) @ P1)
+            want[:3, :3] = _polar_rotation(want[:3, :3])
+            np.testing.assert_allclose(r["T_pred"], want, rtol=0, atol=1e-11,
+                                       err_msg=f"scan {s}: prediction")
+            sigma = math.sqrt(sum(d * d for d in samples) / len(samples)) if samples \
+                else c.sigma0
+            assert r["tau"] == pytest.approx(3.0 * sigma, rel=1e-11), f"scan {s}: tau"
+            assert r["kappa"] == pytest.approx(sigma / 3.0, rel=1e-11), f"scan {s}: kappa"
+            cov, val = orc.scan_covariances(src, c.voxel_size, c.k)
+            a = fm.align(src, cov.astype(np.float32), val, r["T_pred"], r["tau"], r["kappa"],
+                         max_iters=max_iters, eps=eps)
+            assert a["status"] == r["status"], f"scan {s}: align status"
+            np.testing.assert_array_equal(a["T"] if a["status"] == 0 else r["T_pred"], r["T"],
+                                          err_msg=f"scan {s}: align from the prediction")
+            dev = _deviation(r["T_pred"], r["T"], c.r_max)
+            assert r["deviation"] == pytest.approx(dev, rel=1e-9, abs=1e-12), \
+                f"scan {s}: deviation"
+            if dev > min_motion:
+                samples.append(dev)
+        if not full:
+            moved = orc.transform(src, r["T"])
+            caps = orc.asmd_caps(src, moved, c.voxel_size, c.k, c.max_pts_per_voxel, r_near,
+                                 c.r_max)[0] if asmd else None
+            rc, _, _ = fm.insert(moved, caps, check=False)
+            full = rc == 2
+        if evict_radius > 0:
+            fm.evict(r["T"][:3, 3], evict_radius)
+        assert fm.size == r["map_points"], f"scan {s}: map size after the insert"
+    for a, b in zip(fm.export(), m.export()):
+        np.testing.assert_array_equal(a, b, err_msg="map after the sequence")
+
+
+def test_polar_rotation_agrees_with_svd():
+    g = np.random.default_rng(9)
+    for _ in range(20):
+        M = Rotation.from_rotvec(g.normal(size=3)).as_matrix() + 1e-4 * g.normal(size=(3, 3))
+        U, _, Vt = np.linalg.svd(M)
+        np.testing.assert_allclose(_polar_rotation(M), U @ Vt, atol=1e-14)
+
+
+def _run(orc, c, n, **kw):
+    v1 = np.linalg.inv(c.poses[0]) @ c.poses[1]
+    return orc.odometry(c.scans[:n], c.poses[0], v1, c.voxel_size, c.max_pts_per_voxel,
+                        c.min_spacing, c.k, c.map_capacity, c.downsample, c.sigma0, c.r_max,
+                        **kw)
+
+
+def test_odometry_short_sequence_tracks_ground_truth(orc):
+    n = 6
+    c = synth.make_sequence(2, n_scans=n, lidar=synth.Lidar(beams=32, azimuths=512))
+    out, m = _run(orc, c, n)
+    assert [r["status"] for r in out] == [0] * n
+    assert all(out[i]["map_points"] > out[i - 1]["map_points"] for i in range(1, n))
+    for r, T in zip(out, c.poses):
+        assert np.linalg.norm(r["T"][:3, 3] - T[:3, 3]) < 0.1 and _angle_deg(r["T"], T) < 0.3
+    check_odometry_structure(orc, c, out, m, n)
+
+
+def test_odometry_long_sequence_structure_and_drift(orc):
     # 60 scans: long enough for an unprojected constant-velocity predictor
     # (rounding growth about 2.4x per scan) to lose the rotation
     n = 60
     c = synth.make_sequence(2, n_scans=n, lidar=synth.Lidar(beams=32, azimuths=512))
-    v1 = np.linalg.inv(c.poses[0]) @ c.poses[1]
-    out, m = orc.odometry(c.scans, c.poses[0], v1, c.voxel_size, c.max_pts_per_voxel,
-                          c.min_spacing, c.k, c.map_capacity, c.downsample, c.sigma0,
-                          c.r_max)
+    out, m = _run(orc, c, n)
     assert [r["status"] for r in out] == [0] * n
     assert all(out[i]["map_points"] > out[i - 1]["map_points"] for i in range(1, n))
     for r, T in zip(out, c.poses):
-        E = r["T"][:3, :3] @ T[:3, :3].T
-        ang = math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(E) - 1) / 2))))
-        assert np.linalg.norm(r["T"][:3, 3] - T[:3, 3]) < 2.0 and ang < 1.0   # drift, not blow-up
+        assert np.linalg.norm(r["T"][:3, 3] - T[:3, 3]) < 2.0 and _angle_deg(r["T"], T) < 1.0
         np.testing.assert_allclose(r["T"][:3, :3].T @ r["T"][:3, :3], np.eye(3), atol=1e-13)
+    check_odometry_structure(orc, c, out, m, n)
+
+
+def test_odometry_structure_with_density_caps_and_eviction(orc):
+    n = 12
+    c = synth.make_sequence(2, n_scans=n, lidar=synth.Lidar(beams=32, azimuths=512))
+    out, m = _run(orc, c, n, asmd=True, evict_radius=40.0)
+    assert sum(r["evicted"] for r in out) > 0
+    check_odometry_structure(orc, c, out, m, n, asmd=True, evict_radius=40.0)
+
+
+MUTATIONS = ["insert_at_prediction", "threshold_before_align", "threshold_lag",
+             "increment_on_wrong_side", "align_after_insert"]
+
+
+def _loop_with_mistake(orc, c, n, mutation):
+    """The odometry loop with one planted mistake (None: none), written out in
+    the test so that the checker can be shown to catch each of them."""
+    v1 = np.linalg.inv(c.poses[0]) @ c.poses[1]
+    m = orc.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.k,
+                point_capacity=c.map_capacity, voxel_capacity=c.map_capacity)
+    thr = orc.Threshold(c.sigma0, c.r_max, 0.1)
+    out, poses, pending, full = [], [], None, False
+    for s in range(n):
+        raw = c.scans[s]
+        src = orc._soa(raw)[:, orc.downsample(raw, c.downsample)]
+        rec = {"n": src.shape[1]}
+        T_pred = None
+        if s == 0:
+            T = np.array(c.poses[0], dtype=np.float64)
+            rec.update(T_pred=T.copy(), tau=None, kappa=None, status=0, iters=0)
+        else:
+            if s == 1:
+                T_pred = poses[-1] @ v1
+            elif mutation == "increment_on_wrong_side":
+                T_pred = (orc._inv(poses[-2]) @ poses[-1]) @ poses[-1]
+            else:
+                T_pred = poses[-1] @ (orc._inv(poses[-2]) @ poses[-1])
+            T_pred[:3, :3] = orc._nearest_rotation(T_pred[:3, :3])
+            if mutation == "threshold_before_align":
+                dev = thr.update(T_pred, poses[-1])
+            tau, kappa = thr.get()
+            if mutation == "threshold_lag" and pending is not None:
+                thr.update(*pending)
+            cov, val = orc.scan_covariances(src, c.voxel_size, c.k)
+            if mutation == "align_after_insert" and not full:
+                full = m.insert(orc.transform(src, T_pred), check=False)[0] == 2
+            r = m.align(src, cov.astype(np.float32), val, T_pred, tau, kappa, max_iters=10,
+                        eps=0.0)
+            T = r["T"] if r["status"] == 0 else T_pred
+            if mutation == "threshold_lag":
+                pending = (T_pred, T)
+                dev = orc.Threshold(c.sigma0, c.r_max, 0.1).update(T_pred, T)
+            elif mutation != "threshold_before_align":
+                dev = thr.update(T_pred, T)
+            rec.update(T_pred=T_pred, tau=tau, kappa=kappa, status=r["status"],
+                       iters=r["iters"], n_inliers=r["n_inliers"], cost=r["cost"],
+                       deviation=dev)
+        poses.append(T)
+        if not full and not (mutation == "align_after_insert" and s > 0):
+            at = T_pred if (mutation == "insert_at_prediction" and s > 0) else T
+            rc, acc, _ = m.insert(orc.transform(src, at), None, check=False)
+            full = rc == 2
+            rec["inserted"] = acc
+        rec.update(T=T, map_points=m.size, map_voxels=m.n_voxels)
+        out.append(rec)
+    return out, m
+
+
+def test_mistake_harness_is_the_oracle_loop(orc):
+    n = 6
+    c = synth.make_sequence(2, n_scans=n, lidar=synth.Lidar(beams=32, azimuths=512))
+    want, wm = _run(orc, c, n)
+    got, gm = _loop_with_mistake(orc, c, n, None)
+    for a, b in zip(want, got):
+        for k in ("n", "T_pred", "tau", "kappa", "status", "iters", "T", "map_points"):
+            np.testing.assert_array_equal(np.asarray(a[k], dtype=object if a[k] is None else None),
+                                          np.asarray(b[k], dtype=object if b[k] is None else None))
+    for a, b in zip(wm.export(), gm.export()):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("mutation", MUTATIONS)
+def test_structure_check_catches_planted_mistake(orc, mutation):
+    n = 6
+    c = synth.make_sequence(2, n_scans=n, lidar=synth.Lidar(beams=32, azimuths=512))
+    out, m = _loop_with_mistake(orc, c, n, mutation)
+    with pytest.raises(AssertionError):
+        check_odometry_structure(orc, c, out, m, n)
 
 
 @pytest.mark.parametrize("angle", [1e-7, 3e-4, 0.3, 2.0, 3.1, math.pi])

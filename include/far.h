@@ -380,6 +380,24 @@ far_status_t far_undistort_batch(const float* xyz, const float* t, const int64_t
                                  const double* vel, const int64_t* vel_offsets, float* out,
                                  double* t_ref, far_stream_t stream);
 
+/* far_undistort_batch for callers that cannot allocate device memory: code
+ * recorded under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results as
+ * far_undistort_batch; it calls no hipMalloc, hipFree or allocating routine.
+ * Its scratch (per-chunk time maxima and per-scan fit coefficients) is a
+ * fixed device array of about 1.6 MB inside the library, one copy per GPU,
+ * held until the process ends; its address is looked up on the first call
+ * on each device.  Limits: S <= 4096 scans and n_total <= 2^28 points, else
+ * FAR_E_CAPACITY with nothing enqueued.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Not timed by
+ * far_timing_*.  Asynchronous. */
+far_status_t far_undistort_batch_noalloc(const float* xyz, const float* t,
+                                         const int64_t* offsets, int32_t S, int64_t n_total,
+                                         const double* vel_t, const double* vel,
+                                         const int64_t* vel_offsets, float* out, double* t_ref,
+                                         far_stream_t stream);
+
 /* Adaptive submap density (Sec. III-A.3, ASMD): per-point insert caps that
  * follow the current scan's density near the sensor and decay over range
  * (the paper gives no constants; reading): mean = points per voxel of edge v

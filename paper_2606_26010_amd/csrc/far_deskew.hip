@@ -27,6 +27,7 @@
 // Each point costs 16 bytes read (xyz, t) and 12 written.
 
 #include <cmath>
+#include <mutex>
 
 #include "far_internal.h"
 
@@ -416,6 +417,33 @@ __global__ __launch_bounds__(kUdBlock) void k_ud_apply(
   }
 }
 
+// The two launches of an undistortion, on scratch the caller provides:
+// part [ceil(n / kUdChunk)], mid [S], coef [S * kUdCoef].  Every entry the
+// launches read is written by k_ud_scan first, so the scratch needs no
+// clearing and may hold an earlier call's contents.
+far_status_t undistort_launch(const float* xyz, const float* t, const int64_t* off, int32_t S,
+                              int64_t n, const double* vel_t, const double* vel,
+                              const int64_t* voff, int64_t m, float* out, double* t_ref,
+                              int4* part, uint32_t* mid, double* coef, bool timed,
+                              hipStream_t st) {
+  const int64_t n_chunks = (n + kUdChunk - 1) / kUdChunk;
+  {
+    TimedScope ts(timed ? FAR_TIME_UNDISTORT : -1, st);
+    hipLaunchKernelGGL(k_ud_scan, dim3(unsigned(n_chunks + S)), dim3(kUdBlock), 0, st, t, off,
+                       S, n, n_chunks, part, mid, vel_t, vel, voff, m, coef, t_ref);
+    FAR_HIP(hipGetLastError());
+    if (n > 0) {
+      const int64_t n_apply = (n + kUdApply - 1) / kUdApply;
+      const int64_t n_tref = t_ref ? (S + kUdBlock / 64 - 1) / (kUdBlock / 64) : 0;
+      TimedScope ta(timed ? FAR_TIME_UNDISTORT_APPLY : -1, st);
+      hipLaunchKernelGGL(k_ud_apply, dim3(unsigned(n_apply + n_tref)), dim3(kUdBlock), 0, st,
+                         xyz, t, off, S, n, n_apply, coef, part, mid, t_ref, out);
+      FAR_HIP(hipGetLastError());
+    }
+  }
+  return FAR_OK;
+}
+
 far_status_t undistort_impl(const float* xyz, const float* t, const int64_t* off, int32_t S,
                             int64_t n, const double* vel_t, const double* vel,
                             const int64_t* voff, int64_t m, float* out, double* t_ref,
@@ -428,18 +456,51 @@ far_status_t undistort_impl(const float* xyz, const float* t, const int64_t* off
   FAR_TRY(scr.get(&part, size_t(n_chunks)));
   FAR_TRY(scr.get(&mid, size_t(S)));
   FAR_TRY(scr.get(&coef, size_t(S) * kUdCoef));
-  TimedScope ts(FAR_TIME_UNDISTORT, st);
-  hipLaunchKernelGGL(k_ud_scan, dim3(unsigned(n_chunks + S)), dim3(kUdBlock), 0, st, t, off, S,
-                     n, n_chunks, part, mid, vel_t, vel, voff, m, coef, t_ref);
-  FAR_HIP(hipGetLastError());
-  if (n > 0) {
-    const int64_t n_apply = (n + kUdApply - 1) / kUdApply;
-    const int64_t n_tref = t_ref ? (S + kUdBlock / 64 - 1) / (kUdBlock / 64) : 0;
-    TimedScope ta(FAR_TIME_UNDISTORT_APPLY, st);
-    hipLaunchKernelGGL(k_ud_apply, dim3(unsigned(n_apply + n_tref)), dim3(kUdBlock), 0, st, xyz,
-                       t, off, S, n, n_apply, coef, part, mid, t_ref, out);
-    FAR_HIP(hipGetLastError());
+  return undistort_launch(xyz, t, off, S, n, vel_t, vel, voff, m, out, t_ref, part, mid, coef,
+                          true, st);
+}
+
+// ---------------------------------------------------------------- no-alloc
+// Scratch of the allocation-free batch call: a fixed device array, one copy
+// per GPU (each device that loads the library holds it until the process
+// ends).  Its host-side name is not a device address: host code uses only
+// the address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kUdFixedMaxPoints = int64_t(1) << 28;
+constexpr int32_t kUdFixedMaxScans = 4096;
+constexpr size_t kUdFixedPart = size_t(kUdFixedMaxPoints / kUdChunk) * sizeof(int4);
+constexpr size_t kUdFixedMid = (size_t(kUdFixedMaxScans) * sizeof(uint32_t) + 255) & ~size_t(255);
+constexpr size_t kUdFixedCoef = size_t(kUdFixedMaxScans) * kUdCoef * sizeof(double);
+constexpr size_t kUdFixedBytes = kUdFixedPart + kUdFixedMid + kUdFixedCoef;
+static_assert(kUdFixedPart % 256 == 0, "scratch pieces stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kUdFixedBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+char* g_fixed_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device.
+far_status_t fixed_scratch(char** out) {
+  int dev = -1;
+  FAR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("far_undistort_batch_noalloc: device %d beyond the %d the library tracks", dev,
+              kMaxDevices);
+    return FAR_E_UNSUPPORTED;
   }
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("far_undistort_batch_noalloc: hipGetSymbolAddress failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return FAR_E_HIP;
+    }
+    g_fixed_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_fixed_ptr[dev];
   return FAR_OK;
 }
 
@@ -472,6 +533,32 @@ far_status_t far_undistort_batch(const float* xyz, const float* t, const int64_t
   }
   return far::undistort_impl(xyz, t, offsets, S, n_total, vel_t, vel, vel_offsets, 0, out,
                              t_ref, far::S(stream));
+}
+
+far_status_t far_undistort_batch_noalloc(const float* xyz, const float* t,
+                                         const int64_t* offsets, int32_t S, int64_t n_total,
+                                         const double* vel_t, const double* vel,
+                                         const int64_t* vel_offsets, float* out, double* t_ref,
+                                         far_stream_t stream) {
+  if (S <= 0 || n_total < 0 || !offsets || !vel_offsets ||
+      (n_total > 0 && (!xyz || !t || !out))) {
+    far::set_error("far_undistort_batch_noalloc: bad arguments (S %d, n_total %lld)", S,
+                   (long long)n_total);
+    return FAR_E_INVALID;
+  }
+  if (S > far::kUdFixedMaxScans || n_total > far::kUdFixedMaxPoints) {
+    far::set_error("far_undistort_batch_noalloc: S %d, n_total %lld exceed the fixed scratch "
+                   "(at most %d scans, %lld points)", S, (long long)n_total,
+                   far::kUdFixedMaxScans, (long long)far::kUdFixedMaxPoints);
+    return FAR_E_CAPACITY;
+  }
+  char* base = nullptr;
+  FAR_TRY(far::fixed_scratch(&base));
+  int4* part = reinterpret_cast<int4*>(base);
+  uint32_t* mid = reinterpret_cast<uint32_t*>(base + far::kUdFixedPart);
+  double* coef = reinterpret_cast<double*>(base + far::kUdFixedPart + far::kUdFixedMid);
+  return far::undistort_launch(xyz, t, offsets, S, n_total, vel_t, vel, vel_offsets, 0, out,
+                               t_ref, part, mid, coef, false, far::S(stream));
 }
 
 }  // extern "C"

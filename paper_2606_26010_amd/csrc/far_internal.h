@@ -42,7 +42,8 @@ struct TimedScope {
   hipStream_t st;
   hipEvent_t ev0 = nullptr;
   TimedScope(int k, hipStream_t s) : kind(k), st(s) {
-    if (timing_on() && hipEventCreate(&ev0) == hipSuccess) (void)hipEventRecord(ev0, st);
+    // kind < 0: not timed (no event is created)
+    if (k >= 0 && timing_on() && hipEventCreate(&ev0) == hipSuccess) (void)hipEventRecord(ev0, st);
   }
   // Ends the interval early (before a host synchronisation of the call).
   void stop() {

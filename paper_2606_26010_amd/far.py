@@ -123,6 +123,8 @@ _SIGS = {
     "far_undistort": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_int32, _P, _P, _P]),
     "far_undistort_batch": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
                                       _P]),
+    "far_undistort_batch_noalloc": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P,
+                                              _P, _P, _P]),
     "far_threshold_init": (C.c_int, [C.POINTER(far_threshold_t), C.c_double, C.c_double,
                                      C.c_double]),
     "far_threshold_update": (C.c_int, [C.POINTER(far_threshold_t), C.POINTER(C.c_double),
@@ -638,6 +640,30 @@ def far_undistort_batch(xyz, t, offsets, vel_t, vel, vel_offsets, out=None, stre
                                      _dev(out, torch.float32, "out"),
                                      _dev(t_ref, torch.float64, "t_ref"), _stream(stream)),
            "far_undistort_batch")
+    return out, t_ref[:S]
+
+
+def far_undistort_batch_noalloc(xyz, t, offsets, vel_t, vel, vel_offsets, out, t_ref,
+                                stream=None):
+    """far_undistort_batch through the allocation-free entry point: the
+    caller passes out [3, n_total] and t_ref [S] (float64); the library
+    allocates nothing for the call."""
+    p, n = _pts(xyz, "xyz")
+    if t.dim() != 1 or t.shape[0] != n:
+        raise ValueError("t must be [n_total]")
+    S = offsets.shape[0] - 1
+    if vel_offsets.shape[0] != S + 1:
+        raise ValueError("offsets and vel_offsets differ in scan count")
+    if out.shape != xyz.shape or t_ref.dim() != 1 or t_ref.shape[0] < S:
+        raise ValueError("out must be [3, n_total] and t_ref [S]")
+    pt, pv, _ = _samples(vel_t, vel)
+    _check(lib().far_undistort_batch_noalloc(p, _dev(t, torch.float32, "t"),
+                                             _dev(offsets, torch.int64, "offsets"), S, n, pt, pv,
+                                             _dev(vel_offsets, torch.int64, "vel_offsets"),
+                                             _dev(out, torch.float32, "out"),
+                                             _dev(t_ref, torch.float64, "t_ref"),
+                                             _stream(stream)),
+           "far_undistort_batch_noalloc")
     return out, t_ref[:S]
 
 

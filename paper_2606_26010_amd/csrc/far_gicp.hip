@@ -27,6 +27,7 @@ namespace {
 // 128, 256 or 512, chosen per map (far_map_set_schedule / far_autotune).
 constexpr int kTileDefault = 256;
 constexpr int kTileMin = 128;
+constexpr int kTileMax = 512;
 constexpr int kVals = 29;     // 21 H + 6 b + cost + count
 constexpr int kStride = 32;   // partial row stride (doubles)
 
@@ -423,19 +424,12 @@ struct FaceOffsets {
   }
 };
 
+// Exact search over the own voxel (unless own_done: its points were already
+// ranked into top) and the neighbour voxels, continuing from the candidates
+// already in top.
 __device__ inline void nn_lockstep(const MapView& m, double px, double py, double pz,
-                                   int32_t kx, int32_t ky, int32_t kz, double r2, int32_t seed,
-                                   TopK<1>& top) {
-  top.init();
-  // seed: the point's correspondence of the previous iteration (a position in
-  // vox_pts), evaluated exactly at the current pose.  It lies within r <= v,
-  // so inside the 27 voxels searched below: the result is unchanged, but the
-  // bound is tight before the first voxel and prunes most neighbour visits.
-  if (seed >= 0) {
-    const float4 sp = m.vox_pts[seed];
-    const double d = dist2(double(sp.x), double(sp.y), double(sp.z), px, py, pz);
-    if (d <= r2) top.push(d, __float_as_int(sp.w), seed);
-  }
+                                   int32_t kx, int32_t ky, int32_t kz, double r2, bool own_done,
+                                   int32_t own, int32_t cnt, TopK<1>& top) {
   const double v = m.v;
   FaceOffsets fo;
   fo.f[0] = float(px - double(kx) * v);
@@ -445,9 +439,10 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
   fo.slack = float(1e-7 * v);
   Query q = make_query(px, py, pz, r2);
   q.bound_f = screen_bound(fmin(r2, top.bound()), q.m);
-  int32_t cnt;
-  const int32_t own = map_find(m, kx, ky, kz, &cnt);
-  if (own >= 0) scan_voxel_points<1>(m.vox_pts, own * m.nmax, cnt, q, r2, top);
+  if (!own_done) {
+    own = map_find(m, kx, ky, kz, &cnt);
+    if (own >= 0) scan_voxel_points<1>(m.vox_pts, own * m.nmax, cnt, q, r2, top);
+  }
   uint32_t need = 0;
   {
     const float bnd = f32_up(fmin(r2, top.bound()));
@@ -477,6 +472,105 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
   }
 }
 
+// A candidate for a query: its vox_pts slot and point (x, y, z, id bits), its
+// id and its exact squared distance.
+struct Cand {
+  double d;
+  int32_t id;
+  int32_t pos;
+  float4 p;
+};
+
+// Walks from candidate c towards the query's nearest map point over the
+// certificates' neighbour lists: c moves to the best listed point while one
+// ranks before it by (d2, id), at most kCertWalks times.  True when c ends as
+// a point that ranks before all its listed points and lies closer than its
+// rho (its computed d2 below rho^2 (1 - 2^-30): the FP64 rounding of every
+// d2 is far below that margin), so no map point ranks before it.
+constexpr int kCertWalks = 2;
+
+__device__ inline bool certify(const MapView& m, const Query& q, Cand& c) {
+  const int4* rows = reinterpret_cast<const int4*>(m.cert);   // 2 int4 per row
+  for (int w = 0; w <= kCertWalks; ++w) {
+    const int4 r0 = rows[2 * int64_t(c.pos)];
+    const int4 r1 = rows[2 * int64_t(c.pos) + 1];
+    const int32_t nb[kCertK] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+    float4 lp[kCertK];
+#pragma unroll
+    for (int t = 0; t < kCertK; ++t)
+      if (nb[t] >= 0) lp[t] = m.vox_pts[nb[t]];
+    Cand best = c;
+    float bnd = screen_bound(c.d, q.m);
+#pragma unroll
+    for (int t = 0; t < kCertK; ++t)
+      if (nb[t] >= 0) {
+        const float dx = lp[t].x - q.fx, dy = lp[t].y - q.fy, dz = lp[t].z - q.fz;
+        const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        if (d2f <= bnd) {
+          const double d = dist2(double(lp[t].x), double(lp[t].y), double(lp[t].z), q.x, q.y,
+                                 q.z);
+          const int32_t id = __float_as_int(lp[t].w);
+          if (rank_less(d, id, best.d, best.id)) {
+            best.d = d;
+            best.id = id;
+            best.pos = nb[t];
+            best.p = lp[t];
+            bnd = screen_bound(d, q.m);
+          }
+        }
+      }
+    if (best.pos == c.pos) {
+      const double rho = double(__int_as_float(r0.x));
+      return c.d < rho * rho * (1.0 - 0x1p-30);
+    }
+    c = best;
+  }
+  return false;
+}
+
+// First stage of the correspondence search (the nearest map point within
+// sqrt(r2), ranked by (d2, id), as the 27-voxel search finds it).  The first
+// candidate is the seed (the vox_pts slot of the point's match, or nearest
+// point, of the previous iteration) or else the best point of the own voxel
+// within the radius.  True when certify() proves the final candidate c the
+// nearest map point: it is then the answer (none when c.d > r2).  Otherwise
+// c (pos -1: none) is the best candidate seen, to bound the exact search
+// that follows.
+__device__ inline bool nn_cert_try(const MapView& m, double px, double py, double pz,
+                                   int32_t kx, int32_t ky, int32_t kz, double r2, int32_t seed,
+                                   Cand& c) {
+  Query q = make_query(px, py, pz, r2);
+  c.pos = -1;
+  if (seed < 0) {
+    int32_t cnt;
+    const int32_t own = map_find(m, kx, ky, kz, &cnt);
+    TopK<1> t1;
+    t1.init();
+    if (own >= 0) scan_voxel_points<1>(m.vox_pts, own * m.nmax, cnt, q, r2, t1);
+    if (t1.pos[0] < 0) return false;
+    seed = t1.pos[0];
+  }
+  c.pos = seed;
+  c.p = m.vox_pts[seed];
+  c.id = __float_as_int(c.p.w);
+  c.d = dist2(double(c.p.x), double(c.p.y), double(c.p.z), px, py, pz);
+  return certify(m, q, c);
+}
+
+// Second stage: the exact 27-voxel search, starting from candidate c (when
+// within the radius).  Returns the vox_pts slot of the match (-1: none
+// within the radius); *next is the slot to seed the next iteration with.
+__device__ inline int32_t nn_exact_from(const MapView& m, double px, double py, double pz,
+                                        int32_t kx, int32_t ky, int32_t kz, double r2,
+                                        const Cand& c, int32_t* next) {
+  TopK<1> top;
+  top.init();
+  if (c.pos >= 0 && c.d <= r2) top.push(c.d, c.id, c.pos);
+  nn_lockstep(m, px, py, pz, kx, ky, kz, r2, false, -1, 0, top);
+  *next = top.pos[0] >= 0 ? top.pos[0] : c.pos;
+  return top.pos[0];
+}
+
 // Voxel index with an exact multiply when 1/v is exact (power-of-two v),
 // else the division; both give floor(x / v) exactly as the FP64 quotient.
 __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool pow2,
@@ -487,85 +581,249 @@ __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool p
   return true;
 }
 
+// Tile of this block: blocks are dealt to the eight XCDs round-robin, block b
+// taking tile (b mod 8) * chunk + b / 8, so that each XCD works through one
+// contiguous range of tiles and neighbouring tiles (which share map voxels)
+// meet in the same L2.  -1 past the last tile.
+__device__ inline int64_t block_tile(int64_t n_tiles) {
+  const int64_t chunk = (n_tiles + 7) >> 3;
+  const int64_t t = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  return (t >= n_tiles || (blockIdx.x >> 3) >= chunk) ? -1 : t;
+}
+
+// The pose of scan s: R row-major and t.
+struct Pose {
+  double R[9];
+  double tx, ty, tz;
+  __device__ explicit Pose(const double* Ts)
+      : R{Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]},
+        tx(Ts[3]), ty(Ts[7]), tz(Ts[11]) {}
+};
+
+// p = R s + t in FP64 (FMA-free) of packed point a, and its map voxel key;
+// false when the point is not finite or its key is out of range.
+__device__ inline bool locate(const float4& a, const Pose& P, const MapView& m,
+                              const Params& prm, double& px, double& py, double& pz,
+                              int64_t& kx, int64_t& ky, int64_t& kz) {
+  if (!(isfinite(a.x) && isfinite(a.y) && isfinite(a.z))) return false;
+  const double sx = a.x, sy = a.y, sz = a.z;
+  px = ((P.R[0] * sx + P.R[1] * sy) + P.R[2] * sz) + P.tx;
+  py = ((P.R[3] * sx + P.R[4] * sy) + P.R[5] * sz) + P.ty;
+  pz = ((P.R[6] * sx + P.R[7] * sy) + P.R[8] * sz) + P.tz;
+  return voxel_index_fast(px, m.v, prm.inv_v, prm.v_pow2, &kx) &&
+         voxel_index_fast(py, m.v, prm.inv_v, prm.v_pow2, &ky) &&
+         voxel_index_fast(pz, m.v, prm.inv_v, prm.v_pow2, &kz);
+}
+
+// A linearisation after the first iteration of an align is three passes
+// over the active tiles, so that no pass holds a lane idle for another: the
+// certified search (k_cert), seeded with each point's match of the previous
+// iteration, settles most points and queues the rest; the exact search
+// (k_search) runs the queued points densely; the term pass (k_linearize)
+// forms every point's GICP term from its match and reduces them per tile.
+// The first iteration, with no seeds, runs the exact search inside the term
+// pass (kSearch), as a one-off linearisation and the gradient do.
+//
+// The queue is cut into kBins bins; tile t appends its entries to bin
+// t mod kBins (one atomic per tile), so the bins fill without a global
+// prefix.  An entry holds the packed point index, the best candidate of the
+// first pass (a vox_pts slot, -1: none) and the FP64 map-frame position.
+// The order of entries within a bin varies from run to run; every entry's
+// result goes to its own point, so the results do not.
+constexpr int kBins = 64;
+
+struct Queue {
+  uint32_t* idx;
+  int32_t* cand;
+  double* p;          // SoA, cap apart
+  uint32_t* count;    // [kBins]
+  int64_t bin_cap;    // entries per bin
+  int64_t cap;        // kBins * bin_cap
+};
+
+__global__ __launch_bounds__(64) void k_zero_bins(uint32_t* count) {
+  if (threadIdx.x < kBins) count[threadIdx.x] = 0;
+}
+
+// Pass 1, one block of kB lanes per tile: match[i] receives the vox_pts slot
+// of point i's match when the certificates settle it (-1: none), prev[i] the
+// seed of the next iteration; the other points are queued in lane order.
+template <int kB>
+__global__ __launch_bounds__(kB) void k_cert(
+    MapView m, const float4* __restrict__ pA, const int32_t* __restrict__ tile_scan,
+    const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
+    int64_t n_tiles, const double* __restrict__ T, const int32_t* __restrict__ done,
+    Params prm, int32_t* __restrict__ match, int32_t* __restrict__ prev, Queue Q) {
+  constexpr int kWaves = kB / 64;
+  __shared__ int32_t q_wcnt[kWaves];
+  __shared__ uint32_t q_base;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t t = block_tile(n_tiles);
+  if (t < 0) return;
+  const int32_t s = tile_scan[t];
+  if (s < 0 || done[s]) return;
+  const Pose P(T + 16 * int64_t(s));
+  const uint32_t lo = tile_lo[t], hi = tile_hi[t];
+  const uint32_t i = lo + uint32_t(tid);
+  bool queued = false;
+  int32_t qc = -1;
+  double px = 0.0, py = 0.0, pz = 0.0;
+  if (i < hi) {
+    int64_t kx = 0, ky = 0, kz = 0;   // within [-2^20, 2^20) once locate holds
+    const bool have = locate(pA[i], P, m, prm, px, py, pz, kx, ky, kz);
+    Cand c;
+    c.pos = -1;
+    if (have && !nn_cert_try(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
+                             prev[i], c)) {
+      queued = true;
+      qc = c.pos;
+    } else {
+      match[i] = have && c.d <= prm.r2 ? c.pos : -1;
+      prev[i] = have ? c.pos : -1;
+    }
+  }
+  const uint64_t bal = __ballot(queued);
+  if (lane == 0) q_wcnt[wave] = __popcll(bal);
+  __syncthreads();
+  int off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int cw = q_wcnt[w];
+    off += w < wave ? cw : 0;
+    total += cw;
+  }
+  if (total == 0) return;
+  const int64_t bin = t % kBins;
+  if (tid == 0) q_base = atomicAdd(&Q.count[bin], uint32_t(total));
+  __syncthreads();
+  if (queued) {
+    const int64_t q = bin * Q.bin_cap + q_base + off + __popcll(bal & ((uint64_t(1) << lane) - 1));
+    Q.idx[q] = i;
+    Q.cand[q] = qc;
+    Q.p[q] = px;
+    Q.p[Q.cap + q] = py;
+    Q.p[2 * Q.cap + q] = pz;
+  }
+}
+
+// Pass 2: the exact 27-voxel search of every queued point, one per lane,
+// lanes striding over the bins in order (bin of entry g from an LDS prefix
+// of the bin counts), so that the searches fill whole waves.
+constexpr int kSearchThreads = 256;
+__global__ __launch_bounds__(kSearchThreads) void k_search(MapView m, Queue Q, Params prm,
+                                                           int32_t* __restrict__ match,
+                                                           int32_t* __restrict__ prev) {
+  __shared__ uint32_t pre[kBins + 1];
+  if (threadIdx.x < 64) {
+    // inclusive scan of the kBins counts across the first wave
+    uint32_t v = threadIdx.x < kBins ? Q.count[threadIdx.x] : 0u;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = uint32_t(__shfl_up(int(v), d));
+      if (int(threadIdx.x) >= d) v += u;
+    }
+    if (threadIdx.x < kBins) pre[threadIdx.x + 1] = v;
+    if (threadIdx.x == 0) pre[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t total = pre[kBins];
+  for (uint32_t g = blockIdx.x * kSearchThreads + threadIdx.x; g < total;
+       g += gridDim.x * kSearchThreads) {
+    int a = 0, b = kBins - 1;   // the last bin whose start is <= g
+    while (a < b) {
+      const int mid = (a + b + 1) >> 1;
+      if (pre[mid] <= g) a = mid;
+      else b = mid - 1;
+    }
+    const int64_t q = int64_t(a) * Q.bin_cap + (g - pre[a]);
+    const uint32_t i = Q.idx[q];
+    const double px = Q.p[q], py = Q.p[Q.cap + q], pz = Q.p[2 * Q.cap + q];
+    int64_t kx = 0, ky = 0, kz = 0;
+    (void)voxel_index_fast(px, m.v, prm.inv_v, prm.v_pow2, &kx);   // held in pass 1
+    (void)voxel_index_fast(py, m.v, prm.inv_v, prm.v_pow2, &ky);
+    (void)voxel_index_fast(pz, m.v, prm.inv_v, prm.v_pow2, &kz);
+    Cand c;
+    c.pos = Q.cand[q];
+    if (c.pos >= 0) {
+      c.p = m.vox_pts[c.pos];
+      c.id = __float_as_int(c.p.w);
+      c.d = dist2(double(c.p.x), double(c.p.y), double(c.p.z), px, py, pz);
+    }
+    int32_t next = -1;
+    match[i] = nn_exact_from(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, c,
+                             &next);
+    prev[i] = next;
+  }
+}
+
+// Pass 3, the term pass: one block of kB threads per tile, one point per
+// lane, its GICP term from its match (match[i]; with kSearch from the exact
+// search run here, whose result also seeds prev[i] when given), then the
+// tile's sums.
 // kGrad selects the gradient of the cost instead of H, b: 14 sums (the 3x4
 // gradient of [R | t], cost, count) and, when grad_src is given, each
 // point's source gradient written SoA at its original index (n_src apart).
-// Waves per SIMD asked of the FP32 voxel-search instantiation: the kernel
-// waits on chains of dependent gathers, so occupancy is what hides them.
-constexpr int kMinWaves = 7;
-
 // kNoSA (the sparsity-aware case off) is a template parameter: a run-time
 // test in the match block costs the default path 8 %.
-template <class Real, bool kGrad, int kB, bool kFine, bool kNoSA>
-__global__ __launch_bounds__(kB, (std::is_same<Real, float>::value && !kFine) ? kMinWaves : 1)
-void k_linearize(
+template <class Real, bool kGrad, int kB, bool kFine, bool kNoSA, bool kSearch>
+__global__ __launch_bounds__(kB) void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
     const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
     int32_t* __restrict__ corr, float* __restrict__ grad_src, int64_t n_src,
-    int32_t* __restrict__ prev) {
+    const int32_t* __restrict__ match, int32_t* __restrict__ prev) {
   constexpr int kWaves = kB / 64;
   constexpr int kNV = kGrad ? 14 : kVals;
   __shared__ double red[kWaves][kNV];
   __shared__ float tbl[std::is_same<Real, float>::value ? kWaves : 1][kRedChunk * kRedRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t chunk = (n_tiles + 7) >> 3;
-  const int64_t t = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
-  if (t >= n_tiles || (blockIdx.x >> 3) >= chunk) return;
+  const int64_t t = block_tile(n_tiles);
+  if (t < 0) return;
   const int32_t s = tile_scan[t];
   if (s < 0 || done[s]) return;
-  const double* Ts = T + 16 * int64_t(s);
-  const double R[9] = {Ts[0], Ts[1], Ts[2], Ts[4], Ts[5], Ts[6], Ts[8], Ts[9], Ts[10]};
-  const double tx = Ts[3], ty = Ts[7], tz = Ts[11];
+  const Pose P(T + 16 * int64_t(s));
   const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
-  // 32-bit point indices (n < 2^31): one register each where they stay live
-  // across the search
   const uint32_t lo = tile_lo[t], hi = tile_hi[t];
 
   Real acc[kNV];
 #pragma unroll
   for (int q = 0; q < kNV; ++q) acc[q] = Real(0);
-  {
-    const uint32_t i = lo + uint32_t(tid);
-    const bool in_tile = i < hi;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (in_tile) a = pA[i];
-    // p = R s + t in FP64 (FMA-free), and its map voxel key
-    bool have = in_tile && isfinite(a.x) && isfinite(a.y) && isfinite(a.z);
+  const uint32_t i = lo + uint32_t(tid);
+  if (i < hi) {
+    const float4 a = pA[i];
     double px = 0.0, py = 0.0, pz = 0.0;
-    int64_t kx = 0, ky = 0, kz = 0;   // within [-2^20, 2^20) once have holds
-    if (have) {
-      const double sx = a.x, sy = a.y, sz = a.z;
-      px = ((R[0] * sx + R[1] * sy) + R[2] * sz) + tx;
-      py = ((R[3] * sx + R[4] * sy) + R[5] * sz) + ty;
-      pz = ((R[6] * sx + R[7] * sy) + R[8] * sz) + tz;
-      have = voxel_index_fast(px, m.v, prm.inv_v, prm.v_pow2, &kx) &&
-             voxel_index_fast(py, m.v, prm.inv_v, prm.v_pow2, &ky) &&
-             voxel_index_fast(pz, m.v, prm.inv_v, prm.v_pow2, &kz);
+    int32_t res = -1;
+    if constexpr (kSearch) {
+      int64_t kx = 0, ky = 0, kz = 0;
+      if (locate(a, P, m, prm, px, py, pz, kx, ky, kz)) {
+        TopK<1> top;
+        top.init();
+        if constexpr (kFine)
+          knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
+                       [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
+                         return fine_find(m, a0, a1, a2, n);
+                       },
+                       top);
+        else
+          nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, false, -1,
+                      0, top);
+        res = top.pos[0];
+      }
+      if (!kFine && prev) prev[i] = res;
+    } else {
+      res = match[i];
     }
-    TopK<1> top;
-    top.init();
-    if (have) {
-      if constexpr (kFine)
-        knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
-                     [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
-                       return fine_find(m, a0, a1, a2, n);
-                     },
-                     top);
-      else
-        nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
-                    prev ? prev[i] : -1, top);
-    }
-    if (!kFine && prev && in_tile) prev[i] = have ? top.pos[0] : -1;
-    int32_t match = -1;
+    int32_t id_match = -1;
     Real gs[3] = {Real(0), Real(0), Real(0)};
-    if (have && top.pos[0] >= 0) {
-      const int32_t id = top.id[0];
-      const float4 r = kFine ? m.fine_pts[top.pos[0]] : m.vox_pts[top.pos[0]];
-      // the source covariance is read only now: not holding it through the
-      // search keeps the register count (and so the occupancy) down
+    if (res >= 0) {
+      if constexpr (!kSearch) {
+        int64_t kx, ky, kz;
+        (void)locate(a, P, m, prm, px, py, pz, kx, ky, kz);   // held when the match was made
+      }
+      const float4 r = kFine ? m.fine_pts[res] : m.vox_pts[res];
+      const int32_t id = __float_as_int(r.w);
       const float4 sB = pB[i];
       const float2 sC = pC[i];
       const float4 ca = m.cov[2 * int64_t(id)];
@@ -573,22 +831,15 @@ void k_linearize(
       // without the sparsity-aware case a pair lacking either covariance is
       // dropped like an outlier
       if (!kNoSA || (sB.x >= 0.0f && cb.z != 0.0f)) {
-        match = id;
+        id_match = id;
         if constexpr (kGrad)
-          grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, R, prm.kappa2, acc, gs);
+          grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, P.R, prm.kappa2, acc, gs);
         else
-          gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, R, cx, cy, cz, prm.kappa2, acc);
+          gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, P.R, cx, cy, cz, prm.kappa2, acc);
       }
     }
-    if (corr && in_tile) {
-      // the original index is loaded again rather than kept across the
-      // search (it would be spilled there); the empty asm hides that the
-      // address is the one read before, so the load is not merged with it
-      uint32_t ia = i;
-      if constexpr (!kGrad) asm volatile("" : "+v"(ia));
-      corr[__float_as_uint(kGrad ? a.w : pA[ia].w)] = match;
-    }
-    if (kGrad && grad_src && in_tile) {
+    if (corr) corr[__float_as_uint(a.w)] = id_match;
+    if (kGrad && grad_src) {
       const uint32_t o = __float_as_uint(a.w);
       grad_src[o] = float(gs[0]);
       grad_src[n_src + o] = float(gs[1]);
@@ -865,7 +1116,15 @@ struct AlignWS {
   float4* pA = nullptr;
   float4* pB = nullptr;
   float2* pC = nullptr;
-  int32_t* prev = nullptr;      // per packed point: previous correspondence (vox_pts position)
+  int32_t* prev = nullptr;      // per packed point: seed of the next search (vox_pts slot)
+  // the three linearisation passes: per packed point its match, and the
+  // search queue (kBins bins of q_bin_cap entries, SoA FP64 positions)
+  int32_t* match = nullptr;
+  uint32_t* q_idx = nullptr;
+  int32_t* q_cand = nullptr;
+  double* q_p = nullptr;
+  uint32_t* q_count = nullptr;
+  int64_t q_bin_cap = 0;
   uint64_t* okeys = nullptr;
   uint64_t* okeys_alt = nullptr;
   uint32_t* ovals = nullptr;
@@ -888,7 +1147,7 @@ void free_ws(AlignWS* w) {
   if (w->exec) (void)hipGraphExecDestroy(w->exec);
   void* ptrs[] = {w->tile_scan, w->tile_lo, w->tile_hi, w->begin, w->bad, w->done, w->ctr,
                   w->partial, w->offsets, w->T, w->cfix, w->stats, w->gsum, w->pA, w->pB, w->pC,
-                  w->prev,
+                  w->prev, w->match, w->q_idx, w->q_cand, w->q_p, w->q_count,
                   w->okeys, w->okeys_alt, w->ovals, w->ovals_alt, w->arena};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -937,6 +1196,15 @@ far_status_t ensure_ws(far_map_s* m, int32_t S, int64_t max_tiles, int64_t n, Al
   FAR_HIP(hipMalloc(&w->pB, nc * sizeof(float4)));
   FAR_HIP(hipMalloc(&w->pC, nc * sizeof(float2)));
   FAR_HIP(hipMalloc(&w->prev, nc * sizeof(int32_t)));
+  FAR_HIP(hipMalloc(&w->match, nc * sizeof(int32_t)));
+  // a bin holds the queues of its tiles (every kBins-th): at most
+  // ceil(max_tiles / kBins) tiles of at most kTileMax points
+  w->q_bin_cap = ((w->max_tiles + kBins - 1) / kBins) * kTileMax;
+  const size_t qc = size_t(kBins) * size_t(w->q_bin_cap);
+  FAR_HIP(hipMalloc(&w->q_idx, qc * sizeof(uint32_t)));
+  FAR_HIP(hipMalloc(&w->q_cand, qc * sizeof(int32_t)));
+  FAR_HIP(hipMalloc(&w->q_p, 3 * qc * sizeof(double)));
+  FAR_HIP(hipMalloc(&w->q_count, kBins * sizeof(uint32_t)));
   FAR_HIP(hipMalloc(&w->okeys, nc * sizeof(uint64_t)));
   FAR_HIP(hipMalloc(&w->okeys_alt, nc * sizeof(uint64_t)));
   FAR_HIP(hipMalloc(&w->ovals, nc * sizeof(uint32_t)));
@@ -971,32 +1239,64 @@ struct Job {
   int32_t tile = kTileDefault; // points per tile (the map's schedule)
 };
 
-// Launch of the linearisation (or gradient) kernel at the map's tile size.
+// One linearisation (or gradient) at the map's tile size: the term pass
+// with its own exact search when there are no seeds (first), else the
+// certified search, the exact search of the queue and the term pass.
 template <class Real, bool kGrad>
 far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapView& mv,
-                        const AlignWS* w, int64_t max_tiles, const Job& j) {
+                        const AlignWS* w, int64_t max_tiles, const Job& j, bool first) {
   // the fine-cell search only where the index exists for the current map
   const bool fine = j.prm.fine_nn && mv.fine_ok;
-  switch (tile * 4 + (fine ? 2 : 0) + (j.prm.sa_off ? 1 : 0)) {
-#define FAR_LIN_CASE(B, F, N)                                                             \
-  case B * 4 + F * 2 + N:                                                                 \
-    k_linearize<Real, kGrad, B, F, N><<<unsigned(grid), B, 0, st>>>(                     \
+  int32_t* prev = kGrad ? nullptr : w->prev;
+  const bool search = first || fine || !prev;
+  if (!search) {
+    Queue Q{w->q_idx, w->q_cand, w->q_p, w->q_count, w->q_bin_cap, kBins * w->q_bin_cap};
+    k_zero_bins<<<1, 64, 0, st>>>(w->q_count);
+    FAR_HIP(hipGetLastError());
+    switch (tile) {
+      case 128:
+        k_cert<128><<<unsigned(grid), 128, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,
+                                                    w->tile_hi, max_tiles, j.T, w->done, j.prm,
+                                                    w->match, prev, Q);
+        break;
+      case 256:
+        k_cert<256><<<unsigned(grid), 256, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,
+                                                    w->tile_hi, max_tiles, j.T, w->done, j.prm,
+                                                    w->match, prev, Q);
+        break;
+      case 512:
+        k_cert<512><<<unsigned(grid), 512, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,
+                                                    w->tile_hi, max_tiles, j.T, w->done, j.prm,
+                                                    w->match, prev, Q);
+        break;
+      default:
+        set_error("internal: unsupported tile size %d", tile);
+        return FAR_E_INVALID;
+    }
+    FAR_HIP(hipGetLastError());
+    k_search<<<unsigned(8 * device_cu_count()), kSearchThreads, 0, st>>>(mv, Q, j.prm,
+                                                                         w->match, prev);
+    FAR_HIP(hipGetLastError());
+  }
+  switch (tile * 8 + (fine ? 4 : 0) + (j.prm.sa_off ? 2 : 0) + (search ? 1 : 0)) {
+#define FAR_LIN_CASE(B, F, N, X)                                                          \
+  case B * 8 + F * 4 + N * 2 + X:                                                         \
+    k_linearize<Real, kGrad, B, F, N, X><<<unsigned(grid), B, 0, st>>>(                  \
         mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
         w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
-        j.n_total, kGrad ? nullptr : w->prev);                                            \
+        j.n_total, w->match, prev);                                                       \
     break;
-    FAR_LIN_CASE(128, 0, 0)
-    FAR_LIN_CASE(128, 0, 1)
-    FAR_LIN_CASE(128, 1, 0)
-    FAR_LIN_CASE(128, 1, 1)
-    FAR_LIN_CASE(256, 0, 0)
-    FAR_LIN_CASE(256, 0, 1)
-    FAR_LIN_CASE(256, 1, 0)
-    FAR_LIN_CASE(256, 1, 1)
-    FAR_LIN_CASE(512, 0, 0)
-    FAR_LIN_CASE(512, 0, 1)
-    FAR_LIN_CASE(512, 1, 0)
-    FAR_LIN_CASE(512, 1, 1)
+#define FAR_LIN_CASES(B)        \
+    FAR_LIN_CASE(B, 0, 0, 0)    \
+    FAR_LIN_CASE(B, 0, 0, 1)    \
+    FAR_LIN_CASE(B, 0, 1, 0)    \
+    FAR_LIN_CASE(B, 0, 1, 1)    \
+    FAR_LIN_CASE(B, 1, 0, 1)    \
+    FAR_LIN_CASE(B, 1, 1, 1)
+    FAR_LIN_CASES(128)
+    FAR_LIN_CASES(256)
+    FAR_LIN_CASES(512)
+#undef FAR_LIN_CASES
 #undef FAR_LIN_CASE
     default:
       set_error("internal: unsupported tile size %d", tile);
@@ -1041,9 +1341,9 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
   const int64_t grid = ((max_tiles + 7) / 8) * 8;   // one block per tile
   if (j.gsum) {
     if (j.precision == FAR_PREC_FP64)
-      FAR_TRY((launch_lin<double, true>(j.tile, grid, st, mv, w, max_tiles, j)));
+      FAR_TRY((launch_lin<double, true>(j.tile, grid, st, mv, w, max_tiles, j, true)));
     else
-      FAR_TRY((launch_lin<float, true>(j.tile, grid, st, mv, w, max_tiles, j)));
+      FAR_TRY((launch_lin<float, true>(j.tile, grid, st, mv, w, max_tiles, j, true)));
     k_reduce_grad<<<unsigned(j.S), 256, 0, st>>>(w->begin, w->partial, j.gsum, j.T, j.g_c,
                                                   j.g_T, j.g_tw, j.g_cost, j.g_n);
     FAR_HIP(hipGetLastError());
@@ -1054,9 +1354,9 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
     {
       TimedScope ts(FAR_TIME_LINEARIZE, st);
       if (j.precision == FAR_PREC_FP64)
-        FAR_TRY((launch_lin<double, false>(j.tile, grid, st, mv, w, max_tiles, j)));
+        FAR_TRY((launch_lin<double, false>(j.tile, grid, st, mv, w, max_tiles, j, it == 0)));
       else
-        FAR_TRY((launch_lin<float, false>(j.tile, grid, st, mv, w, max_tiles, j)));
+        FAR_TRY((launch_lin<float, false>(j.tile, grid, st, mv, w, max_tiles, j, it == 0)));
     }
     k_reduce_solve<<<unsigned(j.S), 256, 0, st>>>(j.S, w->begin, w->partial, j.T, w->ctr,
                                                   w->done, j.stats, j.prm, j.c_fixed ? 0 : 1);

@@ -94,6 +94,22 @@ struct alignas(16) Slot {
                   // 16-byte probe yields key, voxel and count; scan grid: scan id
 };
 
+// Nearest-neighbour certificate of a map point, stored per slot of vox_pts
+// (voxel-major, so the certificates a search reads lie next to the points it
+// reads): the vox_pts slots of the point's kCertK nearest other map points
+// within v (-1 past the last) and rho, at most half the distance from the
+// point to every map point not in that list (v/2 when fewer than kCertK + 1
+// others lie within v), rounded down.  A query x whose distance to the
+// point q is below rho is farther than that from every unlisted point
+// (triangle inequality: |x - q''| >= |q - q''| - |x - q| >= 2 rho - |x - q|
+// > |x - q|), so q is x's nearest map point once it also ranks before every
+// listed point.
+constexpr int kCertK = 7;
+struct alignas(32) CertRow {
+  float rho;
+  int32_t nbr[kCertK];
+};
+
 // Device view of a map, passed by value to kernels.
 struct MapView {
   const Slot* slots;
@@ -102,6 +118,7 @@ struct MapView {
   const float4* cov;            // [point_cap * 2]: (xx,xy,xz,yy), (yz,zz,valid,0)
   const uint32_t* vox_nbr;      // [voxel_cap * 26]: neighbour voxel << 7 | its count
   const float* pt_xyz;          // [3][point_cap]
+  const CertRow* cert;          // [voxel_cap * nmax], by vox_pts slot
   int64_t point_cap;
   double v;
   int32_t nmax;
@@ -320,6 +337,11 @@ struct far_map_s {
   float* pt_xyz = nullptr;
   int32_t* pt_loc = nullptr;
   int32_t* vox_slot = nullptr;
+  // nearest-neighbour certificates (by vox_pts slot) and the per-voxel marks
+  // of the voxels whose points' certificates an insert recomputes
+  far::CertRow* cert = nullptr;
+  uint32_t* cert_mark = nullptr;
+  uint32_t cert_gen = 0;
   // fine search index, rebuilt lazily after the map changes
   float4* fine_pts = nullptr;
   far::Slot* fine_slots = nullptr;
@@ -339,6 +361,7 @@ struct far_map_s {
     m.cov = cov;
     m.vox_nbr = vox_nbr;
     m.pt_xyz = pt_xyz;
+    m.cert = cert;
     m.point_cap = p.point_capacity;
     m.v = p.voxel_size;
     m.nmax = p.max_pts_per_voxel;

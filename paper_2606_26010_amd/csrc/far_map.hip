@@ -275,13 +275,14 @@ __global__ __launch_bounds__(kT) void k_counts(int64_t n_seg, const int32_t* seg
                                                const uint32_t* acc_flag,
                                                const uint32_t* id_local, int64_t n_commit,
                                                int32_t* vox_count, const int32_t* vox_slot,
-                                               Slot* slots) {
+                                               Slot* slots, uint32_t* seg_changed) {
   int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (s >= n_seg) return;
   int32_t vox = seg_vox[s];
   int32_t c = seg_newcount[s];
+  const int32_t old = vox_count[vox];
   if (truncated) {
-    c = vox_count[vox];
+    c = old;
     for (uint32_t j = seg_start[s]; j < seg_end[s]; ++j) {
       uint32_t i = vals[j];
       if (acc_flag[i] && int64_t(id_local[i]) < n_commit) ++c;
@@ -289,6 +290,58 @@ __global__ __launch_bounds__(kT) void k_counts(int64_t n_seg, const int32_t* seg
   }
   vox_count[vox] = c;
   slots[vox_slot[vox]].aux = c;
+  seg_changed[s] = c != old ? 1u : 0u;
+}
+
+// ---------------------------------------------------------------- certificates
+// Certificates an insert invalidates: those of the points within v of an
+// added point, all of which lie in the 27 voxels around the added point's
+// voxel.  Every voxel run that gained points marks itself and its existing
+// neighbours with this insert's generation (plain stores of one value).
+__global__ __launch_bounds__(kT) void k_cert_mark(int64_t n_seg, const int32_t* seg_vox,
+                                                  const uint32_t* seg_changed,
+                                                  const uint32_t* vox_nbr, uint32_t* mark,
+                                                  uint32_t gen) {
+  const int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg || !seg_changed[s]) return;
+  const int32_t V = seg_vox[s];
+  mark[V] = gen;
+  for (int d = 0; d < 26; ++d) {
+    const uint32_t e = vox_nbr[int64_t(V) * 26 + d];
+    if (e != kNbrNone) mark[e >> kNbrCountBits] = gen;
+  }
+}
+
+// Certificate of every point of the marked voxels (all voxels when mark is
+// null), one lane per voxel slot: the kCertK + 1 nearest other points
+// within v by (d2, id) from the exact 27-voxel search (the point itself,
+// and so kCertK + 2 entries, included), the first kCertK listed, rho half
+// the distance of the next one (v/2 when there is none), shrunk by 2^-20
+// and rounded down to float so that it never exceeds the exact half distance.
+__global__ __launch_bounds__(kT) void k_cert_build(MapView m, int64_t n_vox,
+                                                   const uint32_t* mark, uint32_t gen,
+                                                   CertRow* cert) {
+  const int64_t pos = int64_t(blockIdx.x) * kT + threadIdx.x;
+  const int64_t V = pos / m.nmax;
+  if (V >= n_vox) return;
+  if (mark && mark[V] != gen) return;
+  if (pos - V * m.nmax >= m.vox_count[V]) return;
+  const float4 p = m.vox_pts[pos];
+  TopK<kCertK + 2> top;
+  map_knn_query<kCertK + 2>(m, double(p.x), double(p.y), double(p.z), m.v * m.v, top);
+  CertRow r;
+  int n = 0;
+  double next = -1.0;
+#pragma unroll
+  for (int t = 0; t < kCertK + 2; ++t) {
+    if (top.pos[t] < 0 || top.pos[t] == int32_t(pos)) continue;
+    if (n < kCertK) r.nbr[n++] = top.pos[t];
+    else if (next < 0.0) next = top.d[t];
+  }
+  for (int t = n; t < kCertK; ++t) r.nbr[t] = -1;
+  const double half = 0.5 * (next >= 0.0 ? sqrt(next) : m.v) * (1.0 - 0x1p-20);
+  r.rho = __double2float_rd(half);
+  cert[pos] = r;
 }
 
 // Neighbour table upkeep after an insert, one thread per touched voxel run:
@@ -1174,6 +1227,8 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   size_t b_xyz = size_t(p.point_capacity) * 3 * sizeof(float);
   size_t b_loc = size_t(p.point_capacity) * sizeof(int32_t);
   size_t b_vslot = size_t(m->voxel_cap) * sizeof(int32_t);
+  size_t b_cert = size_t(m->voxel_cap) * p.max_pts_per_voxel * sizeof(CertRow);
+  size_t b_mark = size_t(m->voxel_cap) * sizeof(uint32_t);
   m->fine_log2 = ceil_log2(2 * p.point_capacity);
   if (m->fine_log2 < 10) m->fine_log2 = 10;
   m->fine_nslots = int64_t(1) << m->fine_log2;
@@ -1188,12 +1243,15 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->pt_xyz, b_xyz)) != hipSuccess) return fail(e, "hipMalloc xyz");
   if ((e = hipMalloc(&m->pt_loc, b_loc)) != hipSuccess) return fail(e, "hipMalloc loc");
   if ((e = hipMalloc(&m->vox_slot, b_vslot)) != hipSuccess) return fail(e, "hipMalloc vslot");
+  if ((e = hipMalloc(&m->cert, b_cert)) != hipSuccess) return fail(e, "hipMalloc cert");
+  if ((e = hipMalloc(&m->cert_mark, b_mark)) != hipSuccess) return fail(e, "hipMalloc mark");
   if ((e = hipMalloc(&m->fine_pts, b_fpts)) != hipSuccess) return fail(e, "hipMalloc fine");
   if ((e = hipMalloc(&m->fine_slots, b_fslots)) != hipSuccess) return fail(e, "hipMalloc fine");
-  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_nbr + b_xyz + b_loc + b_vslot + b_fpts +
-                     b_fslots);
+  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_nbr + b_xyz + b_loc + b_vslot +
+                     b_cert + b_mark + b_fpts + b_fslots);
   if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipMemsetAsync(m->vox_count, 0, b_cnt, st)) != hipSuccess) return fail(e, "memset");
+  if ((e = hipMemsetAsync(m->cert_mark, 0, b_mark, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "sync");
   *out = m;
   return FAR_OK;
@@ -1205,7 +1263,7 @@ far_status_t far_map_destroy(far_map_t m) {
   free_ws(m->ws);
   m->ws = nullptr;
   void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->vox_nbr, m->pt_xyz,
-                  m->pt_loc, m->vox_slot, m->fine_pts, m->fine_slots};
+                  m->pt_loc, m->vox_slot, m->cert, m->cert_mark, m->fine_pts, m->fine_slots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -1280,14 +1338,30 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
                                          m->p.point_capacity, m->vox_pts, m->pt_xyz,
                                          m->pt_loc);
   FAR_HIP(hipGetLastError());
+  uint32_t* seg_changed;
+  FAR_TRY(scr.get(&seg_changed, size_t(n_seg)));
   k_counts<<<blocks_for(n_seg), kT, 0, st>>>(n_seg, seg_vox, seg_newcount, truncated, r.vals,
                                              r.seg_start, r.seg_end, acc_flag, id_local,
                                              n_commit, m->vox_count, m->vox_slot,
-                                             m->slots_d);
+                                             m->slots_d, seg_changed);
   FAR_HIP(hipGetLastError());
   k_nbr_update<<<blocks_for(n_seg), kT, 0, st>>>(m->view(), n_seg, seg_vox, is_new, m->vox_key,
                                                  m->vox_count, m->vox_nbr);
   FAR_HIP(hipGetLastError());
+  // certificates of the points within v of an added point
+  if (++m->cert_gen == 0) {
+    FAR_HIP(hipMemsetAsync(m->cert_mark, 0, size_t(m->voxel_cap) * sizeof(uint32_t), st));
+    m->cert_gen = 1;
+  }
+  k_cert_mark<<<blocks_for(n_seg), kT, 0, st>>>(n_seg, seg_vox, seg_changed, m->vox_nbr,
+                                                m->cert_mark, m->cert_gen);
+  FAR_HIP(hipGetLastError());
+  {
+    const int64_t nv = m->n_voxels + n_new;
+    k_cert_build<<<blocks_for(nv * m->p.max_pts_per_voxel), kT, 0, st>>>(
+        m->view(), nv, m->cert_mark, m->cert_gen, m->cert);
+    FAR_HIP(hipGetLastError());
+  }
   FAR_TRY(map_covariances(m->view(), m->cov, m->n_points, m->n_points + n_commit,
                           m->p.k_cov, st));
   m->n_points += n_commit;
@@ -1811,6 +1885,10 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   FAR_HIP(hipGetLastError());
   k_nbr_update<<<blocks_for(n_seg), kT, 0, st>>>(m->view(), n_seg, seg_vox, is_new, m->vox_key,
                                                  m->vox_count, m->vox_nbr);
+  FAR_HIP(hipGetLastError());
+  // every slot changed: all certificates again
+  k_cert_build<<<blocks_for(n_seg * m->p.max_pts_per_voxel), kT, 0, st>>>(
+      m->view(), n_seg, nullptr, 0, m->cert);
   FAR_HIP(hipGetLastError());
   m->n_points = n_keep;
   m->n_voxels = n_seg;

@@ -16,9 +16,14 @@ One step = the whole per-batch hot path with inputs resident in HBM:
 
 value = linearize+kNN points/s = sum over scans of (GN iterations x points)
 divided by the step time.  Also reported: scans/s, the one-scan-per-launch
-path, the roofline of the dominant kernel (HIP-event timed inside the
-library), pose error against the oracle and ground truth, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+path, the roofline of the linearisation (HIP-event timed inside the library:
+the certified search, the exact search of its queue and the term pass of one
+GN iteration) against the 8 TB/s HBM peak and a copy bandwidth measured
+here, with the counter-derived traffic, L2 hit rate and VALU and LDS issue
+fractions of the committed profile when it matches the kernel sources; the
+covariance call on its own; the same batch run to convergence; pose error
+against the oracle and ground truth; and the FP64 CPU oracle timed on a
+bounded sample of the same workload at all host threads and at one.
 """
 import argparse
 import hashlib
@@ -33,9 +38,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CLOCK_GHZ = 2.4           # MI355X peak engine clock
+N_SIMD = 1024             # 256 CUs x 4 SIMDs
+LDS_BYTES_PER_CLK_CU = 128
 KERNEL_SOURCES = ["paper_2606_26010_amd/csrc/far_gicp.hip", "paper_2606_26010_amd/csrc/far_knn.h",
                   "paper_2606_26010_amd/csrc/far_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_linearize_batch64_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "linearize_batch64_counters.txt")
 
 
 def log(*a):
@@ -75,22 +83,57 @@ def touched_voxels(map_keys_counts, scan_xyz, T, v):
     return packed[hit], counts[idx[hit]]
 
 
-def read_traffic(fp, tile):
-    """HBM bytes per linearisation launch from the committed rocprofv3 --pmc
+def read_counters(fp, tile):
+    """Per-linearisation counter totals from the committed rocprofv3 --pmc
     summary, if it was taken on the current kernel sources at this tile."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(COUNTERS_FILE):
         return None
-    kv = {}
-    for line in open(TRAFFIC_FILE):
+    # one section per tile, each starting with its kernel_sources_sha256_16 line
+    sections, kv = [], None
+    for line in open(COUNTERS_FILE):
         if "=" in line and not line.startswith("#"):
-            a, b = line.split("=", 1)
-            kv[a.strip()] = b.strip()
-    if kv.get("kernel_sources_sha256_16") != fp or kv.get("tile") != str(tile):
-        return None
+            a, b = (x.strip() for x in line.split("=", 1))
+            if a == "kernel_sources_sha256_16":
+                kv = {}
+                sections.append(kv)
+            if kv is not None:
+                kv[a] = b
+    for kv in sections:
+        if kv.get("kernel_sources_sha256_16") == fp and kv.get("tile") == str(tile):
+            try:
+                return {k: float(v) for k, v in kv.items()
+                        if k not in ("kernel_sources_sha256_16", "tile", "kernels")}
+            except ValueError:
+                return None
+    return None
+
+
+def copy_gbps(torch, dev, stream, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes per second) of a
+    1 GiB buffer on the benchmark stream, from HIP events."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def cpu_model():
     try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def lib_ms(far, kinds, fn, reps):
@@ -239,9 +282,15 @@ def main():
                     help="stop when |delta| <= eps (the paper's 5e-3; 0: always run --iters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the one-scan-per-launch path")
-    ap.add_argument("--cpu-sample-scans", type=int, default=2)
+    ap.add_argument("--cpu-sample-scans", type=int, default=3)
+    ap.add_argument("--no-converged", action="store_true",
+                    help="skip the secondary run of the same batch to convergence")
+    ap.add_argument("--conv-iters", type=int, default=40)
+    ap.add_argument("--conv-eps", type=float, default=1e-6)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default schedules instead of autotuning them on the batch")
+    ap.add_argument("--tile", type=int, choices=(128, 256, 512), default=0,
+                    help="linearisation tile (skips its autotuning; 0: autotuned)")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the timings of undistortion, gradient, ASMD caps and eviction")
     ap.add_argument("--copy-calib", action="store_true",
@@ -322,17 +371,23 @@ def main():
             thr, thr_ms = far.far_autotune_covariances(src, offs, case.voxel_size, case.k, reps=2)
             cov, val = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
                                                       out=(cov_buf, val_buf))
-            best, lin_ms_c = far.far_autotune(gm.h, src, offs, cov, val, T0, prm, reps=2)
-            stream.synchronize()
-            schedule = {"tile": best["tile"], "fine_cells": best["fine_cells"],
-                        "cov_dense_threshold": thr, "autotuned": True,
-                        "align_ms_by_candidate": {f"tile{t}_{'fine' if f else 'voxel'}":
-                                                  round(lin_ms_c[2 * i + f], 3)
-                                                  for i, t in enumerate((128, 256, 512))
-                                                  for f in (0, 1)},
+            schedule = {"tile": 256, "fine_cells": 0, "cov_dense_threshold": thr,
+                        "autotuned": True,
                         "cov_ms_by_threshold": {str(t): round(x, 3) for t, x in
                                                 zip((0, 16, 32, 64, 128), thr_ms)}}
+            if not args.tile:
+                best, lin_ms_c = far.far_autotune(gm.h, src, offs, cov, val, T0, prm, reps=2)
+                schedule.update({"tile": best["tile"], "fine_cells": best["fine_cells"],
+                                 "align_ms_by_candidate": {
+                                     f"tile{t}_{'fine' if f else 'voxel'}":
+                                     round(lin_ms_c[2 * i + f], 3)
+                                     for i, t in enumerate((128, 256, 512)) for f in (0, 1)}})
+            stream.synchronize()
             log(f"[bench] autotune {time.time() - t_at:.1f}s: {schedule}")
+        if args.tile:
+            far.far_map_set_schedule(gm.h, args.tile, 0)
+            schedule["tile"], schedule["fine_cells"] = args.tile, 0
+            schedule["tile_forced"] = True
         tile = schedule["tile"]
 
         def step():
@@ -361,22 +416,27 @@ def main():
         log(f"[bench] step {t_step * 1e3:.3f} ms, iterations {iters.min()}..{iters.max()}, "
             f"status {np.bincount(stats['status'], minlength=6).tolist()}")
 
-        # ---------------- roofline of the dominant kernel (event-timed launches)
+        # ---------------- roofline of the linearisation (event-timed launches)
         far.far_timing_read(reset=True)
+        far.far_timing_read_kind(far.FAR_TIME_COVARIANCES, reset=True)
         far.far_timing_enable(True)
         n_timed = max(1, min(args.steps, 5))
         for _ in range(n_timed):
             step()
         stream.synchronize()
         lin_ms, lin_launches = far.far_timing_read(reset=True)
+        cov_ms_tot, cov_calls = far.far_timing_read_kind(far.FAR_TIME_COVARIANCES, reset=True)
         far.far_timing_enable(False)
         stats_t = far.decode_stats(stats_buf)
         T_fin = T.cpu().numpy().reshape(S, 4, 4)
-        # algorithmic bytes: every launch reads each active source point
-        # (xyz 12 B, cov6 24 B, valid 1 B), the matched map covariance record of
-        # each inlier (32 B), and once the slot (16 B), count (4 B) and points
-        # (16 B each) of every distinct map voxel its active points touch, and
-        # writes 29 FP64 partials per tile.
+        # Algorithmic bytes of one linearisation (the byte model of the method,
+        # per GN iteration and scan): every active source point's xyz, cov6 and
+        # valid (37 B); each inlier's matched map covariance, valid flag and id
+        # (29 B); per distinct map voxel in the 27-neighbourhoods of the scan's
+        # points, its slot and count (16 B) and its points (12 B each); the
+        # scan's 29 FP64 sums (232 B).  Voxels are counted per scan (each scan
+        # must read its own neighbourhood); the union over the active scans
+        # (a voxel read once per launch) is reported beside it.
         mx, _, _ = gm.export()
         mk = np.floor(mx.cpu().numpy().astype(np.float64) / case.voxel_size).astype(np.int64)
         mp = ((mk[0] + (1 << 20)) << 42) | ((mk[1] + (1 << 20)) << 21) | (mk[2] + (1 << 20))
@@ -386,24 +446,51 @@ def main():
         it_t = stats_t["iters"].astype(np.int64) + (stats_t["status"] != 0)
         n_inl = stats_t["n_inliers"].astype(np.int64)
         launches_per_step = args.iters
-        bytes_step = 0.0
+        bytes_step = bytes_union_step = 0.0
         for it in range(launches_per_step):
             active = np.nonzero(it_t > it)[0]
             if active.size == 0:
                 continue
+            per = sum(16.0 * per_scan_vox[s][0].size + 12.0 * per_scan_vox[s][1].sum()
+                      for s in active)
+            bytes_step += 37.0 * sizes[active].sum() + 29.0 * n_inl[active].sum() + per + \
+                232.0 * active.size
             vk = np.concatenate([per_scan_vox[s][0] for s in active])
             vc = np.concatenate([per_scan_vox[s][1] for s in active])
             uk, ui = np.unique(vk, return_index=True)
-            tiles = int(np.sum((sizes[active] + tile - 1) // tile))
-            bytes_step += (37.0 * sizes[active].sum() + 32.0 * n_inl[active].sum()
-                           + 20.0 * uk.size + 16.0 * vc[ui].sum() + 29 * 8.0 * tiles)
+            bytes_union_step += (37.0 * sizes[active].sum() + 29.0 * n_inl[active].sum()
+                                 + 16.0 * uk.size + 12.0 * vc[ui].sum() + 232.0 * active.size)
         bytes_per_launch = bytes_step / launches_per_step
+        bytes_union_per_launch = bytes_union_step / launches_per_step
         avg_launch_ms = lin_ms / max(lin_launches, 1)
         achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
         fp = kernel_fingerprint()
-        traffic = read_traffic(fp, tile)
-        log(f"[bench] linearize: {lin_launches} launches, avg {avg_launch_ms * 1e3:.1f} us, "
-            f"{bytes_per_launch / 1e6:.1f} MB algorithmic per launch, {achieved:.0f} GB/s")
+        ctr = read_counters(fp, tile)
+        copy_bw = copy_gbps(torch, dev, stream)
+        t_s = avg_launch_ms * 1e-3
+        roof_extra = {"copy_gbps": round(copy_bw, 1),
+                      "frac_of_copy": round(achieved / copy_bw, 5),
+                      "traffic": None, "l2_hit": None, "valu_frac": None, "lds_frac": None}
+        if ctr is not None:
+            roof_extra["traffic"] = ctr["fabric_read_bytes"] + ctr["fabric_write_bytes"]
+            roof_extra["l2_hit"] = round(ctr["tcc_hit"] / max(ctr["tcc_hit"] + ctr["tcc_miss"], 1), 4)
+            roof_extra["valu_frac"] = round(4.0 * ctr["valu_insts"] / (N_SIMD * CLOCK_GHZ * 1e9 * t_s), 4)
+            roof_extra["lds_frac"] = round(ctr["lds_insts"] * 64 * 4 /
+                                           (LDS_BYTES_PER_CLK_CU * 256 * CLOCK_GHZ * 1e9 * t_s), 4)
+        log(f"[bench] linearisation: {lin_launches} launches, avg {avg_launch_ms * 1e3:.1f} us, "
+            f"{bytes_per_launch / 1e6:.1f} MB algorithmic per launch "
+            f"({bytes_union_per_launch / 1e6:.1f} MB with voxels counted once), "
+            f"{achieved:.0f} GB/s, copy {copy_bw:.0f} GB/s, counters "
+            f"{'matched' if ctr else 'not matched'}")
+        # the covariance call on its own: n (12 + 8 + 4 + 24 + 1) per point plus,
+        # per occupied (scan, voxel) run, its slot (16 B) and its points (12 B each)
+        cov_ms = cov_ms_tot / max(cov_calls, 1)
+        runs = sum(np.unique(np.floor(sc / case.voxel_size).astype(np.int64), axis=1).shape[1]
+                   for sc in case.scans)
+        cov_bytes = 49.0 * N + 16.0 * runs + 12.0 * N
+        cov_row = {"ms": round(cov_ms, 4), "points_per_s": round(N / (cov_ms * 1e-3), 1),
+                   "runs": int(runs), "roofline": hbm_roofline(cov_bytes, cov_ms)}
+        log(f"[bench] covariances: {cov_ms:.3f} ms per call, {runs} (scan, voxel) runs")
 
         # ---------------- one-scan-per-launch path (same work, per-scan calls)
         single = None
@@ -436,6 +523,46 @@ def main():
 
         gt_err = [pose_err(T_gpu[s], case.T_gt[s]) for s in range(S)]
 
+        # ---------------- the same batch run to convergence (secondary line)
+        conv = None
+        if not args.no_converged:
+            prm_c = far.align_params(case.tau, case.kappa, max_iters=args.conv_iters,
+                                     eps=args.conv_eps, recenter=1, precision=prec)
+
+            def step_c():
+                cv, vl = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
+                                                        out=(cov_buf, val_buf))
+                T.copy_(T0)
+                far.far_gicp_align_batch(gm.h, src, offs, cv, vl, T, prm_c, stats=stats_buf)
+
+            step_c()
+            stream.synchronize()
+            n_c = max(1, min(args.steps, 5))
+            t0 = time.perf_counter()
+            for _ in range(n_c):
+                step_c()
+            stream.synchronize()
+            t_c = (time.perf_counter() - t0) / n_c
+            st_c = far.decode_stats(stats_buf)
+            T_c = T.cpu().numpy().reshape(S, 4, 4)
+            it_c = st_c["iters"].astype(np.int64)
+            lins_c = int(np.sum((it_c + (st_c["status"] != 0)) * sizes))
+            e_c = [pose_err(T_c[s], case.T_gt[s]) for s in range(S)]
+            conv = {"iters_max": args.conv_iters, "eps": args.conv_eps,
+                    "ms_per_step": round(t_c * 1e3, 3), "scans_per_s": round(S / t_c, 2),
+                    "points_per_s": round(lins_c / t_c, 1),
+                    "iterations": {"min": int(it_c.min()), "median": float(np.median(it_c)),
+                                   "max": int(it_c.max()),
+                                   "converged": int(st_c["converged"].sum())},
+                    "pose_err_vs_gt": {"median_m": float(np.median([e[0] for e in e_c])),
+                                       "max_m": max(e[0] for e in e_c),
+                                       "median_deg": float(np.median([e[1] for e in e_c])),
+                                       "max_deg": max(e[1] for e in e_c),
+                                       "scans_over_0.1m": int(sum(e[0] > 0.1 for e in e_c)),
+                                       "scans_over_0.05m": int(sum(e[0] > 0.05 for e in e_c))}}
+            log(f"[bench] converged run: {t_c * 1e3:.2f} ms/step, iterations "
+                f"{it_c.min()}..{it_c.max()}, median GT error {conv['pose_err_vs_gt']['median_m']:.4f} m")
+
         rows = None
         if not args.no_rows:
             t_rows = time.time()
@@ -457,21 +584,31 @@ def main():
                     break
             log(f"[bench] oracle map built in {time.time() - t0:.1f}s ({om.size} points)")
             ns = min(args.cpu_sample_scans, S)
-            t0 = time.perf_counter()
-            o_lins, o_res = 0, []
-            for s in range(ns):
-                oc, ov = O.scan_covariances(case.scans[s], case.voxel_size, case.k)
-                r = om.align(case.scans[s], oc.astype(np.float32), ov, case.T0[s], case.tau,
-                             case.kappa, max_iters=args.iters, eps=args.eps)
-                o_res.append(r)
-                o_lins += (r["iters"] + (1 if r["status"] else 0)) * case.scans[s].shape[1]
-            t_cpu = time.perf_counter() - t0
-            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+            def oracle_sample():
+                t0 = time.perf_counter()
+                o_lins, o_res = 0, []
+                for s in range(ns):
+                    oc, ov = O.scan_covariances(case.scans[s], case.voxel_size, case.k)
+                    r = om.align(case.scans[s], oc.astype(np.float32), ov, case.T0[s], case.tau,
+                                 case.kappa, max_iters=args.iters, eps=args.eps)
+                    o_res.append(r)
+                    o_lins += (r["iters"] + (1 if r["status"] else 0)) * case.scans[s].shape[1]
+                return o_lins, time.perf_counter() - t0, o_res
+
+            threads = O.get_threads()
+            o_lins, t_cpu, o_res = oracle_sample()
+            O.set_threads(1)
+            o_lins1, t_cpu1, _ = oracle_sample()
+            O.set_threads(threads)
             cpu = {"value": round(o_lins / t_cpu, 1), "unit": "points/s", "cores": threads,
-                   "kind": "oracle",
+                   "kind": "oracle", "cpu_model": cpu_model(),
                    "sample": f"{ns} of {S} scans ({int(sizes[:ns].sum())} points): FP64 oracle "
                              f"scan covariances + align, {args.iters} GN iterations max, "
-                             f"{t_cpu:.1f} s"}
+                             f"{t_cpu:.2f} s at {threads} threads, {t_cpu1:.2f} s at 1",
+                   "one_core": {"value": round(o_lins1 / t_cpu1, 1), "cores": 1}}
+            log(f"[bench] oracle: {t_cpu:.2f} s at {threads} threads, {t_cpu1:.2f} s at 1 "
+                f"({cpu['cpu_model']})")
             oracle_err = [pose_err(T_gpu[s], o_res[s]["T"]) for s in range(ns)]
 
     result = {
@@ -498,10 +635,18 @@ def main():
         "point_linearizations_per_step": point_lins,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic, "kernel": "k_linearize<float>",
+                     "traffic": roof_extra["traffic"],
+                     "kernel": "linearisation",
                      "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                      "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                     "algorithmic_bytes_union_per_launch": round(bytes_union_per_launch),
+                     "copy_gbps": roof_extra["copy_gbps"],
+                     "frac_of_copy": roof_extra["frac_of_copy"],
+                     "l2_hit": roof_extra["l2_hit"], "valu_frac": roof_extra["valu_frac"],
+                     "lds_frac": roof_extra["lds_frac"],
                      "kernel_sources_sha256_16": fp},
+        "covariances": cov_row,
+        "converged": conv,
         "cpu_baseline": cpu,
         "single_scan_path": single,
         "pose_err_vs_gt": {"max_m": max(e[0] for e in gt_err),
@@ -518,8 +663,10 @@ def main():
                       "mean_probe": mstats["mean_probe"], "max_probe": mstats["max_probe"],
                       "load_factor": mstats["load_factor"]},
     }
-    result["roofline"]["kernel"] = (f"k_linearize<{'double' if prec == far.FAR_PREC_FP64 else 'float'}"
-                                    f", false, {tile}, false, false>")
+    result["roofline"]["kernel"] = (
+        f"linearisation at tile {tile}: k_zero_bins + k_cert<{tile}> + k_search + "
+        f"k_linearize<{'double' if prec == far.FAR_PREC_FP64 else 'float'}, false, {tile}, "
+        f"false, false, false> (the first iteration: k_linearize<..., true> with its own search)")
     print(json.dumps(result), flush=True)
     gm.close()
 

@@ -194,6 +194,27 @@ far_status_t far_gicp_linearize(far_map_t map, const float* src, const float* co
                                 int32_t precision, int32_t* corr, far_lin_t* out,
                                 far_stream_t stream);
 
+/* far_gicp_linearize with its result left on the device: out [dev, one
+ * far_lin_t] is written stream-ordered; no host synchronisation, so the call
+ * can be recorded in a graph (after far_map_reserve covers n, it allocates
+ * nothing).  n == 0 writes a zero result. */
+far_status_t far_gicp_linearize_async(far_map_t map, const float* src, const float* cov6,
+                                      const uint8_t* valid, int64_t n, const double T[16],
+                                      double tau, double kappa, const double c[3],
+                                      int32_t precision, int32_t* corr, far_lin_t* out,
+                                      far_stream_t stream);
+
+/* Reserves the map's registration workspace (packed source, tile tables,
+ * search queue, partial sums, sort buffers) for scans or batches of up to
+ * max_points points and max_scans scans (the paper preallocates its GPU
+ * memory, Sec. IV-B).  Linearize, align and gradient calls within these
+ * limits then allocate no workspace and never synchronise the device to grow
+ * it; larger calls grow it (device synchronisation, reallocation).  Owned by
+ * the map, freed by far_map_destroy.  Synchronises the device when the
+ * workspace grows. */
+far_status_t far_map_reserve(far_map_t map, int64_t max_points, int32_t max_scans,
+                             far_stream_t stream);
+
 /* Gradient of the GICP cost (Eq. 4 with the Cauchy rho of Eq. 5) at pose T
  * [host], with each point's correspondence (nearest map point within
  * min(tau, v), searched again here) and the source covariances held fixed;
@@ -525,7 +546,8 @@ typedef enum {
   FAR_TIME_GRADIENT = 3,         /* each far_gicp_gradient call              */
   FAR_TIME_ASMD = 4,             /* each far_asmd_caps call                  */
   FAR_TIME_EVICT = 5,            /* each far_map_evict call                  */
-  FAR_TIME_KINDS = 6
+  FAR_TIME_COVARIANCES = 6,      /* each far_scan_covariances(_batch) call   */
+  FAR_TIME_KINDS = 7
 } far_time_kind_t;
 
 far_status_t far_timing_enable(int32_t on);

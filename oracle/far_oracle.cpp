@@ -10,6 +10,7 @@
 // OpenMP is used only across independent queries; every sum is taken
 // sequentially in point order, so results do not depend on the thread count.
 
+#include <omp.h>
 #include "far_oracle.h"
 
 #include <algorithm>
@@ -1198,3 +1199,12 @@ void orc_undistort(const float* xyz, const float* t, int64_t n, const double* ts
 }
 
 }  // extern "C"
+
+// Threads of the OpenMP loops (timing of the oracle at a stated core count;
+// results do not depend on it).
+extern "C" int orc_set_threads(int n) {
+  if (n < 1) return 1;
+  omp_set_num_threads(n);
+  return 0;
+}
+extern "C" int orc_get_threads(void) { return omp_get_max_threads(); }

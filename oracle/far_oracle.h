@@ -180,6 +180,12 @@ void orc_fit_twist(const double* ts, const double* xi, int64_t m, double* tbar, 
 void orc_undistort(const float* xyz, const float* t, int64_t n, const double* ts,
                    const double* xi, int64_t m, float* out, double* t_ref);
 
+
+/* Threads of the OpenMP loops (n >= 1; returns 1 for n < 1), and the current
+ * maximum.  Only the timing depends on it. */
+int orc_set_threads(int n);
+int orc_get_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,8 +98,20 @@ def lib():
         L.orc_threshold_update.argtypes = [C.POINTER(_ThresholdState), _f64p, _f64p]
         L.orc_threshold_get.argtypes = [C.POINTER(_ThresholdState), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (timing only; results do not
+    depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def _soa(xyz):

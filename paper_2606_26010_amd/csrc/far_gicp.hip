@@ -450,9 +450,15 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
     for (int rank = 1; rank < 27; ++rank)
       if (fo.lb2(nbr_code(rank)) <= bnd) need |= 1u << rank;
   }
-  // neighbours of an existing voxel come from its row of the neighbour table
-  // (absent ones cost nothing); a point outside the map's voxels probes
+  // neighbours come from the neighbour-table row of the own voxel, or of its
+  // ghost when it is empty (absent ones cost nothing); an empty voxel that
+  // is not a ghost has no occupied neighbour, so nothing lies within v
   const uint32_t* row = own >= 0 ? m.vox_nbr + int64_t(own) * 26 : nullptr;
+  if (own < 0 && m.ghost_ok) {
+    const int32_t g = ghost_find(m, kx, ky, kz);
+    if (g < 0) return;
+    row = m.gnbr + int64_t(g) * 26;
+  }
   while (need) {
     const int rank = __builtin_ctz(need);
     need &= need - 1;
@@ -490,35 +496,42 @@ struct Cand {
 constexpr int kCertWalks = 2;
 
 __device__ inline bool certify(const MapView& m, const Query& q, Cand& c) {
+  static_assert(sizeof(CertRow) == 32 && kCertK == 7, "a row is two 16-byte loads");
   const int4* rows = reinterpret_cast<const int4*>(m.cert);   // 2 int4 per row
   for (int w = 0; w <= kCertWalks; ++w) {
     const int4 r0 = rows[2 * int64_t(c.pos)];
     const int4 r1 = rows[2 * int64_t(c.pos) + 1];
-    const int32_t nb[kCertK] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-    float4 lp[kCertK];
-#pragma unroll
-    for (int t = 0; t < kCertK; ++t)
-      if (nb[t] >= 0) lp[t] = m.vox_pts[nb[t]];
     Cand best = c;
     float bnd = screen_bound(c.d, q.m);
+    // the listed points in two groups of loads, to bound the registers
+    auto group = [&](const int32_t* nb, int cnt) {
+      float4 lp[4];
 #pragma unroll
-    for (int t = 0; t < kCertK; ++t)
-      if (nb[t] >= 0) {
-        const float dx = lp[t].x - q.fx, dy = lp[t].y - q.fy, dz = lp[t].z - q.fz;
-        const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-        if (d2f <= bnd) {
-          const double d = dist2(double(lp[t].x), double(lp[t].y), double(lp[t].z), q.x, q.y,
-                                 q.z);
-          const int32_t id = __float_as_int(lp[t].w);
-          if (rank_less(d, id, best.d, best.id)) {
-            best.d = d;
-            best.id = id;
-            best.pos = nb[t];
-            best.p = lp[t];
-            bnd = screen_bound(d, q.m);
+      for (int t = 0; t < 4; ++t)
+        if (t < cnt && nb[t] >= 0) lp[t] = m.vox_pts[nb[t]];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < cnt && nb[t] >= 0) {
+          const float dx = lp[t].x - q.fx, dy = lp[t].y - q.fy, dz = lp[t].z - q.fz;
+          const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+          if (d2f <= bnd) {
+            const double d = dist2(double(lp[t].x), double(lp[t].y), double(lp[t].z), q.x,
+                                   q.y, q.z);
+            const int32_t id = __float_as_int(lp[t].w);
+            if (rank_less(d, id, best.d, best.id)) {
+              best.d = d;
+              best.id = id;
+              best.pos = nb[t];
+              best.p = lp[t];
+              bnd = screen_bound(d, q.m);
+            }
           }
         }
-      }
+    };
+    const int32_t g0[4] = {r0.y, r0.z, r0.w, r1.x};
+    const int32_t g1[4] = {r1.y, r1.z, r1.w, -1};
+    group(g0, 4);
+    group(g1, 3);
     if (best.pos == c.pos) {
       const double rho = double(__int_as_float(r0.x));
       return c.d < rho * rho * (1.0 - 0x1p-30);
@@ -1391,7 +1404,9 @@ far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph
   // the captured map view holds the fine-index flag: a graph captured with a
   // different flag must not be replayed
   const void* key[10] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
-                         m->vox_pts, reinterpret_cast<const void*>(intptr_t(m->fine_ok))};
+                         m->vox_pts,
+                         reinterpret_cast<const void*>(intptr_t(m->fine_ok) |
+                                                       (intptr_t(m->ghost_ok) << 1))};
   bool same = w->exec && w->key_n == j.n_total && w->key_S == j.S &&
               w->key_prec == j.precision && w->key_tile == j.tile &&
               memcmp(w->key, key, sizeof(key)) == 0 && same_params(w->key_prm, j.prm);
@@ -1465,6 +1480,16 @@ Params make_params(const far_map_s* m, double tau, double kappa, double eps, int
 
 void lin_from_stats(const far_align_stats_t& st, far_lin_t* out) { *out = st.last; }
 
+// The linearisation a one-scan job left in its stats (zero without one),
+// copied to the caller's device buffer by the lanes of one wave.
+__global__ void k_copy_lin(const far_align_stats_t* st, far_lin_t* out) {
+  constexpr int kWords = int(sizeof(far_lin_t) / sizeof(double));
+  static_assert(sizeof(far_lin_t) % sizeof(double) == 0, "far_lin_t is whole doubles");
+  const double* src = st ? reinterpret_cast<const double*>(&st->last) : nullptr;
+  double* dst = reinterpret_cast<double*>(out);
+  for (int q = threadIdx.x; q < kWords; q += blockDim.x) dst[q] = src ? src[q] : 0.0;
+}
+
 }  // namespace
 }  // namespace far
 
@@ -1512,6 +1537,46 @@ far_status_t far_gicp_linearize(far_map_t m, const float* src, const float* cov6
   FAR_HIP(hipStreamSynchronize(st));
   lin_from_stats(hs, out);
   return FAR_OK;
+}
+
+far_status_t far_gicp_linearize_async(far_map_t m, const float* src, const float* cov6,
+                                      const uint8_t* valid, int64_t n, const double T[16],
+                                      double tau, double kappa, const double c[3],
+                                      int32_t precision, int32_t* corr, far_lin_t* out,
+                                      far_stream_t stream) {
+  if (!m || !T || !out || n < 0 || n >= (int64_t(1) << 31) || !(tau > 0.0) ||
+      !(kappa > 0.0) || (n > 0 && (!src || !cov6 || !valid)) ||
+      !precision_ok(precision)) {
+    set_error("far_gicp_linearize_async: invalid argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  if (n == 0) {
+    k_copy_lin<<<1, 64, 0, st>>>(nullptr, out);
+    FAR_HIP(hipGetLastError());
+    return FAR_OK;
+  }
+  AlignWS* w = nullptr;
+  FAR_TRY(ensure_ws(m, 1, (n + kTileMin - 1) / kTileMin + 1, n, &w));
+  FAR_TRY(set_single(w, n, T, c ? c : kOrigin, true, st));
+  Job j{src, w->offsets, 1, n, cov6, valid, w->T, w->stats, w->cfix, corr,
+        make_params(m, tau, kappa, 0.0, 1, 0, precision), precision_of(precision)};
+  FAR_TRY(run_job(m, j, st, false));
+  k_copy_lin<<<1, 64, 0, st>>>(w->stats, out);
+  FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
+
+far_status_t far_map_reserve(far_map_t m, int64_t max_points, int32_t max_scans,
+                             far_stream_t stream) {
+  (void)stream;
+  if (!m || max_points < 0 || max_points >= (int64_t(1) << 31) || max_scans < 1) {
+    set_error("far_map_reserve: invalid argument");
+    return FAR_E_INVALID;
+  }
+  AlignWS* w = nullptr;
+  return ensure_ws(m, max_scans, (max_points + kTileMin - 1) / kTileMin + max_scans,
+                   max_points, &w);
 }
 
 far_status_t far_gicp_gradient(far_map_t m, const float* src, const float* cov6,

@@ -119,6 +119,14 @@ struct MapView {
   const uint32_t* vox_nbr;      // [voxel_cap * 26]: neighbour voxel << 7 | its count
   const float* pt_xyz;          // [3][point_cap]
   const CertRow* cert;          // [voxel_cap * nmax], by vox_pts slot
+  // ghost voxels: the empty voxels next to an occupied one, each with a
+  // neighbour-table row like an occupied voxel's (ghost_ok: the table holds
+  // every such voxel, else searches probe the neighbours one by one)
+  const Slot* gslots;           // key, vox = ghost index
+  const uint32_t* gnbr;         // [ghost_cap * 26]
+  uint32_t gmask;
+  int32_t glog2;
+  int32_t ghost_ok;
   int64_t point_cap;
   double v;
   int32_t nmax;
@@ -141,6 +149,20 @@ struct MapView {
 constexpr uint32_t kNbrNone = 0xFFFFFFFFu;
 constexpr int kNbrCountBits = 7;
 __host__ __device__ inline int nbr_dir(int code) { return code < 13 ? code : code - 1; }
+
+// Ghost index of empty voxel (kx, ky, kz) next to the map, or -1.
+__device__ inline int32_t ghost_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz) {
+  if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
+  const uint64_t key = pack_key(kx, ky, kz);
+  uint32_t s = voxel_hash(kx, ky, kz, m.glog2);
+  for (uint32_t probe = 0; probe <= m.gmask; ++probe) {
+    const Slot sl = m.gslots[s];
+    if (sl.key == key) return sl.vox;
+    if (sl.key == kEmptyKey) return -1;
+    s = (s + 1) & m.gmask;
+  }
+  return -1;
+}
 
 // Run [start, start + *cnt) of fine cell (kx, ky, kz) in fine_pts, or -1.
 __device__ inline int32_t fine_find(const MapView& m, int64_t kx, int64_t ky, int64_t kz,
@@ -342,6 +364,17 @@ struct far_map_s {
   far::CertRow* cert = nullptr;
   uint32_t* cert_mark = nullptr;
   uint32_t cert_gen = 0;
+  // ghost voxels (empty voxels next to an occupied one): hash table, keys
+  // and neighbour rows by ghost index, the device count of ghosts claimed
+  far::Slot* gslots = nullptr;
+  uint64_t* gkey = nullptr;
+  uint32_t* gnbr = nullptr;
+  uint32_t* gcount = nullptr;
+  int64_t ghost_cap = 0;
+  int64_t gslots_n = 0;
+  int glog2 = 0;
+  int64_t n_ghosts = 0;         // as of the last map update (host copy)
+  bool ghost_ok = true;
   // fine search index, rebuilt lazily after the map changes
   float4* fine_pts = nullptr;
   far::Slot* fine_slots = nullptr;
@@ -362,6 +395,11 @@ struct far_map_s {
     m.vox_nbr = vox_nbr;
     m.pt_xyz = pt_xyz;
     m.cert = cert;
+    m.gslots = gslots;
+    m.gnbr = gnbr;
+    m.gmask = uint32_t(gslots_n - 1);
+    m.glog2 = glog2;
+    m.ghost_ok = ghost_ok ? 1 : 0;
     m.point_cap = p.point_capacity;
     m.v = p.voxel_size;
     m.nmax = p.max_pts_per_voxel;

@@ -374,6 +374,94 @@ __global__ __launch_bounds__(kT) void k_nbr_update(MapView m, int64_t n_seg, con
   }
 }
 
+// ---------------------------------------------------------------- ghosts
+// Ghost voxels are the empty voxels next to an occupied one.  Each has a
+// neighbour-table row, so that a search from a point in an empty voxel reads
+// its occupied neighbours from one row instead of probing the hash for each
+// of the 26; a point whose voxel is neither occupied nor a ghost has no map
+// point in its 27 voxels.  Ghosts are claimed around every new voxel, their
+// rows filled from the hash, and the rows of the ghosts around every voxel
+// whose count changed are updated with its new entry.  A ghost whose key
+// later becomes occupied keeps its slot; the occupied voxel shadows it.
+
+// Claims the empty neighbours of each new voxel run as ghosts (index from
+// gcount; beyond ghost_cap a ghost gets no row and the host switches the
+// ghosts off).
+__global__ __launch_bounds__(kT) void k_ghost_claim(MapView m, int64_t n_seg,
+                                                    const int32_t* seg_vox,
+                                                    const uint32_t* is_new,
+                                                    const uint64_t* vox_key, Slot* gslots,
+                                                    uint64_t* gkey, uint32_t* gcount,
+                                                    int64_t ghost_cap) {
+  const int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg || (is_new && !is_new[s])) return;
+  const uint64_t key = vox_key[seg_vox[s]];
+  const int64_t kx = key_x(key), ky = key_y(key), kz = key_z(key);
+  for (int code = 0; code < 27; ++code) {
+    if (code == 13) continue;
+    const int64_t nx = kx + code / 9 - 1, ny = ky + (code / 3) % 3 - 1, nz = kz + code % 3 - 1;
+    if (!key_ok(nx) || !key_ok(ny) || !key_ok(nz)) continue;
+    int32_t c;
+    if (map_find(m, nx, ny, nz, &c) >= 0) continue;
+    const uint64_t nk = pack_key(nx, ny, nz);
+    uint32_t h = voxel_hash(nx, ny, nz, m.glog2);
+    for (uint32_t probe = 0; probe <= m.gmask; ++probe) {
+      const unsigned long long old = atomicCAS(
+          reinterpret_cast<unsigned long long*>(&gslots[h].key), (unsigned long long)kEmptyKey,
+          (unsigned long long)nk);
+      if (old == kEmptyKey) {
+        const uint32_t g = atomicAdd(gcount, 1u);
+        gslots[h].vox = int64_t(g) < ghost_cap ? int32_t(g) : -1;
+        if (int64_t(g) < ghost_cap) gkey[g] = nk;
+        break;
+      }
+      if (old == nk) break;
+      h = (h + 1) & m.gmask;
+    }
+  }
+}
+
+// Full neighbour rows of the ghosts with index in [g0, min(*gcount, cap)).
+__global__ __launch_bounds__(kT) void k_ghost_fill(MapView m, const uint64_t* gkey,
+                                                   const uint32_t* gcount, int64_t g0,
+                                                   int64_t n, int64_t ghost_cap,
+                                                   uint32_t* gnbr) {
+  const int64_t g = g0 + int64_t(blockIdx.x) * kT + threadIdx.x;
+  const int64_t end = int64_t(*gcount) < ghost_cap ? int64_t(*gcount) : ghost_cap;
+  if (g >= end || g >= g0 + n) return;
+  const uint64_t key = gkey[g];
+  const int64_t kx = key_x(key), ky = key_y(key), kz = key_z(key);
+  for (int code = 0; code < 27; ++code) {
+    if (code == 13) continue;
+    int32_t c;
+    const int32_t N = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1,
+                               kz + code % 3 - 1, &c);
+    gnbr[g * 26 + nbr_dir(code)] =
+        N >= 0 ? (uint32_t(N) << kNbrCountBits) | uint32_t(c) : kNbrNone;
+  }
+}
+
+// The entry of every voxel run whose count changed, written into the rows
+// of the ghosts around it (one writer per entry, as in k_nbr_update).
+__global__ __launch_bounds__(kT) void k_ghost_update(MapView m, int64_t n_seg,
+                                                     const int32_t* seg_vox,
+                                                     const uint32_t* seg_changed,
+                                                     const uint64_t* vox_key,
+                                                     const int32_t* vox_count, uint32_t* gnbr) {
+  const int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (s >= n_seg || !seg_changed[s]) return;
+  const int32_t V = seg_vox[s];
+  const uint64_t key = vox_key[V];
+  const int64_t kx = key_x(key), ky = key_y(key), kz = key_z(key);
+  const uint32_t eV = (uint32_t(V) << kNbrCountBits) | uint32_t(vox_count[V]);
+  for (int code = 0; code < 27; ++code) {
+    if (code == 13) continue;
+    const int32_t g = ghost_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1,
+                                 kz + code % 3 - 1);
+    if (g >= 0) gnbr[int64_t(g) * 26 + nbr_dir(26 - code)] = eV;
+  }
+}
+
 // ---------------------------------------------------------------- ASMD
 // Near-range points of the scan (sensor range <= r_near) and the distinct
 // map-frame voxels they fall in, counted through a temporary hash set of
@@ -1159,6 +1247,48 @@ far_status_t fine_build(far_map_s* m, hipStream_t st) {
   return FAR_OK;
 }
 
+// No ghosts (the voxel structures were cleared): an empty table, ghosts on.
+far_status_t ghosts_reset(far_map_s* m, hipStream_t st) {
+  FAR_HIP(hipMemsetAsync(m->gslots, 0xFF, size_t(m->gslots_n) * sizeof(Slot), st));
+  FAR_HIP(hipMemsetAsync(m->gcount, 0, sizeof(uint32_t), st));
+  m->n_ghosts = 0;
+  m->ghost_ok = true;
+  return FAR_OK;
+}
+
+// Ghost upkeep after the voxels of runs seg_vox changed: claim the empty
+// neighbours of the new voxels (every run when is_new is NULL), fill the new
+// ghosts' rows, and update the rows around the changed voxels (when
+// seg_changed is given); then (one small copy; the callers synchronise
+// anyway) the host learns the ghost count and switches the ghosts off when
+// they no longer fit.
+far_status_t ghosts_update(far_map_s* m, int64_t n_seg, const int32_t* seg_vox,
+                           const uint32_t* is_new, const uint32_t* seg_changed, int64_t n_new,
+                           hipStream_t st) {
+  if (!m->ghost_ok || n_seg == 0) return FAR_OK;
+  const MapView mv = m->view();
+  k_ghost_claim<<<blocks_for(n_seg), kT, 0, st>>>(mv, n_seg, seg_vox, is_new, m->vox_key,
+                                                  m->gslots, m->gkey, m->gcount, m->ghost_cap);
+  FAR_HIP(hipGetLastError());
+  const int64_t fresh = 26 * n_new;   // at most this many new ghosts
+  if (fresh > 0) {
+    k_ghost_fill<<<blocks_for(fresh), kT, 0, st>>>(mv, m->gkey, m->gcount, m->n_ghosts, fresh,
+                                                   m->ghost_cap, m->gnbr);
+    FAR_HIP(hipGetLastError());
+  }
+  if (seg_changed) {
+    k_ghost_update<<<blocks_for(n_seg), kT, 0, st>>>(mv, n_seg, seg_vox, seg_changed,
+                                                     m->vox_key, m->vox_count, m->gnbr);
+    FAR_HIP(hipGetLastError());
+  }
+  uint32_t h = 0;
+  FAR_HIP(hipMemcpyAsync(&h, m->gcount, sizeof(h), hipMemcpyDeviceToHost, st));
+  FAR_HIP(hipStreamSynchronize(st));
+  m->n_ghosts = h;
+  if (int64_t(h) > m->ghost_cap) m->ghost_ok = false;
+  return FAR_OK;
+}
+
 }  // namespace far
 
 using namespace far;
@@ -1229,6 +1359,14 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   size_t b_vslot = size_t(m->voxel_cap) * sizeof(int32_t);
   size_t b_cert = size_t(m->voxel_cap) * p.max_pts_per_voxel * sizeof(CertRow);
   size_t b_mark = size_t(m->voxel_cap) * sizeof(uint32_t);
+  // ghosts: four per voxel of capacity (a surface map has about two)
+  m->ghost_cap = 4 * m->voxel_cap;
+  m->glog2 = ceil_log2(2 * m->ghost_cap);
+  if (m->glog2 < 10) m->glog2 = 10;
+  m->gslots_n = int64_t(1) << m->glog2;
+  size_t b_gslots = size_t(m->gslots_n) * sizeof(Slot);
+  size_t b_gkey = size_t(m->ghost_cap) * sizeof(uint64_t);
+  size_t b_gnbr = size_t(m->ghost_cap) * 26 * sizeof(uint32_t);
   m->fine_log2 = ceil_log2(2 * p.point_capacity);
   if (m->fine_log2 < 10) m->fine_log2 = 10;
   m->fine_nslots = int64_t(1) << m->fine_log2;
@@ -1245,13 +1383,21 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->vox_slot, b_vslot)) != hipSuccess) return fail(e, "hipMalloc vslot");
   if ((e = hipMalloc(&m->cert, b_cert)) != hipSuccess) return fail(e, "hipMalloc cert");
   if ((e = hipMalloc(&m->cert_mark, b_mark)) != hipSuccess) return fail(e, "hipMalloc mark");
+  if ((e = hipMalloc(&m->gslots, b_gslots)) != hipSuccess) return fail(e, "hipMalloc ghosts");
+  if ((e = hipMalloc(&m->gkey, b_gkey)) != hipSuccess) return fail(e, "hipMalloc ghosts");
+  if ((e = hipMalloc(&m->gnbr, b_gnbr)) != hipSuccess) return fail(e, "hipMalloc ghosts");
+  if ((e = hipMalloc(&m->gcount, sizeof(uint32_t))) != hipSuccess) return fail(e, "hipMalloc ghosts");
   if ((e = hipMalloc(&m->fine_pts, b_fpts)) != hipSuccess) return fail(e, "hipMalloc fine");
   if ((e = hipMalloc(&m->fine_slots, b_fslots)) != hipSuccess) return fail(e, "hipMalloc fine");
   m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_nbr + b_xyz + b_loc + b_vslot +
-                     b_cert + b_mark + b_fpts + b_fslots);
+                     b_cert + b_mark + b_gslots + b_gkey + b_gnbr + sizeof(uint32_t) + b_fpts +
+                     b_fslots);
   if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipMemsetAsync(m->vox_count, 0, b_cnt, st)) != hipSuccess) return fail(e, "memset");
   if ((e = hipMemsetAsync(m->cert_mark, 0, b_mark, st)) != hipSuccess) return fail(e, "memset");
+  if ((e = hipMemsetAsync(m->gslots, 0xFF, b_gslots, st)) != hipSuccess) return fail(e, "memset");
+  if ((e = hipMemsetAsync(m->gcount, 0, sizeof(uint32_t), st)) != hipSuccess)
+    return fail(e, "memset");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "sync");
   *out = m;
   return FAR_OK;
@@ -1263,7 +1409,8 @@ far_status_t far_map_destroy(far_map_t m) {
   free_ws(m->ws);
   m->ws = nullptr;
   void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->vox_nbr, m->pt_xyz,
-                  m->pt_loc, m->vox_slot, m->cert, m->cert_mark, m->fine_pts, m->fine_slots};
+                  m->pt_loc, m->vox_slot, m->cert, m->cert_mark, m->gslots, m->gkey,
+                  m->gnbr, m->gcount, m->fine_pts, m->fine_slots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -1362,6 +1509,7 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
         m->view(), nv, m->cert_mark, m->cert_gen, m->cert);
     FAR_HIP(hipGetLastError());
   }
+  FAR_TRY(ghosts_update(m, n_seg, seg_vox, is_new, seg_changed, n_new, st));
   FAR_TRY(map_covariances(m->view(), m->cov, m->n_points, m->n_points + n_commit,
                           m->p.k_cov, st));
   m->n_points += n_commit;
@@ -1543,6 +1691,7 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
                                   int64_t n, double voxel_size, int32_t k, float* cov6,
                                   uint8_t* valid, hipStream_t st, const char* who) {
   Scratch scr(st);
+  TimedScope ts(FAR_TIME_COVARIANCES, st);
   GridView g{};
   uint32_t oor = 0;
   int64_t n_seg = 0;
@@ -1810,6 +1959,7 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
     if (m->n_voxels > 0) {
       FAR_HIP(hipMemsetAsync(m->slots_d, 0xFF, size_t(m->slots) * sizeof(Slot), st));
       FAR_HIP(hipMemsetAsync(m->vox_count, 0, size_t(m->n_voxels) * sizeof(int32_t), st));
+      FAR_TRY(ghosts_reset(m, st));
       FAR_HIP(hipStreamSynchronize(st));
       m->n_voxels = 0;
       m->fine_ok = false;
@@ -1844,6 +1994,7 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   // clear the voxel structures, then store the survivors and rebuild them
   FAR_HIP(hipMemsetAsync(m->slots_d, 0xFF, size_t(m->slots) * sizeof(Slot), st));
   FAR_HIP(hipMemsetAsync(m->vox_count, 0, size_t(m->n_voxels) * sizeof(int32_t), st));
+  FAR_TRY(ghosts_reset(m, st));
   m->n_points = 0;
   m->n_voxels = 0;
   m->fine_ok = false;
@@ -1886,10 +2037,11 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   k_nbr_update<<<blocks_for(n_seg), kT, 0, st>>>(m->view(), n_seg, seg_vox, is_new, m->vox_key,
                                                  m->vox_count, m->vox_nbr);
   FAR_HIP(hipGetLastError());
-  // every slot changed: all certificates again
+  // every slot changed: all certificates again, and the ghosts
   k_cert_build<<<blocks_for(n_seg * m->p.max_pts_per_voxel), kT, 0, st>>>(
       m->view(), n_seg, nullptr, 0, m->cert);
   FAR_HIP(hipGetLastError());
+  FAR_TRY(ghosts_update(m, n_seg, seg_vox, nullptr, nullptr, n_seg, st));
   m->n_points = n_keep;
   m->n_voxels = n_seg;
   ts3.stop();

@@ -103,6 +103,10 @@ _SIGS = {
     "far_gicp_linearize": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                      C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.c_int32, _P, C.POINTER(far_lin_t), _P]),
+    "far_gicp_linearize_async": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
+                                           C.c_double, C.c_double, C.POINTER(C.c_double),
+                                           C.c_int32, _P, _P, _P]),
+    "far_map_reserve": (C.c_int, [_P, C.c_int64, C.c_int32, _P]),
     "far_gicp_gradient": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                     C.c_double, C.c_double, C.POINTER(C.c_double), C.c_int32,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double), _P,
@@ -305,7 +309,7 @@ def far_timing_enable(on: bool):
 
 
 FAR_TIME_LINEARIZE, FAR_TIME_UNDISTORT, FAR_TIME_UNDISTORT_APPLY = 0, 1, 2
-FAR_TIME_GRADIENT, FAR_TIME_ASMD, FAR_TIME_EVICT = 3, 4, 5
+FAR_TIME_GRADIENT, FAR_TIME_ASMD, FAR_TIME_EVICT, FAR_TIME_COVARIANCES = 3, 4, 5, 6
 
 
 def far_timing_read_kind(kind: int, reset: bool = False):
@@ -342,6 +346,37 @@ def far_gicp_linearize(h, src, cov6, valid, T, tau, kappa, c=None, precision=FAR
     if want_corr:
         d["corr"] = corr
     return d
+
+
+LIN_WORDS = C.sizeof(far_lin_t) // 8
+
+
+def far_gicp_linearize_async(h, src, cov6, valid, T, tau, kappa, out, c=None,
+                             precision=FAR_PREC_FP32, corr=None, stream=None):
+    """far_gicp_linearize with the result written to out, a float64 device
+    tensor of LIN_WORDS words (decode with lin_from_words); no host sync."""
+    p, n = _pts(src, "src")
+    if out.numel() < LIN_WORDS:
+        raise ValueError(f"out must hold {LIN_WORDS} float64 words")
+    cc = None if c is None else (C.c_double * 3)(*[float(x) for x in c])
+    _check(lib().far_gicp_linearize_async(h, p, _dev(cov6, torch.float32, "cov6"),
+                                          _dev(valid, torch.uint8, "valid"), n, _mat4(T), tau,
+                                          kappa, cc, precision, _dev(corr, torch.int32, "corr"),
+                                          _dev(out, torch.float64, "out"), _stream(stream)),
+           "far_gicp_linearize_async")
+    return out
+
+
+def lin_from_words(words):
+    """Decode a far_lin_t read back as LIN_WORDS float64 words."""
+    buf = np.ascontiguousarray(np.asarray(words, dtype=np.float64)[:LIN_WORDS])
+    out = far_lin_t.from_buffer_copy(buf.tobytes())
+    return _lin_dict(out)
+
+
+def far_map_reserve(h, max_points, max_scans=1, stream=None):
+    _check(lib().far_map_reserve(h, int(max_points), int(max_scans), _stream(stream)),
+           "far_map_reserve")
 
 
 def far_gicp_gradient(h, src, cov6, valid, T, tau, kappa, c=None, precision=FAR_PREC_FP32,
@@ -456,6 +491,12 @@ class Map:
 
     def linearize(self, *a, **kw):
         return far_gicp_linearize(self.h, *a, **kw)
+
+    def linearize_async(self, *a, **kw):
+        return far_gicp_linearize_async(self.h, *a, **kw)
+
+    def reserve(self, max_points, max_scans=1, stream=None):
+        return far_map_reserve(self.h, max_points, max_scans, stream)
 
     def evict(self, center, radius, stream=None):
         return far_map_evict(self.h, center, radius, stream)

@@ -145,3 +145,26 @@ def test_seeded_iterations_match_the_oracle_align(far, orc):
         say(f"FP64 align, {iters} iterations: |dt| {dt:.2e} m, max |dR| {dr:.2e}")
         assert st == 0 and dt < 1e-9 and dr < 1e-9
     gm.close()
+
+
+def test_queries_in_empty_voxels_next_to_the_map(far, orc):
+    """Queries in empty voxels: next to an occupied one (their ghost's
+    neighbour row lists the occupied neighbours), two or more voxels away
+    (no ghost: nothing within v), and the same with the ghost table too small
+    for the map (isolated voxels have 26 ghosts each), where the search
+    probes the neighbours one by one."""
+    r = np.random.default_rng(23)
+    # isolated clusters of points 5 m apart, each within one voxel
+    centres = np.stack(np.meshgrid(np.arange(4) * 5.0, np.arange(4) * 5.0, [0.0],
+                                   indexing="ij")).reshape(3, -1) + 0.5
+    pts = np.concatenate([c[:, None] + r.uniform(-0.45, 0.45, size=(3, 12))
+                          for c in centres.T], axis=1).astype(np.float32)
+    q = np.concatenate([c[:, None] + r.uniform(-2.0, 2.0, size=(3, 300))
+                        for c in centres.T], axis=1).astype(np.float32)
+    for voxel_cap, what in ((0, "ghosts held"), (16, "ghost table too small")):
+        gm = far.Map(1.0, 20, 0.0, 1 << 12, voxel_cap, 5)
+        om = orc.Map(1.0, 20, 0.0, 5, point_capacity=1 << 12, voxel_capacity=1 << 12)
+        gm.insert(dev(pts))
+        om.insert(pts)
+        check_corr(gm, om, orc, q, np.eye(4), 1.0, what)
+        gm.close()

@@ -478,6 +478,69 @@ __device__ inline void nn_lockstep(const MapView& m, double px, double py, doubl
   }
 }
 
+// The exact search of the dense queue pass: as nn_lockstep from scratch, with
+// the neighbour row (the own voxel's or its ghost's) copied into this lane's
+// stretch of LDS by 13 independent 8-byte loads first, so that a visit waits
+// for its points only, and the points loaded eight at a time.
+constexpr int kRowWords = 27;   // per-lane LDS row stride (26 entries, padded)
+__device__ inline void nn_search_dense(const MapView& m, double px, double py, double pz,
+                                       int32_t kx, int32_t ky, int32_t kz, double r2,
+                                       uint32_t* lrow, TopK<1>& top) {
+  const double v = m.v;
+  FaceOffsets fo;
+  fo.f[0] = float(px - double(kx) * v);
+  fo.f[1] = float(py - double(ky) * v);
+  fo.f[2] = float(pz - double(kz) * v);
+  fo.v = float(v);
+  fo.slack = float(1e-7 * v);
+  Query q = make_query(px, py, pz, r2);
+  q.bound_f = screen_bound(fmin(r2, top.bound()), q.m);
+  int32_t cnt;
+  const int32_t own = map_find(m, kx, ky, kz, &cnt);
+  const uint32_t* row = own >= 0 ? m.vox_nbr + int64_t(own) * 26 : nullptr;
+  if (own < 0 && m.ghost_ok) {
+    const int32_t g = ghost_find(m, kx, ky, kz);
+    if (g < 0) return;
+    row = m.gnbr + int64_t(g) * 26;
+  }
+  if (row) {
+    const uint2* r2p = reinterpret_cast<const uint2*>(row);   // rows are 8-byte aligned
+    uint2 e[13];
+#pragma unroll
+    for (int t = 0; t < 13; ++t) e[t] = r2p[t];
+#pragma unroll
+    for (int t = 0; t < 13; ++t) {
+      lrow[2 * t] = e[t].x;
+      lrow[2 * t + 1] = e[t].y;
+    }
+  }
+  if (own >= 0) scan_voxel_points<1, 8>(m.vox_pts, own * m.nmax, cnt, q, r2, top);
+  uint32_t need = 0;
+  {
+    const float bnd = f32_up(fmin(r2, top.bound()));
+#pragma unroll
+    for (int rank = 1; rank < 27; ++rank)
+      if (fo.lb2(nbr_code(rank)) <= bnd) need |= 1u << rank;
+  }
+  while (need) {
+    const int rank = __builtin_ctz(need);
+    need &= need - 1;
+    const int code = nbr_code(rank);
+    if (double(fo.lb2(code)) > fmin(r2, top.bound())) continue;
+    int32_t vox;
+    if (row) {
+      const uint32_t e = lrow[nbr_dir(code)];
+      if (e == kNbrNone) continue;
+      vox = int32_t(e >> kNbrCountBits);
+      cnt = int32_t(e & ((1u << kNbrCountBits) - 1u));
+    } else {
+      vox = map_find(m, kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
+      if (vox < 0) continue;
+    }
+    scan_voxel_points<1, 8>(m.vox_pts, vox * m.nmax, cnt, q, r2, top);
+  }
+}
+
 // A candidate for a query: its vox_pts slot and point (x, y, z, id bits), its
 // id and its exact squared distance.
 struct Cand {
@@ -727,6 +790,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(MapView m, Queue Q, P
                                                            int32_t* __restrict__ match,
                                                            int32_t* __restrict__ prev) {
   __shared__ uint32_t pre[kBins + 1];
+  __shared__ uint32_t rows[kSearchThreads * kRowWords];
   if (threadIdx.x < 64) {
     // inclusive scan of the kBins counts across the first wave
     uint32_t v = threadIdx.x < kBins ? Q.count[threadIdx.x] : 0u;
@@ -762,10 +826,13 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(MapView m, Queue Q, P
       c.id = __float_as_int(c.p.w);
       c.d = dist2(double(c.p.x), double(c.p.y), double(c.p.z), px, py, pz);
     }
-    int32_t next = -1;
-    match[i] = nn_exact_from(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, c,
-                             &next);
-    prev[i] = next;
+    TopK<1> top;
+    top.init();
+    if (c.pos >= 0 && c.d <= prm.r2) top.push(c.d, c.id, c.pos);
+    nn_search_dense(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
+                    rows + threadIdx.x * kRowWords, top);
+    match[i] = top.pos[0];
+    prev[i] = top.pos[0] >= 0 ? top.pos[0] : c.pos;
   }
 }
 
@@ -839,8 +906,11 @@ __global__ __launch_bounds__(kB) void k_linearize(
       const int32_t id = __float_as_int(r.w);
       const float4 sB = pB[i];
       const float2 sC = pC[i];
-      const float4 ca = m.cov[2 * int64_t(id)];
-      const float4 cb = m.cov[2 * int64_t(id) + 1];
+      // the match's covariance record, by vox_pts slot (beside the points the
+      // search read) or, for the fine index, by id
+      const float4* cr = kFine ? m.cov + 2 * int64_t(id) : m.vox_cov + 2 * int64_t(res);
+      const float4 ca = cr[0];
+      const float4 cb = cr[1];
       // without the sparsity-aware case a pair lacking either covariance is
       // dropped like an outlier
       if (!kNoSA || (sB.x >= 0.0f && cb.z != 0.0f)) {

@@ -116,6 +116,7 @@ struct MapView {
   const int32_t* vox_count;     // [voxel_cap]
   const float4* vox_pts;        // [voxel_cap * nmax]: x, y, z, id (int bits)
   const float4* cov;            // [point_cap * 2]: (xx,xy,xz,yy), (yz,zz,valid,0)
+  const float4* vox_cov;        // [voxel_cap * nmax * 2]: the same records by vox_pts slot
   const uint32_t* vox_nbr;      // [voxel_cap * 26]: neighbour voxel << 7 | its count
   const float* pt_xyz;          // [3][point_cap]
   const CertRow* cert;          // [voxel_cap * nmax], by vox_pts slot
@@ -355,6 +356,7 @@ struct far_map_s {
   uint64_t* vox_key = nullptr;
   float4* vox_pts = nullptr;
   float4* cov = nullptr;
+  float4* vox_cov = nullptr;
   uint32_t* vox_nbr = nullptr;
   float* pt_xyz = nullptr;
   int32_t* pt_loc = nullptr;
@@ -392,6 +394,7 @@ struct far_map_s {
     m.vox_count = vox_count;
     m.vox_pts = vox_pts;
     m.cov = cov;
+    m.vox_cov = vox_cov;
     m.vox_nbr = vox_nbr;
     m.pt_xyz = pt_xyz;
     m.cert = cert;

@@ -105,17 +105,18 @@ __device__ inline Query make_query(double x, double y, double z, double r2) {
 }
 
 // Rank the cnt points stored at pts[base ...] against q.  Loads are issued
-// four at a time so that they overlap instead of waiting one by one.
-template <int K>
+// kW at a time (4 by default) so that they overlap instead of waiting one by
+// one.
+template <int K, int kW = 4>
 __device__ inline void scan_voxel_points(const float4* pts, int32_t base, int32_t cnt,
                                          Query& q, double r2, TopK<K>& top) {
-  for (int32_t j = 0; j < cnt; j += 4) {
-    float4 p[4];
+  for (int32_t j = 0; j < cnt; j += kW) {
+    float4 p[kW];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kW; ++u)
       if (j + u < cnt) p[u] = pts[base + j + u];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kW; ++u)
       if (j + u < cnt) {
         const float dx = p[u].x - q.fx, dy = p[u].y - q.fy, dz = p[u].z - q.fz;
         const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));

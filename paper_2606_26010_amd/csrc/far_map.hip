@@ -615,6 +615,17 @@ __global__ __launch_bounds__(kT) void k_map_cov(MapView m, float4* cov, int64_t 
   cov[2 * id + 1] = make_float4(float(c6[4]), float(c6[5]), ok ? 1.0f : 0.0f, 0.0f);
 }
 
+// Copies of the covariance records of ids [id0, id1) at their vox_pts slots,
+// so that a search reads a match's covariance beside its neighbours'.
+__global__ __launch_bounds__(kT) void k_vox_cov(const float4* cov, const int32_t* pt_loc,
+                                                int64_t id0, int64_t id1, float4* vox_cov) {
+  const int64_t id = id0 + int64_t(blockIdx.x) * kT + threadIdx.x;
+  if (id >= id1) return;
+  const int64_t pos = pt_loc[id];
+  vox_cov[2 * pos] = cov[2 * id];
+  vox_cov[2 * pos + 1] = cov[2 * id + 1];
+}
+
 template <int K>
 __global__ __launch_bounds__(kT) void k_map_knn(MapView m, const float* q, int64_t n, int32_t k,
                                                 double r2, int32_t* idx, float* d2,
@@ -1353,6 +1364,7 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   size_t b_key = size_t(m->voxel_cap) * sizeof(uint64_t);
   size_t b_pts = size_t(m->voxel_cap) * p.max_pts_per_voxel * sizeof(float4);
   size_t b_cov = size_t(p.point_capacity) * 2 * sizeof(float4);
+  size_t b_vcov = size_t(m->voxel_cap) * p.max_pts_per_voxel * 2 * sizeof(float4);
   size_t b_nbr = size_t(m->voxel_cap) * 26 * sizeof(uint32_t);
   size_t b_xyz = size_t(p.point_capacity) * 3 * sizeof(float);
   size_t b_loc = size_t(p.point_capacity) * sizeof(int32_t);
@@ -1377,6 +1389,7 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->vox_key, b_key)) != hipSuccess) return fail(e, "hipMalloc keys");
   if ((e = hipMalloc(&m->vox_pts, b_pts)) != hipSuccess) return fail(e, "hipMalloc points");
   if ((e = hipMalloc(&m->cov, b_cov)) != hipSuccess) return fail(e, "hipMalloc cov");
+  if ((e = hipMalloc(&m->vox_cov, b_vcov)) != hipSuccess) return fail(e, "hipMalloc cov");
   if ((e = hipMalloc(&m->vox_nbr, b_nbr)) != hipSuccess) return fail(e, "hipMalloc nbr");
   if ((e = hipMalloc(&m->pt_xyz, b_xyz)) != hipSuccess) return fail(e, "hipMalloc xyz");
   if ((e = hipMalloc(&m->pt_loc, b_loc)) != hipSuccess) return fail(e, "hipMalloc loc");
@@ -1389,7 +1402,7 @@ far_status_t far_map_create(const far_map_params_t* params, far_stream_t stream,
   if ((e = hipMalloc(&m->gcount, sizeof(uint32_t))) != hipSuccess) return fail(e, "hipMalloc ghosts");
   if ((e = hipMalloc(&m->fine_pts, b_fpts)) != hipSuccess) return fail(e, "hipMalloc fine");
   if ((e = hipMalloc(&m->fine_slots, b_fslots)) != hipSuccess) return fail(e, "hipMalloc fine");
-  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_nbr + b_xyz + b_loc + b_vslot +
+  m->bytes = int64_t(b_slots + b_cnt + b_key + b_pts + b_cov + b_vcov + b_nbr + b_xyz + b_loc + b_vslot +
                      b_cert + b_mark + b_gslots + b_gkey + b_gnbr + sizeof(uint32_t) + b_fpts +
                      b_fslots);
   if ((e = hipMemsetAsync(m->slots_d, 0xFF, b_slots, st)) != hipSuccess) return fail(e, "memset");
@@ -1408,7 +1421,8 @@ far_status_t far_map_destroy(far_map_t m) {
   hipError_t e = hipDeviceSynchronize();
   free_ws(m->ws);
   m->ws = nullptr;
-  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->vox_nbr, m->pt_xyz,
+  void* ptrs[] = {m->slots_d, m->vox_count, m->vox_key, m->vox_pts, m->cov, m->vox_cov,
+                  m->vox_nbr, m->pt_xyz,
                   m->pt_loc, m->vox_slot, m->cert, m->cert_mark, m->gslots, m->gkey,
                   m->gnbr, m->gcount, m->fine_pts, m->fine_slots};
   for (void* p : ptrs)
@@ -1512,6 +1526,11 @@ far_status_t far_map_insert(far_map_t m, const float* xyz, int64_t n, const int3
   FAR_TRY(ghosts_update(m, n_seg, seg_vox, is_new, seg_changed, n_new, st));
   FAR_TRY(map_covariances(m->view(), m->cov, m->n_points, m->n_points + n_commit,
                           m->p.k_cov, st));
+  if (n_commit > 0) {
+    k_vox_cov<<<blocks_for(n_commit), kT, 0, st>>>(m->cov, m->pt_loc, m->n_points,
+                                                   m->n_points + n_commit, m->vox_cov);
+    FAR_HIP(hipGetLastError());
+  }
   m->n_points += n_commit;
   m->n_voxels += n_new;
   if (n_accepted) *n_accepted = n_commit;
@@ -2036,6 +2055,8 @@ far_status_t far_map_evict(far_map_t m, const double c[3], double radius, int64_
   FAR_HIP(hipGetLastError());
   k_nbr_update<<<blocks_for(n_seg), kT, 0, st>>>(m->view(), n_seg, seg_vox, is_new, m->vox_key,
                                                  m->vox_count, m->vox_nbr);
+  FAR_HIP(hipGetLastError());
+  k_vox_cov<<<blocks_for(n_keep), kT, 0, st>>>(m->cov, m->pt_loc, 0, n_keep, m->vox_cov);
   FAR_HIP(hipGetLastError());
   // every slot changed: all certificates again, and the ghosts
   k_cert_build<<<blocks_for(n_seg * m->p.max_pts_per_voxel), kT, 0, st>>>(

@@ -291,6 +291,9 @@ def main():
                     help="keep the default schedules instead of autotuning them on the batch")
     ap.add_argument("--tile", type=int, choices=(128, 256, 512), default=0,
                     help="linearisation tile (skips its autotuning; 0: autotuned)")
+    ap.add_argument("--lin-grid", type=int, default=-1,
+                    help="blocks per CU of a persistent launch of the tile passes (0: one "
+                         "block per tile; -1: timed on the batch and the faster kept)")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the timings of undistortion, gradient, ASMD caps and eviction")
     ap.add_argument("--copy-calib", action="store_true",
@@ -389,6 +392,31 @@ def main():
             schedule["tile"], schedule["fine_cells"] = args.tile, 0
             schedule["tile_forced"] = True
         tile = schedule["tile"]
+        # launch of the tile passes: one block per tile or a persistent grid of
+        # n blocks per CU taking tiles in turn (identical results); timed on
+        # the align of this batch and the faster kept, unless forced
+        schedule["lin_blocks_per_cu"] = args.lin_grid if args.lin_grid >= 0 else 0
+        if args.lin_grid < 0 and not args.no_autotune:
+            cov_g, val_g = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
+                                                          out=(cov_buf, val_buf))
+            grid_ms = {}
+            for g in (0, 4, 8, 16):
+                far.far_set_linearize_grid(g)
+                T_g = T0.clone()
+                far.far_gicp_align_batch(gm.h, src, offs, cov_g, val_g, T_g, prm, stats=stats_buf)
+                stream.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    T_g.copy_(T0)
+                    far.far_gicp_align_batch(gm.h, src, offs, cov_g, val_g, T_g, prm,
+                                             stats=stats_buf)
+                stream.synchronize()
+                grid_ms[str(g)] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+            best_g = min(grid_ms, key=lambda k: grid_ms[k])
+            schedule["lin_blocks_per_cu"] = int(best_g)
+            schedule["align_ms_by_lin_blocks_per_cu"] = grid_ms
+            log(f"[bench] tile-pass launch: {grid_ms} ms per align, kept {best_g} blocks per CU")
+        far.far_set_linearize_grid(schedule["lin_blocks_per_cu"])
 
         def step():
             cov, val = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
@@ -474,9 +502,18 @@ def main():
         if ctr is not None:
             roof_extra["traffic"] = ctr["fabric_read_bytes"] + ctr["fabric_write_bytes"]
             roof_extra["l2_hit"] = round(ctr["tcc_hit"] / max(ctr["tcc_hit"] + ctr["tcc_miss"], 1), 4)
-            roof_extra["valu_frac"] = round(4.0 * ctr["valu_insts"] / (N_SIMD * CLOCK_GHZ * 1e9 * t_s), 4)
+            # a wave64 VALU instruction occupies its SIMD for 2 cycles at the
+            # chip's 32-bit rate (157.3 TFLOP/s = 256 CUs x 4 SIMDs x 32 lanes x
+            # 2 x 2.4 GHz; FP64 instructions take 4, so this is a lower bound)
+            roof_extra["valu_frac"] = round(2.0 * ctr["valu_insts"] / (N_SIMD * CLOCK_GHZ * 1e9 * t_s), 4)
             roof_extra["lds_frac"] = round(ctr["lds_insts"] * 64 * 4 /
                                            (LDS_BYTES_PER_CLK_CU * 256 * CLOCK_GHZ * 1e9 * t_s), 4)
+            if "ta_ta_busy_sum" in ctr:   # texture-address units, one per CU
+                roof_extra["ta_busy_frac"] = round(ctr["ta_ta_busy_sum"] /
+                                                   (256 * CLOCK_GHZ * 1e9 * t_s), 4)
+            if ctr.get("tcp_tcc_read_req_sum"):
+                roof_extra["l2_read_latency_cycles"] = round(
+                    ctr["tcp_tcc_read_req_latency_sum"] / ctr["tcp_tcc_read_req_sum"], 1)
         log(f"[bench] linearisation: {lin_launches} launches, avg {avg_launch_ms * 1e3:.1f} us, "
             f"{bytes_per_launch / 1e6:.1f} MB algorithmic per launch "
             f"({bytes_union_per_launch / 1e6:.1f} MB with voxels counted once), "
@@ -644,6 +681,8 @@ def main():
                      "frac_of_copy": roof_extra["frac_of_copy"],
                      "l2_hit": roof_extra["l2_hit"], "valu_frac": roof_extra["valu_frac"],
                      "lds_frac": roof_extra["lds_frac"],
+                     "ta_busy_frac": roof_extra.get("ta_busy_frac"),
+                     "l2_read_latency_cycles": roof_extra.get("l2_read_latency_cycles"),
                      "kernel_sources_sha256_16": fp},
         "covariances": cov_row,
         "converged": conv,

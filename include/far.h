@@ -204,6 +204,14 @@ far_status_t far_gicp_linearize_async(far_map_t map, const float* src, const flo
                                       int32_t precision, int32_t* corr, far_lin_t* out,
                                       far_stream_t stream);
 
+/* Launch of the linearisation's tile passes (process-wide): blocks_per_cu 0
+ * (the default) launches one block per tile; n > 0 launches a persistent grid
+ * of n blocks per CU (rounded to a multiple of 8) in which each block takes
+ * tiles in turn, every tile staying on the XCD it has in the one-block-per-
+ * tile launch.  Results are identical for every setting; far_get_* reads it. */
+far_status_t far_set_linearize_grid(int32_t blocks_per_cu);
+far_status_t far_get_linearize_grid(int32_t* blocks_per_cu);
+
 /* Reserves the map's registration workspace (packed source, tile tables,
  * search queue, partial sums, sort buffers) for scans or batches of up to
  * max_points points and max_scans scans (the paper preallocates its GPU

@@ -661,11 +661,18 @@ __device__ inline bool voxel_index_fast(double x, double v, double inv_v, bool p
 // taking tile (b mod 8) * chunk + b / 8, so that each XCD works through one
 // contiguous range of tiles and neighbouring tiles (which share map voxels)
 // meet in the same L2.  -1 past the last tile.
-__device__ inline int64_t block_tile(int64_t n_tiles) {
+__device__ inline int64_t block_tile(int64_t n_tiles, int64_t b = -1) {
+  if (b < 0) b = blockIdx.x;
   const int64_t chunk = (n_tiles + 7) >> 3;
-  const int64_t t = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
-  return (t >= n_tiles || (blockIdx.x >> 3) >= chunk) ? -1 : t;
+  const int64_t t = (b & 7) * chunk + (b >> 3);
+  return (t >= n_tiles || (b >> 3) >= chunk) ? -1 : t;
 }
+
+// The tile passes run either one block per tile (gridDim = the virtual grid
+// vgrid, a multiple of 8) or as a persistent grid of fewer blocks, also a
+// multiple of 8, each taking virtual blocks b, b + gridDim.x, ... in turn
+// (so every virtual block keeps its XCD); the loop runs once in the first
+// case.
 
 // The pose of scan s: R row-major and t.
 struct Pose {
@@ -724,61 +731,71 @@ __global__ __launch_bounds__(64) void k_zero_bins(uint32_t* count) {
 // Pass 1, one block of kB lanes per tile: match[i] receives the vox_pts slot
 // of point i's match when the certificates settle it (-1: none), prev[i] the
 // seed of the next iteration; the other points are queued in lane order.
-template <int kB>
+template <int kB, bool kLoop>
 __global__ __launch_bounds__(kB) void k_cert(
     MapView m, const float4* __restrict__ pA, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,
     int64_t n_tiles, const double* __restrict__ T, const int32_t* __restrict__ done,
-    Params prm, int32_t* __restrict__ match, int32_t* __restrict__ prev, Queue Q) {
+    Params prm, int32_t* __restrict__ match, int32_t* __restrict__ prev, Queue Q,
+    int64_t vgrid) {
   constexpr int kWaves = kB / 64;
   __shared__ int32_t q_wcnt[kWaves];
   __shared__ uint32_t q_base;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t t = block_tile(n_tiles);
-  if (t < 0) return;
-  const int32_t s = tile_scan[t];
-  if (s < 0 || done[s]) return;
-  const Pose P(T + 16 * int64_t(s));
-  const uint32_t lo = tile_lo[t], hi = tile_hi[t];
-  const uint32_t i = lo + uint32_t(tid);
-  bool queued = false;
-  int32_t qc = -1;
-  double px = 0.0, py = 0.0, pz = 0.0;
-  if (i < hi) {
-    int64_t kx = 0, ky = 0, kz = 0;   // within [-2^20, 2^20) once locate holds
-    const bool have = locate(pA[i], P, m, prm, px, py, pz, kx, ky, kz);
-    Cand c;
-    c.pos = -1;
-    if (have && !nn_cert_try(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
-                             prev[i], c)) {
-      queued = true;
-      qc = c.pos;
-    } else {
-      match[i] = have && c.d <= prm.r2 ? c.pos : -1;
-      prev[i] = have ? c.pos : -1;
+  // one tile (virtual block vb)
+  auto tile_pass = [&](int64_t vb) {
+    const int64_t t = block_tile(n_tiles, vb);
+    if (t < 0) return;
+    const int32_t s = tile_scan[t];
+    if (s < 0 || done[s]) return;
+    const Pose P(T + 16 * int64_t(s));
+    const uint32_t lo = tile_lo[t], hi = tile_hi[t];
+    const uint32_t i = lo + uint32_t(tid);
+    bool queued = false;
+    int32_t qc = -1;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    if (i < hi) {
+      int64_t kx = 0, ky = 0, kz = 0;   // within [-2^20, 2^20) once locate holds
+      const bool have = locate(pA[i], P, m, prm, px, py, pz, kx, ky, kz);
+      Cand c;
+      c.pos = -1;
+      if (have && !nn_cert_try(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
+                               prev[i], c)) {
+        queued = true;
+        qc = c.pos;
+      } else {
+        match[i] = have && c.d <= prm.r2 ? c.pos : -1;
+        prev[i] = have ? c.pos : -1;
+      }
     }
-  }
-  const uint64_t bal = __ballot(queued);
-  if (lane == 0) q_wcnt[wave] = __popcll(bal);
-  __syncthreads();
-  int off = 0, total = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const int cw = q_wcnt[w];
-    off += w < wave ? cw : 0;
-    total += cw;
-  }
-  if (total == 0) return;
-  const int64_t bin = t % kBins;
-  if (tid == 0) q_base = atomicAdd(&Q.count[bin], uint32_t(total));
-  __syncthreads();
-  if (queued) {
-    const int64_t q = bin * Q.bin_cap + q_base + off + __popcll(bal & ((uint64_t(1) << lane) - 1));
-    Q.idx[q] = i;
-    Q.cand[q] = qc;
-    Q.p[q] = px;
-    Q.p[Q.cap + q] = py;
-    Q.p[2 * Q.cap + q] = pz;
+    const uint64_t bal = __ballot(queued);
+    if (lane == 0) q_wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0, total = 0;
+  #pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const int cw = q_wcnt[w];
+      off += w < wave ? cw : 0;
+      total += cw;
+    }
+    if (total == 0) return;
+    const int64_t bin = t % kBins;
+    if (tid == 0) q_base = atomicAdd(&Q.count[bin], uint32_t(total));
+    __syncthreads();
+    if (queued) {
+      const int64_t q = bin * Q.bin_cap + q_base + off + __popcll(bal & ((uint64_t(1) << lane) - 1));
+      Q.idx[q] = i;
+      Q.cand[q] = qc;
+      Q.p[q] = px;
+      Q.p[Q.cap + q] = py;
+      Q.p[2 * Q.cap + q] = pz;
+    }
+    __syncthreads();   // the LDS words are rewritten for the next tile
+  };
+  if constexpr (kLoop) {
+    for (int64_t vb = blockIdx.x; vb < vgrid; vb += gridDim.x) tile_pass(vb);
+  } else {
+    tile_pass(blockIdx.x);
   }
 }
 
@@ -845,7 +862,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_search(MapView m, Queue Q, P
 // point's source gradient written SoA at its original index (n_src apart).
 // kNoSA (the sparsity-aware case off) is a template parameter: a run-time
 // test in the match block costs the default path 8 %.
-template <class Real, bool kGrad, int kB, bool kFine, bool kNoSA, bool kSearch>
+template <class Real, bool kGrad, int kB, bool kFine, bool kNoSA, bool kSearch, bool kLoop>
 __global__ __launch_bounds__(kB) void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
     const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
@@ -853,116 +870,125 @@ __global__ __launch_bounds__(kB) void k_linearize(
     int64_t n_tiles, const double* __restrict__ T, const double* __restrict__ ctr,
     const int32_t* __restrict__ done, Params prm, double* __restrict__ partial,
     int32_t* __restrict__ corr, float* __restrict__ grad_src, int64_t n_src,
-    const int32_t* __restrict__ match, int32_t* __restrict__ prev) {
+    const int32_t* __restrict__ match, int32_t* __restrict__ prev, int64_t vgrid) {
   constexpr int kWaves = kB / 64;
   constexpr int kNV = kGrad ? 14 : kVals;
   __shared__ double red[kWaves][kNV];
   __shared__ float tbl[std::is_same<Real, float>::value ? kWaves : 1][kRedChunk * kRedRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t t = block_tile(n_tiles);
-  if (t < 0) return;
-  const int32_t s = tile_scan[t];
-  if (s < 0 || done[s]) return;
-  const Pose P(T + 16 * int64_t(s));
-  const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
-  const uint32_t lo = tile_lo[t], hi = tile_hi[t];
+  // one tile (virtual block vb)
+  auto tile_pass = [&](int64_t vb) {
+    const int64_t t = block_tile(n_tiles, vb);
+    if (t < 0) return;
+    const int32_t s = tile_scan[t];
+    if (s < 0 || done[s]) return;
+    const Pose P(T + 16 * int64_t(s));
+    const double cx = ctr[3 * s], cy = ctr[3 * s + 1], cz = ctr[3 * s + 2];
+    const uint32_t lo = tile_lo[t], hi = tile_hi[t];
 
-  Real acc[kNV];
-#pragma unroll
-  for (int q = 0; q < kNV; ++q) acc[q] = Real(0);
-  const uint32_t i = lo + uint32_t(tid);
-  if (i < hi) {
-    const float4 a = pA[i];
-    double px = 0.0, py = 0.0, pz = 0.0;
-    int32_t res = -1;
-    if constexpr (kSearch) {
-      int64_t kx = 0, ky = 0, kz = 0;
-      if (locate(a, P, m, prm, px, py, pz, kx, ky, kz)) {
-        TopK<1> top;
-        top.init();
-        if constexpr (kFine)
-          knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
-                       [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
-                         return fine_find(m, a0, a1, a2, n);
-                       },
-                       top);
-        else
-          nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, false, -1,
-                      0, top);
-        res = top.pos[0];
+    Real acc[kNV];
+  #pragma unroll
+    for (int q = 0; q < kNV; ++q) acc[q] = Real(0);
+    const uint32_t i = lo + uint32_t(tid);
+    if (i < hi) {
+      const float4 a = pA[i];
+      double px = 0.0, py = 0.0, pz = 0.0;
+      int32_t res = -1;
+      if constexpr (kSearch) {
+        int64_t kx = 0, ky = 0, kz = 0;
+        if (locate(a, P, m, prm, px, py, pz, kx, ky, kz)) {
+          TopK<1> top;
+          top.init();
+          if constexpr (kFine)
+            knn_cells<1>(px, py, pz, m.fc, m.inv_fc, true, true, prm.r2, m.fine_pts,
+                         [&](int64_t a0, int64_t a1, int64_t a2, int32_t* n) {
+                           return fine_find(m, a0, a1, a2, n);
+                         },
+                         top);
+          else
+            nn_lockstep(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2, false, -1,
+                        0, top);
+          res = top.pos[0];
+        }
+        if (!kFine && prev) prev[i] = res;
+      } else {
+        res = match[i];
       }
-      if (!kFine && prev) prev[i] = res;
+      int32_t id_match = -1;
+      Real gs[3] = {Real(0), Real(0), Real(0)};
+      if (res >= 0) {
+        if constexpr (!kSearch) {
+          int64_t kx, ky, kz;
+          (void)locate(a, P, m, prm, px, py, pz, kx, ky, kz);   // held when the match was made
+        }
+        const float4 r = kFine ? m.fine_pts[res] : m.vox_pts[res];
+        const int32_t id = __float_as_int(r.w);
+        const float4 sB = pB[i];
+        const float2 sC = pC[i];
+        // the match's covariance record, by vox_pts slot (beside the points the
+        // search read) or, for the fine index, by id
+        const float4* cr = kFine ? m.cov + 2 * int64_t(id) : m.vox_cov + 2 * int64_t(res);
+        const float4 ca = cr[0];
+        const float4 cb = cr[1];
+        // without the sparsity-aware case a pair lacking either covariance is
+        // dropped like an outlier
+        if (!kNoSA || (sB.x >= 0.0f && cb.z != 0.0f)) {
+          id_match = id;
+          if constexpr (kGrad)
+            grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, P.R, prm.kappa2, acc, gs);
+          else
+            gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, P.R, cx, cy, cz, prm.kappa2, acc);
+        }
+      }
+      if (corr) corr[__float_as_uint(a.w)] = id_match;
+      if (kGrad && grad_src) {
+        const uint32_t o = __float_as_uint(a.w);
+        grad_src[o] = float(gs[0]);
+        grad_src[n_src + o] = float(gs[1]);
+        grad_src[2 * n_src + o] = float(gs[2]);
+      }
+    }
+    // wave sums in FP64, then the block's waves
+    if constexpr (std::is_same<Real, float>::value) {
+      float* tb = tbl[wave];
+      const int v = lane >> 2, quarter = lane & 3;
+  #pragma unroll
+      for (int c0 = 0; c0 < kNV; c0 += kRedChunk) {
+        if (c0 > 0) __syncthreads();   // the previous pass's reads are done
+  #pragma unroll
+        for (int q = 0; q < kRedChunk; ++q)
+          if (c0 + q < kNV) tb[q * kRedRow + lane] = acc[c0 + q];
+        __syncthreads();
+        double sv = 0.0;
+        if (c0 + v < kNV) {
+          const float* row = tb + v * kRedRow + 16 * quarter;
+  #pragma unroll
+          for (int e = 0; e < 16; ++e) sv += double(row[e]);
+        }
+        sv += dpp_partner<0xB1>(sv);
+        sv += dpp_partner<0x4E>(sv);
+        if (quarter == 0 && c0 + v < kNV) red[wave][c0 + v] = sv;
+      }
     } else {
-      res = match[i];
-    }
-    int32_t id_match = -1;
-    Real gs[3] = {Real(0), Real(0), Real(0)};
-    if (res >= 0) {
-      if constexpr (!kSearch) {
-        int64_t kx, ky, kz;
-        (void)locate(a, P, m, prm, px, py, pz, kx, ky, kz);   // held when the match was made
-      }
-      const float4 r = kFine ? m.fine_pts[res] : m.vox_pts[res];
-      const int32_t id = __float_as_int(r.w);
-      const float4 sB = pB[i];
-      const float2 sC = pC[i];
-      // the match's covariance record, by vox_pts slot (beside the points the
-      // search read) or, for the fine index, by id
-      const float4* cr = kFine ? m.cov + 2 * int64_t(id) : m.vox_cov + 2 * int64_t(res);
-      const float4 ca = cr[0];
-      const float4 cb = cr[1];
-      // without the sparsity-aware case a pair lacking either covariance is
-      // dropped like an outlier
-      if (!kNoSA || (sB.x >= 0.0f && cb.z != 0.0f)) {
-        id_match = id;
-        if constexpr (kGrad)
-          grad_term<Real>(px, py, pz, a, r, ca, cb, sB, sC, P.R, prm.kappa2, acc, gs);
-        else
-          gicp_term<Real>(px, py, pz, r, ca, cb, sB, sC, P.R, cx, cy, cz, prm.kappa2, acc);
+  #pragma unroll
+      for (int q = 0; q < kNV; ++q) {
+        const double sv = wave_sum(acc[q]);
+        if (lane == 0) red[wave][q] = sv;
       }
     }
-    if (corr) corr[__float_as_uint(a.w)] = id_match;
-    if (kGrad && grad_src) {
-      const uint32_t o = __float_as_uint(a.w);
-      grad_src[o] = float(gs[0]);
-      grad_src[n_src + o] = float(gs[1]);
-      grad_src[2 * n_src + o] = float(gs[2]);
+    __syncthreads();
+    if (tid < kNV) {
+      double sum = 0.0;
+  #pragma unroll
+      for (int w = 0; w < kWaves; ++w) sum += red[w][tid];
+      partial[t * kStride + tid] = sum;
     }
-  }
-  // wave sums in FP64, then the block's waves
-  if constexpr (std::is_same<Real, float>::value) {
-    float* tb = tbl[wave];
-    const int v = lane >> 2, quarter = lane & 3;
-#pragma unroll
-    for (int c0 = 0; c0 < kNV; c0 += kRedChunk) {
-      if (c0 > 0) __syncthreads();   // the previous pass's reads are done
-#pragma unroll
-      for (int q = 0; q < kRedChunk; ++q)
-        if (c0 + q < kNV) tb[q * kRedRow + lane] = acc[c0 + q];
-      __syncthreads();
-      double sv = 0.0;
-      if (c0 + v < kNV) {
-        const float* row = tb + v * kRedRow + 16 * quarter;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) sv += double(row[e]);
-      }
-      sv += dpp_partner<0xB1>(sv);
-      sv += dpp_partner<0x4E>(sv);
-      if (quarter == 0 && c0 + v < kNV) red[wave][c0 + v] = sv;
-    }
+    __syncthreads();   // the LDS tables are rewritten for the next tile
+  };
+  if constexpr (kLoop) {
+    for (int64_t vb = blockIdx.x; vb < vgrid; vb += gridDim.x) tile_pass(vb);
   } else {
-#pragma unroll
-    for (int q = 0; q < kNV; ++q) {
-      const double sv = wave_sum(acc[q]);
-      if (lane == 0) red[wave][q] = sv;
-    }
-  }
-  __syncthreads();
-  if (tid < kNV) {
-    double sum = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) sum += red[w][tid];
-    partial[t * kStride + tid] = sum;
+    tile_pass(blockIdx.x);
   }
 }
 
@@ -1322,6 +1348,10 @@ struct Job {
   int32_t tile = kTileDefault; // points per tile (the map's schedule)
 };
 
+// Blocks per CU of the persistent launch of the tile passes (k_cert and the
+// term pass); 0: one block per tile.
+int32_t g_lin_blocks_per_cu = 0;
+
 // One linearisation (or gradient) at the map's tile size: the term pass
 // with its own exact search when there are no seeds (first), else the
 // certified search, the exact search of the queue and the term pass.
@@ -1332,26 +1362,30 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
   const bool fine = j.prm.fine_nn && mv.fine_ok;
   int32_t* prev = kGrad ? nullptr : w->prev;
   const bool search = first || fine || !prev;
+  const int64_t vgrid = grid;
+  if (g_lin_blocks_per_cu > 0) {
+    const int64_t pg = ((int64_t(g_lin_blocks_per_cu) * device_cu_count() + 7) / 8) * 8;
+    if (pg < grid) grid = pg;
+  }
   if (!search) {
     Queue Q{w->q_idx, w->q_cand, w->q_p, w->q_count, w->q_bin_cap, kBins * w->q_bin_cap};
     k_zero_bins<<<1, 64, 0, st>>>(w->q_count);
     FAR_HIP(hipGetLastError());
-    switch (tile) {
-      case 128:
-        k_cert<128><<<unsigned(grid), 128, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,
-                                                    w->tile_hi, max_tiles, j.T, w->done, j.prm,
-                                                    w->match, prev, Q);
-        break;
-      case 256:
-        k_cert<256><<<unsigned(grid), 256, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,
-                                                    w->tile_hi, max_tiles, j.T, w->done, j.prm,
-                                                    w->match, prev, Q);
-        break;
-      case 512:
-        k_cert<512><<<unsigned(grid), 512, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,
-                                                    w->tile_hi, max_tiles, j.T, w->done, j.prm,
-                                                    w->match, prev, Q);
-        break;
+    const bool loop = grid < vgrid;
+    switch (tile * 2 + (loop ? 1 : 0)) {
+#define FAR_CERT_CASE(B, L)                                                               \
+  case B * 2 + L:                                                                         \
+    k_cert<B, L><<<unsigned(grid), B, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,      \
+                                               w->tile_hi, max_tiles, j.T, w->done, j.prm, \
+                                               w->match, prev, Q, vgrid);                 \
+    break;
+      FAR_CERT_CASE(128, 0)
+      FAR_CERT_CASE(128, 1)
+      FAR_CERT_CASE(256, 0)
+      FAR_CERT_CASE(256, 1)
+      FAR_CERT_CASE(512, 0)
+      FAR_CERT_CASE(512, 1)
+#undef FAR_CERT_CASE
       default:
         set_error("internal: unsupported tile size %d", tile);
         return FAR_E_INVALID;
@@ -1361,21 +1395,29 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
                                                                          w->match, prev);
     FAR_HIP(hipGetLastError());
   }
-  switch (tile * 8 + (fine ? 4 : 0) + (j.prm.sa_off ? 2 : 0) + (search ? 1 : 0)) {
-#define FAR_LIN_CASE(B, F, N, X)                                                          \
-  case B * 8 + F * 4 + N * 2 + X:                                                         \
-    k_linearize<Real, kGrad, B, F, N, X><<<unsigned(grid), B, 0, st>>>(                  \
+  const bool loop = grid < vgrid;
+  switch (tile * 16 + (fine ? 8 : 0) + (j.prm.sa_off ? 4 : 0) + (search ? 2 : 0) +
+          (loop ? 1 : 0)) {
+#define FAR_LIN_CASE(B, F, N, X, L)                                                       \
+  case B * 16 + F * 8 + N * 4 + X * 2 + L:                                                \
+    k_linearize<Real, kGrad, B, F, N, X, L><<<unsigned(grid), B, 0, st>>>(               \
         mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
         w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
-        j.n_total, w->match, prev);                                                       \
+        j.n_total, w->match, prev, vgrid);                                                \
     break;
-#define FAR_LIN_CASES(B)        \
-    FAR_LIN_CASE(B, 0, 0, 0)    \
-    FAR_LIN_CASE(B, 0, 0, 1)    \
-    FAR_LIN_CASE(B, 0, 1, 0)    \
-    FAR_LIN_CASE(B, 0, 1, 1)    \
-    FAR_LIN_CASE(B, 1, 0, 1)    \
-    FAR_LIN_CASE(B, 1, 1, 1)
+#define FAR_LIN_CASES(B)           \
+    FAR_LIN_CASE(B, 0, 0, 0, 0)    \
+    FAR_LIN_CASE(B, 0, 0, 0, 1)    \
+    FAR_LIN_CASE(B, 0, 0, 1, 0)    \
+    FAR_LIN_CASE(B, 0, 0, 1, 1)    \
+    FAR_LIN_CASE(B, 0, 1, 0, 0)    \
+    FAR_LIN_CASE(B, 0, 1, 0, 1)    \
+    FAR_LIN_CASE(B, 0, 1, 1, 0)    \
+    FAR_LIN_CASE(B, 0, 1, 1, 1)    \
+    FAR_LIN_CASE(B, 1, 0, 1, 0)    \
+    FAR_LIN_CASE(B, 1, 0, 1, 1)    \
+    FAR_LIN_CASE(B, 1, 1, 1, 0)    \
+    FAR_LIN_CASE(B, 1, 1, 1, 1)
     FAR_LIN_CASES(128)
     FAR_LIN_CASES(256)
     FAR_LIN_CASES(512)
@@ -1634,6 +1676,24 @@ far_status_t far_gicp_linearize_async(far_map_t m, const float* src, const float
   FAR_TRY(run_job(m, j, st, false));
   k_copy_lin<<<1, 64, 0, st>>>(w->stats, out);
   FAR_HIP(hipGetLastError());
+  return FAR_OK;
+}
+
+far_status_t far_set_linearize_grid(int32_t blocks_per_cu) {
+  if (blocks_per_cu < 0 || blocks_per_cu > 64) {
+    set_error("far_set_linearize_grid: blocks_per_cu must be in [0, 64]");
+    return FAR_E_INVALID;
+  }
+  g_lin_blocks_per_cu = blocks_per_cu;
+  return FAR_OK;
+}
+
+far_status_t far_get_linearize_grid(int32_t* blocks_per_cu) {
+  if (!blocks_per_cu) {
+    set_error("far_get_linearize_grid: null argument");
+    return FAR_E_INVALID;
+  }
+  *blocks_per_cu = g_lin_blocks_per_cu;
   return FAR_OK;
 }
 

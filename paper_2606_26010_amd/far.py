@@ -107,6 +107,8 @@ _SIGS = {
                                            C.c_double, C.c_double, C.POINTER(C.c_double),
                                            C.c_int32, _P, _P, _P]),
     "far_map_reserve": (C.c_int, [_P, C.c_int64, C.c_int32, _P]),
+    "far_set_linearize_grid": (C.c_int, [C.c_int32]),
+    "far_get_linearize_grid": (C.c_int, [C.POINTER(C.c_int32)]),
     "far_gicp_gradient": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_double),
                                     C.c_double, C.c_double, C.POINTER(C.c_double), C.c_int32,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double), _P,
@@ -372,6 +374,16 @@ def lin_from_words(words):
     buf = np.ascontiguousarray(np.asarray(words, dtype=np.float64)[:LIN_WORDS])
     out = far_lin_t.from_buffer_copy(buf.tobytes())
     return _lin_dict(out)
+
+
+def far_set_linearize_grid(blocks_per_cu):
+    _check(lib().far_set_linearize_grid(int(blocks_per_cu)), "far_set_linearize_grid")
+
+
+def far_get_linearize_grid():
+    v = C.c_int32(0)
+    _check(lib().far_get_linearize_grid(C.byref(v)), "far_get_linearize_grid")
+    return v.value
 
 
 def far_map_reserve(h, max_points, max_scans=1, stream=None):

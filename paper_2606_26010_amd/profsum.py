@@ -2,6 +2,7 @@
 
     python -m paper_2606_26010_amd.profsum trace <kernel_stats.csv>
     python -m paper_2606_26010_amd.profsum counters <tile> <counter_collection.csv>...
+    python -m paper_2606_26010_amd.profsum kernel <name prefix> <counter_collection.csv>...
 
 `trace` prints calls, total and average duration per kernel.  `counters`
 prints, per GN-iteration linearisation of the batched align (its passes
@@ -23,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ["paper_2606_26010_amd/csrc/far_gicp.hip", "paper_2606_26010_amd/csrc/far_knn.h",
                   "paper_2606_26010_amd/csrc/far_internal.h"]
-LIN_PASSES = ("k_zero_bins", "k_cert", "k_search", "k_linearize")
+LIN_PASSES = ("k_zero_bins", "k_cert<", "k_search", "k_linearize<")
 
 
 def short(name):
@@ -55,7 +56,7 @@ def counters(tile, paths):
         lin = set()
         for r in csv.DictReader(open(p)):
             k = short(r["Kernel_Name"])
-            if not k.startswith(LIN_PASSES):
+            if not (k.startswith(LIN_PASSES[1:]) or k == LIN_PASSES[0]):
                 continue
             if k.startswith("k_linearize<"):
                 targs = [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")]
@@ -68,7 +69,7 @@ def counters(tile, paths):
         sys.exit(f"linearisation counts differ between runs or are zero: {n_lin}")
     per = {k: v / n for k, v in tot.items()}
     out = {"kernel_sources_sha256_16": fingerprint(), "tile": str(tile),
-           "kernels": "+".join(LIN_PASSES), "linearisations": n}
+           "kernels": "k_zero_bins+k_cert+k_search+k_linearize", "linearisations": n}
     g = per.get
     if "TCC_EA0_RDREQ_128B_sum" in per:
         out["fabric_read_bytes"] = (32 * g("TCC_EA0_RDREQ_32B_sum", 0) +
@@ -83,11 +84,38 @@ def counters(tile, paths):
              "SQ_WAVES": "waves", "SQ_WAVE_CYCLES": "wave_cycles",
              "SQ_BUSY_CU_CYCLES": "busy_cu_cycles", "FETCH_SIZE": "fetch_size_kib",
              "WRITE_SIZE": "write_size_kib"}
-    for c, k in names.items():
-        if c in per:
-            out[k] = per[c]
+    for c, v in sorted(per.items()):
+        out[names.get(c, c.lower())] = v
     for k, v in out.items():
         print(f"{k} = {v:.1f}" if isinstance(v, float) else f"{k} = {v}")
+
+
+def kernel(prefix, paths):
+    """Per-dispatch averages of every counter of the kernels whose name
+    starts with prefix, with the L2-to-fabric bytes as in counters()."""
+    tot = collections.defaultdict(float)
+    n_disp = {}
+    for p in paths:
+        disp = set()
+        for r in csv.DictReader(open(p)):
+            if short(r["Kernel_Name"]).startswith(prefix):
+                disp.add(r["Dispatch_Id"])
+                tot[r["Counter_Name"]] += float(r["Counter_Value"])
+        n_disp[p] = len(disp)
+    n = max(n_disp.values()) if n_disp else 0
+    if n == 0 or len(set(n_disp.values())) != 1:
+        sys.exit(f"dispatch counts differ between runs or are zero: {n_disp}")
+    per = {k: v / n for k, v in tot.items()}
+    print(f"kernel = {prefix}")
+    print(f"dispatches = {n}")
+    g = per.get
+    if "TCC_EA0_RDREQ_128B_sum" in per:
+        print(f"fabric_read_bytes = {32 * g('TCC_EA0_RDREQ_32B_sum', 0) + 64 * g('TCC_EA0_RDREQ_64B_sum', 0) + 128 * g('TCC_EA0_RDREQ_128B_sum', 0):.1f}")
+    if "TCC_EA0_WRREQ_sum" in per:
+        w64 = g("TCC_EA0_WRREQ_64B_sum", 0)
+        print(f"fabric_write_bytes = {64 * w64 + 32 * (g('TCC_EA0_WRREQ_sum') - w64):.1f}")
+    for c, v in sorted(per.items()):
+        print(f"{c.lower()} = {v:.1f}")
 
 
 def main(argv):
@@ -95,6 +123,8 @@ def main(argv):
         trace(argv[1])
     elif len(argv) >= 3 and argv[0] == "counters":
         counters(int(argv[1]), argv[2:])
+    elif len(argv) >= 3 and argv[0] == "kernel":
+        kernel(argv[1], argv[2:])
     else:
         sys.exit(__doc__)
 

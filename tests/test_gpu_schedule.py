@@ -125,3 +125,38 @@ def test_covariance_schedules_identical(small, orc):
         assert ms[(0, 16, 32, 64, 128).index(best)] <= 1.02 * min(ms)
     finally:
         far.far_set_covariance_schedule(saved)
+
+
+@pytest.mark.parametrize("tile", (128, 256, 512))
+def test_persistent_tile_passes_identical(small, tile):
+    """A persistent grid of the tile passes (each block taking tiles in turn)
+    gives the same poses and statistics, bit for bit, as one block per tile,
+    at every tile size and precision."""
+    far, c, gm, om, covs = small
+    far.far_map_set_schedule(gm.h, tile, 0)
+    sizes = np.array([s.shape[1] for s in c.scans])
+    offs = dev(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    src = dev(np.concatenate(c.scans, 1))
+    cov = dev(np.concatenate([cv[0] for cv in covs], 1).astype(np.float32))
+    val = dev(np.concatenate([cv[1] for cv in covs]))
+    T0 = dev(np.stack([t.reshape(16) for t in c.T0]))
+    try:
+        for prec in (0, 1):
+            prm = far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0,
+                                   precision=prec)
+            res = []
+            for g in (0, 1, 4):
+                far.far_set_linearize_grid(g)
+                assert far.far_get_linearize_grid() == g
+                T = T0.clone()
+                st = far.decode_stats(gm.align_batch(src, offs, cov, val, T, prm))
+                torch.cuda.synchronize()
+                res.append((host(T), st))
+            for T, st in res[1:]:
+                np.testing.assert_array_equal(T, res[0][0])
+                for k in ("iters", "status", "n_inliers", "cost"):
+                    np.testing.assert_array_equal(st[k], res[0][1][k])
+        print(f"tile {tile}: persistent grids of 1 and 4 blocks per CU identical", flush=True)
+    finally:
+        far.far_set_linearize_grid(0)
+        far.far_map_set_schedule(gm.h, 256, 0)

@@ -153,7 +153,6 @@ __device__ inline double wave_sum(double v) {
   v += __shfl_xor(v, 32, 64);
   return v;
 }
-__device__ inline double wave_sum(float v) { return wave_sum(double(v)); }
 
 // Wave sums of many FP32 values per lane through LDS (the FP32 kernels):
 // each lane stores its values as one column of a [value][lane] table whose
@@ -631,20 +630,6 @@ __device__ inline bool nn_cert_try(const MapView& m, double px, double py, doubl
   c.id = __float_as_int(c.p.w);
   c.d = dist2(double(c.p.x), double(c.p.y), double(c.p.z), px, py, pz);
   return certify(m, q, c);
-}
-
-// Second stage: the exact 27-voxel search, starting from candidate c (when
-// within the radius).  Returns the vox_pts slot of the match (-1: none
-// within the radius); *next is the slot to seed the next iteration with.
-__device__ inline int32_t nn_exact_from(const MapView& m, double px, double py, double pz,
-                                        int32_t kx, int32_t ky, int32_t kz, double r2,
-                                        const Cand& c, int32_t* next) {
-  TopK<1> top;
-  top.init();
-  if (c.pos >= 0 && c.d <= r2) top.push(c.d, c.id, c.pos);
-  nn_lockstep(m, px, py, pz, kx, ky, kz, r2, false, -1, 0, top);
-  *next = top.pos[0] >= 0 ? top.pos[0] : c.pos;
-  return top.pos[0];
 }
 
 // Voxel index with an exact multiply when 1/v is exact (power-of-two v),

@@ -264,22 +264,85 @@ __device__ inline float lb_down_sq(double g) {
   return __double2float_rd(g * g) * (1.0f - 0x1p-20f);
 }
 
+// Rank the cnt points of a run stored at pts[st ...] against q, taking them
+// outward from position i0 (the right side from i0 up, the left side from
+// i0 - 1 down), two per side at a time so that four loads are in flight.
+// In a run sorted by x up to a quantum, no point after the last one taken on
+// a side lies more than mx back towards the query along x than it, so the
+// side stops once that point's x gap less mx exceeds the current bound on
+// the distance (every later point is then strictly farther than the K-th
+// best or the radius).  mx = infinity never stops: the whole run is ranked.
+// The set ranked is a superset of the candidates that can enter, so the
+// result is the K best by (d2, id) whatever i0 is.
+template <int K>
+__device__ inline void scan_run_x(const float4* pts, int32_t st, int32_t cnt, int32_t i0,
+                                  Query& q, double r2, double mx, TopK<K>& top) {
+  const int32_t e = st + cnt;
+  int32_t r = i0, l = i0 - 1;
+  bool ra = r < e, la = l >= st;
+  while (ra || la) {
+    const bool u0 = ra, u1 = ra && r + 1 < e, u2 = la, u3 = la && l - 1 >= st;
+    float4 p0, p1, p2, p3;
+    if (u0) p0 = pts[r];
+    if (u1) p1 = pts[r + 1];
+    if (u2) p2 = pts[l];
+    if (u3) p3 = pts[l - 1];
+    auto rank_one = [&](const float4& pp, int32_t at) {
+      const float dx = pp.x - q.fx, dy = pp.y - q.fy, dz = pp.z - q.fz;
+      const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+      if (d2f <= q.bound_f) {
+        const double d = dist2(double(pp.x), double(pp.y), double(pp.z), q.x, q.y, q.z);
+        const int32_t id = __float_as_int(pp.w);
+        if (d <= r2 && rank_less(d, id, top.d[K - 1], top.id[K - 1])) {
+          top.push(d, id, at);
+          q.bound_f = screen_bound(fmin(r2, top.bound()), q.m);
+        }
+      }
+    };
+    if (u0) rank_one(p0, r);
+    if (u1) rank_one(p1, r + 1);
+    if (u2) rank_one(p2, l);
+    if (u3) rank_one(p3, l - 1);
+    // a gap g beats the bound b when g > 0 and g^2 (shrunk by 2^-40 against
+    // the rounding of the FP64 distances it stands for) exceeds b
+    const double b = fmin(r2, top.bound());
+    if (ra) {
+      const double g = (double(u1 ? p1.x : p0.x) - q.x) - mx;
+      r += u1 ? 2 : 1;
+      ra = r < e && !(g > 0.0 && g * g * (1.0 - 0x1p-40) > b);
+    }
+    if (la) {
+      const double g = (q.x - double(u3 ? p3.x : p2.x)) - mx;
+      l -= u3 ? 2 : 1;
+      la = l >= st && !(g > 0.0 && g * g * (1.0 - 0x1p-40) > b);
+    }
+  }
+}
+
 // Exact K nearest points within sqrt(r2) of p over a grid of cells of edge
 // c >= sqrt(r2) (the 27 cells around p's own cell hold every candidate),
 // with the visiting rule of knn_cells for range 1: own cell, then each
 // neighbour cell whose conservative lower bound can still beat the current
 // K-th best, taken in lockstep from a per-lane bit mask.  Bounds are kept as
-// floats and cell indices as 32-bit integers to save registers.
+// floats to save registers.  find(code, &cnt) gives the start of the run in
+// the cell at offset code = (ox+1)*9 + (oy+1)*3 + oz+1 from p's own cell (or
+// -1) and its length.  Each cell's
+// run is ranked by scan_run_x from where p's x falls in it: p's own sorted
+// position own in its own cell (own < 0: the run's start), the run's start
+// or end for the cells beside or behind p's along x, and for the cells of
+// p's own x layer the position that p's fraction of the cell width gives
+// (exact for any start; near p's x when the run's points spread evenly).
 template <int K, class Find>
 __device__ inline void knn_cells27(double px, double py, double pz, double c, double inv_c,
-                                   bool pow2, double r2, const float4* pts, Find find,
-                                   TopK<K>& top) {
+                                   bool pow2, double r2, const float4* pts, int32_t own,
+                                   double mx, Find find, TopK<K>& top) {
   top.init();
-  const double fx = floor(pow2 ? px * inv_c : px / c), fy = floor(pow2 ? py * inv_c : py / c),
+  const double tx = pow2 ? px * inv_c : px / c;
+  const double fx = floor(tx), fy = floor(pow2 ? py * inv_c : py / c),
                fz = floor(pow2 ? pz * inv_c : pz / c);
   const double lim = double(kKeyBias);
   if (!(fx >= -lim && fx < lim && fy >= -lim && fy < lim && fz >= -lim && fz < lim)) return;
-  const int32_t kx = int32_t(fx), ky = int32_t(fy), kz = int32_t(fz);
+  const float ux = float(tx - fx);     // p's fraction of its cell along x, in [0, 1]
   const double slack = 1e-7 * c;
   float gl2[3], gh2[3];
   gl2[0] = lb_down_sq(fmax(px - fx * c - slack, 0.0)); gh2[0] = lb_down_sq(fmax((fx + 1.0) * c - px - slack, 0.0));
@@ -287,8 +350,8 @@ __device__ inline void knn_cells27(double px, double py, double pz, double c, do
   gl2[2] = lb_down_sq(fmax(pz - fz * c - slack, 0.0)); gh2[2] = lb_down_sq(fmax((fz + 1.0) * c - pz - slack, 0.0));
   Query q = make_query(px, py, pz, r2);
   int32_t cnt;
-  int32_t st = find(kx, ky, kz, &cnt);
-  if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+  int32_t st = find(13, &cnt);
+  if (st >= 0) scan_run_x<K>(pts, st, cnt, own >= 0 ? own : st, q, r2, mx, top);
   // two plain selects per axis (a nested conditional compiles to divergent
   // branches for a run-time code); the value is the same
   auto gap = [](int o, float lo, float hi) {
@@ -318,8 +381,14 @@ __device__ inline void knn_cells27(double px, double py, double pz, double c, do
     need &= need - 1;
     const int code = nbr_code(rank);
     if (lb(code) > fmin(r2, top.bound())) continue;
-    st = find(kx + code / 9 - 1, ky + (code / 3) % 3 - 1, kz + code % 3 - 1, &cnt);
-    if (st >= 0) scan_voxel_points<K>(pts, st, cnt, q, r2, top);
+    const int ox = code / 9 - 1;
+    st = find(code, &cnt);
+    if (st >= 0) {
+      // start: cnt * (p's x position in cells from the cell's low face),
+      // clamped to the run: its end for ox = -1, its start for ox = 1
+      const float w = fminf(fmaxf(float(cnt) * (ux - float(ox)), 0.0f), float(cnt));
+      scan_run_x<K>(pts, st, cnt, st + min(int32_t(w), cnt), q, r2, mx, top);
+    }
   }
 }
 

@@ -666,25 +666,60 @@ struct GridView {
   double c;          // grid cell edge (v / 2 when v is a power of two, else v)
   double inv_c;
   int32_t pow2;
-  int32_t log2_slots;
-  uint32_t slot_mask;
+  const int64_t* part;        // scan offsets: the slots of each scan (NULL: one scan)
+  uint32_t n_slots;           // two per point
+  double mx;         // runs sorted by x up to a quantum: how far a later point of
+                     // a run can lie below an earlier one along x (infinity:
+                     // runs unordered)
+  const uint32_t* head;       // 1 where a run starts
+  const uint32_t* head_scan;  // exclusive prefix of head: run of j = head_scan + head - 1
+  const uint2* nbt;           // per run, its 27 cells (code (ox+1)*9 + (oy+1)*3 + oz+1) as
+                              // (start, count) in sorted; count 0: no run there
 };
 
-__device__ inline uint32_t grid_hash(int64_t kx, int64_t ky, int64_t kz, uint32_t sid,
-                                     int log2_slots) {
-  return voxel_hash(kx ^ int64_t(sid * 2654435761u), ky, kz, log2_slots);
+// Slots of scan sc: two per point of the scan (its points are positions
+// offsets[sc] .. offsets[sc + 1] of the sorted order, so at most half of its
+// slots fill), or the whole table for a single scan.  Each scan's cells are
+// hashed into its own stretch, so that the lookups of one scan, which the
+// sorted order brings together, stay in a few MB of the table (one XCD's L2).
+__device__ inline void grid_part(const GridView& g, uint32_t sc, uint32_t* base,
+                                 uint32_t* size) {
+  if (g.part) {
+    const int64_t a = g.part[sc], b = g.part[sc + 1];
+    *base = uint32_t(2 * a);
+    *size = uint32_t(2 * (b - a));
+  } else {
+    *base = 0;
+    *size = g.n_slots;
+  }
 }
 
+__device__ inline uint32_t grid_hash(int64_t kx, int64_t ky, int64_t kz, uint32_t size) {
+  const uint32_t h = (uint32_t(kx) * 73856093u) ^ (uint32_t(ky) * 19349669u) ^
+                     (uint32_t(kz) * 83492791u);
+  const uint32_t m = uint32_t((uint64_t(h) * 0x9E3779B97F4A7C15ull) >> 32);
+  return uint32_t((uint64_t(m) * size) >> 32);
+}
+
+// Run of cell (kx, ky, kz) of scan sid: its start in sorted (or -1) and in
+// *cnt its length.  A slot holds the cell's key, the run's start and its
+// length (the scan is implied by the stretch of slots).
 __device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, int64_t kz,
-                                    uint32_t sid) {
+                                    uint32_t sid, int32_t* cnt) {
+  *cnt = 0;
   if (!key_ok(kx) || !key_ok(ky) || !key_ok(kz)) return -1;
-  uint64_t key = pack_key(kx, ky, kz);
-  uint32_t s = grid_hash(kx, ky, kz, sid, g.log2_slots);
-  for (uint32_t probe = 0; probe <= g.slot_mask; ++probe) {
-    const Slot sl = g.slots[s];
-    if (sl.key == key && uint32_t(sl.aux) == sid) return sl.vox;
+  const uint64_t key = pack_key(kx, ky, kz);
+  uint32_t base, size;
+  grid_part(g, sid, &base, &size);
+  uint32_t s = grid_hash(kx, ky, kz, size);
+  for (uint32_t probe = 0; probe < size; ++probe) {
+    const Slot sl = g.slots[base + s];
+    if (sl.key == key) {
+      *cnt = sl.aux;
+      return sl.vox;
+    }
     if (sl.key == kEmptyKey) return -1;
-    s = (s + 1) & g.slot_mask;
+    s = s + 1 == size ? 0 : s + 1;
   }
   return -1;
 }
@@ -814,6 +849,7 @@ struct CompactKey {
   int32_t mx, my, mz;   // per-axis minimum
   int32_t by, bz;       // bits of y and z
   int32_t kb;           // key bits (x, y, z); 1 << kb marks an empty key
+  int32_t fb;           // bits of the point's x within its cell, below the key
 };
 
 __global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n, double v,
@@ -831,14 +867,19 @@ __global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n
     }
     s = lo;
   }
-  uint64_t key = uint64_t(1) << ck.kb;
+  uint64_t key = uint64_t(1) << (ck.kb + ck.fb);
   const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
   int64_t kx, ky, kz;
   if (isfinite(x) && isfinite(y) && isfinite(z) && voxel_index(double(x), v, &kx) &&
-      voxel_index(double(y), v, &ky) && voxel_index(double(z), v, &kz))
-    key = (uint64_t(kx - ck.mx) << (ck.by + ck.bz)) | (uint64_t(ky - ck.my) << ck.bz) |
-          uint64_t(kz - ck.mz);
-  keys[i] = (uint64_t(s) << (ck.kb + 1)) | key;
+      voxel_index(double(y), v, &ky) && voxel_index(double(z), v, &kz)) {
+    // x / v less its floor is exact and non-decreasing in x within a cell,
+    // so the fb bits below the key sort each run by x up to 2^-fb cells
+    const double t = double(x) / v;
+    const uint64_t xq = uint64_t(fmin((t - floor(t)) * ldexp(1.0, ck.fb), ldexp(1.0, ck.fb) - 1.0));
+    key = (((uint64_t(kx - ck.mx) << (ck.by + ck.bz)) | (uint64_t(ky - ck.my) << ck.bz) |
+            uint64_t(kz - ck.mz)) << ck.fb) | xq;
+  }
+  keys[i] = (uint64_t(s) << (ck.kb + ck.fb + 1)) | key;
   vals[i] = uint32_t(i);
 }
 
@@ -849,7 +890,7 @@ __global__ __launch_bounds__(kT) void k_keys_expand(const uint64_t* ckeys, int64
                                                     uint32_t* sid) {
   const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
   if (i >= n) return;
-  const uint64_t c = ckeys[i];
+  const uint64_t c = ckeys[i] >> ck.fb;
   const uint64_t k = c & ((uint64_t(2) << ck.kb) - 1);
   if (sid) sid[i] = uint32_t(c >> (ck.kb + 1));
   if (k >> ck.kb) {
@@ -894,27 +935,56 @@ __global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t 
   sorted[j] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], __int_as_float(int32_t(i)));
 }
 
-__global__ __launch_bounds__(kT) void k_grid_claim(Slot* slots, uint32_t slot_mask,
-                                                   int log2_slots, const uint64_t* keys,
-                                                   const uint32_t* sid,
-                                                   const uint32_t* seg_start, int64_t n_seg) {
-  int64_t s = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (s >= n_seg) return;
-  uint32_t j = seg_start[s];
-  uint64_t key = keys[j];
-  uint32_t sc = sid ? sid[j] : 0u;
-  uint32_t h = grid_hash(key_x(key), key_y(key), key_z(key), sc, log2_slots);
-  for (uint32_t probe = 0; probe <= slot_mask; ++probe) {
-    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[h].key),
+// Runs into the slots of their scans, one thread per run; blocks dealt to
+// the XCDs in contiguous ranges of runs (so one XCD fills one scan's slots).
+__global__ __launch_bounds__(kT) void k_grid_claim(GridView g, Slot* slots, int64_t n_seg) {
+  const int64_t nb = (n_seg + kT - 1) / kT, chunk = (nb + 7) >> 3;
+  const int64_t r = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * kT + threadIdx.x;
+  if ((blockIdx.x >> 3) >= chunk || r >= n_seg) return;
+  const uint32_t j = g.seg_start[r];
+  const uint64_t key = g.keys[j];
+  const uint32_t sc = g.sid ? g.sid[j] : 0u;
+  uint32_t base, size;
+  grid_part(g, sc, &base, &size);
+  uint32_t h = grid_hash(key_x(key), key_y(key), key_z(key), size);
+  for (uint32_t probe = 0; probe < size; ++probe) {
+    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[base + h].key),
                                        (unsigned long long)kEmptyKey,
                                        (unsigned long long)key);
     if (old == kEmptyKey) {
-      slots[h].vox = int32_t(s);
-      slots[h].aux = int32_t(sc);
+      slots[base + h].vox = int32_t(j);
+      slots[base + h].aux = int32_t(g.seg_end[r] - j);
       return;
     }
-    h = (h + 1) & slot_mask;
+    h = h + 1 == size ? 0 : h + 1;
   }
+}
+
+// Neighbour table of the runs: per run, the (start, count) of the run of the
+// same scan in each of its 27 cells, so that a point's search reads its
+// cells from its run's row instead of probing the hash for each.  One thread
+// per (run, cell), blocks dealt to the XCDs in contiguous ranges (one XCD
+// probes one scan's stretch of slots at a time); the rows are written with
+// non-temporal stores so that they stream past the L2 holding the slots.
+__global__ __launch_bounds__(kT) void k_grid_nbr_table(GridView g, int64_t n_seg, uint2* nbt) {
+  const int64_t nb = (n_seg * 27 + kT - 1) / kT, chunk = (nb + 7) >> 3;
+  const int64_t t = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * kT + threadIdx.x;
+  if ((blockIdx.x >> 3) >= chunk || t >= n_seg * 27) return;
+  const int64_t r = t / 27;
+  const int code = int(t - r * 27);
+  const uint32_t s0 = g.seg_start[r];
+  uint32_t a = s0, c = g.seg_end[r] - s0;
+  if (code != 13) {
+    const uint64_t key = g.keys[s0];
+    const uint32_t sc = g.sid ? g.sid[s0] : 0u;
+    int32_t cnt;
+    const int32_t f = grid_find(g, key_x(key) + code / 9 - 1, key_y(key) + (code / 3) % 3 - 1,
+                                key_z(key) + code % 3 - 1, sc, &cnt);
+    a = f < 0 ? 0u : uint32_t(f);
+    c = f < 0 ? 0u : uint32_t(cnt);
+  }
+  __builtin_nontemporal_store(a, &nbt[t].x);
+  __builtin_nontemporal_store(c, &nbt[t].y);
 }
 
 // Squared face distance as a float never above the FP64 value (rounded
@@ -923,10 +993,10 @@ __device__ inline float face_lb(double g) { return __double2float_rd(g * g) * (1
 
 // Covariances, one wave per grid run (the points of one scan in one voxel of
 // edge v).  All of a run's queries share one 27-voxel neighbourhood (every
-// point within v of them lies in it), so the wave looks the 26 neighbours up
-// once and walks each needed voxel's points at wave-uniform addresses, every
-// lane testing the same candidate against its own query; a voxel that no
-// lane's current k-th distance can reach is skipped.  Exact, like the
+// point within v of them lies in it), so the wave reads the run's row of the
+// neighbour table once and walks each needed voxel's points at wave-uniform
+// addresses, every lane testing the same candidate against its own query; a
+// voxel that no lane's current k-th distance can reach is skipped.  Exact, like the
 // per-point search: ranking by (d2, id) over a superset of the candidates.
 // Runs are dealt to the XCDs in contiguous ranges, as the linearisation's
 // tiles are.  Only runs of at least `dense` points are taken: in sparse runs
@@ -944,22 +1014,11 @@ __global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg,
   const uint32_t s0 = g.seg_start[sg], s1 = g.seg_end[sg];
   if (int64_t(s1 - s0) < dense) return;   // sparse runs: the per-point search
   const uint64_t key = g.keys[s0];
-  const uint32_t sc = g.sid ? g.sid[s0] : 0u;
   const int64_t kx = key_x(key), ky = key_y(key), kz = key_z(key);
-  if (lane < 27) {
-    int32_t st = -1, cnt = 0;
-    if (lane == 13) {
-      st = int32_t(s0);
-      cnt = int32_t(s1 - s0);
-    } else {
-      const int32_t r = grid_find(g, kx + lane / 9 - 1, ky + (lane / 3) % 3 - 1, kz + lane % 3 - 1, sc);
-      if (r >= 0) {
-        st = int32_t(g.seg_start[r]);
-        cnt = int32_t(g.seg_end[r] - g.seg_start[r]);
-      }
-    }
-    nb_start[lane] = st;
-    nb_cnt[lane] = cnt;
+  if (lane < 27) {   // the run's row of the neighbour table
+    const uint2 e = g.nbt[sg * 27 + lane];
+    nb_start[lane] = e.y ? int32_t(e.x) : -1;
+    nb_cnt[lane] = int32_t(e.y);
   }
   __syncthreads();
   const double v = g.v, r2 = v * v, slack = 1e-7 * v;
@@ -1017,8 +1076,13 @@ template <int K>
 __global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32_t dense, int64_t n,
                                                                int32_t k, int32_t reg,
                                                                float* cov6, uint8_t* valid) {
-  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n) return;
+  // blocks dealt to the eight XCDs in contiguous ranges of the sorted
+  // points: the neighbour voxels a block reads are those of the blocks
+  // around it, which then share that XCD's L2
+  const int64_t nb = (n + kT - 1) / kT, chunk = (nb + 7) >> 3;
+  const int64_t b = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  const int64_t j = b * kT + threadIdx.x;
+  if ((blockIdx.x >> 3) >= chunk || j >= n) return;
   const float4 me = g.sorted[j];
   if (g.keys[j] == kEmptyKey) {   // a non-finite point: zero covariance, invalid
     const int64_t i = __float_as_int(me.w);
@@ -1027,23 +1091,17 @@ __global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32
     valid[i] = 0;
     return;
   }
-  const uint32_t sc = g.sid ? g.sid[j] : 0u;
   const double qx = me.x, qy = me.y, qz = me.z;
-  if (dense > 0) {
-    const uint64_t own = g.keys[j];
-    const int32_t so = grid_find(g, key_x(own), key_y(own), key_z(own), sc);
-    if (so >= 0 && int32_t(g.seg_end[so] - g.seg_start[so]) >= dense) return;
-  }
+  // the cells around the point's own cell (the cell of its run's key: the
+  // same coordinates and cell edge) from its run's row of the neighbour table
+  const uint2* row = g.nbt + int64_t(g.head_scan[j] + g.head[j] - 1) * 27;
+  if (dense > 0 && int32_t(row[13].y) >= dense) return;
   TopK<K> top;
-  knn_cells27<K>(qx, qy, qz, g.c, g.inv_c, g.pow2 != 0, g.v * g.v, g.sorted,
-                 [&](int32_t a0, int32_t a1, int32_t a2, int32_t* cnt) {
-                   const int32_t s = grid_find(g, a0, a1, a2, sc);
-                   if (s < 0) {
-                     *cnt = 0;
-                     return int32_t(-1);
-                   }
-                   *cnt = int32_t(g.seg_end[s] - g.seg_start[s]);
-                   return int32_t(g.seg_start[s]);
+  knn_cells27<K>(qx, qy, qz, g.c, g.inv_c, g.pow2 != 0, g.v * g.v, g.sorted, int32_t(j), g.mx,
+                 [&](int code, int32_t* cnt) {
+                   const uint2 e = row[code];
+                   *cnt = int32_t(e.y);
+                   return e.y ? int32_t(e.x) : int32_t(-1);
                  },
                  top);
   double c6[6] = {0, 0, 0, 0, 0, 0};
@@ -1567,14 +1625,17 @@ far_status_t far_map_knn(far_map_t m, const float* q, int64_t n, int32_t k, doub
 // *oor receives the number of points whose cell key is out of range (the
 // grid is then not built).
 // The runs of a scan grid sorted by (scan, key) through compact keys (see
-// k_key_range).  *used = false when the batch has no finite point or its key
+// k_key_range), and each run by x up to 2^-*fb_out cells (*fb_out = 0: runs
+// unordered).  *used = false when the batch has no finite point or its key
 // range needs more than 62 bits with the scan id; *oor receives the points
 // whose keys leave [-2^20, 2^20) (nothing else is done then).
 static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets, int32_t S_,
                                        int64_t n, double cell, hipStream_t st, Scratch& scr,
-                                       Runs& r, uint32_t** sid_out, bool* used, uint32_t* oor) {
+                                       Runs& r, uint32_t** sid_out, bool* used, uint32_t* oor,
+                                       int* fb_out) {
   *used = false;
   *oor = 0;
+  *fb_out = 0;
   const int64_t nb = (n + int64_t(kT) * kRangePts - 1) / (int64_t(kT) * kRangePts);
   int32_t *part, *rng;
   uint32_t* part_oor;
@@ -1598,8 +1659,11 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
   ck.by = ceil_log2(int64_t(h[4]) - h[1] + 1);
   ck.bz = ceil_log2(int64_t(h[5]) - h[2] + 1);
   ck.kb = bx + ck.by + ck.bz;
-  const int bits = (S_ > 1 ? ceil_log2(S_) : 0) + ck.kb + 1;
-  if (bits > 62) return FAR_OK;
+  const int key_bits = (S_ > 1 ? ceil_log2(S_) : 0) + ck.kb + 1;
+  if (key_bits > 62) return FAR_OK;
+  // x bits: one more radix pass of 8 bits (8 to 15 bits), within 62 in all
+  ck.fb = std::min(((key_bits + 15) / 8) * 8 - key_bits, 62 - key_bits);
+  const int bits = key_bits + ck.fb;
   uint64_t *ckeys, *ckeys_alt;
   uint32_t* vals_alt;
   FAR_TRY(scr.get(&ckeys, size_t(n)));
@@ -1631,6 +1695,7 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
   FAR_HIP(hipGetLastError());
   *sid_out = sid;
   *used = true;
+  *fb_out = ck.fb;
   return FAR_OK;
 }
 
@@ -1640,7 +1705,8 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   Runs r;
   uint32_t* sid = nullptr;
   bool compact = false;
-  FAR_TRY(build_runs_compact(xyz, offsets, S_, n, cell, st, scr, r, &sid, &compact, oor));
+  int fb = 0;
+  FAR_TRY(build_runs_compact(xyz, offsets, S_, n, cell, st, scr, r, &sid, &compact, oor, &fb));
   if (*oor > 0) return FAR_OK;
   if (!compact) FAR_TRY(build_runs(xyz, n, cell, st, scr, r));
   uint64_t* keys = r.keys;
@@ -1680,9 +1746,8 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   }
   const int64_t n_seg = h_cnt[2];
   if (runs) *runs = n_seg;
-  int log2_slots = ceil_log2(2 * (n_seg > 0 ? n_seg : 1));
-  if (log2_slots < 6) log2_slots = 6;
-  const int64_t n_slots = int64_t(1) << log2_slots;
+  // two slots per point, each scan's in its own stretch (n < 2^31)
+  const int64_t n_slots = 2 * n;
   Slot* slots;
   float4* sorted;
   FAR_TRY(scr.get(&slots, size_t(n_slots)));
@@ -1690,15 +1755,24 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
   k_gather_sorted<<<blocks_for(n), kT, 0, st>>>(xyz, n, vals, sorted);
   FAR_HIP(hipGetLastError());
-  if (n_seg > 0) {
-    k_grid_claim<<<blocks_for(n_seg), kT, 0, st>>>(slots, uint32_t(n_slots - 1), log2_slots,
-                                                   keys, sid, r.seg_start, n_seg);
-    FAR_HIP(hipGetLastError());
-  }
   int e2 = 0;
   const int32_t pow2 = std::frexp(cell, &e2) == 0.5 ? 1 : 0;
+  // a later point of an x-sorted run lies at most one quantum (2^-fb cells,
+  // plus the rounding of x / cell) below an earlier one; twice that is kept
+  const double mx = compact && fb > 0 ? std::ldexp(cell, 1 - fb) : HUGE_VAL;
   *out = GridView{slots, sorted, keys, sid, r.seg_start, r.seg_end, v, cell, 1.0 / cell, pow2,
-                  log2_slots, uint32_t(n_slots - 1)};
+                  S_ > 1 ? offsets : nullptr, uint32_t(n_slots), mx, r.head, r.head_scan,
+                  nullptr};
+  if (n_seg > 0) {
+    uint2* nbt;
+    FAR_TRY(scr.get(&nbt, size_t(n_seg) * 27));
+    k_grid_claim<<<unsigned(((blocks_for(n_seg) + 7) / 8) * 8), kT, 0, st>>>(*out, slots, n_seg);
+    FAR_HIP(hipGetLastError());
+    k_grid_nbr_table<<<unsigned(((blocks_for(n_seg * 27) + 7) / 8) * 8), kT, 0, st>>>(*out, n_seg,
+                                                                                   nbt);
+    FAR_HIP(hipGetLastError());
+    out->nbt = nbt;
+  }
   return FAR_OK;
 }
 
@@ -1727,7 +1801,8 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
   }
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
-    k_grid_cov<K><<<blocks_for(n), kT, 0, st>>>(g, dense, n, k, g_cov_reg, cov6, valid);
+    const int64_t cov_grid = ((blocks_for(n) + 7) / 8) * 8;
+    k_grid_cov<K><<<unsigned(cov_grid), kT, 0, st>>>(g, dense, n, k, g_cov_reg, cov6, valid);
     FAR_HIP(hipGetLastError());
     if (dense > 0) {
       const int64_t grid = ((n_seg + 7) / 8) * 8;

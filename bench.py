@@ -283,6 +283,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the one-scan-per-launch path")
     ap.add_argument("--cpu-sample-scans", type=int, default=3)
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the steps pipelined over two streams")
     ap.add_argument("--no-converged", action="store_true",
                     help="skip the secondary run of the same batch to convergence")
     ap.add_argument("--conv-iters", type=int, default=40)
@@ -437,12 +439,55 @@ def main():
         t_step = (time.perf_counter() - t0) / args.steps
         stats = far.decode_stats(stats_buf)
         T_gpu = T.cpu().numpy().reshape(S, 4, 4)
+
         iters = stats["iters"].astype(np.int64)
         failed = stats["status"] != 0
         lin_per_scan = iters + failed.astype(np.int64)   # a failing iteration still linearised
         point_lins = int(np.sum(lin_per_scan * sizes))
         log(f"[bench] step {t_step * 1e3:.3f} ms, iterations {iters.min()}..{iters.max()}, "
             f"status {np.bincount(stats['status'], minlength=6).tolist()}")
+
+        # ---------------- the same steps pipelined over two streams: the
+        # covariances of batch k+1 on one stream beside the align of batch k
+        # on another (default priorities, double-buffered covariances); every
+        # step still does all of its work.  Reported beside the headline.
+        piped = None
+        if not args.no_pipelined:
+            s_al = torch.cuda.Stream()
+            cov_b = [cov_buf, torch.empty_like(cov_buf)]
+            val_b = [val_buf, torch.empty_like(val_buf)]
+            ev_cov = [torch.cuda.Event(), torch.cuda.Event()]
+            ev_al = [torch.cuda.Event(), torch.cuda.Event()]
+            for e in ev_al:
+                e.record(s_al)
+
+            def step_piped(k):
+                b = k % 2
+                stream.wait_event(ev_al[b])     # the align that read buffer b is done
+                far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
+                                               out=(cov_b[b], val_b[b]))
+                ev_cov[b].record(stream)
+                with torch.cuda.stream(s_al):
+                    s_al.wait_event(ev_cov[b])
+                    T.copy_(T0)
+                    far.far_gicp_align_batch(gm.h, src, offs, cov_b[b], val_b[b], T, prm,
+                                             stats=stats_buf)
+                    ev_al[b].record(s_al)
+
+            for k in range(max(args.warmup, 4)):   # both buffers' aligns captured
+                step_piped(k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                step_piped(k)
+            torch.cuda.synchronize()
+            t_piped = (time.perf_counter() - t0) / args.steps
+            same = bool(np.array_equal(T.cpu().numpy().reshape(S, 4, 4), T_gpu))
+            piped = {"ms_per_step": round(t_piped * 1e3, 4),
+                     "value": round(point_lins / t_piped, 1),
+                     "scans_per_s": round(S / t_piped, 2), "same_poses": same}
+            log(f"[bench] pipelined over two streams: {t_piped * 1e3:.3f} ms per step, "
+                f"poses {'identical' if same else 'DIFFER'}")
 
         # ---------------- roofline of the linearisation (event-timed launches)
         far.far_timing_read(reset=True)
@@ -685,6 +730,7 @@ def main():
                      "l2_read_latency_cycles": roof_extra.get("l2_read_latency_cycles"),
                      "kernel_sources_sha256_16": fp},
         "covariances": cov_row,
+        "pipelined_two_streams": piped,
         "converged": conv,
         "cpu_baseline": cpu,
         "single_scan_path": single,

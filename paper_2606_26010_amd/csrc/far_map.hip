@@ -675,6 +675,7 @@ struct GridView {
   const uint32_t* head_scan;  // exclusive prefix of head: run of j = head_scan + head - 1
   const uint2* nbt;           // per run, its 27 cells (code (ox+1)*9 + (oy+1)*3 + oz+1) as
                               // (start, count) in sorted; count 0: no run there
+  const uint32_t* n_runs;     // the number of runs (device)
 };
 
 // Slots of scan sc: two per point of the scan (its points are positions
@@ -935,12 +936,22 @@ __global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t 
   sorted[j] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], __int_as_float(int32_t(i)));
 }
 
-// Runs into the slots of their scans, one thread per run; blocks dealt to
-// the XCDs in contiguous ranges of runs (so one XCD fills one scan's slots).
-__global__ __launch_bounds__(kT) void k_grid_claim(GridView g, Slot* slots, int64_t n_seg) {
-  const int64_t nb = (n_seg + kT - 1) / kT, chunk = (nb + 7) >> 3;
-  const int64_t r = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * kT + threadIdx.x;
-  if ((blockIdx.x >> 3) >= chunk || r >= n_seg) return;
+// The run count stays on the device: the grid-wide kernels over runs are
+// persistent grids (kGridBlocks blocks, a multiple of 8) that split the items
+// into eight contiguous ranges, one per XCD, and walk their range in steps
+// of the XCD's blocks.
+constexpr int kGridBlocks = 8 * 1024;
+
+template <class F>
+__device__ inline void xcd_ranges(int64_t total, F f) {
+  const int64_t chunk = (total + 7) >> 3;
+  const int64_t lo = int64_t(blockIdx.x & 7) * chunk, hi = min(lo + chunk, total);
+  const int64_t step = int64_t(gridDim.x >> 3) * kT;
+  for (int64_t t = lo + int64_t(blockIdx.x >> 3) * kT + threadIdx.x; t < hi; t += step) f(t);
+}
+
+// Run r into the slots of its scan (one XCD fills one scan's slots at a time).
+__device__ inline void grid_claim_run(const GridView& g, Slot* slots, int64_t r) {
   const uint32_t j = g.seg_start[r];
   const uint64_t key = g.keys[j];
   const uint32_t sc = g.sid ? g.sid[j] : 0u;
@@ -960,16 +971,17 @@ __global__ __launch_bounds__(kT) void k_grid_claim(GridView g, Slot* slots, int6
   }
 }
 
+__global__ __launch_bounds__(kT) void k_grid_claim(GridView g, Slot* slots) {
+  xcd_ranges(*g.n_runs, [&](int64_t r) { grid_claim_run(g, slots, r); });
+}
+
 // Neighbour table of the runs: per run, the (start, count) of the run of the
 // same scan in each of its 27 cells, so that a point's search reads its
 // cells from its run's row instead of probing the hash for each.  One thread
-// per (run, cell), blocks dealt to the XCDs in contiguous ranges (one XCD
-// probes one scan's stretch of slots at a time); the rows are written with
-// non-temporal stores so that they stream past the L2 holding the slots.
-__global__ __launch_bounds__(kT) void k_grid_nbr_table(GridView g, int64_t n_seg, uint2* nbt) {
-  const int64_t nb = (n_seg * 27 + kT - 1) / kT, chunk = (nb + 7) >> 3;
-  const int64_t t = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * kT + threadIdx.x;
-  if ((blockIdx.x >> 3) >= chunk || t >= n_seg * 27) return;
+// per (run, cell) entry t, the entries in XCD ranges (one XCD probes one
+// scan's stretch of slots at a time); the rows are written with non-temporal
+// stores so that they stream past the L2 holding the slots.
+__device__ inline void grid_nbr_entry(const GridView& g, uint2* nbt, int64_t t) {
   const int64_t r = t / 27;
   const int code = int(t - r * 27);
   const uint32_t s0 = g.seg_start[r];
@@ -987,6 +999,10 @@ __global__ __launch_bounds__(kT) void k_grid_nbr_table(GridView g, int64_t n_seg
   __builtin_nontemporal_store(c, &nbt[t].y);
 }
 
+__global__ __launch_bounds__(kT) void k_grid_nbr_table(GridView g, uint2* nbt) {
+  xcd_ranges(int64_t(*g.n_runs) * 27, [&](int64_t t) { grid_nbr_entry(g, nbt, t); });
+}
+
 // Squared face distance as a float never above the FP64 value (rounded
 // down, shrunk by 2^-20 to cover the float sums of three terms).
 __device__ inline float face_lb(double g) { return __double2float_rd(g * g) * (1.0f - 0x1p-20f); }
@@ -996,21 +1012,17 @@ __device__ inline float face_lb(double g) { return __double2float_rd(g * g) * (1
 // point within v of them lies in it), so the wave reads the run's row of the
 // neighbour table once and walks each needed voxel's points at wave-uniform
 // addresses, every lane testing the same candidate against its own query; a
-// voxel that no lane's current k-th distance can reach is skipped.  Exact, like the
-// per-point search: ranking by (d2, id) over a superset of the candidates.
-// Runs are dealt to the XCDs in contiguous ranges, as the linearisation's
-// tiles are.  Only runs of at least `dense` points are taken: in sparse runs
+// voxel that no lane's current k-th distance can reach is skipped.  Exact,
+// like the per-point search: ranking by (d2, id) over a superset of the
+// candidates.  Only runs of at least `dense` points are taken: in sparse runs
 // most lanes would idle while the wave walks the neighbourhood.
 template <int K>
-__global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg, int32_t dense,
-                                                      int64_t n, int32_t k, int32_t reg,
-                                                      float* cov6, uint8_t* valid) {
-  __shared__ int32_t nb_start[27];
-  __shared__ int32_t nb_cnt[27];
-  const int64_t chunk = (n_seg + 7) >> 3;
-  const int64_t sg = int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
-  if (sg >= n_seg || (blockIdx.x >> 3) >= chunk) return;
+__device__ inline void grid_cov_run(const GridView& g, int64_t sg, int32_t dense, int64_t n,
+                                    int32_t k, int32_t reg, float* cov6, uint8_t* valid,
+                                    int32_t* nb_start, int32_t* nb_cnt) {
   const int lane = threadIdx.x;
+  __syncthreads();   // the previous run's readers of nb_start and nb_cnt are done
+  __syncthreads();   // the previous run's readers of nb_start and nb_cnt are done
   const uint32_t s0 = g.seg_start[sg], s1 = g.seg_end[sg];
   if (int64_t(s1 - s0) < dense) return;   // sparse runs: the per-point search
   const uint64_t key = g.keys[s0];
@@ -1061,6 +1073,21 @@ __global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int64_t n_seg,
       valid[i] = ok ? 1 : 0;
     }
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_grid_cov_wave(GridView g, int32_t dense, int64_t n,
+                                                      int32_t k, int32_t reg, float* cov6,
+                                                      uint8_t* valid) {
+  __shared__ int32_t nb_start[27];
+  __shared__ int32_t nb_cnt[27];
+  // the runs in eight contiguous ranges, one per XCD; each block of an XCD
+  // takes every (gridDim / 8)-th run of its range
+  const int64_t n_seg = *g.n_runs;
+  const int64_t chunk = (n_seg + 7) >> 3;
+  const int64_t lo = int64_t(blockIdx.x & 7) * chunk, hi = min(lo + chunk, n_seg);
+  for (int64_t sg = lo + (blockIdx.x >> 3); sg < hi; sg += gridDim.x >> 3)
+    grid_cov_run<K>(g, sg, dense, n, k, reg, cov6, valid, nb_start, nb_cnt);
 }
 
 // Covariance of every scan point from its k nearest points of the same scan
@@ -1701,7 +1728,7 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
 
 static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t S_, int64_t n,
                                double v, double cell, hipStream_t st, Scratch& scr,
-                               GridView* out, uint32_t* oor, int64_t* runs = nullptr) {
+                               GridView* out, uint32_t* oor) {
   Runs r;
   uint32_t* sid = nullptr;
   bool compact = false;
@@ -1737,15 +1764,15 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
                                                 r.seg_start, r.seg_end);
     FAR_HIP(hipGetLastError());
   }
-  uint32_t h_cnt[4];
-  FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
-  FAR_HIP(hipStreamSynchronize(st));
-  if (!compact) {
+  if (!compact) {   // keys out of range are found by the full-key pass only
+    uint32_t h_cnt[4];
+    FAR_HIP(hipMemcpyAsync(h_cnt, r.counters, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+    FAR_HIP(hipStreamSynchronize(st));
     *oor = h_cnt[1];
     if (h_cnt[1] > 0) return FAR_OK;
   }
-  const int64_t n_seg = h_cnt[2];
-  if (runs) *runs = n_seg;
+  // The number of runs stays on the device (r.counters[2]): the kernels below
+  // are launched for one run per point and read it.
   // two slots per point, each scan's in its own stretch (n < 2^31)
   const int64_t n_slots = 2 * n;
   Slot* slots;
@@ -1760,19 +1787,15 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   // a later point of an x-sorted run lies at most one quantum (2^-fb cells,
   // plus the rounding of x / cell) below an earlier one; twice that is kept
   const double mx = compact && fb > 0 ? std::ldexp(cell, 1 - fb) : HUGE_VAL;
+  uint2* nbt;
+  FAR_TRY(scr.get(&nbt, size_t(n) * 27));
   *out = GridView{slots, sorted, keys, sid, r.seg_start, r.seg_end, v, cell, 1.0 / cell, pow2,
                   S_ > 1 ? offsets : nullptr, uint32_t(n_slots), mx, r.head, r.head_scan,
-                  nullptr};
-  if (n_seg > 0) {
-    uint2* nbt;
-    FAR_TRY(scr.get(&nbt, size_t(n_seg) * 27));
-    k_grid_claim<<<unsigned(((blocks_for(n_seg) + 7) / 8) * 8), kT, 0, st>>>(*out, slots, n_seg);
-    FAR_HIP(hipGetLastError());
-    k_grid_nbr_table<<<unsigned(((blocks_for(n_seg * 27) + 7) / 8) * 8), kT, 0, st>>>(*out, n_seg,
-                                                                                   nbt);
-    FAR_HIP(hipGetLastError());
-    out->nbt = nbt;
-  }
+                  nbt, r.counters + 2};
+  k_grid_claim<<<kGridBlocks, kT, 0, st>>>(*out, slots);
+  FAR_HIP(hipGetLastError());
+  k_grid_nbr_table<<<kGridBlocks, kT, 0, st>>>(*out, nbt);
+  FAR_HIP(hipGetLastError());
   return FAR_OK;
 }
 
@@ -1787,27 +1810,21 @@ static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int3
   TimedScope ts(FAR_TIME_COVARIANCES, st);
   GridView g{};
   uint32_t oor = 0;
-  int64_t n_seg = 0;
-  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor, &n_seg));
+  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor));
   if (oor > 0) {
     set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, oor);
     return FAR_E_INVALID;
   }
   const int32_t dense = g_dense_threshold;
-  if (n_seg == 0) {   // no finite point: every covariance zero, invalid
-    FAR_HIP(hipMemsetAsync(cov6, 0, size_t(n) * 6 * sizeof(float), st));
-    FAR_HIP(hipMemsetAsync(valid, 0, size_t(n), st));
-    return FAR_OK;
-  }
+  // (a batch with no finite point has no runs: every point takes the
+  // non-finite branch of k_grid_cov, zero covariance and invalid)
   return dispatch_k(k, [&](auto KK) -> far_status_t {
     constexpr int K = decltype(KK)::value;
     const int64_t cov_grid = ((blocks_for(n) + 7) / 8) * 8;
     k_grid_cov<K><<<unsigned(cov_grid), kT, 0, st>>>(g, dense, n, k, g_cov_reg, cov6, valid);
     FAR_HIP(hipGetLastError());
-    if (dense > 0) {
-      const int64_t grid = ((n_seg + 7) / 8) * 8;
-      k_grid_cov_wave<K><<<unsigned(grid), 64, 0, st>>>(g, n_seg, dense, n, k, g_cov_reg,
-                                                        cov6, valid);
+    if (dense > 0) {   // a persistent grid of 64 waves per CU over the runs
+      k_grid_cov_wave<K><<<256 * 64, 64, 0, st>>>(g, dense, n, k, g_cov_reg, cov6, valid);
       FAR_HIP(hipGetLastError());
     }
     return FAR_OK;

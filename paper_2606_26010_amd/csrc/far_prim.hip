@@ -102,55 +102,106 @@ __global__ __launch_bounds__(kThreads) void k_rs_hist(const uint64_t* keys, int6
   hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one 8-bit digit.  Each block walks its tile in rounds of
-// 256 elements in index order; within a round an element's rank among equal
-// digits is (equal digits in lower waves) + (equal digits in lower lanes),
-// the latter found with eight ballots.
+// Stable scatter of one 8-bit digit.  Each block ranks its tile in LDS, then
+// writes it out digit by digit, so that equal digits of a tile land in
+// consecutive addresses (whole cache lines) instead of one scattered element
+// per lane.  Each wave ranks its own contiguous quarter of the tile in index
+// order, 64 elements a round: an element's rank among equal digits is the
+// wave's running count of its digit plus its equal digits in lower lanes
+// (found with eight ballots); one prefix over the waves per digit then
+// places the quarters after each other.  hist holds the exclusive prefix,
+// digit-major, of the per-block digit counts, so a block's count of digit d
+// is the difference of its entry and the next one (n after the last).
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint64_t* kin,
                                                          const uint32_t* vin, uint64_t* kout,
                                                          uint32_t* vout, int64_t n, int shift,
                                                          const uint32_t* hist,
                                                          int64_t nblocks) {
-  __shared__ uint32_t base[256];
+  constexpr int kPerWave = kSortTile / kWaves;
+  constexpr int kRounds = kPerWave / 64;
+  __shared__ uint64_t lkey[kSortTile];
+  __shared__ uint32_t lval[kSortTile];
+  __shared__ uint32_t gbase[256];   // global start of this block's digit d
+  __shared__ uint32_t lbase[256];   // local start of digit d in the tile
   __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t wsum[kWaves];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  base[t] = hist[int64_t(t) * nblocks + blockIdx.x];
+  const int64_t blk = int64_t(blockIdx.x) * kSortTile;
+  const int64_t wbase = blk + int64_t(wave) * kPerWave;
+  // the wave's quarter into registers first, so that ranking does not wait
+  uint64_t kr[kRounds];
+  uint32_t vr[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    kr[r] = i < n ? kin[i] : 0ull;
+    vr[r] = i < n ? vin[i] : 0u;
+  }
+  const int64_t hi = int64_t(t) * nblocks + blockIdx.x;
+  const uint32_t g0 = hist[hi];
+  const uint32_t cnt = (hi + 1 < 256 * nblocks ? hist[hi + 1] : uint32_t(n)) - g0;
+  gbase[t] = g0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) wcnt[w][t] = 0;
+  // exclusive prefix of the 256 counts: within each wave, then across waves
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
   __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  lbase[t] = before + incl - cnt;
+  // rank inside the wave's quarter (the wave's LDS operations stay in order,
+  // so a group's leader updates the count after every lane of it has read it)
   const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
-  const int64_t blk = int64_t(blockIdx.x) * kSortTile;
-  for (int r = 0; r < kSortItems; ++r) {
-    int64_t i = blk + int64_t(r) * kThreads + t;
-    bool ok = i < n;
-    uint64_t k = ok ? kin[i] : 0ull;
-    uint32_t val = ok ? vin[i] : 0u;
-    uint32_t d = uint32_t(k >> shift) & 255u;
+  uint32_t pos[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool ok = wbase + r * 64 + lane < n;
+    const uint32_t d = uint32_t(kr[r] >> shift) & 255u;
     uint64_t m = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      bool bit = (d >> b) & 1u;
-      uint64_t bal = __ballot(bit);
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
       m &= bit ? bal : ~bal;
     }
-    uint32_t rank = __popcll(m & lower);
-    if (ok && rank == 0) wcnt[wave][d] = __popcll(m);
-    __syncthreads();
-    if (ok) {
-      uint32_t off = base[d] + rank;
-      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
-      kout[off] = k;
-      vout[off] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    const uint32_t rank = __popcll(m & lower);
+    const uint32_t prev = wcnt[wave][d];
+    pos[r] = prev + rank;
+    if (ok && rank == 0) wcnt[wave][d] = prev + __popcll(m);
+  }
+  __syncthreads();
+  // per digit, the waves' quarters one after the other from the digit's start
+  uint32_t run = lbase[t];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      add += wcnt[w][t];
-      wcnt[w][t] = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t c = wcnt[w][t];
+    wcnt[w][t] = run;
+    run += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r)
+    if (wbase + r * 64 + lane < n) {
+      const uint32_t off = wcnt[wave][uint32_t(kr[r] >> shift) & 255u] + pos[r];
+      lkey[off] = kr[r];
+      lval[off] = vr[r];
     }
-    base[t] += add;
-    __syncthreads();
+  __syncthreads();
+  // write out in local order: consecutive positions of one digit go to
+  // consecutive global addresses
+  const int tile = int(min(int64_t(kSortTile), n - blk));
+  for (int p = t; p < tile; p += kThreads) {
+    const uint64_t k = lkey[p];
+    const uint32_t d = uint32_t(k >> shift) & 255u;
+    const uint32_t off = gbase[d] + uint32_t(p) - lbase[d];
+    kout[off] = k;
+    vout[off] = lval[p];
   }
 }
 

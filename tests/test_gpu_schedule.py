@@ -160,3 +160,39 @@ def test_persistent_tile_passes_identical(small, tile):
     finally:
         far.far_set_linearize_grid(0)
         far.far_map_set_schedule(gm.h, 256, 0)
+
+
+def test_two_buffers_replay_captured_aligns(small):
+    """Aligns that take two covariance buffers in turn (as steps pipelined over
+    two streams do) are captured once each and replayed: every call gives
+    the poses and statistics of the first, bit for bit, including after the
+    tile-pass launch changes (a graph captured for one launch is not replayed
+    for another)."""
+    far, c, gm, om, covs = small
+    sizes = np.array([s.shape[1] for s in c.scans])
+    offs = dev(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    src = dev(np.concatenate(c.scans, 1))
+    cov = dev(np.concatenate([cv[0] for cv in covs], 1).astype(np.float32))
+    val = dev(np.concatenate([cv[1] for cv in covs]))
+    bufs = [(cov, val), (cov.clone(), val.clone())]
+    T0 = dev(np.stack([t.reshape(16) for t in c.T0]))
+    prm = far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0)
+    stream = torch.cuda.Stream()
+    res = []
+    try:
+        with torch.cuda.stream(stream):
+            for g in (0, 4):
+                far.far_set_linearize_grid(g)
+                for k in range(6):
+                    cv, vl = bufs[k % 2]
+                    T = T0.clone()
+                    st = far.decode_stats(gm.align_batch(src, offs, cv, vl, T, prm))
+                    stream.synchronize()
+                    res.append((host(T), st))
+    finally:
+        far.far_set_linearize_grid(0)
+    for T, st in res[1:]:
+        np.testing.assert_array_equal(T, res[0][0])
+        for k in ("iters", "status", "n_inliers", "cost"):
+            np.testing.assert_array_equal(st[k], res[0][1][k])
+    print(f"{len(res)} aligns over two buffers and two launches identical", flush=True)

@@ -216,10 +216,21 @@ __global__ __launch_bounds__(256) void k_fill_none(int32_t* a, int64_t n) {
   if (i < n) a[i] = -1;
 }
 
+// Index of this thread's item when blocks are dealt to the eight XCDs in
+// contiguous ranges (a grid of 8 * ceil(blocks / 8)); -1 past the end.  The
+// sort keeps each scan's points in the scan's own index range, so the
+// scattered writes of a block stay in the few MB of the scans its XCD works
+// through, in that XCD's L2.
+__device__ inline int64_t xcd_item(int64_t n) {
+  const int64_t nb = (n + 255) / 256, chunk = (nb + 7) >> 3;
+  const int64_t i = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * 256 + threadIdx.x;
+  return ((blockIdx.x >> 3) >= chunk || i >= n) ? -1 : i;
+}
+
 __global__ __launch_bounds__(256) void k_invert(const uint32_t* perm, int64_t n,
                                                 uint32_t* inv) {
-  int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (m < n) inv[perm[m]] = uint32_t(m);
+  const int64_t m = xcd_item(n);
+  if (m >= 0) inv[perm[m]] = uint32_t(m);
 }
 
 // Pack in key order: read the caller's SoA arrays in their own order
@@ -228,8 +239,8 @@ __global__ __launch_bounds__(256) void k_pack(const float* src, const float* cov
                                               const uint8_t* valid, int64_t n,
                                               const uint32_t* inv, float4* A, float4* B,
                                               float2* C) {
-  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i = xcd_item(n);
+  if (i < 0) return;
   uint32_t m = inv[i];
   A[m] = make_float4(src[i], src[n + i], src[2 * n + i], __int_as_float(int32_t(i)));
   bool ok = valid[i] != 0;
@@ -1451,9 +1462,10 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
                              24 + ceil_log2_i(j.S), st, scr, &in_alt));
     uint32_t* perm = in_alt ? w->ovals_alt : w->ovals;
     uint32_t* inv = in_alt ? w->ovals : w->ovals_alt;
-    k_invert<<<nb, 256, 0, st>>>(perm, j.n_total, inv);
+    const unsigned nb8 = ((nb + 7) / 8) * 8;
+    k_invert<<<nb8, 256, 0, st>>>(perm, j.n_total, inv);
     FAR_HIP(hipGetLastError());
-    k_pack<<<nb, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total, inv, w->pA, w->pB, w->pC);
+    k_pack<<<nb8, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total, inv, w->pA, w->pB, w->pC);
     FAR_HIP(hipGetLastError());
     k_fill_none<<<nb, 256, 0, st>>>(w->prev, j.n_total);
     FAR_HIP(hipGetLastError());

@@ -765,8 +765,18 @@ __global__ __launch_bounds__(kT) void k_apply_perm(const uint32_t* perm, int64_t
 // atomics); points without a finite, in-range key sort last in their scan.
 constexpr int kRangePts = 16;                // points per lane of the range pass
 
+// floor(x / v) as voxel_index computes it, through an exact multiply by 1/v
+// when v is a power of two.
+__device__ inline bool voxel_index_p2(double x, double v, double inv_v, bool pow2, int64_t* k) {
+  const double f = floor(pow2 ? x * inv_v : x / v);
+  if (!(f >= -double(kKeyBias) && f < double(kKeyBias))) return false;
+  *k = int64_t(f);
+  return true;
+}
+
 __global__ __launch_bounds__(kT) void k_key_range(const float* xyz, int64_t n, double v,
-                                                  int32_t* part, uint32_t* part_oor) {
+                                                  double inv_v, int32_t pow2, int32_t* part,
+                                                  uint32_t* part_oor) {
   __shared__ int32_t s_r[kT / 64][6];
   __shared__ uint32_t s_o[kT / 64];
   int32_t r[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
@@ -778,8 +788,9 @@ __global__ __launch_bounds__(kT) void k_key_range(const float* xyz, int64_t n, d
     const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
     if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
     int64_t kx, ky, kz;
-    if (voxel_index(double(x), v, &kx) && voxel_index(double(y), v, &ky) &&
-        voxel_index(double(z), v, &kz)) {
+    if (voxel_index_p2(double(x), v, inv_v, pow2, &kx) &&
+        voxel_index_p2(double(y), v, inv_v, pow2, &ky) &&
+        voxel_index_p2(double(z), v, inv_v, pow2, &kz)) {
       r[0] = min(r[0], int32_t(kx)); r[3] = max(r[3], int32_t(kx));
       r[1] = min(r[1], int32_t(ky)); r[4] = max(r[4], int32_t(ky));
       r[2] = min(r[2], int32_t(kz)); r[5] = max(r[5], int32_t(kz));
@@ -854,6 +865,7 @@ struct CompactKey {
 };
 
 __global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n, double v,
+                                                     double inv_v, int32_t pow2,
                                                      const int64_t* offsets, int32_t S,
                                                      CompactKey ck, uint64_t* keys,
                                                      uint32_t* vals) {
@@ -871,11 +883,13 @@ __global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n
   uint64_t key = uint64_t(1) << (ck.kb + ck.fb);
   const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
   int64_t kx, ky, kz;
-  if (isfinite(x) && isfinite(y) && isfinite(z) && voxel_index(double(x), v, &kx) &&
-      voxel_index(double(y), v, &ky) && voxel_index(double(z), v, &kz)) {
+  if (isfinite(x) && isfinite(y) && isfinite(z) &&
+      voxel_index_p2(double(x), v, inv_v, pow2, &kx) &&
+      voxel_index_p2(double(y), v, inv_v, pow2, &ky) &&
+      voxel_index_p2(double(z), v, inv_v, pow2, &kz)) {
     // x / v less its floor is exact and non-decreasing in x within a cell,
     // so the fb bits below the key sort each run by x up to 2^-fb cells
-    const double t = double(x) / v;
+    const double t = pow2 ? double(x) * inv_v : double(x) / v;
     const uint64_t xq = uint64_t(fmin((t - floor(t)) * ldexp(1.0, ck.fb), ldexp(1.0, ck.fb) - 1.0));
     key = (((uint64_t(kx - ck.mx) << (ck.by + ck.bz)) | (uint64_t(ky - ck.my) << ck.bz) |
             uint64_t(kz - ck.mz)) << ck.fb) | xq;
@@ -928,10 +942,14 @@ __global__ __launch_bounds__(kT) void k_grid_bounds(const uint64_t* keys, const 
     seg_end[s] = uint32_t(j + 1);
 }
 
+// Sorted points as float4, blocks dealt to the XCDs in contiguous ranges (a
+// scan's points stay in the scan's index range, so each XCD gathers from the
+// few MB of its own scans).
 __global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t n,
                                                       const uint32_t* vals, float4* sorted) {
-  int64_t j = int64_t(blockIdx.x) * kT + threadIdx.x;
-  if (j >= n) return;
+  const int64_t nb = (n + kT - 1) / kT, chunk = (nb + 7) >> 3;
+  const int64_t j = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * kT + threadIdx.x;
+  if ((blockIdx.x >> 3) >= chunk || j >= n) return;
   uint32_t i = vals[j];
   sorted[j] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], __int_as_float(int32_t(i)));
 }
@@ -1669,7 +1687,9 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
   FAR_TRY(scr.get(&part, size_t(nb) * 6));
   FAR_TRY(scr.get(&part_oor, size_t(nb)));
   FAR_TRY(scr.get(&rng, 7));
-  k_key_range<<<unsigned(nb), kT, 0, st>>>(xyz, n, cell, part, part_oor);
+  int e2 = 0;
+  const int32_t pow2 = std::frexp(cell, &e2) == 0.5 ? 1 : 0;
+  k_key_range<<<unsigned(nb), kT, 0, st>>>(xyz, n, cell, 1.0 / cell, pow2, part, part_oor);
   FAR_HIP(hipGetLastError());
   k_key_range_final<<<1, kT, 0, st>>>(part, part_oor, nb, rng);
   FAR_HIP(hipGetLastError());
@@ -1706,8 +1726,9 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
   uint32_t* sid = nullptr;
   if (S_ > 1) FAR_TRY(scr.get(&sid, size_t(n)));
   FAR_HIP(hipMemsetAsync(r.counters, 0, 4 * sizeof(uint32_t), st));
-  k_keys_compact<<<blocks_for(n), kT, 0, st>>>(xyz, n, cell, S_ > 1 ? offsets : nullptr, S_,
-                                                ck, ckeys, r.vals);
+  k_keys_compact<<<blocks_for(n), kT, 0, st>>>(xyz, n, cell, 1.0 / cell, pow2,
+                                                S_ > 1 ? offsets : nullptr, S_, ck, ckeys,
+                                                r.vals);
   FAR_HIP(hipGetLastError());
   bool alt = false;
   FAR_TRY(radix_sort_pairs(ckeys, r.vals, ckeys_alt, vals_alt, n, bits, st, scr, &alt));
@@ -1780,7 +1801,7 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   FAR_TRY(scr.get(&slots, size_t(n_slots)));
   FAR_TRY(scr.get(&sorted, size_t(n)));
   FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
-  k_gather_sorted<<<blocks_for(n), kT, 0, st>>>(xyz, n, vals, sorted);
+  k_gather_sorted<<<unsigned(((blocks_for(n) + 7) / 8) * 8), kT, 0, st>>>(xyz, n, vals, sorted);
   FAR_HIP(hipGetLastError());
   int e2 = 0;
   const int32_t pow2 = std::frexp(cell, &e2) == 0.5 ? 1 : 0;

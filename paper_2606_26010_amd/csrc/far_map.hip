@@ -1040,7 +1040,6 @@ __device__ inline void grid_cov_run(const GridView& g, int64_t sg, int32_t dense
                                     int32_t* nb_start, int32_t* nb_cnt) {
   const int lane = threadIdx.x;
   __syncthreads();   // the previous run's readers of nb_start and nb_cnt are done
-  __syncthreads();   // the previous run's readers of nb_start and nb_cnt are done
   const uint32_t s0 = g.seg_start[sg], s1 = g.seg_end[sg];
   if (int64_t(s1 - s0) < dense) return;   // sparse runs: the per-point search
   const uint64_t key = g.keys[s0];

@@ -976,13 +976,16 @@ __device__ inline void grid_claim_run(const GridView& g, Slot* slots, int64_t r)
   uint32_t base, size;
   grid_part(g, sc, &base, &size);
   uint32_t h = grid_hash(key_x(key), key_y(key), key_z(key), size);
+  const uint32_t cnt = g.seg_end[r] - j;   // >= 1, so never the empty word
+  // every run is a different cell, so a slot is claimed on its length word
+  // alone (a 32-bit compare-and-swap); key and start follow as plain stores,
+  // read only by later kernels
   for (uint32_t probe = 0; probe < size; ++probe) {
-    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&slots[base + h].key),
-                                       (unsigned long long)kEmptyKey,
-                                       (unsigned long long)key);
-    if (old == kEmptyKey) {
+    const uint32_t old = atomicCAS(reinterpret_cast<uint32_t*>(&slots[base + h].aux),
+                                   0xFFFFFFFFu, cnt);
+    if (old == 0xFFFFFFFFu) {
+      slots[base + h].key = key;
       slots[base + h].vox = int32_t(j);
-      slots[base + h].aux = int32_t(g.seg_end[r] - j);
       return;
     }
     h = h + 1 == size ? 0 : h + 1;

@@ -178,6 +178,19 @@ far_status_t far_scan_covariances_batch(const float* xyz, const int64_t* offsets
                                         int64_t n_total, double voxel_size, int32_t k,
                                         float* cov6, uint8_t* valid, far_stream_t stream);
 
+/* far_scan_covariances_batch that also returns the order its grid sorted the
+ * points in: order [dev, n_total] uint32 receives, for each position j of
+ * the (scan, voxel key, x) order, the index of the point there.  Each scan's
+ * points keep the scan's own index range, and points of one voxel are
+ * adjacent, so the order is a spatially compact layout of every scan; the
+ * align below takes it in place of sorting the source itself.  Ownership:
+ * order is the caller's; it is written in full (n_total entries).  Errors as
+ * far_scan_covariances_batch, and FAR_E_INVALID when order is null. */
+far_status_t far_scan_covariances_batch_order(const float* xyz, const int64_t* offsets,
+                                              int32_t S, int64_t n_total, double voxel_size,
+                                              int32_t k, float* cov6, uint8_t* valid,
+                                              uint32_t* order, far_stream_t stream);
+
 /* One GICP linearisation (Eqs. 3-5, sparsity-aware) of the scan src
  * [dev, SoA 3 x n] with covariances cov6 [dev, SoA 6 x n] and valid [dev, n]
  * against the map at pose T [host]: p = R s + t in FP64; correspondence = the
@@ -282,6 +295,22 @@ far_status_t far_gicp_align_batch(far_map_t map, const float* src, const int64_t
                                   const uint8_t* valid, double* T,
                                   const far_align_params_t* params,
                                   far_align_stats_t* stats, far_stream_t stream);
+
+/* far_gicp_align_batch with the source packed in the caller's order instead
+ * of its own locality sort (a sort by scan and Morton code of the
+ * sensor-frame voxel): order [dev, n_total] uint32 must be a permutation
+ * that keeps every scan's points in the scan's own index range, such as the
+ * one far_scan_covariances_batch_order returns for the same batch, so the
+ * step sorts its points once.  The order changes only the rounding order of
+ * the FP64 sums.  An order that is not such a permutation gives meaningless
+ * poses (entries out of range are skipped, nothing is written out of
+ * bounds).  FAR_E_INVALID when order is null and n_total > 0. */
+far_status_t far_gicp_align_batch_ordered(far_map_t map, const float* src,
+                                          const int64_t* offsets, int32_t S, int64_t n_total,
+                                          const float* cov6, const uint8_t* valid,
+                                          const uint32_t* order, double* T,
+                                          const far_align_params_t* params,
+                                          far_align_stats_t* stats, far_stream_t stream);
 
 /* Launch schedule of the linearisation on a map (the tile and probe schedule
  * of the batched iteration).  tile: points per block and tile, 128, 256

@@ -227,10 +227,13 @@ __device__ inline int64_t xcd_item(int64_t n) {
   return ((blockIdx.x >> 3) >= chunk || i >= n) ? -1 : i;
 }
 
+// inv = perm^-1.  A caller's order is trusted to be a permutation of its
+// scans' own ranges (else the results are meaningless); entries out of range
+// are skipped so that nothing is written out of bounds.
 __global__ __launch_bounds__(256) void k_invert(const uint32_t* perm, int64_t n,
                                                 uint32_t* inv) {
   const int64_t m = xcd_item(n);
-  if (m >= 0) inv[perm[m]] = uint32_t(m);
+  if (m >= 0 && perm[m] < uint64_t(n)) inv[perm[m]] = uint32_t(m);
 }
 
 // Pack in key order: read the caller's SoA arrays in their own order
@@ -242,6 +245,7 @@ __global__ __launch_bounds__(256) void k_pack(const float* src, const float* cov
   const int64_t i = xcd_item(n);
   if (i < 0) return;
   uint32_t m = inv[i];
+  if (m >= uint64_t(n)) return;   // not a permutation (a caller's order): no write
   A[m] = make_float4(src[i], src[n + i], src[2 * n + i], __int_as_float(int32_t(i)));
   bool ok = valid[i] != 0;
   B[m] = make_float4(ok ? cov6[i] : -1.0f, cov6[n + i], cov6[2 * n + i], cov6[3 * n + i]);
@@ -1240,7 +1244,7 @@ struct AlignWS {
   // with the argument set it was captured for; the older one is replaced.
   struct Captured {
     hipGraphExec_t exec = nullptr;
-    const void* key[10] = {};
+    const void* key[11] = {};
     int64_t n = -1;
     Params prm{};
     int32_t prec = -1;
@@ -1252,8 +1256,8 @@ struct AlignWS {
   Captured cap[2];
   uint64_t clock = 0;
   // the argument sets of the last two direct launches
-  const void* pending[10] = {};
-  const void* pending2[10] = {};
+  const void* pending[11] = {};
+  const void* pending2[11] = {};
 };
 
 void free_ws(AlignWS* w) {
@@ -1352,6 +1356,7 @@ struct Job {
   double* g_cost = nullptr;
   int64_t* g_n = nullptr;
   int32_t tile = kTileDefault; // points per tile (the map's schedule)
+  const uint32_t* order = nullptr;   // caller's locality order of the source, or null
 };
 
 // Blocks per CU of the persistent launch of the tile passes (k_cert and the
@@ -1453,15 +1458,19 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
   FAR_HIP(hipGetLastError());
   if (j.n_total > 0) {
     const unsigned nb = unsigned((j.n_total + 255) / 256);
-    k_order_keys<<<nb, 256, 0, st>>>(j.src, j.n_total, j.offsets, j.S, m->p.voxel_size,
-                                     w->okeys, w->ovals);
-    FAR_HIP(hipGetLastError());
-    Scratch scr(st, w->arena, w->arena_cap);
-    bool in_alt = false;
-    FAR_TRY(radix_sort_pairs(w->okeys, w->ovals, w->okeys_alt, w->ovals_alt, j.n_total,
-                             24 + ceil_log2_i(j.S), st, scr, &in_alt));
-    uint32_t* perm = in_alt ? w->ovals_alt : w->ovals;
-    uint32_t* inv = in_alt ? w->ovals : w->ovals_alt;
+    const uint32_t* perm = j.order;   // the caller's order (e.g. the covariance grid's)
+    uint32_t* inv = w->ovals_alt;
+    if (!perm) {
+      k_order_keys<<<nb, 256, 0, st>>>(j.src, j.n_total, j.offsets, j.S, m->p.voxel_size,
+                                       w->okeys, w->ovals);
+      FAR_HIP(hipGetLastError());
+      Scratch scr(st, w->arena, w->arena_cap);
+      bool in_alt = false;
+      FAR_TRY(radix_sort_pairs(w->okeys, w->ovals, w->okeys_alt, w->ovals_alt, j.n_total,
+                               24 + ceil_log2_i(j.S), st, scr, &in_alt));
+      perm = in_alt ? w->ovals_alt : w->ovals;
+      inv = in_alt ? w->ovals : w->ovals_alt;
+    }
     const unsigned nb8 = ((nb + 7) / 8) * 8;
     k_invert<<<nb8, 256, 0, st>>>(perm, j.n_total, inv);
     FAR_HIP(hipGetLastError());
@@ -1522,7 +1531,8 @@ far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph
   if (!use_graph || st == nullptr || timing_on()) return enqueue(m, w, j, max_tiles, st);
   // the captured map view holds the fine-index flag: a graph captured with a
   // different flag must not be replayed
-  const void* key[10] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
+  const void* key[11] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
+                         j.order,
                          m->vox_pts,
                          reinterpret_cast<const void*>(intptr_t(m->fine_ok) |
                                                        (intptr_t(m->ghost_ok) << 1))};
@@ -1946,14 +1956,15 @@ far_status_t far_autotune(far_map_t m, const float* src, const int64_t* offsets,
   return FAR_OK;
 }
 
-far_status_t far_gicp_align_batch(far_map_t m, const float* src, const int64_t* offsets,
-                                  int32_t S_, int64_t n_total, const float* cov6,
-                                  const uint8_t* valid, double* T,
-                                  const far_align_params_t* params, far_align_stats_t* stats,
-                                  far_stream_t stream) {
+static far_status_t align_batch_impl(far_map_t m, const float* src, const int64_t* offsets,
+                                     int32_t S_, int64_t n_total, const float* cov6,
+                                     const uint8_t* valid, const uint32_t* order, double* T,
+                                     const far_align_params_t* params,
+                                     far_align_stats_t* stats, far_stream_t stream,
+                                     const char* who) {
   if (!m || !offsets || !T || !stats || !params_ok(params) || S_ < 1 || n_total < 0 ||
       n_total >= (int64_t(1) << 31) || (n_total > 0 && (!src || !cov6 || !valid))) {
-    set_error("far_gicp_align_batch: invalid argument");
+    set_error("%s: invalid argument", who);
     return FAR_E_INVALID;
   }
   hipStream_t st = S(stream);
@@ -1961,7 +1972,31 @@ far_status_t far_gicp_align_batch(far_map_t m, const float* src, const int64_t* 
         make_params(m, params->tau, params->kappa, params->eps, params->max_iters,
                     params->recenter, params->precision),
         precision_of(params->precision)};
+  j.order = order;
   return run_job(m, j, st, true);
+}
+
+far_status_t far_gicp_align_batch(far_map_t m, const float* src, const int64_t* offsets,
+                                  int32_t S_, int64_t n_total, const float* cov6,
+                                  const uint8_t* valid, double* T,
+                                  const far_align_params_t* params, far_align_stats_t* stats,
+                                  far_stream_t stream) {
+  return align_batch_impl(m, src, offsets, S_, n_total, cov6, valid, nullptr, T, params, stats,
+                          stream, "far_gicp_align_batch");
+}
+
+far_status_t far_gicp_align_batch_ordered(far_map_t m, const float* src,
+                                          const int64_t* offsets, int32_t S_, int64_t n_total,
+                                          const float* cov6, const uint8_t* valid,
+                                          const uint32_t* order, double* T,
+                                          const far_align_params_t* params,
+                                          far_align_stats_t* stats, far_stream_t stream) {
+  if (n_total > 0 && !order) {
+    set_error("far_gicp_align_batch_ordered: invalid argument");
+    return FAR_E_INVALID;
+  }
+  return align_batch_impl(m, src, offsets, S_, n_total, cov6, valid, order, T, params, stats,
+                          stream, "far_gicp_align_batch_ordered");
 }
 
 }  // extern "C"

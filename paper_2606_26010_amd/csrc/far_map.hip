@@ -942,16 +942,19 @@ __global__ __launch_bounds__(kT) void k_grid_bounds(const uint64_t* keys, const 
     seg_end[s] = uint32_t(j + 1);
 }
 
-// Sorted points as float4, blocks dealt to the XCDs in contiguous ranges (a
-// scan's points stay in the scan's index range, so each XCD gathers from the
-// few MB of its own scans).
+// Sorted points as float4 (and, when order is not null, the sorted order
+// itself: order[j] = the original index of sorted point j), blocks dealt to
+// the XCDs in contiguous ranges (a scan's points stay in the scan's index
+// range, so each XCD gathers from the few MB of its own scans).
 __global__ __launch_bounds__(kT) void k_gather_sorted(const float* xyz, int64_t n,
-                                                      const uint32_t* vals, float4* sorted) {
+                                                      const uint32_t* vals, float4* sorted,
+                                                      uint32_t* order) {
   const int64_t nb = (n + kT - 1) / kT, chunk = (nb + 7) >> 3;
   const int64_t j = (int64_t(blockIdx.x & 7) * chunk + (blockIdx.x >> 3)) * kT + threadIdx.x;
   if ((blockIdx.x >> 3) >= chunk || j >= n) return;
   uint32_t i = vals[j];
   sorted[j] = make_float4(xyz[i], xyz[n + i], xyz[2 * n + i], __int_as_float(int32_t(i)));
+  if (order) order[j] = i;
 }
 
 // The run count stays on the device: the grid-wide kernels over runs are
@@ -1751,7 +1754,7 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
 
 static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t S_, int64_t n,
                                double v, double cell, hipStream_t st, Scratch& scr,
-                               GridView* out, uint32_t* oor) {
+                               GridView* out, uint32_t* oor, uint32_t* order = nullptr) {
   Runs r;
   uint32_t* sid = nullptr;
   bool compact = false;
@@ -1803,7 +1806,8 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   FAR_TRY(scr.get(&slots, size_t(n_slots)));
   FAR_TRY(scr.get(&sorted, size_t(n)));
   FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
-  k_gather_sorted<<<unsigned(((blocks_for(n) + 7) / 8) * 8), kT, 0, st>>>(xyz, n, vals, sorted);
+  k_gather_sorted<<<unsigned(((blocks_for(n) + 7) / 8) * 8), kT, 0, st>>>(xyz, n, vals, sorted,
+                                                                        order);
   FAR_HIP(hipGetLastError());
   int e2 = 0;
   const int32_t pow2 = std::frexp(cell, &e2) == 0.5 ? 1 : 0;
@@ -1828,12 +1832,13 @@ static int32_t g_dense_threshold = 0;
 
 static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
                                   int64_t n, double voxel_size, int32_t k, float* cov6,
-                                  uint8_t* valid, hipStream_t st, const char* who) {
+                                  uint8_t* valid, hipStream_t st, const char* who,
+                                  uint32_t* order = nullptr) {
   Scratch scr(st);
   TimedScope ts(FAR_TIME_COVARIANCES, st);
   GridView g{};
   uint32_t oor = 0;
-  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor));
+  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor, order));
   if (oor > 0) {
     set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, oor);
     return FAR_E_INVALID;
@@ -1877,6 +1882,21 @@ far_status_t far_scan_covariances_batch(const float* xyz, const int64_t* offsets
   if (n_total == 0) return FAR_OK;
   return scan_cov_impl(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid, S(stream),
                        "far_scan_covariances_batch");
+}
+
+far_status_t far_scan_covariances_batch_order(const float* xyz, const int64_t* offsets,
+                                              int32_t S_, int64_t n_total, double voxel_size,
+                                              int32_t k, float* cov6, uint8_t* valid,
+                                              uint32_t* order, far_stream_t stream) {
+  if (S_ < 1 || !offsets || n_total < 0 || n_total >= (int64_t(1) << 31) ||
+      !(voxel_size > 0.0) || k < 1 || k > 32 ||
+      (n_total > 0 && (!xyz || !cov6 || !valid || !order))) {
+    set_error("far_scan_covariances_batch_order: invalid argument");
+    return FAR_E_INVALID;
+  }
+  if (n_total == 0) return FAR_OK;
+  return scan_cov_impl(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid, S(stream),
+                       "far_scan_covariances_batch_order", order);
 }
 
 far_status_t far_voxel_downsample(const float* xyz, int64_t n, double v, float* out,

@@ -92,6 +92,8 @@ _SIGS = {
     "far_scan_covariances": (C.c_int, [_P, C.c_int64, C.c_double, C.c_int32, _P, _P, _P]),
     "far_scan_covariances_batch": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double,
                                              C.c_int32, _P, _P, _P]),
+    "far_scan_covariances_batch_order": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double,
+                                                   C.c_int32, _P, _P, _P, _P]),
     "far_set_covariance_regularisation": (C.c_int, [C.c_int32]),
     "far_get_covariance_regularisation": (C.c_int, [C.POINTER(C.c_int32)]),
     "far_timing_enable": (C.c_int, [C.c_int32]),
@@ -118,6 +120,8 @@ _SIGS = {
                                  C.POINTER(far_align_stats_t), _P]),
     "far_gicp_align_batch": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P,
                                        C.POINTER(far_align_params_t), _P, _P]),
+    "far_gicp_align_batch_ordered": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P,
+                                               _P, C.POINTER(far_align_params_t), _P, _P]),
     "far_map_stats": (C.c_int, [_P, C.POINTER(far_map_stats_t), _P]),
     "far_map_export": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
     "far_voxel_downsample": (C.c_int, [_P, C.c_int64, C.c_double, _P, _P,
@@ -265,7 +269,10 @@ def far_scan_covariances(xyz, voxel_size, k, stream=None):
     return cov, val
 
 
-def far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=None, stream=None):
+def far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=None, stream=None,
+                               order=None):
+    """order: an int32 tensor [n] on the GPU (far_scan_covariances_batch_order:
+    it receives the grid's sorted order) or None."""
     p, n = _pts(xyz)
     S = offsets.shape[0] - 1
     if out is None:
@@ -273,11 +280,28 @@ def far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=None, stream=Non
         val = torch.empty(n, dtype=torch.uint8, device=xyz.device)
     else:
         cov, val = out
-    _check(lib().far_scan_covariances_batch(p, _dev(offsets, torch.int64, "offsets"), S, n,
-                                            voxel_size, k, _dev(cov, torch.float32, "cov6"),
-                                            _dev(val, torch.uint8, "valid"), _stream(stream)),
-           "far_scan_covariances_batch")
+    if order is None:
+        _check(lib().far_scan_covariances_batch(p, _dev(offsets, torch.int64, "offsets"), S, n,
+                                                voxel_size, k, _dev(cov, torch.float32, "cov6"),
+                                                _dev(val, torch.uint8, "valid"), _stream(stream)),
+               "far_scan_covariances_batch")
+    else:
+        if order.numel() != n:
+            raise ValueError("order must hold one entry per point")
+        _check(lib().far_scan_covariances_batch_order(
+            p, _dev(offsets, torch.int64, "offsets"), S, n, voxel_size, k,
+            _dev(cov, torch.float32, "cov6"), _dev(val, torch.uint8, "valid"),
+            _dev(order, torch.int32, "order"), _stream(stream)),
+            "far_scan_covariances_batch_order")
     return cov, val
+
+
+def far_scan_covariances_batch_order(xyz, offsets, voxel_size, k, order, out=None,
+                                     stream=None):
+    """far_scan_covariances_batch that also fills order (int32 [n] on the GPU)
+    with the grid's sorted order."""
+    return far_scan_covariances_batch(xyz, offsets, voxel_size, k, out=out, stream=stream,
+                                      order=order)
 
 
 FAR_REG_EQ1, FAR_REG_PLANE = 0, 1
@@ -431,21 +455,35 @@ def far_gicp_align(h, src, cov6, valid, T0, params: far_align_params_t, stream=N
 
 
 def far_gicp_align_batch(h, src, offsets, cov6, valid, T, params: far_align_params_t,
-                         stats=None, stream=None):
+                         stats=None, stream=None, order=None):
     """T: float64 [S, 16] on the GPU (in/out).  stats: uint8 [S * sizeof] buffer or
-    None (allocated).  Asynchronous; returns the stats buffer (decode with
-    decode_stats after synchronising)."""
+    None (allocated).  order: None (the align sorts the source itself) or an
+    int32 tensor [n] on the GPU (far_gicp_align_batch_ordered), e.g. the one
+    far_scan_covariances_batch(..., order=...) filled.  Asynchronous; returns
+    the stats buffer (decode with decode_stats after synchronising)."""
     p, n = _pts(src, "src")
     S = offsets.shape[0] - 1
     if stats is None:
         stats = torch.empty(S * STATS_DTYPE.itemsize, dtype=torch.uint8, device=src.device)
-    _check(lib().far_gicp_align_batch(h, p, _dev(offsets, torch.int64, "offsets"), S, n,
-                                      _dev(cov6, torch.float32, "cov6"),
-                                      _dev(valid, torch.uint8, "valid"),
-                                      _dev(T, torch.float64, "T"), C.byref(params),
-                                      _dev(stats, torch.uint8, "stats"), _stream(stream)),
-           "far_gicp_align_batch")
+    args = (_dev(offsets, torch.int64, "offsets"), S, n, _dev(cov6, torch.float32, "cov6"),
+            _dev(valid, torch.uint8, "valid"))
+    rest = (_dev(T, torch.float64, "T"), C.byref(params), _dev(stats, torch.uint8, "stats"),
+            _stream(stream))
+    if order is None:
+        _check(lib().far_gicp_align_batch(h, p, *args, *rest), "far_gicp_align_batch")
+    else:
+        if order.numel() != n:
+            raise ValueError("order must hold one entry per point")
+        _check(lib().far_gicp_align_batch_ordered(h, p, *args, _dev(order, torch.int32, "order"),
+                                                  *rest), "far_gicp_align_batch_ordered")
     return stats
+
+
+def far_gicp_align_batch_ordered(h, src, offsets, cov6, valid, order, T,
+                                 params: far_align_params_t, stats=None, stream=None):
+    """far_gicp_align_batch with the source packed in the given order."""
+    return far_gicp_align_batch(h, src, offsets, cov6, valid, T, params, stats=stats,
+                                stream=stream, order=order)
 
 
 def decode_stats(stats: torch.Tensor):

@@ -1,0 +1,120 @@
+"""The step's one sort: the covariance grid's order handed to the align.
+
+far_scan_covariances_batch_order returns the (scan, voxel key, x) order its
+grid sorted the points in; far_gicp_align_batch_ordered packs the source in
+that order instead of sorting it again.  The order must be a permutation
+that keeps each scan in its own range with each voxel's points adjacent and
+the voxels in key order; the covariances are the same bits as without it;
+the ordered align lands on the oracle's poses (the order only changes the
+rounding order of the sums) and repeats bit for bit."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_26010_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def angle_deg(A, B):
+    E = A[:3, :3] @ B[:3, :3].T
+    s = np.array([E[2, 1] - E[1, 2], E[0, 2] - E[2, 0], E[1, 0] - E[0, 1]])
+    return math.degrees(math.atan2(0.5 * np.linalg.norm(s), 0.5 * (np.trace(E) - 1)))
+
+
+@pytest.fixture(scope="module")
+def batch(orc):
+    from paper_2606_26010_amd import far
+    c = synth.make_batch(11, n_scans=6, n_min=3000, n_max=40000, map_points=300_000,
+                         map_batch=300_000, n_map_batches=2)
+    gm = far.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.map_capacity,
+                 c.map_capacity, c.k)
+    om = orc.Map(c.voxel_size, c.max_pts_per_voxel, c.min_spacing, c.k,
+                 point_capacity=c.map_capacity, voxel_capacity=c.map_capacity)
+    for b in c.map_batches:
+        gm.insert(dev(b))
+        om.insert(b, check=False)
+    scans = [s.copy() for s in c.scans]
+    scans[2][:, ::97] = np.nan                    # non-finite points sort last in their scan
+    sizes = np.array([s.shape[1] for s in scans])
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    yield far, c, gm, om, scans, offs
+    gm.close()
+
+
+def test_covariance_order_is_the_grid_order(batch):
+    far, c, gm, om, scans, offs = batch
+    pts = np.concatenate(scans, 1)
+    n = pts.shape[1]
+    cov0, val0 = far.far_scan_covariances_batch(dev(pts), dev(offs), c.voxel_size, c.k)
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cov1, val1 = far.far_scan_covariances_batch_order(dev(pts), dev(offs), c.voxel_size, c.k,
+                                                      order)
+    np.testing.assert_array_equal(host(cov1), host(cov0))
+    np.testing.assert_array_equal(host(val1), host(val0))
+    o = host(order).astype(np.int64)
+    assert np.array_equal(np.sort(o), np.arange(n))                 # a permutation
+    for s in range(len(scans)):
+        a, b = offs[s], offs[s + 1]
+        seg = o[a:b]
+        assert seg.min() >= a and seg.max() < b                      # the scan's own range
+        p = pts[:, seg].astype(np.float64)
+        fin = np.isfinite(p).all(0)
+        nf = int((~fin).sum())
+        assert fin[:len(seg) - nf].all() and not fin[len(seg) - nf:].any()   # non-finite last
+        k = np.floor(p[:, fin] / c.voxel_size).astype(np.int64)
+        key = (k[0] << 42) + (k[1] << 21) + k[2]
+        assert np.all(np.diff(key) >= 0)                             # voxels in key order
+    print(f"order: a permutation of {n} points, scans in place, voxels in key order",
+          flush=True)
+
+
+def test_ordered_align_matches_oracle_and_repeats(batch, orc):
+    far, c, gm, om, scans, offs = batch
+    pts = np.concatenate(scans, 1)
+    n = pts.shape[1]
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cov, val = far.far_scan_covariances_batch_order(dev(pts), dev(offs), c.voxel_size, c.k,
+                                                    order)
+    T0 = dev(np.stack([t.reshape(16) for t in c.T0]))
+    prm = far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0)
+    src = dev(pts)
+    stream = torch.cuda.Stream()
+    res = []
+    with torch.cuda.stream(stream):
+        for k in range(4):              # direct launches, then the captured graph
+            T = T0.clone()
+            st = far.decode_stats(far.far_gicp_align_batch_ordered(gm.h, src, dev(offs), cov,
+                                                                  val, order, T, prm))
+            stream.synchronize()
+            res.append((host(T), st))
+        T_own = T0.clone()
+        far.far_gicp_align_batch(gm.h, src, dev(offs), cov, val, T_own, prm)
+        stream.synchronize()
+    for T, st in res[1:]:
+        np.testing.assert_array_equal(T, res[0][0])
+        for key in ("iters", "status", "n_inliers", "cost"):
+            np.testing.assert_array_equal(st[key], res[0][1][key])
+    Tb = res[0][0].reshape(-1, 4, 4)
+    To = host(T_own).reshape(-1, 4, 4)
+    assert (res[0][1]["status"] == 0).all()
+    for s in (0, 3):
+        ocov, oval = orc.scan_covariances(scans[s], c.voxel_size, c.k)
+        ref = om.align(scans[s], ocov.astype(np.float32), oval, c.T0[s], c.tau, c.kappa,
+                       max_iters=c.max_iters, eps=0.0)
+        assert ref["status"] == 0
+        assert np.linalg.norm(Tb[s][:3, 3] - ref["T"][:3, 3]) <= 1e-3
+        assert angle_deg(Tb[s], ref["T"]) <= 1e-2
+    dt = max(float(np.linalg.norm(Tb[s][:3, 3] - To[s][:3, 3])) for s in range(len(scans)))
+    assert dt <= 1e-4
+    print(f"ordered align: 4 runs identical, own-sort align within {dt:.2e} m", flush=True)

@@ -857,12 +857,24 @@ __global__ __launch_bounds__(kT) void k_key_range_final(const int32_t* part,
   }
 }
 
+// Compact cell key: the cell's offsets from the batch's per-axis minima,
+// bx, by, bz bits (each at least 2), laid out as 4 x 4 x 4 blocks of cells -
+// the block's offsets (bx-2, by-2, bz-2 bits, x major) above the cell's place
+// in the block (2 + 2 + 2 bits, x major) - so that sorted points fill whole
+// blocks in turn: a stretch of the order is a compact patch of space.
 struct CompactKey {
   int32_t mx, my, mz;   // per-axis minimum
-  int32_t by, bz;       // bits of y and z
+  int32_t bx, by, bz;   // bits of x, y and z (>= 2)
   int32_t kb;           // key bits (x, y, z); 1 << kb marks an empty key
   int32_t fb;           // bits of the point's x within its cell, below the key
 };
+
+__device__ inline uint64_t compact_cell(const CompactKey& ck, int64_t cx, int64_t cy,
+                                        int64_t cz) {
+  const uint64_t hi = (uint64_t(cx >> 2) << (ck.by + ck.bz - 4)) |
+                      (uint64_t(cy >> 2) << (ck.bz - 2)) | uint64_t(cz >> 2);
+  return (hi << 6) | (uint64_t(cx & 3) << 4) | (uint64_t(cy & 3) << 2) | uint64_t(cz & 3);
+}
 
 __global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n, double v,
                                                      double inv_v, int32_t pow2,
@@ -891,8 +903,7 @@ __global__ __launch_bounds__(kT) void k_keys_compact(const float* xyz, int64_t n
     // so the fb bits below the key sort each run by x up to 2^-fb cells
     const double t = pow2 ? double(x) * inv_v : double(x) / v;
     const uint64_t xq = uint64_t(fmin((t - floor(t)) * ldexp(1.0, ck.fb), ldexp(1.0, ck.fb) - 1.0));
-    key = (((uint64_t(kx - ck.mx) << (ck.by + ck.bz)) | (uint64_t(ky - ck.my) << ck.bz) |
-            uint64_t(kz - ck.mz)) << ck.fb) | xq;
+    key = (compact_cell(ck, kx - ck.mx, ky - ck.my, kz - ck.mz) << ck.fb) | xq;
   }
   keys[i] = (uint64_t(s) << (ck.kb + ck.fb + 1)) | key;
   vals[i] = uint32_t(i);
@@ -911,9 +922,13 @@ __global__ __launch_bounds__(kT) void k_keys_expand(const uint64_t* ckeys, int64
   if (k >> ck.kb) {
     keys[i] = kEmptyKey;
   } else {
-    const int64_t kx = int64_t(k >> (ck.by + ck.bz)) + ck.mx;
-    const int64_t ky = int64_t((k >> ck.bz) & ((uint64_t(1) << ck.by) - 1)) + ck.my;
-    const int64_t kz = int64_t(k & ((uint64_t(1) << ck.bz) - 1)) + ck.mz;
+    const uint64_t hi = k >> 6;
+    const int64_t hx = int64_t(hi >> (ck.by + ck.bz - 4));
+    const int64_t hy = int64_t((hi >> (ck.bz - 2)) & ((uint64_t(1) << (ck.by - 2)) - 1));
+    const int64_t hz = int64_t(hi & ((uint64_t(1) << (ck.bz - 2)) - 1));
+    const int64_t kx = ((hx << 2) | int64_t((k >> 4) & 3)) + ck.mx;
+    const int64_t ky = ((hy << 2) | int64_t((k >> 2) & 3)) + ck.my;
+    const int64_t kz = ((hz << 2) | int64_t(k & 3)) + ck.mz;
     keys[i] = pack_key(kx, ky, kz);
   }
 }
@@ -1707,10 +1722,10 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
   ck.mx = h[0];
   ck.my = h[1];
   ck.mz = h[2];
-  const int bx = ceil_log2(int64_t(h[3]) - h[0] + 1);
-  ck.by = ceil_log2(int64_t(h[4]) - h[1] + 1);
-  ck.bz = ceil_log2(int64_t(h[5]) - h[2] + 1);
-  ck.kb = bx + ck.by + ck.bz;
+  ck.bx = std::max(ceil_log2(int64_t(h[3]) - h[0] + 1), 2);
+  ck.by = std::max(ceil_log2(int64_t(h[4]) - h[1] + 1), 2);
+  ck.bz = std::max(ceil_log2(int64_t(h[5]) - h[2] + 1), 2);
+  ck.kb = ck.bx + ck.by + ck.bz;
   const int key_bits = (S_ > 1 ? ceil_log2(S_) : 0) + ck.kb + 1;
   if (key_bits > 62) return FAR_OK;
   // x bits: one more radix pass of 8 bits (8 to 15 bits), within 62 in all

@@ -4,7 +4,7 @@ far_scan_covariances_batch_order returns the (scan, voxel key, x) order its
 grid sorted the points in; far_gicp_align_batch_ordered packs the source in
 that order instead of sorting it again.  The order must be a permutation
 that keeps each scan in its own range with each voxel's points adjacent and
-the voxels in key order; the covariances are the same bits as without it;
+each 4 x 4 x 4 block of voxels together; the covariances are the same bits as without it;
 the ordered align lands on the oracle's poses (the order only changes the
 rounding order of the sums) and repeats bit for bit."""
 import math
@@ -64,6 +64,8 @@ def test_covariance_order_is_the_grid_order(batch):
     np.testing.assert_array_equal(host(val1), host(val0))
     o = host(order).astype(np.int64)
     assert np.array_equal(np.sort(o), np.arange(n))                 # a permutation
+    allk = np.floor(pts[:, np.isfinite(pts).all(0)].astype(np.float64) / c.voxel_size)
+    kmin = allk.min(1).astype(np.int64)[:, None]     # blocks count from the batch's minima
     for s in range(len(scans)):
         a, b = offs[s], offs[s + 1]
         seg = o[a:b]
@@ -74,9 +76,13 @@ def test_covariance_order_is_the_grid_order(batch):
         assert fin[:len(seg) - nf].all() and not fin[len(seg) - nf:].any()   # non-finite last
         k = np.floor(p[:, fin] / c.voxel_size).astype(np.int64)
         key = (k[0] << 42) + (k[1] << 21) + k[2]
-        assert np.all(np.diff(key) >= 0)                             # voxels in key order
-    print(f"order: a permutation of {n} points, scans in place, voxels in key order",
-          flush=True)
+        runs = 1 + int(np.count_nonzero(np.diff(key)))
+        assert runs == np.unique(key).size                           # a voxel's points adjacent
+        kb = (k - kmin) >> 2
+        b4 = (kb[0] << 42) + (kb[1] << 21) + kb[2]
+        assert 1 + int(np.count_nonzero(np.diff(b4))) == np.unique(b4).size   # and its block's
+    print(f"order: a permutation of {n} points, scans in place, voxels and 4^3 blocks "
+          f"contiguous", flush=True)
 
 
 def test_ordered_align_matches_oracle_and_repeats(batch, orc):

@@ -10,8 +10,8 @@ All data is seeded and synthetic (the paper's datasets are not available).
 
 One step = the whole per-batch hot path with inputs resident in HBM:
   1. regularised covariances of every scan against itself (one batched call),
-     which also returns the (scan, voxel, x) order its grid sorted the
-     points in;
+     which also returns the (scan, block of cells, cell, x) order its grid
+     sorted the points in;
   2. batched Gauss-Newton align of all scans, its source packed in that
      order (the step sorts its points once): each iteration is one
      linearisation launch over all scans' point tiles plus one

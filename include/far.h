@@ -180,10 +180,11 @@ far_status_t far_scan_covariances_batch(const float* xyz, const int64_t* offsets
 
 /* far_scan_covariances_batch that also returns the order its grid sorted the
  * points in: order [dev, n_total] uint32 receives, for each position j of
- * the (scan, voxel key, x) order, the index of the point there.  Each scan's
- * points keep the scan's own index range, and points of one voxel are
- * adjacent, so the order is a spatially compact layout of every scan; the
- * align below takes it in place of sorting the source itself.  Ownership:
+ * the (scan, 4 x 4 x 4 block of cells, cell, x) order, the index of the
+ * point there.  Each scan's points keep the scan's own index range, the
+ * points of one voxel and of one block are adjacent, so the order is a
+ * spatially compact layout of every scan; the align below takes it in place
+ * of sorting the source itself.  Ownership:
  * order is the caller's; it is written in full (n_total entries).  Errors as
  * far_scan_covariances_batch, and FAR_E_INVALID when order is null. */
 far_status_t far_scan_covariances_batch_order(const float* xyz, const int64_t* offsets,

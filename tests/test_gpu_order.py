@@ -1,7 +1,7 @@
 """The step's one sort: the covariance grid's order handed to the align.
 
-far_scan_covariances_batch_order returns the (scan, voxel key, x) order its
-grid sorted the points in; far_gicp_align_batch_ordered packs the source in
+far_scan_covariances_batch_order returns the (scan, 4 x 4 x 4 block of cells,
+cell, x) order its grid sorted the points in; far_gicp_align_batch_ordered packs the source in
 that order instead of sorting it again.  The order must be a permutation
 that keeps each scan in its own range with each voxel's points adjacent and
 each 4 x 4 x 4 block of voxels together; the covariances are the same bits as without it;

@@ -423,9 +423,9 @@ def main():
             log(f"[bench] tile-pass launch: {grid_ms} ms per align, kept {best_g} blocks per CU")
         far.far_set_linearize_grid(schedule["lin_blocks_per_cu"])
 
-        # The step sorts its points once: the covariance grid's (scan, voxel,
-        # x) order is handed to the align, which packs the source in it
-        # instead of sorting the source again.
+        # The step sorts its points once: the covariance grid's (scan, block
+        # of cells, cell, x) order is handed to the align, which packs the
+        # source in it instead of sorting the source again.
         order_buf = torch.empty(N, dtype=torch.int32, device=dev)
 
         def step():

@@ -10,10 +10,10 @@ All data is seeded and synthetic (the paper's datasets are not available).
 
 One step = the whole per-batch hot path with inputs resident in HBM:
   1. regularised covariances of every scan against itself (one batched call),
-     which also returns the (scan, block of cells, cell, x) order its grid
-     sorted the points in;
-  2. batched Gauss-Newton align of all scans, its source packed in that
-     order (the step sorts its points once): each iteration is one
+     which also writes the align's packed source in the (scan, block of
+     cells, cell, x) order its grid sorted the points in;
+  2. batched Gauss-Newton align of all scans on that packed source (the step
+     sorts and packs its points once): each iteration is one
      linearisation launch over all scans' point tiles plus one
      reduce-and-solve launch, the whole align replayed as one HIP graph.
 
@@ -423,17 +423,17 @@ def main():
             log(f"[bench] tile-pass launch: {grid_ms} ms per align, kept {best_g} blocks per CU")
         far.far_set_linearize_grid(schedule["lin_blocks_per_cu"])
 
-        # The step sorts its points once: the covariance grid's (scan, block
-        # of cells, cell, x) order is handed to the align, which packs the
-        # source in it instead of sorting the source again.
-        order_buf = torch.empty(N, dtype=torch.int32, device=dev)
+        # The step sorts and packs its points once: the covariance call
+        # writes the align's packed source in its grid's (scan, block of
+        # cells, cell, x) order beside cov6 and valid, and the align reads it
+        # as it is (no sort or pack of its own).
+        packed_buf = torch.empty(10 * N, dtype=torch.float32, device=dev)
 
         def step():
-            cov, val = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
-                                                      out=(cov_buf, val_buf), order=order_buf)
+            cov, val = far.far_scan_covariances_batch_packed(src, offs, case.voxel_size, case.k,
+                                                             packed_buf, out=(cov_buf, val_buf))
             T.copy_(T0)
-            far.far_gicp_align_batch(gm.h, src, offs, cov, val, T, prm, stats=stats_buf,
-                                     order=order_buf)
+            far.far_gicp_align_batch_packed(gm.h, packed_buf, offs, T, prm, stats=stats_buf)
             return cov, val
 
         for _ in range(args.warmup):
@@ -465,7 +465,7 @@ def main():
             s_al = torch.cuda.Stream()
             cov_b = [cov_buf, torch.empty_like(cov_buf)]
             val_b = [val_buf, torch.empty_like(val_buf)]
-            ord_b = [order_buf, torch.empty_like(order_buf)]
+            pk_b = [packed_buf, torch.empty_like(packed_buf)]
             ev_cov = [torch.cuda.Event(), torch.cuda.Event()]
             ev_al = [torch.cuda.Event(), torch.cuda.Event()]
             for e in ev_al:
@@ -474,14 +474,14 @@ def main():
             def step_piped(k):
                 b = k % 2
                 stream.wait_event(ev_al[b])     # the align that read buffer b is done
-                far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
-                                               out=(cov_b[b], val_b[b]), order=ord_b[b])
+                far.far_scan_covariances_batch_packed(src, offs, case.voxel_size, case.k,
+                                                      pk_b[b], out=(cov_b[b], val_b[b]))
                 ev_cov[b].record(stream)
                 with torch.cuda.stream(s_al):
                     s_al.wait_event(ev_cov[b])
                     T.copy_(T0)
-                    far.far_gicp_align_batch(gm.h, src, offs, cov_b[b], val_b[b], T, prm,
-                                             stats=stats_buf, order=ord_b[b])
+                    far.far_gicp_align_batch_packed(gm.h, pk_b[b], offs, T, prm,
+                                                    stats=stats_buf)
                     ev_al[b].record(s_al)
 
             for k in range(max(args.warmup, 4)):   # both buffers' aligns captured
@@ -622,11 +622,11 @@ def main():
                                      eps=args.conv_eps, recenter=1, precision=prec)
 
             def step_c():
-                cv, vl = far.far_scan_covariances_batch(src, offs, case.voxel_size, case.k,
-                                                        out=(cov_buf, val_buf), order=order_buf)
+                far.far_scan_covariances_batch_packed(src, offs, case.voxel_size, case.k,
+                                                      packed_buf, out=(cov_buf, val_buf))
                 T.copy_(T0)
-                far.far_gicp_align_batch(gm.h, src, offs, cv, vl, T, prm_c, stats=stats_buf,
-                                         order=order_buf)
+                far.far_gicp_align_batch_packed(gm.h, packed_buf, offs, T, prm_c,
+                                                stats=stats_buf)
 
             step_c()
             stream.synchronize()

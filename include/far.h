@@ -192,6 +192,20 @@ far_status_t far_scan_covariances_batch_order(const float* xyz, const int64_t* o
                                               int32_t k, float* cov6, uint8_t* valid,
                                               uint32_t* order, far_stream_t stream);
 
+/* far_scan_covariances_batch that also writes the source in the packed form
+ * the batched align reads, in the grid's order (as for
+ * far_scan_covariances_batch_order), so that the align neither sorts nor
+ * packs: packed [dev, 40 x n_total bytes, 16-byte aligned] receives A float4
+ * [n_total] (x, y, z, the point's index as int32 bits), then B float4
+ * [n_total] (xx, or -1 when the covariance is invalid, xy, xz, yy), then C
+ * float2 [n_total] (yz, zz), the covariance words as written to cov6.
+ * Ownership: packed is the caller's.  Errors as far_scan_covariances_batch,
+ * and FAR_E_INVALID when packed is null or misaligned. */
+far_status_t far_scan_covariances_batch_packed(const float* xyz, const int64_t* offsets,
+                                               int32_t S, int64_t n_total, double voxel_size,
+                                               int32_t k, float* cov6, uint8_t* valid,
+                                               void* packed, far_stream_t stream);
+
 /* One GICP linearisation (Eqs. 3-5, sparsity-aware) of the scan src
  * [dev, SoA 3 x n] with covariances cov6 [dev, SoA 6 x n] and valid [dev, n]
  * against the map at pose T [host]: p = R s + t in FP64; correspondence = the
@@ -312,6 +326,18 @@ far_status_t far_gicp_align_batch_ordered(far_map_t map, const float* src,
                                           const uint32_t* order, double* T,
                                           const far_align_params_t* params,
                                           far_align_stats_t* stats, far_stream_t stream);
+
+/* far_gicp_align_batch on a source packed by
+ * far_scan_covariances_batch_packed (packed [dev, 40 x n_total bytes] as
+ * described there; offsets and the rest as for far_gicp_align_batch).  The
+ * packed order must keep each scan's points in the scan's own range, as
+ * the grid's order does; the results equal far_gicp_align_batch_ordered's
+ * with that order, bit for bit.  FAR_E_INVALID when packed is null or not
+ * 16-byte aligned. */
+far_status_t far_gicp_align_batch_packed(far_map_t map, const void* packed,
+                                         const int64_t* offsets, int32_t S, int64_t n_total,
+                                         double* T, const far_align_params_t* params,
+                                         far_align_stats_t* stats, far_stream_t stream);
 
 /* Launch schedule of the linearisation on a map (the tile and probe schedule
  * of the batched iteration).  tile: points per block and tile, 128, 256

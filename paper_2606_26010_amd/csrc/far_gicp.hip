@@ -1244,7 +1244,7 @@ struct AlignWS {
   // with the argument set it was captured for; the older one is replaced.
   struct Captured {
     hipGraphExec_t exec = nullptr;
-    const void* key[11] = {};
+    const void* key[12] = {};
     int64_t n = -1;
     Params prm{};
     int32_t prec = -1;
@@ -1256,8 +1256,8 @@ struct AlignWS {
   Captured cap[2];
   uint64_t clock = 0;
   // the argument sets of the last two direct launches
-  const void* pending[11] = {};
-  const void* pending2[11] = {};
+  const void* pending[12] = {};
+  const void* pending2[12] = {};
 };
 
 void free_ws(AlignWS* w) {
@@ -1357,6 +1357,11 @@ struct Job {
   int64_t* g_n = nullptr;
   int32_t tile = kTileDefault; // points per tile (the map's schedule)
   const uint32_t* order = nullptr;   // caller's locality order of the source, or null
+  // the source already packed by the caller (A, B, C as the pack writes
+  // them, in a locality order), or null
+  const float4* in_A = nullptr;
+  const float4* in_B = nullptr;
+  const float2* in_C = nullptr;
 };
 
 // Blocks per CU of the persistent launch of the tile passes (k_cert and the
@@ -1378,6 +1383,9 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
     const int64_t pg = ((int64_t(g_lin_blocks_per_cu) * device_cu_count() + 7) / 8) * 8;
     if (pg < grid) grid = pg;
   }
+  const float4* pA = j.in_A ? j.in_A : w->pA;
+  const float4* pB = j.in_A ? j.in_B : w->pB;
+  const float2* pC = j.in_A ? j.in_C : w->pC;
   if (!search) {
     Queue Q{w->q_idx, w->q_cand, w->q_p, w->q_count, w->q_bin_cap, kBins * w->q_bin_cap};
     k_zero_bins<<<1, 64, 0, st>>>(w->q_count);
@@ -1386,7 +1394,7 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
     switch (tile * 2 + (loop ? 1 : 0)) {
 #define FAR_CERT_CASE(B, L)                                                               \
   case B * 2 + L:                                                                         \
-    k_cert<B, L><<<unsigned(grid), B, 0, st>>>(mv, w->pA, w->tile_scan, w->tile_lo,      \
+    k_cert<B, L><<<unsigned(grid), B, 0, st>>>(mv, pA, w->tile_scan, w->tile_lo,         \
                                                w->tile_hi, max_tiles, j.T, w->done, j.prm, \
                                                w->match, prev, Q, vgrid);                 \
     break;
@@ -1412,7 +1420,7 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
 #define FAR_LIN_CASE(B, F, N, X, L)                                                       \
   case B * 16 + F * 8 + N * 4 + X * 2 + L:                                                \
     k_linearize<Real, kGrad, B, F, N, X, L><<<unsigned(grid), B, 0, st>>>(               \
-        mv, w->pA, w->pB, w->pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,   \
+        mv, pA, pB, pC, w->tile_scan, w->tile_lo, w->tile_hi, max_tiles, j.T,            \
         w->ctr, w->done, j.prm, w->partial, j.corr, kGrad ? j.grad_src : nullptr,        \
         j.n_total, w->match, prev, vgrid);                                                \
     break;
@@ -1456,7 +1464,7 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
   k_init<<<(j.S + 255) / 256, 256, 0, st>>>(j.S, j.T, w->bad, j.prm.recenter, j.c_fixed,
                                             j.stats, w->done, w->ctr);
   FAR_HIP(hipGetLastError());
-  if (j.n_total > 0) {
+  if (j.n_total > 0 && !j.in_A) {   // (a source packed by the caller is used as it is)
     const unsigned nb = unsigned((j.n_total + 255) / 256);
     const uint32_t* perm = j.order;   // the caller's order (e.g. the covariance grid's)
     uint32_t* inv = w->ovals_alt;
@@ -1476,7 +1484,9 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
     FAR_HIP(hipGetLastError());
     k_pack<<<nb8, 256, 0, st>>>(j.src, j.cov6, j.valid, j.n_total, inv, w->pA, w->pB, w->pC);
     FAR_HIP(hipGetLastError());
-    k_fill_none<<<nb, 256, 0, st>>>(w->prev, j.n_total);
+  }
+  if (j.n_total > 0) {
+    k_fill_none<<<unsigned((j.n_total + 255) / 256), 256, 0, st>>>(w->prev, j.n_total);
     FAR_HIP(hipGetLastError());
   }
   const int64_t grid = ((max_tiles + 7) / 8) * 8;   // one block per tile
@@ -1531,8 +1541,8 @@ far_status_t run_job(far_map_s* m, const Job& j0, hipStream_t st, bool use_graph
   if (!use_graph || st == nullptr || timing_on()) return enqueue(m, w, j, max_tiles, st);
   // the captured map view holds the fine-index flag: a graph captured with a
   // different flag must not be replayed
-  const void* key[11] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
-                         j.order,
+  const void* key[12] = {j.src, j.offsets, j.cov6, j.valid, j.T, j.stats, j.c_fixed, j.corr,
+                         j.order, j.in_A,
                          m->vox_pts,
                          reinterpret_cast<const void*>(intptr_t(m->fine_ok) |
                                                        (intptr_t(m->ghost_ok) << 1))};
@@ -1983,6 +1993,28 @@ far_status_t far_gicp_align_batch(far_map_t m, const float* src, const int64_t* 
                                   far_stream_t stream) {
   return align_batch_impl(m, src, offsets, S_, n_total, cov6, valid, nullptr, T, params, stats,
                           stream, "far_gicp_align_batch");
+}
+
+far_status_t far_gicp_align_batch_packed(far_map_t m, const void* packed,
+                                         const int64_t* offsets, int32_t S_, int64_t n_total,
+                                         double* T, const far_align_params_t* params,
+                                         far_align_stats_t* stats, far_stream_t stream) {
+  if (!m || !offsets || !T || !stats || !params_ok(params) || S_ < 1 || n_total < 0 ||
+      n_total >= (int64_t(1) << 31) || (n_total > 0 && !packed) ||
+      (reinterpret_cast<uintptr_t>(packed) & 15) != 0) {
+    set_error("far_gicp_align_batch_packed: invalid argument");
+    return FAR_E_INVALID;
+  }
+  hipStream_t st = S(stream);
+  Job j{nullptr, offsets, S_, n_total, nullptr, nullptr, T, stats, nullptr, nullptr,
+        make_params(m, params->tau, params->kappa, params->eps, params->max_iters,
+                    params->recenter, params->precision),
+        precision_of(params->precision)};
+  const char* b = static_cast<const char*>(packed);
+  j.in_A = reinterpret_cast<const float4*>(b);
+  j.in_B = reinterpret_cast<const float4*>(b + 16 * n_total);
+  j.in_C = reinterpret_cast<const float2*>(b + 32 * n_total);
+  return run_job(m, j, st, true);
 }
 
 far_status_t far_gicp_align_batch_ordered(far_map_t m, const float* src,

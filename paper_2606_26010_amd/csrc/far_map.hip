@@ -676,7 +676,17 @@ struct GridView {
   const uint2* nbt;           // per run, its 27 cells (code (ox+1)*9 + (oy+1)*3 + oz+1) as
                               // (start, count) in sorted; count 0: no run there
   const uint32_t* n_runs;     // the number of runs (device)
+  float4* pk_B;               // the source packed for the align by sorted position
+  float2* pk_C;               // (B, C as the align's pack writes them), or null
 };
+
+// The align's packed covariance words of sorted point j: B = (xx, or -1 when
+// invalid, xy, xz, yy), C = (yz, zz), from the values written to cov6.
+__device__ inline void write_packed(const GridView& g, int64_t j, const float c[6], bool ok) {
+  if (!g.pk_B) return;
+  g.pk_B[j] = make_float4(ok ? c[0] : -1.0f, c[1], c[2], c[3]);
+  g.pk_C[j] = make_float2(c[4], c[5]);
+}
 
 // Slots of scan sc: two per point of the scan (its points are positions
 // offsets[sc] .. offsets[sc + 1] of the sorted order, so at most half of its
@@ -1106,9 +1116,14 @@ __device__ inline void grid_cov_run(const GridView& g, int64_t sg, int32_t dense
       const bool ok = top.found() >= k;
       if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6, reg);
       const int64_t i = __float_as_int(me.w);
+      float cf[6];
 #pragma unroll
-      for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
+      for (int t = 0; t < 6; ++t) {
+        cf[t] = float(c6[t]);
+        cov6[t * n + i] = cf[t];
+      }
       valid[i] = ok ? 1 : 0;
+      write_packed(g, j, cf, ok);
     }
   }
 }
@@ -1154,6 +1169,8 @@ __global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32
 #pragma unroll
     for (int t = 0; t < 6; ++t) cov6[t * n + i] = 0.0f;
     valid[i] = 0;
+    const float z[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    write_packed(g, j, z, false);
     return;
   }
   const double qx = me.x, qy = me.y, qz = me.z;
@@ -1173,8 +1190,19 @@ __global__ __launch_bounds__(kT, kCovMinWaves) void k_grid_cov(GridView g, int32
   const bool ok = top.found() >= k;
   if (ok) regularised_cov<K>(top, k, [&](int32_t pos) { return g.sorted[pos]; }, c6, reg);
   const int64_t i = __float_as_int(me.w);
-#pragma unroll
-  for (int t = 0; t < 6; ++t) cov6[t * n + i] = float(c6[t]);
+  const float f0 = float(c6[0]), f1 = float(c6[1]), f2 = float(c6[2]), f3 = float(c6[3]),
+              f4 = float(c6[4]), f5 = float(c6[5]);
+  if (g.pk_B) {   // the align's packed words at the sorted position (n < 2^31)
+    const uint32_t j32 = uint32_t(j);
+    g.pk_B[j32] = make_float4(ok ? f0 : -1.0f, f1, f2, f3);
+    g.pk_C[j32] = make_float2(f4, f5);
+  }
+  cov6[i] = f0;
+  cov6[n + i] = f1;
+  cov6[2 * n + i] = f2;
+  cov6[3 * n + i] = f3;
+  cov6[4 * n + i] = f4;
+  cov6[5 * n + i] = f5;
   valid[i] = ok ? 1 : 0;
 }
 
@@ -1769,7 +1797,8 @@ static far_status_t build_runs_compact(const float* xyz, const int64_t* offsets,
 
 static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t S_, int64_t n,
                                double v, double cell, hipStream_t st, Scratch& scr,
-                               GridView* out, uint32_t* oor, uint32_t* order = nullptr) {
+                               GridView* out, uint32_t* oor, uint32_t* order = nullptr,
+                               float4* sorted_in = nullptr) {
   Runs r;
   uint32_t* sid = nullptr;
   bool compact = false;
@@ -1819,7 +1848,10 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   Slot* slots;
   float4* sorted;
   FAR_TRY(scr.get(&slots, size_t(n_slots)));
-  FAR_TRY(scr.get(&sorted, size_t(n)));
+  if (sorted_in)
+    sorted = sorted_in;   // the caller's packed A words: the sorted points are exactly those
+  else
+    FAR_TRY(scr.get(&sorted, size_t(n)));
   FAR_HIP(hipMemsetAsync(slots, 0xFF, size_t(n_slots) * sizeof(Slot), st));
   k_gather_sorted<<<unsigned(((blocks_for(n) + 7) / 8) * 8), kT, 0, st>>>(xyz, n, vals, sorted,
                                                                         order);
@@ -1833,7 +1865,7 @@ static far_status_t build_grid(const float* xyz, const int64_t* offsets, int32_t
   FAR_TRY(scr.get(&nbt, size_t(n) * 27));
   *out = GridView{slots, sorted, keys, sid, r.seg_start, r.seg_end, v, cell, 1.0 / cell, pow2,
                   S_ > 1 ? offsets : nullptr, uint32_t(n_slots), mx, r.head, r.head_scan,
-                  nbt, r.counters + 2};
+                  nbt, r.counters + 2, nullptr, nullptr};
   k_grid_claim<<<kGridBlocks, kT, 0, st>>>(*out, slots);
   FAR_HIP(hipGetLastError());
   k_grid_nbr_table<<<kGridBlocks, kT, 0, st>>>(*out, nbt);
@@ -1848,12 +1880,18 @@ static int32_t g_dense_threshold = 0;
 static far_status_t scan_cov_impl(const float* xyz, const int64_t* offsets, int32_t S_,
                                   int64_t n, double voxel_size, int32_t k, float* cov6,
                                   uint8_t* valid, hipStream_t st, const char* who,
-                                  uint32_t* order = nullptr) {
+                                  uint32_t* order = nullptr, void* packed = nullptr) {
   Scratch scr(st);
   TimedScope ts(FAR_TIME_COVARIANCES, st);
   GridView g{};
   uint32_t oor = 0;
-  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor, order));
+  char* pk = static_cast<char*>(packed);
+  FAR_TRY(build_grid(xyz, offsets, S_, n, voxel_size, voxel_size, st, scr, &g, &oor, order,
+                     reinterpret_cast<float4*>(pk)));
+  if (pk) {
+    g.pk_B = reinterpret_cast<float4*>(pk + 16 * n);
+    g.pk_C = reinterpret_cast<float2*>(pk + 32 * n);
+  }
   if (oor > 0) {
     set_error("%s: %u points have voxel keys outside [-2^20, 2^20)", who, oor);
     return FAR_E_INVALID;
@@ -1912,6 +1950,22 @@ far_status_t far_scan_covariances_batch_order(const float* xyz, const int64_t* o
   if (n_total == 0) return FAR_OK;
   return scan_cov_impl(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid, S(stream),
                        "far_scan_covariances_batch_order", order);
+}
+
+far_status_t far_scan_covariances_batch_packed(const float* xyz, const int64_t* offsets,
+                                               int32_t S_, int64_t n_total, double voxel_size,
+                                               int32_t k, float* cov6, uint8_t* valid,
+                                               void* packed, far_stream_t stream) {
+  if (S_ < 1 || !offsets || n_total < 0 || n_total >= (int64_t(1) << 31) ||
+      !(voxel_size > 0.0) || k < 1 || k > 32 ||
+      (n_total > 0 && (!xyz || !cov6 || !valid || !packed)) ||
+      (reinterpret_cast<uintptr_t>(packed) & 15) != 0) {
+    set_error("far_scan_covariances_batch_packed: invalid argument");
+    return FAR_E_INVALID;
+  }
+  if (n_total == 0) return FAR_OK;
+  return scan_cov_impl(xyz, offsets, S_, n_total, voxel_size, k, cov6, valid, S(stream),
+                       "far_scan_covariances_batch_packed", nullptr, packed);
 }
 
 far_status_t far_voxel_downsample(const float* xyz, int64_t n, double v, float* out,

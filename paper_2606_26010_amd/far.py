@@ -94,6 +94,8 @@ _SIGS = {
                                              C.c_int32, _P, _P, _P]),
     "far_scan_covariances_batch_order": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double,
                                                    C.c_int32, _P, _P, _P, _P]),
+    "far_scan_covariances_batch_packed": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_double,
+                                                    C.c_int32, _P, _P, _P, _P]),
     "far_set_covariance_regularisation": (C.c_int, [C.c_int32]),
     "far_get_covariance_regularisation": (C.c_int, [C.POINTER(C.c_int32)]),
     "far_timing_enable": (C.c_int, [C.c_int32]),
@@ -122,6 +124,8 @@ _SIGS = {
                                        C.POINTER(far_align_params_t), _P, _P]),
     "far_gicp_align_batch_ordered": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, _P, _P,
                                                _P, C.POINTER(far_align_params_t), _P, _P]),
+    "far_gicp_align_batch_packed": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P,
+                                              C.POINTER(far_align_params_t), _P, _P]),
     "far_map_stats": (C.c_int, [_P, C.POINTER(far_map_stats_t), _P]),
     "far_map_export": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
     "far_voxel_downsample": (C.c_int, [_P, C.c_int64, C.c_double, _P, _P,
@@ -304,6 +308,28 @@ def far_scan_covariances_batch_order(xyz, offsets, voxel_size, k, order, out=Non
                                       order=order)
 
 
+def far_scan_covariances_batch_packed(xyz, offsets, voxel_size, k, packed, out=None,
+                                      stream=None):
+    """far_scan_covariances_batch that also writes the align's packed source
+    into packed (a float32 tensor of 10 n values on the GPU: A float4 [n],
+    B float4 [n], C float2 [n] in the grid's order)."""
+    p, n = _pts(xyz)
+    S = offsets.shape[0] - 1
+    if out is None:
+        cov = torch.empty((6, n), dtype=torch.float32, device=xyz.device)
+        val = torch.empty(n, dtype=torch.uint8, device=xyz.device)
+    else:
+        cov, val = out
+    if packed.numel() != 10 * n:
+        raise ValueError("packed must hold 10 floats per point")
+    _check(lib().far_scan_covariances_batch_packed(
+        p, _dev(offsets, torch.int64, "offsets"), S, n, voxel_size, k,
+        _dev(cov, torch.float32, "cov6"), _dev(val, torch.uint8, "valid"),
+        _dev(packed, torch.float32, "packed"), _stream(stream)),
+        "far_scan_covariances_batch_packed")
+    return cov, val
+
+
 FAR_REG_EQ1, FAR_REG_PLANE = 0, 1
 
 
@@ -484,6 +510,23 @@ def far_gicp_align_batch_ordered(h, src, offsets, cov6, valid, order, T,
     """far_gicp_align_batch with the source packed in the given order."""
     return far_gicp_align_batch(h, src, offsets, cov6, valid, T, params, stats=stats,
                                 stream=stream, order=order)
+
+
+def far_gicp_align_batch_packed(h, packed, offsets, T, params: far_align_params_t, stats=None,
+                                stream=None):
+    """far_gicp_align_batch on a source already packed by
+    far_scan_covariances_batch_packed (packed: float32 [10 n] on the GPU)."""
+    n = packed.numel() // 10
+    S = offsets.shape[0] - 1
+    if stats is None:
+        stats = torch.empty(S * STATS_DTYPE.itemsize, dtype=torch.uint8, device=packed.device)
+    _check(lib().far_gicp_align_batch_packed(h, _dev(packed, torch.float32, "packed"),
+                                             _dev(offsets, torch.int64, "offsets"), S, n,
+                                             _dev(T, torch.float64, "T"), C.byref(params),
+                                             _dev(stats, torch.uint8, "stats"),
+                                             _stream(stream)),
+           "far_gicp_align_batch_packed")
+    return stats
 
 
 def decode_stats(stats: torch.Tensor):

@@ -124,3 +124,49 @@ def test_ordered_align_matches_oracle_and_repeats(batch, orc):
     dt = max(float(np.linalg.norm(Tb[s][:3, 3] - To[s][:3, 3])) for s in range(len(scans)))
     assert dt <= 1e-4
     print(f"ordered align: 4 runs identical, own-sort align within {dt:.2e} m", flush=True)
+
+
+def test_packed_source_equals_ordered_pack(batch):
+    """far_scan_covariances_batch_packed writes the align's packed source in
+    the grid's order; the align on it equals the ordered align bit for bit."""
+    far, c, gm, om, scans, offs = batch
+    pts = np.concatenate(scans, 1)
+    n = pts.shape[1]
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cov, val = far.far_scan_covariances_batch_order(dev(pts), dev(offs), c.voxel_size, c.k,
+                                                    order)
+    packed = torch.empty(10 * n, dtype=torch.float32, device="cuda")
+    cov_p, val_p = far.far_scan_covariances_batch_packed(dev(pts), dev(offs), c.voxel_size,
+                                                         c.k, packed)
+    np.testing.assert_array_equal(host(cov_p), host(cov))
+    np.testing.assert_array_equal(host(val_p), host(val))
+    o = host(order).astype(np.int64)
+    pk = host(packed)
+    A = pk[:4 * n].reshape(n, 4)
+    B = pk[4 * n:8 * n].reshape(n, 4)
+    Cc = pk[8 * n:].reshape(n, 2)
+    np.testing.assert_array_equal(A[:, :3], pts[:, o].T)                   # x, y, z
+    np.testing.assert_array_equal(A[:, 3].view(np.int32), o)              # index bits
+    cv, vl = host(cov)[:, o], host(val)[o]
+    np.testing.assert_array_equal(B[:, 0], np.where(vl != 0, cv[0], -1.0).astype(np.float32))
+    np.testing.assert_array_equal(B[:, 1:], cv[1:4].T)
+    np.testing.assert_array_equal(Cc, cv[4:6].T)
+    T0 = dev(np.stack([t.reshape(16) for t in c.T0]))
+    prm = far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        Ta = T0.clone()
+        sa = far.decode_stats(far.far_gicp_align_batch_ordered(gm.h, dev(pts), dev(offs), cov,
+                                                              val, order, Ta, prm))
+        res = []
+        for _ in range(3):              # a direct launch, then the captured graph
+            Tp = T0.clone()
+            sp = far.decode_stats(far.far_gicp_align_batch_packed(gm.h, packed, dev(offs), Tp,
+                                                                 prm))
+            stream.synchronize()
+            res.append((host(Tp), sp))
+    for Tp, sp in res:
+        np.testing.assert_array_equal(Tp, host(Ta))
+        for key in ("iters", "status", "n_inliers", "cost"):
+            np.testing.assert_array_equal(sp[key], sa[key])
+    print(f"packed source: {n} points, align identical to the ordered align", flush=True)

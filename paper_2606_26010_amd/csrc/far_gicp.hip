@@ -564,56 +564,51 @@ struct Cand {
   float4 p;
 };
 
-// Walks from candidate c towards the query's nearest map point over the
-// certificates' neighbour lists: c moves to the best listed point while one
-// ranks before it by (d2, id), at most kCertWalks times.  True when c ends as
-// a point that ranks before all its listed points and lies closer than its
-// rho (its computed d2 below rho^2 (1 - 2^-30): the FP64 rounding of every
-// d2 is far below that margin), so no map point ranks before it.
+// Walks from candidate c (its slot; its d2 is taken from its row) towards
+// the query's nearest map point over the certificates' neighbour lists: c
+// moves to the best listed point while one ranks before it by (d2, id), at
+// most kCertWalks times.  True when c ends as a point that ranks before all
+// its listed points and lies closer than its rho (its computed d2 below
+// rho^2 (1 - 2^-30): the FP64 rounding of every d2 is far below that
+// margin), so no map point ranks before it.  Each step reads the one
+// 128-byte row of c's certificate; ids are read only to break a tie in d2.
 constexpr int kCertWalks = 2;
 
 __device__ inline bool certify(const MapView& m, const Query& q, Cand& c) {
-  static_assert(sizeof(CertRow) == 32 && kCertK == 7, "a row is two 16-byte loads");
-  const int4* rows = reinterpret_cast<const int4*>(m.cert);   // 2 int4 per row
+  static_assert(sizeof(CertRow) == 128 && kCertK == 7, "a row is eight 16-byte loads");
+  const float4* rows = reinterpret_cast<const float4*>(m.cert);
   for (int w = 0; w <= kCertWalks; ++w) {
-    const int4 r0 = rows[2 * int64_t(c.pos)];
-    const int4 r1 = rows[2 * int64_t(c.pos) + 1];
-    Cand best = c;
-    float bnd = screen_bound(c.d, q.m);
-    // the listed points in two groups of loads, to bound the registers
-    auto group = [&](const int32_t* nb, int cnt) {
-      float4 lp[4];
+    const float4* row = rows + 8 * int64_t(c.pos);
+    float4 e[8];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < cnt && nb[t] >= 0) lp[t] = m.vox_pts[nb[t]];
+    for (int t = 0; t < 8; ++t) e[t] = row[t];
+    if (w == 0) c.d = dist2(double(e[0].x), double(e[0].y), double(e[0].z), q.x, q.y, q.z);
+    int32_t bpos = c.pos;
+    double bd = c.d;
+    float bnd = screen_bound(bd, q.m);
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < cnt && nb[t] >= 0) {
-          const float dx = lp[t].x - q.fx, dy = lp[t].y - q.fy, dz = lp[t].z - q.fz;
-          const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-          if (d2f <= bnd) {
-            const double d = dist2(double(lp[t].x), double(lp[t].y), double(lp[t].z), q.x,
-                                   q.y, q.z);
-            const int32_t id = __float_as_int(lp[t].w);
-            if (rank_less(d, id, best.d, best.id)) {
-              best.d = d;
-              best.id = id;
-              best.pos = nb[t];
-              best.p = lp[t];
-              bnd = screen_bound(d, q.m);
-            }
-          }
+    for (int t = 1; t < 8; ++t) {
+      const int32_t pos = __float_as_int(e[t].w);
+      if (pos < 0) break;
+      const float dx = e[t].x - q.fx, dy = e[t].y - q.fy, dz = e[t].z - q.fz;
+      const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+      if (d2f <= bnd) {
+        const double d = dist2(double(e[t].x), double(e[t].y), double(e[t].z), q.x, q.y, q.z);
+        // distinct points: a tie in d2 goes to the smaller id
+        if (d < bd || (d == bd && __float_as_int(m.vox_pts[pos].w) <
+                                      __float_as_int(m.vox_pts[bpos].w))) {
+          bd = d;
+          bpos = pos;
+          bnd = screen_bound(d, q.m);
         }
-    };
-    const int32_t g0[4] = {r0.y, r0.z, r0.w, r1.x};
-    const int32_t g1[4] = {r1.y, r1.z, r1.w, -1};
-    group(g0, 4);
-    group(g1, 3);
-    if (best.pos == c.pos) {
-      const double rho = double(__int_as_float(r0.x));
+      }
+    }
+    if (bpos == c.pos) {
+      const double rho = double(e[0].w);
       return c.d < rho * rho * (1.0 - 0x1p-30);
     }
-    c = best;
+    c.pos = bpos;
+    c.d = bd;
   }
   return false;
 }
@@ -641,9 +636,6 @@ __device__ inline bool nn_cert_try(const MapView& m, double px, double py, doubl
     seed = t1.pos[0];
   }
   c.pos = seed;
-  c.p = m.vox_pts[seed];
-  c.id = __float_as_int(c.p.w);
-  c.d = dist2(double(c.p.x), double(c.p.y), double(c.p.z), px, py, pz);
   return certify(m, q, c);
 }
 

@@ -96,18 +96,22 @@ struct alignas(16) Slot {
 
 // Nearest-neighbour certificate of a map point, stored per slot of vox_pts
 // (voxel-major, so the certificates a search reads lie next to the points it
-// reads): the vox_pts slots of the point's kCertK nearest other map points
-// within v (-1 past the last) and rho, at most half the distance from the
-// point to every map point not in that list (v/2 when fewer than kCertK + 1
-// others lie within v), rounded down.  A query x whose distance to the
-// point q is below rho is farther than that from every unlisted point
-// (triangle inequality: |x - q''| >= |q - q''| - |x - q| >= 2 rho - |x - q|
-// > |x - q|), so q is x's nearest map point once it also ranks before every
-// listed point.
+// reads): the point's own coordinates and rho, then its kCertK nearest other
+// map points within v, each as (x, y, z, vox_pts slot bits) (slot -1 past
+// the last), so that a certificate reads one 128-byte row and no point by
+// its slot.  rho is at most half the distance from the point to every map
+// point not in that list (v/2 when fewer than kCertK + 1 others lie within
+// v), rounded down.  A query x whose distance to the point q is below rho is
+// farther than that from every unlisted point (triangle inequality:
+// |x - q''| >= |q - q''| - |x - q| >= 2 rho - |x - q| > |x - q|), so q is x's
+// nearest map point once it also ranks before every listed point.  A row
+// stays valid while the listed slots keep their points: an insert only adds
+// points to free slots (the rows of the points within v of an added point are
+// rebuilt) and an eviction, which moves points, rebuilds every row.
 constexpr int kCertK = 7;
-struct alignas(32) CertRow {
-  float rho;
-  int32_t nbr[kCertK];
+struct alignas(128) CertRow {
+  float x, y, z, rho;
+  float4 nbr[kCertK];
 };
 
 // Device view of a map, passed by value to kernels.

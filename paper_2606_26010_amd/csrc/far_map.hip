@@ -315,9 +315,10 @@ __global__ __launch_bounds__(kT) void k_cert_mark(int64_t n_seg, const int32_t* 
 // Certificate of every point of the marked voxels (all voxels when mark is
 // null), one lane per voxel slot: the kCertK + 1 nearest other points
 // within v by (d2, id) from the exact 27-voxel search (the point itself,
-// and so kCertK + 2 entries, included), the first kCertK listed, rho half
-// the distance of the next one (v/2 when there is none), shrunk by 2^-20
-// and rounded down to float so that it never exceeds the exact half distance.
+// and so kCertK + 2 entries, included), the first kCertK listed with their
+// coordinates, rho half the distance of the next one (v/2 when there is
+// none), shrunk by 2^-20 and rounded down to float so that it never exceeds
+// the exact half distance.
 __global__ __launch_bounds__(kT) void k_cert_build(MapView m, int64_t n_vox,
                                                    const uint32_t* mark, uint32_t gen,
                                                    CertRow* cert) {
@@ -330,15 +331,22 @@ __global__ __launch_bounds__(kT) void k_cert_build(MapView m, int64_t n_vox,
   TopK<kCertK + 2> top;
   map_knn_query<kCertK + 2>(m, double(p.x), double(p.y), double(p.z), m.v * m.v, top);
   CertRow r;
+  r.x = p.x;
+  r.y = p.y;
+  r.z = p.z;
   int n = 0;
   double next = -1.0;
 #pragma unroll
   for (int t = 0; t < kCertK + 2; ++t) {
     if (top.pos[t] < 0 || top.pos[t] == int32_t(pos)) continue;
-    if (n < kCertK) r.nbr[n++] = top.pos[t];
-    else if (next < 0.0) next = top.d[t];
+    if (n < kCertK) {
+      const float4 u = m.vox_pts[top.pos[t]];
+      r.nbr[n++] = make_float4(u.x, u.y, u.z, __int_as_float(top.pos[t]));
+    } else if (next < 0.0) {
+      next = top.d[t];
+    }
   }
-  for (int t = n; t < kCertK; ++t) r.nbr[t] = -1;
+  for (int t = n; t < kCertK; ++t) r.nbr[t] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
   const double half = 0.5 * (next >= 0.0 ? sqrt(next) : m.v) * (1.0 - 0x1p-20);
   r.rho = __double2float_rd(half);
   cert[pos] = r;

@@ -170,3 +170,61 @@ def test_packed_source_equals_ordered_pack(batch):
         for key in ("iters", "status", "n_inliers", "cost"):
             np.testing.assert_array_equal(sp[key], sa[key])
     print(f"packed source: {n} points, align identical to the ordered align", flush=True)
+
+
+def test_packed_source_ragged_and_empty_scans(batch):
+    """The packed path on a batch with an empty scan, a one-point scan and a
+    scan of non-finite points between two ordinary ones, and on a batch of
+    empty scans only: the packed words follow the grid's order, the align on
+    them equals the ordered align bit for bit, and every scan's status is the
+    one the align on the unsorted source gives."""
+    far, c, gm, om, scans, offs = batch
+    nan = np.full((3, 50), np.nan, np.float32)
+    parts = [scans[0][:, :5000], np.zeros((3, 0), np.float32), scans[1][:, :1], nan,
+             scans[3][:, :7000]]
+    pts = np.ascontiguousarray(np.concatenate(parts, 1))
+    off = np.concatenate([[0], np.cumsum([p.shape[1] for p in parts])]).astype(np.int64)
+    n = pts.shape[1]
+    S = len(parts)
+    T0 = dev(np.stack([c.T0[s % len(c.T0)].reshape(16) for s in range(S)]))
+    prm = far.align_params(c.tau, c.kappa, max_iters=c.max_iters, eps=0.0)
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    cov, val = far.far_scan_covariances_batch_order(dev(pts), dev(off), c.voxel_size, c.k, order)
+    packed = torch.empty(10 * n, dtype=torch.float32, device="cuda")
+    cov_p, val_p = far.far_scan_covariances_batch_packed(dev(pts), dev(off), c.voxel_size, c.k,
+                                                         packed)
+    np.testing.assert_array_equal(host(cov_p), host(cov))
+    np.testing.assert_array_equal(host(val_p), host(val))
+    o = host(order).astype(np.int64)
+    A = host(packed)[:4 * n].reshape(n, 4)
+    np.testing.assert_array_equal(A[:, 3].view(np.int32), o)
+    fin = np.isfinite(pts[:, o]).all(0)
+    np.testing.assert_array_equal(A[fin, :3], pts[:, o].T[fin])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        To, Tu, Tp = T0.clone(), T0.clone(), T0.clone()
+        so = far.decode_stats(far.far_gicp_align_batch_ordered(gm.h, dev(pts), dev(off), cov, val,
+                                                              order, To, prm))
+        su = far.decode_stats(far.far_gicp_align_batch(gm.h, dev(pts), dev(off), cov, val, Tu,
+                                                      prm))
+        sp = far.decode_stats(far.far_gicp_align_batch_packed(gm.h, packed, dev(off), Tp, prm))
+        stream.synchronize()
+    np.testing.assert_array_equal(host(Tp), host(To))
+    for key in ("iters", "status", "n_inliers", "cost"):
+        np.testing.assert_array_equal(sp[key], so[key])
+    np.testing.assert_array_equal(sp["status"], su["status"])
+    for s in (1, 2, 3):                                  # nothing to align: T untouched
+        assert sp["status"][s] != 0
+        np.testing.assert_array_equal(host(Tp)[s], host(T0)[s])
+    # a batch of empty scans only
+    off0 = dev(np.zeros(3, np.int64))
+    empty = torch.empty(0, dtype=torch.float32, device="cuda")
+    T2 = T0[:2].clone()
+    far.far_scan_covariances_batch_packed(torch.empty((3, 0), dtype=torch.float32,
+                                                      device="cuda"), off0, c.voxel_size, c.k,
+                                          empty)
+    s0 = far.decode_stats(far.far_gicp_align_batch_packed(gm.h, empty, off0, T2, prm))
+    torch.cuda.synchronize()
+    assert (s0["status"] != 0).all()
+    np.testing.assert_array_equal(host(T2), host(T0[:2]))
+    print(f"packed source, ragged batch of {n} points: statuses {[int(x) for x in sp['status']]}", flush=True)

@@ -760,7 +760,7 @@ def main():
                       "load_factor": mstats["load_factor"]},
     }
     result["roofline"]["kernel"] = (
-        f"linearisation at tile {tile}: k_zero_bins + k_cert<{tile}> + k_search + "
+        f"linearisation at tile {tile}: k_cert<{tile}> + k_search + "
         f"k_linearize<{'double' if prec == far.FAR_PREC_FP64 else 'float'}, false, {tile}, "
         f"false, false, false> (the first iteration: k_linearize<..., true> with its own search)")
     print(json.dumps(result), flush=True)

@@ -716,10 +716,6 @@ struct Queue {
   int64_t cap;        // kBins * bin_cap
 };
 
-__global__ __launch_bounds__(64) void k_zero_bins(uint32_t* count) {
-  if (threadIdx.x < kBins) count[threadIdx.x] = 0;
-}
-
 // Pass 1, one block of kB lanes per tile: match[i] receives the vox_pts slot
 // of point i's match when the certificates settle it (-1: none), prev[i] the
 // seed of the next iteration; the other points are queued in lane order.
@@ -1035,9 +1031,13 @@ __global__ __launch_bounds__(256) void k_reduce_solve(int32_t S, const int32_t* 
                                                       const double* partial, double* T,
                                                       double* ctr, int32_t* done,
                                                       far_align_stats_t* stats, Params prm,
-                                                      int32_t solve) {
+                                                      int32_t solve, uint32_t* bins) {
+  // the next iteration's queue starts empty (this iteration's search has
+  // read its bins)
+  if (bins && blockIdx.x == 0 && threadIdx.x < kBins) bins[threadIdx.x] = 0u;
   // eight groups of 32 lanes: group g sums tiles begin+g, begin+g+8, ... of
-  // the scan, then the eight group sums are added in group order
+  // the scan in that order, then the eight group sums are added in group
+  // order; the loads go out sixteen at a time (the sums wait on them)
   __shared__ double part[8][kVals];
   __shared__ double lin[kVals];
   const int32_t s = blockIdx.x;
@@ -1046,8 +1046,15 @@ __global__ __launch_bounds__(256) void k_reduce_solve(int32_t S, const int32_t* 
   if (v < kVals) {
     double acc = 0.0;
     const int32_t t1 = begin[s + 1];
-#pragma unroll 4
-    for (int32_t t = begin[s] + g; t < t1; t += 8) acc += partial[int64_t(t) * kStride + v];
+    int32_t t = begin[s] + g;
+    for (; t + 8 * 15 < t1; t += 8 * 16) {
+      double x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) x[u] = partial[int64_t(t + 8 * u) * kStride + v];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += x[u];
+    }
+    for (; t < t1; t += 8) acc += partial[int64_t(t) * kStride + v];
     part[g][v] = acc;
   }
   __syncthreads();
@@ -1379,9 +1386,8 @@ far_status_t launch_lin(int32_t tile, int64_t grid, hipStream_t st, const MapVie
   const float4* pB = j.in_A ? j.in_B : w->pB;
   const float2* pC = j.in_A ? j.in_C : w->pC;
   if (!search) {
+    // the bins were cleared by the solve of the previous iteration
     Queue Q{w->q_idx, w->q_cand, w->q_p, w->q_count, w->q_bin_cap, kBins * w->q_bin_cap};
-    k_zero_bins<<<1, 64, 0, st>>>(w->q_count);
-    FAR_HIP(hipGetLastError());
     const bool loop = grid < vgrid;
     switch (tile * 2 + (loop ? 1 : 0)) {
 #define FAR_CERT_CASE(B, L)                                                               \
@@ -1502,7 +1508,8 @@ far_status_t enqueue(far_map_s* m, AlignWS* w, const Job& j, int64_t max_tiles,
         FAR_TRY((launch_lin<float, false>(j.tile, grid, st, mv, w, max_tiles, j, it == 0)));
     }
     k_reduce_solve<<<unsigned(j.S), 256, 0, st>>>(j.S, w->begin, w->partial, j.T, w->ctr,
-                                                  w->done, j.stats, j.prm, j.c_fixed ? 0 : 1);
+                                                  w->done, j.stats, j.prm, j.c_fixed ? 0 : 1,
+                                                  it + 1 < iters ? w->q_count : nullptr);
     FAR_HIP(hipGetLastError());
   }
   return FAR_OK;

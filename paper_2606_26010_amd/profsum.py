@@ -6,7 +6,7 @@
 
 `trace` prints calls, total and average duration per kernel.  `counters`
 prints, per GN-iteration linearisation of the batched align (its passes
-k_zero_bins, k_cert, k_search and the term pass k_linearize), the totals of
+k_cert, k_search and the term pass k_linearize), the totals of
 every counter the given runs collected, divided by the number of
 linearisations (term-pass dispatches), with the bytes moved between the L2
 and the fabric (Infinity Cache and HBM) from the request-size counters:
@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SOURCES = ["paper_2606_26010_amd/csrc/far_gicp.hip", "paper_2606_26010_amd/csrc/far_knn.h",
                   "paper_2606_26010_amd/csrc/far_internal.h"]
-LIN_PASSES = ("k_zero_bins", "k_cert<", "k_search", "k_linearize<")
+LIN_PASSES = ("k_cert<", "k_search", "k_linearize<")
 
 
 def short(name):
@@ -69,7 +69,7 @@ def counters(tile, paths):
         sys.exit(f"linearisation counts differ between runs or are zero: {n_lin}")
     per = {k: v / n for k, v in tot.items()}
     out = {"kernel_sources_sha256_16": fingerprint(), "tile": str(tile),
-           "kernels": "k_zero_bins+k_cert+k_search+k_linearize", "linearisations": n}
+           "kernels": "k_cert+k_search+k_linearize", "linearisations": n}
     g = per.get
     if "TCC_EA0_RDREQ_128B_sum" in per:
         out["fabric_read_bytes"] = (32 * g("TCC_EA0_RDREQ_32B_sum", 0) +

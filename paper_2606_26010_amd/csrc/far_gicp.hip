@@ -789,11 +789,13 @@ __global__ __launch_bounds__(kB) void k_cert(
 
 // Pass 2: the exact 27-voxel search of every queued point, one per lane,
 // lanes striding over the bins in order (bin of entry g from an LDS prefix
-// of the bin counts), so that the searches fill whole waves.
+// of the bin counts), so that the searches fill whole waves.  Five waves
+// per SIMD (at most 96 registers, five blocks' LDS rows per CU): the
+// searches wait on chains of loads, so more waves in flight hide more.
 constexpr int kSearchThreads = 256;
-__global__ __launch_bounds__(kSearchThreads) void k_search(MapView m, Queue Q, Params prm,
-                                                           int32_t* __restrict__ match,
-                                                           int32_t* __restrict__ prev) {
+__global__ __launch_bounds__(kSearchThreads, 5) void k_search(MapView m, Queue Q, Params prm,
+                                                              int32_t* __restrict__ match,
+                                                              int32_t* __restrict__ prev) {
   __shared__ uint32_t pre[kBins + 1];
   __shared__ uint32_t rows[kSearchThreads * kRowWords];
   if (threadIdx.x < 64) {

@@ -853,7 +853,8 @@ __global__ __launch_bounds__(kSearchThreads, 5) void k_search(MapView m, Queue Q
 // kNoSA (the sparsity-aware case off) is a template parameter: a run-time
 // test in the match block costs the default path 8 %.
 template <class Real, bool kGrad, int kB, bool kFine, bool kNoSA, bool kSearch, bool kLoop>
-__global__ __launch_bounds__(kB) void k_linearize(
+__global__ __launch_bounds__(kB, (kSearch && !kGrad && !kFine && !kLoop && sizeof(Real) == 4) ? 8 : 1)
+void k_linearize(
     MapView m, const float4* __restrict__ pA, const float4* __restrict__ pB,
     const float2* __restrict__ pC, const int32_t* __restrict__ tile_scan,
     const uint32_t* __restrict__ tile_lo, const uint32_t* __restrict__ tile_hi,

@@ -56,7 +56,7 @@ def counters(tile, paths):
         lin = set()
         for r in csv.DictReader(open(p)):
             k = short(r["Kernel_Name"])
-            if not (k.startswith(LIN_PASSES[1:]) or k == LIN_PASSES[0]):
+            if not k.startswith(LIN_PASSES):
                 continue
             if k.startswith("k_linearize<"):
                 targs = [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")]

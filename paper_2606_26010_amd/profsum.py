@@ -60,8 +60,9 @@ def counters(tile, paths):
                 continue
             if k.startswith("k_linearize<"):
                 targs = [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")]
-                if targs[1] == "false":     # not the gradient
-                    lin.add(r["Dispatch_Id"])
+                if targs[1] != "false":     # the gradient's term pass is no linearisation
+                    continue
+                lin.add(r["Dispatch_Id"])
             tot[r["Counter_Name"]] += float(r["Counter_Value"])
         n_lin[p] = len(lin)
     n = max(n_lin.values()) if n_lin else 0

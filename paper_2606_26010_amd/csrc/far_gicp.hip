@@ -680,7 +680,9 @@ struct Pose {
 __device__ inline bool locate(const float4& a, const Pose& P, const MapView& m,
                               const Params& prm, double& px, double& py, double& pz,
                               int64_t& kx, int64_t& ky, int64_t& kz) {
-  if (!(isfinite(a.x) && isfinite(a.y) && isfinite(a.z))) return false;
+  // the three tests at once (a short-circuit test loads the coordinates one
+  // after the other, a memory round trip each)
+  if (!(isfinite(a.x) & isfinite(a.y) & isfinite(a.z))) return false;
   const double sx = a.x, sy = a.y, sz = a.z;
   px = ((P.R[0] * sx + P.R[1] * sy) + P.R[2] * sz) + P.tx;
   py = ((P.R[3] * sx + P.R[4] * sy) + P.R[5] * sz) + P.ty;
@@ -743,12 +745,15 @@ __global__ __launch_bounds__(kB) void k_cert(
     int32_t qc = -1;
     double px = 0.0, py = 0.0, pz = 0.0;
     if (i < hi) {
+      // the point and its seed are loaded together, ahead of the transform
+      const float4 a = pA[i];
+      const int32_t seed = prev[i];
       int64_t kx = 0, ky = 0, kz = 0;   // within [-2^20, 2^20) once locate holds
-      const bool have = locate(pA[i], P, m, prm, px, py, pz, kx, ky, kz);
+      const bool have = locate(a, P, m, prm, px, py, pz, kx, ky, kz);
       Cand c;
       c.pos = -1;
       if (have && !nn_cert_try(m, px, py, pz, int32_t(kx), int32_t(ky), int32_t(kz), prm.r2,
-                               prev[i], c)) {
+                               seed, c)) {
         queued = true;
         qc = c.pos;
       } else {

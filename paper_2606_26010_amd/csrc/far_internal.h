@@ -94,6 +94,21 @@ struct alignas(16) Slot {
                   // 16-byte probe yields key, voxel and count; scan grid: scan id
 };
 
+// A slot in one memory round trip.  Read field by field (or even as one
+// 16-byte vector), the compiler fetches the key, compares it and only then
+// fetches voxel and count; the empty asm statement takes those two words
+// where the load is, so all four arrive together.
+__device__ inline Slot load_slot(const Slot* p) {
+  const uint4 w = *reinterpret_cast<const uint4*>(p);
+  uint32_t vox = w.z, aux = w.w;
+  asm volatile("" : "+v"(vox), "+v"(aux));
+  Slot s;
+  s.key = uint64_t(w.x) | (uint64_t(w.y) << 32);
+  s.vox = int32_t(vox);
+  s.aux = int32_t(aux);
+  return s;
+}
+
 // Nearest-neighbour certificate of a map point, stored per slot of vox_pts
 // (voxel-major, so the certificates a search reads lie next to the points it
 // reads): the point's own coordinates and rho, then its kCertK nearest other
@@ -161,7 +176,7 @@ __device__ inline int32_t ghost_find(const MapView& m, int64_t kx, int64_t ky, i
   const uint64_t key = pack_key(kx, ky, kz);
   uint32_t s = voxel_hash(kx, ky, kz, m.glog2);
   for (uint32_t probe = 0; probe <= m.gmask; ++probe) {
-    const Slot sl = m.gslots[s];
+    const Slot sl = load_slot(&m.gslots[s]);
     if (sl.key == key) return sl.vox;
     if (sl.key == kEmptyKey) return -1;
     s = (s + 1) & m.gmask;
@@ -177,7 +192,7 @@ __device__ inline int32_t fine_find(const MapView& m, int64_t kx, int64_t ky, in
   const uint64_t key = pack_key(kx, ky, kz);
   uint32_t s = voxel_hash(kx, ky, kz, m.fine_log2);
   for (uint32_t probe = 0; probe <= m.fine_mask; ++probe) {
-    const Slot sl = m.fine_slots[s];
+    const Slot sl = load_slot(&m.fine_slots[s]);
     if (sl.key == key) {
       *cnt = sl.aux;
       return sl.vox;
@@ -197,7 +212,7 @@ __device__ inline int32_t map_find(const MapView& m, int64_t kx, int64_t ky, int
   uint64_t key = pack_key(kx, ky, kz);
   uint32_t s = voxel_hash(kx, ky, kz, m.log2_slots);
   for (uint32_t probe = 0; probe <= m.slot_mask; ++probe) {
-    const Slot sl = m.slots[s];
+    const Slot sl = load_slot(&m.slots[s]);
     if (sl.key == key) {
       *cnt = sl.aux;
       return sl.vox;

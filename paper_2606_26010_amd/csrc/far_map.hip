@@ -732,7 +732,7 @@ __device__ inline int32_t grid_find(const GridView& g, int64_t kx, int64_t ky, i
   grid_part(g, sid, &base, &size);
   uint32_t s = grid_hash(kx, ky, kz, size);
   for (uint32_t probe = 0; probe < size; ++probe) {
-    const Slot sl = g.slots[base + s];
+    const Slot sl = load_slot(&g.slots[base + s]);
     if (sl.key == key) {
       *cnt = sl.aux;
       return sl.vox;

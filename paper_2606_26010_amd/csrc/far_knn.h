@@ -282,11 +282,14 @@ __device__ inline void scan_run_x(const float4* pts, int32_t st, int32_t cnt, in
   bool ra = r < e, la = l >= st;
   while (ra || la) {
     const bool u0 = ra, u1 = ra && r + 1 < e, u2 = la, u3 = la && l - 1 >= st;
-    float4 p0, p1, p2, p3;
-    if (u0) p0 = pts[r];
-    if (u1) p1 = pts[r + 1];
-    if (u2) p2 = pts[l];
-    if (u3) p3 = pts[l - 1];
+    // the four loads unconditional, at indices clamped into the run (the
+    // loop runs only on a run of at least one point), so that they go out
+    // together: loads under their own conditions were issued one after the
+    // other, each waiting for the one before
+    const float4 p0 = pts[min(r, e - 1)];
+    const float4 p1 = pts[min(r + 1, e - 1)];
+    const float4 p2 = pts[max(l, st)];
+    const float4 p3 = pts[max(l - 1, st)];
     auto rank_one = [&](const float4& pp, int32_t at) {
       const float dx = pp.x - q.fx, dy = pp.y - q.fy, dz = pp.z - q.fz;
       const float d2f = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
